@@ -1,0 +1,149 @@
+"""Oracle PISO pins (paper Sec. "PISO as divergence-free constrained message passing" and
+"Windkessel RCR outlet condition"): exact conservation identities, analytic flows, and the exact
+exponential Windkessel update."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15920_amd import meshgen as mg
+
+
+def lid_values(m, speed=1.0):
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    lid = m.patch("lid")
+    Ub[lid.start - Fi:lid.start - Fi + lid.size, 0] = speed
+    return Ub
+
+
+def test_cavity_conservation_identities():
+    """Closed cavity: boundary fluxes vanish exactly (lid faces have S_x = 0, walls have U_b = 0);
+    the z velocity of the 2D case stays exactly zero; the continuity error is the final pressure
+    residual, so it sits at the solver tolerance."""
+    m = mg.cavity(16)
+    Ub = lid_values(m)
+    prm = O.piso_params(0.01, 1e-3, tol_p=1e-10)
+    U, p = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
+    phi = O.initial_flux(m, U, Ub)
+    U, p, phi, pc, it, res, st = O.piso_run(m, prm, U, p, phi, Ub, np.zeros(m.n_boundary_faces), nsteps=5)
+    assert st == 0
+    Fi = m.n_internal_faces
+    assert np.all(phi[Fi:] == 0.0)
+    assert np.all(U[:, 2] == 0.0)
+    D = O.div(m, phi, table=O.TABLE_U)
+    scale = O.div(m, np.abs(phi), table=O.TABLE_U, absterms=True)
+    assert np.abs(D).max() <= 1e-7 * scale.max()
+    assert np.all(it[:, 3:] > 0) and np.all(res[:, 3:] <= 1e-10)
+    # the lid drags the fluid along +x next to it: positive net x-momentum in the top row
+    top = m.C[:, 1] > 1 - 1.0 / 16
+    assert (m.V[top] * U[top, 0]).sum() > 0
+
+
+def _poiseuille(ny, nu=0.05, dt=0.05, length=3.0, nsteps=100):
+    m = mg.quad_channel(int(length * ny), ny, length)
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    inl = m.patch("inlet")
+    y = m.Cf[inl.start:inl.start + inl.size, 1]
+    Ub[inl.start - Fi:inl.start - Fi + inl.size, 0] = 4 * y * (1 - y)
+    prm = O.piso_params(nu, dt, tol_p=1e-10, tol_u=1e-10, maxit_p=5000)
+    U, p = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
+    phi = O.initial_flux(m, U, Ub)
+    U, p, phi, pc, it, res, st = O.piso_run(m, prm, U, p, phi, Ub, np.zeros(m.n_boundary_faces), nsteps=nsteps)
+    assert st == 0
+    x, yc = m.C[:, 0], m.C[:, 1]
+    sel = (x > 1.0) & (x < 2.0)
+    e = U[sel, 0] - 4 * yc[sel] * (1 - yc[sel])
+    eu = math.sqrt((m.V[sel] * e * e).sum() / m.V[sel].sum())
+    A = np.stack([x[sel], np.ones(sel.sum())], 1)
+    dpdx = np.linalg.lstsq(A, p[sel], rcond=None)[0][0]
+    return eu, dpdx / (-8 * nu)
+
+
+def test_poiseuille_channel():
+    """Plane Poiseuille flow u = 4 Umax y(1-y)/H^2, dp/dx = -8 nu Umax / H^2, from rest with a
+    parabolic inlet and p = 0 at the outlet: the developed section converges to it at second order."""
+    r = [_poiseuille(ny) for ny in (8, 16, 32)]
+    eu = [a for a, _ in r]
+    assert eu[1] < 0.01
+    assert abs(r[1][1] - 1.0) < 0.02 and abs(r[2][1] - 1.0) < 0.005
+    orders = [math.log2(eu[i] / eu[i + 1]) for i in range(2)]
+    assert min(orders) >= 1.5, (eu, orders)
+
+
+def _taylor_green(n, amp=1.0, nu=0.05, dt=0.01, nsteps=20):
+    h = math.pi
+    m = mg.hex_box(n, n, 1, A=np.diag([h, h, h / n]), origin=(-h / 2, -h / 2, 0.0),
+                   patches={s: ("walls", mg.U_FIXED, mg.P_ZEROGRAD, -1) for s in ("x0", "x1", "y0", "y1")}
+                   | {s: ("frontAndBack", mg.U_EMPTY, mg.P_EMPTY, -1) for s in ("z0", "z1")})
+    Fi = m.n_internal_faces
+
+    def exact(x, t):
+        F = amp * math.exp(-2 * nu * t)
+        u = np.zeros((x.shape[0], 3))
+        u[:, 0] = -np.cos(x[:, 0]) * np.sin(x[:, 1]) * F
+        u[:, 1] = np.sin(x[:, 0]) * np.cos(x[:, 1]) * F
+        return u
+    prm = O.piso_params(nu, dt, tol_p=1e-11, tol_u=1e-11, maxit_p=5000)
+    U = exact(m.C, 0.0)
+    p = -0.25 * amp * amp * (np.cos(2 * m.C[:, 0]) + np.cos(2 * m.C[:, 1]))
+    phi = O.initial_flux(m, U, exact(m.Cf[Fi:], 0.0))
+    ke0 = (m.V * (U ** 2).sum(1)).sum()
+    for k in range(nsteps):
+        Ub = exact(m.Cf[Fi:], (k + 1) * dt)     # wall values at the new time level
+        U, p, phi, pc, it, res, st = O.piso_run(m, prm, U, p, phi, Ub, np.zeros(m.n_boundary_faces), nsteps=1)
+        assert st == 0
+    T = nsteps * dt
+    ke = (m.V * (U ** 2).sum(1)).sum()
+    e = U - exact(m.C, T)
+    l2 = math.sqrt((m.V * (e ** 2).sum(1)).sum() / m.V.sum())
+    return ke / ke0, math.exp(-4 * nu * T), l2
+
+
+def test_taylor_green_decay():
+    """Taylor-Green vortex on [-pi/2, pi/2]^2 with the exact velocity on the walls (time-varying
+    fixed values) and zeroGradient p (exact, dp/dn = 0 there).  At low amplitude (Re ~ 0.6) the
+    kinetic energy decays as exp(-4 nu t) within 1 % and the field error converges at second order;
+    at unit amplitude first-order upwind convection dominates and the error converges at first order."""
+    r = [_taylor_green(n, amp=0.01) for n in (16, 32, 64)]
+    for ratio, expect, _ in r:
+        assert abs(ratio / expect - 1) < 0.001, r
+    l2 = [c for _, _, c in r]
+    orders = [math.log2(l2[i] / l2[i + 1]) for i in range(2)]
+    assert orders[0] >= 1.3 and orders[1] >= 1.7, (l2, orders)
+    r = [_taylor_green(n, amp=1.0) for n in (16, 32)]
+    assert abs(r[1][0] / r[1][1] - 1) < 0.02, r
+    assert math.log2(r[0][2] / r[1][2]) >= 0.8, r
+
+
+def test_windkessel_exact_exponential():
+    """With a steady inflow the outlet flow is constant from the second step on (continuity), and the
+    capacitor pressure follows the ODE's closed form p_c(t) = Rd Q + (p_c(t1) - Rd Q) exp(-(t-t1)/(Rd C))
+    at every step (eq. windkessel_discrete is exact for piecewise-constant Q)."""
+    m = mg.quad_channel(12, 4, 3.0)
+    m.patch("outlet").p_type = mg.P_WINDKESSEL
+    m.patch("outlet").wk_id = 0
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    inl = m.patch("inlet")
+    y = m.Cf[inl.start:inl.start + inl.size, 1]
+    Ub[inl.start - Fi:inl.start - Fi + inl.size, 0] = 4 * y * (1 - y)
+    Q = -(Ub[inl.start - Fi:inl.start - Fi + inl.size] * m.Sf[inl.start:inl.start + inl.size]).sum()
+    Rp, Cc, Rd, dt = 0.3, 0.7, 2.0, 0.05
+    prm = O.piso_params(0.05, dt, tol_p=1e-12, tol_u=1e-12)
+    U, p = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
+    phi = O.initial_flux(m, U, Ub)
+    pc = np.array([0.25])
+    hist = []
+    for k in range(12):
+        U, p, phi, pc, it, res, st = O.piso_run(m, prm, U, p, phi, Ub, np.zeros(m.n_boundary_faces),
+                                                wk=np.array([[Rp, Cc, Rd]]), pc=pc, nsteps=1)
+        hist.append(pc[0])
+    hist = np.array(hist)
+    t = dt * np.arange(1, 12)
+    closed = Rd * Q + (hist[0] - Rd * Q) * np.exp(-t / (Rd * Cc))
+    np.testing.assert_allclose(hist[1:], closed, rtol=1e-9)
+    outlet = m.patch("outlet")
+    np.testing.assert_allclose(phi[outlet.start:outlet.start + outlet.size].sum(), Q, rtol=1e-9)
