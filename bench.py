@@ -1,0 +1,260 @@
+"""Benchmark: FP64 PISO steps/s on the 1,053,696-tet Kuhn cube (56^3 hexes, node jitter 0.15h) set up
+as a channel (parabolic inlet at x=0, Windkessel RCR outlet at x=1, no-slip walls), two correctors,
+PCG tol 1e-8, BiCGStab momentum.  Also reports per-operator throughput on the same mesh in FP64 and
+FP32 (faces/s and fraction of the 8 TB/s HBM roofline), the roofline of the dominant kernel measured
+live with HIP events, and the CPU oracle timed on the host on a bounded sample.
+
+Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PISO steps/s & faces/s/operator at 1M cells FP64 (% HBM peak); adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def channel_setup(mg, n=56, seed=2603002):
+    m = mg.kuhn_cube(n, jitter=0.15, patches="channel", seed=seed)
+    Fi = m.n_internal_faces
+    import numpy as np
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    inl = m.patch("inlet")
+    c = m.Cf[inl.start:inl.start + inl.size]
+    Ub[inl.start - Fi:inl.start - Fi + inl.size, 0] = 16 * c[:, 1] * (1 - c[:, 1]) * c[:, 2] * (1 - c[:, 2])
+    q_in = -float((Ub[inl.start - Fi:inl.start - Fi + inl.size] * m.Sf[inl.start:inl.start + inl.size]).sum())
+    # nominal RCR for a single outlet: Rd = 1/Q, Rp = Rd/9, C = tau/Rd with tau = 0.1
+    Rd = 1.0 / q_in
+    wk = (Rd / 9.0, 0.1 / Rd, Rd)
+    return m, Ub, wk, q_in
+
+
+# algorithmic bytes per launch (each input read once, each output written once; int32 indices)
+def op_bytes(op, nfi, nfb, nc, fp):
+    i4 = 4
+    if op == "grad":
+        return nfi * (2 * i4 + fp + 3 * fp) + nfb * (i4 + 3 * fp + fp) + nc * (fp + fp + 3 * fp)
+    if op == "laplacian":
+        return nfi * (2 * i4 + fp + 3 * fp + fp) + nfb * (i4 + fp + fp) + nc * (fp + 3 * fp + fp)
+    if op == "div_upwind_vec":
+        return nfi * (2 * i4 + fp) + nfb * (i4 + fp + 3 * fp) + nc * (3 * fp + 3 * fp)
+    if op == "spmv":
+        return nfi * (2 * i4 + fp + fp) + nc * 3 * fp
+    if op == "spmv_sym":
+        return nfi * (2 * i4 + fp) + nc * 3 * fp
+    if op == "interp":
+        return nfi * (2 * i4 + fp + fp) + nfb * (i4 + fp + fp) + nc * fp
+    raise KeyError(op)
+
+
+def operator_sweep(B, M, m, torch, reps=30):
+    """Per-operator kernel time with HIP events on the launch stream; the 256 MB Infinity Cache is
+    flushed by a 1 GiB write before every timed launch (cold numbers), warm numbers back to back."""
+    import numpy as np
+    from paper_2603_15920_amd import meshgen as mg
+    nc, nfi, nfb = m.n_cells, m.n_internal_faces, m.n_boundary_faces
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dtype=dt)
+    f = mg.sinusoid_field(2603012)
+    phi_u = f(m.C)
+    phib_u = f(m.Cf[nfi:])
+    U_u = np.stack([mg.sinusoid_field(2603013 + k)(m.C) for k in range(3)], 1)
+    Ub_u = np.stack([mg.sinusoid_field(2603013 + k)(m.Cf[nfi:]) for k in range(3)], 1)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+    out = {}
+    s = torch.cuda.current_stream()
+    for dt, tag, fp in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
+        phi = M.to_internal(dev(phi_u, dt), B.KIND_CELL)
+        phib = M.to_internal(dev(phib_u, dt), B.KIND_BFACE)
+        U = M.to_internal(dev(U_u, dt), B.KIND_CELL)
+        Ub = M.to_internal(dev(Ub_u, dt), B.KIND_BFACE)
+        g = torch.empty((nc, 3), dtype=dt, device="cuda:0")
+        B.difvm_op_grad(M.h, 1, B.BC_ALL_FIXED, phi, phib, g)
+        Uf = torch.empty((nfi + nfb, 3), dtype=dt, device="cuda:0")
+        B.difvm_op_interp(M.h, 3, B.BC_ALL_FIXED, U, Ub, Uf)
+        # face flux F = U_f . S in internal order (built from the library's interpolation, only as input)
+        S = torch.from_numpy(np.ascontiguousarray(m.Sf)).to("cuda:0", dtype=dt)
+        flux = M.to_internal((M.to_user(Uf, B.KIND_FACE) * S).sum(1).contiguous(), B.KIND_FACE_FLUX)
+        diag = torch.full((nc,), 6.0, dtype=dt, device="cuda:0")
+        up = -torch.rand(nfi, dtype=dt, device="cuda:0")
+        lo = -torch.rand(nfi, dtype=dt, device="cuda:0")
+        o1 = torch.empty(nc, dtype=dt, device="cuda:0")
+        o3 = torch.empty((nc, 3), dtype=dt, device="cuda:0")
+        of = torch.empty(nfi + nfb, dtype=dt, device="cuda:0")
+        A = B.ldu(diag, up, lo)
+        As = B.ldu(diag, up)
+        ops = {
+            "grad": lambda: B.difvm_op_grad(M.h, 1, B.BC_ALL_FIXED, phi, phib, o3),
+            "laplacian": lambda: B.difvm_op_laplacian(M.h, B.BC_ALL_FIXED, None, phi, g, phib, o1),
+            "div_upwind_vec": lambda: B.difvm_op_div(M.h, B.SCHEME_UPWIND, 3, B.BC_ALL_FIXED, flux, U, Ub, o3),
+            "spmv": lambda: B.difvm_ldu_spmv(M.h, 1, 0, A, phi, o1),
+            "spmv_sym": lambda: B.difvm_ldu_spmv(M.h, 1, 0, As, phi, o1),
+            "interp": lambda: B.difvm_op_interp(M.h, 1, B.BC_ALL_FIXED, phi, phib, of),
+        }
+        for name, fn in ops.items():
+            for _ in range(5):
+                fn()
+            cold = []
+            for _ in range(reps):
+                flush.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                fn()
+                e1.record(s)
+                e1.synchronize()
+                cold.append(e0.elapsed_time(e1) * 1e-3)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                fn()
+            e1.record(s)
+            e1.synchronize()
+            warm = e0.elapsed_time(e1) * 1e-3 / reps
+            tc = sorted(cold)[len(cold) // 2]
+            nbytes = op_bytes(name, nfi, nfb, nc, fp)
+            out[f"{name}_{tag}"] = {
+                "us_cold": round(tc * 1e6, 2), "us_warm": round(warm * 1e6, 2),
+                "faces_per_s": round(nfi / tc, 0), "alg_MB": round(nbytes / 1e6, 2),
+                "GBps_cold": round(nbytes / tc / 1e9, 1), "frac_hbm_cold": round(nbytes / tc / 1e9 / HBM_PEAK_GBS, 3),
+                "GBps_warm": round(nbytes / warm / 1e9, 1)}
+            log(name, tag, out[f"{name}_{tag}"])
+    del flush
+    return out
+
+
+def cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model or platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=56, help="hexes per side of the Kuhn cube")
+    ap.add_argument("--no-ops", action="store_true", help="skip the per-operator sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing in this build uses a second GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_15920_amd import binding as B
+    from paper_2603_15920_amd import meshgen as mg
+
+    t0 = time.time()
+    m, Ub, wk, q_in = channel_setup(mg, args.n)
+    nc, nfi, nfb = m.n_cells, m.n_internal_faces, m.n_boundary_faces
+    log(f"mesh {nc} cells {nfi} internal faces {nfb} boundary faces ({time.time() - t0:.1f}s)")
+    nu, dt = 0.005, 1e-3   # Re = Umax L / nu = 200, diffusion number nu dt / h^2 = 0.016
+    ctx = B.Context(0)
+    M = B.Mesh(ctx, m)
+    log("device mesh", M.info)
+    prm = B.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
+    P = B.Piso(M, prm)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    P.set_boundary(dev(Ub), dev(np.zeros(nfb)))
+    P.set_windkessel(0, *wk, 0.0)
+    U0, p0 = np.zeros((nc, 3)), np.zeros(nc)
+    P.set_state(dev(U0), dev(p0), None)
+    torch.cuda.synchronize()
+
+    first_step_s = None
+    for k in range(args.warmup):
+        ts = time.time()
+        st, it, res = P.step(1)
+        torch.cuda.synchronize()
+        if k == 0:
+            first_step_s = time.time() - ts
+            first_iters = it[0].tolist()
+        log(f"warmup step {k}: {time.time() - ts:.3f}s iters {it[0].tolist()} status {st}")
+
+    B.difvm_ctx_profile(ctx.h, 1)
+    B.difvm_ctx_profile_read(ctx.h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, it, res = P.step(args.steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = B.difvm_ctx_profile_read(ctx.h)
+    B.difvm_ctx_profile(ctx.h, 0)
+    elapsed = t2 - t1
+    steps_per_s = args.steps / elapsed
+    log(f"timed {args.steps} steps in {elapsed:.3f}s -> {steps_per_s:.3f} steps/s; status {st}")
+    log("kernel events", prof)
+    pcg_iters = it[:, 3:].sum()
+
+    # dominant kernel: the PCG matrix-vector product with its p.q reduction
+    name = "pcg_spmv_dot"
+    launches, total_ms = prof.get(name, (0, 0.0))
+    avg_s = total_ms * 1e-3 / max(launches, 1)
+    alg = op_bytes("spmv_sym", nfi, nfb, nc, 8)
+    achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = None
+    roofline = {"bound": "hbm", "kernel": "k_pcg_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                "active_iterations": int(pcg_iters)}
+    phase_ms = {k: round(v[1], 3) for k, v in prof.items()}
+
+    ops = None
+    if not args.no_ops:
+        ops = operator_sweep(B, M, m, torch)
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        oprm = O.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
+        phi0 = O.initial_flux(m, U0, Ub)
+        tc = time.time()
+        r = O.piso_run(m, oprm, U0, p0, phi0, Ub, np.zeros(nfb), wk=np.array([wk]), pc=np.zeros(1), nsteps=1)
+        tcpu = time.time() - tc
+        cpu = {"value": round(1.0 / tcpu, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"first PISO step from rest on the same mesh and setup (oracle iterations {r[4][0].tolist()}); "
+                         f"the GPU's first warm-up step took {first_step_s:.4f}s with iterations {first_iters}",
+               "seconds": round(tcpu, 2), "cpu_model": cpu_info(), "gpu_first_step_s": round(first_step_s, 4)}
+        log("cpu oracle", cpu)
+
+    line = {
+        "metric": METRIC, "value": round(steps_per_s, 4), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"PISO channel on the Kuhn cube {args.n}^3 hexes -> {nc} tets (jitter 0.15h), "
+                               "parabolic inlet, Windkessel outlet, Re 200, dt 1e-3, 2 correctors, PCG tol 1e-8",
+                   "cells": nc, "internal_faces": nfi, "boundary_faces": nfb, "nu": nu, "dt": dt, "n_corr": 2,
+                   "tol_p": 1e-8, "tol_u": 1e-8},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+                   "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st)},
+        "kernel_ms_timed_region": phase_ms,
+        "operators": ops,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

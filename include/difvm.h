@@ -1,0 +1,274 @@
+/* difvm.h -- C ABI of the MI355X face-graph finite-volume / PISO library.
+ *
+ * The library computes the hot path of DiFVM (arXiv 2603.15920): the finite-volume operators of an
+ * incompressible PISO step on an unstructured polyhedral mesh, written as gather/flux/aggregate
+ * passes over the mesh graph (paper Sec. "Graph-Based Reformulation of the FVM Solver"), and the
+ * Krylov solves inside the step.
+ *
+ * Conventions for every entry point
+ *  - Plain C: integers are int32, floating point is double (DIFVM_F64) or float (DIFVM_F32).
+ *  - "device" pointers are HIP device memory on the context's device (for example the data pointer
+ *    of a contiguous torch tensor); "host" pointers are ordinary CPU memory.
+ *  - Host arrays passed in are borrowed for the duration of the call and copied.  Device arrays are
+ *    owned by the caller and must stay alive until the work queued on the context's stream ends.
+ *  - Work is queued on the context's HIP stream and the call returns without waiting, except where
+ *    a function is documented to synchronise (mesh creation, exports, solves, PISO steps: these
+ *    wait because their Krylov loops read a convergence flag).
+ *  - Return value: 0 success; > 0 a warning with outputs written (e.g. not converged); < 0 an
+ *    error with outputs untouched.  difvm_last_error() gives a message for the calling thread.
+ *  - Field arrays passed to operators are in the library's INTERNAL order (cells renumbered by
+ *    reverse Cuthill-McKee, faces re-oriented and sorted); difvm_permute converts.  Vector fields
+ *    are cell-major [n][3]; gradients of an ncomp-component field are [n][ncomp][3].
+ *  - Boundary-face arrays are [n_boundary_faces * ncomp] in internal boundary order; values are read
+ *    only where the selected boundary table says "fixed value".
+ */
+#ifndef DIFVM_H
+#define DIFVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIFVM_ABI_VERSION 1
+
+typedef int32_t difvm_status;
+enum {
+  DIFVM_OK = 0,
+  DIFVM_WARN_NOT_CONVERGED = 1,
+  DIFVM_WARN_BREAKDOWN = 2,
+  DIFVM_ERR_INVALID_ARG = -1,
+  DIFVM_ERR_INVALID_MESH = -2,
+  DIFVM_ERR_HIP = -3,
+  DIFVM_ERR_OOM = -4,
+  DIFVM_ERR_UNSUPPORTED = -5,
+  DIFVM_ERR_NONFINITE = -6
+};
+
+enum { DIFVM_F64 = 0, DIFVM_F32 = 1 };
+
+/* boundary types per patch (paper Sec. "Supported Boundary Conditions"): fixedValue (Dirichlet),
+ * zeroGradient (Neumann), empty (2D front/back, excluded from every sum), Windkessel RCR outlet */
+enum { DIFVM_U_FIXED = 0, DIFVM_U_ZEROGRAD = 1, DIFVM_U_EMPTY = 2 };
+enum { DIFVM_P_ZEROGRAD = 0, DIFVM_P_FIXED = 1, DIFVM_P_WINDKESSEL = 2, DIFVM_P_EMPTY = 3 };
+
+/* which boundary table an operator uses: the patches' velocity types, their pressure types
+ * (Windkessel counts as fixed), or every non-empty face fixed / zeroGradient */
+enum { DIFVM_BC_U = 0, DIFVM_BC_P = 1, DIFVM_BC_ALL_FIXED = 2, DIFVM_BC_ALL_ZEROGRAD = 3 };
+
+/* face value used by the divergence operator (eqs. conv_face_flux, upwind) */
+enum { DIFVM_SCHEME_ONE = 0, DIFVM_SCHEME_UPWIND = 1, DIFVM_SCHEME_LINEAR = 2 };
+
+/* array kinds for difvm_permute */
+enum {
+  DIFVM_KIND_CELL = 0,      /* [n_cells * ncomp]                                                 */
+  DIFVM_KIND_FACE = 1,      /* [(n_internal + n_boundary) * ncomp], values (no sign change)      */
+  DIFVM_KIND_FACE_FLUX = 2, /* as FACE, but a re-oriented internal face changes sign (fluxes)    */
+  DIFVM_KIND_BFACE = 3      /* [n_boundary * ncomp]                                              */
+};
+enum { DIFVM_TO_INTERNAL = 0, DIFVM_FROM_INTERNAL = 1 };
+
+#define DIFVM_RENUMBER_RCM 1u
+
+typedef struct difvm_ctx difvm_ctx;
+typedef struct difvm_mesh difvm_mesh;
+typedef struct difvm_piso difvm_piso;
+
+int difvm_abi_version(void);
+const char* difvm_last_error(void);
+
+/* ---- context ------------------------------------------------------------------------------
+ * device: HIP device ordinal.  hip_stream: a hipStream_t (NULL = the default stream).  The context
+ * owns nothing of the caller's; destroy waits for its stream. */
+difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out);
+difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream);
+difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
+
+/* Kernel timing for benchmarks.  While enabled, each launch of the library's solver kernels inside
+ * difvm_solve_* and difvm_piso_step is bracketed by a pair of HIP events on the context's stream (the
+ * stream the kernels run on).  difvm_ctx_profile_read synchronises, returns per-kernel launch counts
+ * and summed event durations (kernel names in out[k].name), and clears the record. */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  double total_ms;
+} difvm_kernel_time;
+difvm_status difvm_ctx_profile(difvm_ctx* ctx, int enable);
+difvm_status difvm_ctx_profile_read(difvm_ctx* ctx, difvm_kernel_time* out, int32_t max_out, int32_t* n_out);
+
+/* ---- mesh ----------------------------------------------------------------------------------
+ * The paper's static graph (Sec. "Structural isomorphism ... static graph construction"): owner and
+ * neighbour per face, face area vectors Sf pointing out of the owner, face centroids Cf, cell
+ * centroids C, cell volumes V, and boundary patches.  Faces [0, Fi) are internal; boundary faces
+ * [Fi, Fi+Fb) are grouped in patches that tile that range in order.  w is the owner interpolation
+ * weight per internal face; NULL means w = S.(C_N - C_f) / S.(C_N - C_O) (the point where the line
+ * between the two centroids meets the face plane).  All arrays are HOST memory in user order. */
+typedef struct {
+  int32_t start, size;   /* boundary-face range [start, start+size), absolute face indices  */
+  int32_t u_type;        /* DIFVM_U_*                                                        */
+  int32_t p_type;        /* DIFVM_P_*                                                        */
+  int32_t windkessel_id; /* >= 0 for DIFVM_P_WINDKESSEL patches, else -1                     */
+} difvm_patch;
+
+typedef struct {
+  size_t struct_size; /* sizeof(difvm_mesh_desc) */
+  int32_t n_cells, n_internal_faces, n_boundary_faces, n_patches;
+  const int32_t* owner;     /* [Fi+Fb]       */
+  const int32_t* neighbour; /* [Fi]          */
+  const double* Sf;         /* [(Fi+Fb)*3]   */
+  const double* Cf;         /* [(Fi+Fb)*3]   */
+  const double* C;          /* [Nc*3]        */
+  const double* V;          /* [Nc]          */
+  const double* w;          /* [Fi] or NULL  */
+  const difvm_patch* patches;
+} difvm_mesh_desc;
+
+typedef struct {
+  int32_t n_cells, n_internal_faces, n_boundary_faces, n_patches;
+  int32_t n_slices, n_slots;        /* cell-slot layout: 64-cell slices, one slot per non-empty face side */
+  int32_t bandwidth_in, bandwidth_out; /* max |O-N| before and after renumbering */
+  int32_t n_windkessel;
+  int32_t has_fixed_p;              /* 1 if some face carries a fixed or Windkessel pressure */
+} difvm_mesh_info;
+
+/* Host-only renumbering (no device needed): reverse Cuthill-McKee cell order (flag
+ * DIFVM_RENUMBER_RCM; 0 keeps the order), internal faces re-oriented so owner < neighbour (a flip
+ * negates S and maps w to 1-w) and sorted by (owner, neighbour), boundary faces stably sorted by new
+ * owner inside each patch, and the neighbour-sorted face list ("losort").  Outputs are host arrays
+ * (new -> old where a permutation): cell_perm[Nc], face_perm[Fi], face_flip[Fi], owner[Fi],
+ * neighbour[Fi], own_start[Nc+1], losort[Fi], losort_start[Nc+1], bface_perm[Fb] (indices within the
+ * boundary block), bowner[Fb].  Optional (NULL to skip) permuted geometry: S[(Fi+Fb)*3], w[Fi],
+ * delta[Fi+Fb] (|S|^2/(S.d), boundary d = Cf - C_O), k[Fi*3] (S - delta d, eq. nonortho_flux). */
+difvm_status difvm_mesh_renumber_host(const difvm_mesh_desc* desc, uint32_t flags, int32_t* cell_perm,
+                                      int32_t* face_perm, uint8_t* face_flip, int32_t* owner, int32_t* neighbour,
+                                      int32_t* own_start, int32_t* losort, int32_t* losort_start,
+                                      int32_t* bface_perm, int32_t* bowner, double* S, double* w, double* delta,
+                                      double* k);
+
+/* Validates, renumbers and uploads a mesh (synchronises).  Errors: DIFVM_ERR_INVALID_MESH for
+ * counts that do not match, patches that do not tile the boundary block, indices out of range,
+ * neighbour == owner, V <= 0 or S.d <= 0 on a non-empty face. */
+difvm_status difvm_mesh_create(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, difvm_mesh** out);
+difvm_status difvm_mesh_get_info(const difvm_mesh* mesh, difvm_mesh_info* info);
+difvm_status difvm_mesh_destroy(difvm_mesh* mesh); /* NULL is a no-op; waits for the stream */
+
+/* Reorders a field between user and internal order (device arrays, src != dst). */
+difvm_status difvm_permute(const difvm_mesh* mesh, int dtype, int ncomp, int kind, int dir, const void* src,
+                           void* dst);
+
+/* ---- operators (device arrays, internal order; dtype F64 or F32) -------------------------- */
+
+/* Linear face interpolation (Sec. "Spatial discretization", the face value of eq. gauss_green):
+ * phi_f = w phi_O + (1-w) phi_N; boundary: fixed -> phi_b, zeroGradient -> phi_O, empty -> 0.
+ * phi[Nc*ncomp] -> phi_f[(Fi+Fb)*ncomp]. */
+difvm_status difvm_op_interp(const difvm_mesh* mesh, int dtype, int ncomp, int bc, const void* phi,
+                             const void* phi_b, void* phi_f);
+
+/* Gauss-Green gradient (eq. gauss_green): G_i = (1/V_i) sum_f sigma phi_f S_f with phi_f from the
+ * linear interpolation above.  phi[Nc*ncomp] -> grad[Nc*ncomp*3]. */
+difvm_status difvm_op_grad(const difvm_mesh* mesh, int dtype, int ncomp, int bc, const void* phi, const void* phi_b,
+                           void* grad);
+
+/* Face-sum divergence (eqs. conv_face_flux, upwind, aggregate): D_i = sum_f sigma F_f psi_f, not
+ * divided by V.  flux[Fi+Fb] (internal orientation), psi[Nc*ncomp], psi_b[Fb*ncomp] ->
+ * out[Nc*ncomp].  Upwind picks the owner value when F >= 0. */
+difvm_status difvm_op_div(const difvm_mesh* mesh, int dtype, int scheme, int ncomp, int bc, const void* flux,
+                          const void* psi, const void* psi_b, void* out);
+
+/* Laplacian with over-relaxed non-orthogonal correction (eqs. diff_ortho, nonortho_flux):
+ * L_i = sum_f sigma G_f [delta_f (phi_N - phi_O) + k_f . (w g_O + (1-w) g_N)]
+ *       + sum_{b fixed} G_b delta_b (phi_b - phi_O).
+ * gamma_f[Fi+Fb] or NULL (= 1), phi[Nc], grad_phi[Nc*3] (given), phi_b[Fb] -> out[Nc]. */
+difvm_status difvm_op_laplacian(const difvm_mesh* mesh, int dtype, int bc, const void* gamma_f, const void* phi,
+                                const void* grad_phi, const void* phi_b, void* out);
+
+/* LDU matrix (OpenFOAM-style, the form behind eq. Ap_H): diag[Nc], upper[Fi] (row owner, column
+ * neighbour), lower[Fi] (row neighbour, column owner); lower == NULL means symmetric. */
+typedef struct {
+  int32_t dtype;
+  void* diag;
+  void* upper;
+  void* lower;
+} difvm_ldu;
+
+/* y = A x (transpose = 0) or A^T x; x, y [Nc*ncomp], ncomp in {1, 3}. */
+difvm_status difvm_ldu_spmv(const difvm_mesh* mesh, int ncomp, int transpose, const difvm_ldu* A, const void* x,
+                            void* y);
+
+/* SPD orthogonal part of -div(G grad phi) (F64): upper_f = -G_f delta_f, diag = sum G_f delta_f +
+ * sum_{b fixed} G_b delta_b, rhs_bc = sum_{b fixed} G_b delta_b phi_b.  A->lower is not written. */
+difvm_status difvm_ldu_assemble_laplace(const difvm_mesh* mesh, int bc, const void* gamma_f, const void* phi_b,
+                                        difvm_ldu* A, void* rhs_bc);
+
+/* Momentum matrix of the implicit predictor (F64): implicit Euler, implicit upwind convection of the
+ * lagged flux, implicit orthogonal diffusion; b carries V/dt U^n, fixed-value boundary terms and the
+ * explicit non-orthogonal diffusion from grad(U^n).  flux[Fi+Fb], U[Nc*3], U_b[Fb*3] (velocity
+ * table) -> A (diag, upper, lower), b[Nc*3]. */
+difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* mesh, double nu, double dt, const void* flux,
+                                         const void* U, const void* U_b, difvm_ldu* A, void* b);
+
+typedef struct {
+  int32_t iters[3];
+  double residual[3]; /* final ||r||_2 / ||b||_2 per component */
+  int32_t status;
+} difvm_solve_stats;
+
+/* Jacobi-preconditioned CG on a symmetric F64 LDU matrix (A->lower ignored).  Stops when
+ * ||r||_2 <= tol ||b||_2 (checked before the first iteration and after each update); b = 0 gives
+ * x = 0.  x holds the initial guess on entry.  Synchronises; stats is a host struct (may be NULL). */
+difvm_status difvm_solve_pcg(const difvm_mesh* mesh, const difvm_ldu* A, const void* b, void* x, double tol,
+                             int32_t maxit, difvm_solve_stats* stats);
+
+/* Right-Jacobi BiCGStab (van der Vorst) on an F64 LDU matrix, ncomp in {1, 3} independent systems
+ * sharing the matrix (b, x interleaved [Nc*ncomp]).  Same stopping rule and synchronisation. */
+difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, int ncomp, const void* b, void* x,
+                                  double tol, int32_t maxit, difvm_solve_stats* stats);
+
+/* ---- PISO (paper Sec. "PISO as divergence-free constrained message passing") --------------- */
+typedef struct {
+  size_t struct_size;     /* sizeof(difvm_piso_params) */
+  double nu, dt;          /* kinematic viscosity, time step (p is kinematic, rho = 1)        */
+  int32_t n_corr;         /* pressure correctors per step (paper: typically 2), 1..8        */
+  double tol_p, tol_u;    /* relative residual tolerances of the pressure / momentum solves  */
+  int32_t maxit_p, maxit_u;
+  int32_t p_ref_cell;     /* user cell fixing the pressure level when no pressure is fixed  */
+  double p_ref_value;
+} difvm_piso_params;
+
+typedef struct {
+  int32_t it_u[3];
+  double res_u[3];
+  int32_t it_p[8];
+  double res_p[8];
+  int32_t status;
+} difvm_step_stats;
+
+difvm_status difvm_piso_create(const difvm_mesh* mesh, const difvm_piso_params* params, difvm_piso** out);
+difvm_status difvm_piso_destroy(difvm_piso* piso);
+
+/* Fixed boundary values in USER boundary order, device arrays: U_b[Fb*3] (read on fixed-U faces),
+ * p_b[Fb] (read on fixed-p faces); either may be NULL to keep the current values (initially 0).
+ * May be called between steps (time-varying inflow). */
+difvm_status difvm_piso_set_boundary(difvm_piso* piso, const void* U_b, const void* p_b);
+
+/* Three-element Windkessel of outlet id (eqs. windkessel_ode, windkessel_discrete): proximal
+ * resistance Rp, compliance C, distal resistance Rd, capacitor pressure pc. */
+difvm_status difvm_piso_set_windkessel(difvm_piso* piso, int32_t id, double Rp, double C, double Rd, double pc);
+
+/* State in USER order (device arrays): U[Nc*3], p[Nc], phi[Fi+Fb] (user orientation).  phi == NULL
+ * in set_state computes phi = interp(U).S with boundary values from the velocity table.
+ * get_state also returns the Windkessel capacitor pressures to pc_host[n_windkessel] (may be NULL);
+ * it synchronises. */
+difvm_status difvm_piso_set_state(difvm_piso* piso, const void* U, const void* p, const void* phi);
+difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi, double* pc_host);
+
+/* Advances nsteps time steps.  stats_host[nsteps] (may be NULL) receives solver iterations and
+ * residuals per step.  Synchronises.  Returns the worst solver status over the steps. */
+difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats* stats_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFVM_H */

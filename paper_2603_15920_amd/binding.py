@@ -1,0 +1,439 @@
+"""ctypes binding of libdifvm.so (include/difvm.h).  Argument marshalling only: every computation runs
+in the library's HIP kernels.  Device arrays are contiguous torch tensors on the context's device;
+torch supplies memory and the stream.
+
+The ``difvm_*`` functions mirror the C entry points one to one (raising ``DifvmError`` on a negative
+status and returning warnings); ``Context``, ``Mesh`` and ``Piso`` own the C handles.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdifvm.so")
+
+F64, F32 = 0, 1
+BC_U, BC_P, BC_ALL_FIXED, BC_ALL_ZEROGRAD = 0, 1, 2, 3
+SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
+KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
+TO_INTERNAL, FROM_INTERNAL = 0, 1
+RENUMBER_RCM = 1
+OK, WARN_NOT_CONVERGED, WARN_BREAKDOWN = 0, 1, 2
+ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED, ERR_NONFINITE = -1, -2, -3, -4, -5, -6
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+_vp = C.c_void_p
+
+
+class DifvmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"difvm status {status}: {msg}")
+        self.status = status
+
+
+class Patch(C.Structure):
+    _fields_ = [("start", C.c_int32), ("size", C.c_int32), ("u_type", C.c_int32), ("p_type", C.c_int32),
+                ("windkessel_id", C.c_int32)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("n_cells", C.c_int32), ("n_internal_faces", C.c_int32),
+                ("n_boundary_faces", C.c_int32), ("n_patches", C.c_int32), ("owner", _i32p), ("neighbour", _i32p),
+                ("Sf", _f64p), ("Cf", _f64p), ("C", _f64p), ("V", _f64p), ("w", _f64p), ("patches", C.POINTER(Patch))]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_cells", "n_internal_faces", "n_boundary_faces", "n_patches", "n_slices",
+                                          "n_slots", "bandwidth_in", "bandwidth_out", "n_windkessel", "has_fixed_p")]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("total_ms", C.c_double)]
+
+
+class Ldu(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("diag", _vp), ("upper", _vp), ("lower", _vp)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 3), ("residual", C.c_double * 3), ("status", C.c_int32)]
+
+
+class PisoParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("nu", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
+                ("tol_p", C.c_double), ("tol_u", C.c_double), ("maxit_p", C.c_int32), ("maxit_u", C.c_int32),
+                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("it_u", C.c_int32 * 3), ("res_u", C.c_double * 3), ("it_p", C.c_int32 * 8), ("res_p", C.c_double * 8),
+                ("status", C.c_int32)]
+
+
+_LIB = None
+
+_SIGS = {
+    "difvm_abi_version": (C.c_int, []),
+    "difvm_last_error": (C.c_char_p, []),
+    "difvm_ctx_create": (C.c_int32, [C.c_int, _vp, C.POINTER(_vp)]),
+    "difvm_ctx_set_stream": (C.c_int32, [_vp, _vp]),
+    "difvm_ctx_destroy": (C.c_int32, [_vp]),
+    "difvm_ctx_profile": (C.c_int32, [_vp, C.c_int]),
+    "difvm_ctx_profile_read": (C.c_int32, [_vp, C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]),
+    "difvm_mesh_renumber_host": (C.c_int32, [C.POINTER(MeshDesc), C.c_uint32] + [_vp] * 14),
+    "difvm_mesh_create": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.POINTER(_vp)]),
+    "difvm_mesh_get_info": (C.c_int32, [_vp, C.POINTER(MeshInfo)]),
+    "difvm_mesh_destroy": (C.c_int32, [_vp]),
+    "difvm_permute": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp]),
+    "difvm_op_interp": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "difvm_op_grad": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "difvm_op_div": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
+    "difvm_op_laplacian": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "difvm_ldu_spmv": (C.c_int32, [_vp, C.c_int, C.c_int, C.POINTER(Ldu), _vp, _vp]),
+    "difvm_ldu_assemble_laplace": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.POINTER(Ldu), _vp]),
+    "difvm_ldu_assemble_momentum": (C.c_int32, [_vp, C.c_double, C.c_double, _vp, _vp, _vp, C.POINTER(Ldu), _vp]),
+    "difvm_solve_pcg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
+    "difvm_solve_bicgstab": (C.c_int32, [_vp, C.POINTER(Ldu), C.c_int, _vp, _vp, C.c_double, C.c_int32,
+                                         C.POINTER(SolveStats)]),
+    "difvm_piso_create": (C.c_int32, [_vp, C.POINTER(PisoParams), C.POINTER(_vp)]),
+    "difvm_piso_destroy": (C.c_int32, [_vp]),
+    "difvm_piso_set_boundary": (C.c_int32, [_vp, _vp, _vp]),
+    "difvm_piso_set_windkessel": (C.c_int32, [_vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
+    "difvm_piso_get_state": (C.c_int32, [_vp, _vp, _vp, _vp, _f64p]),
+    "difvm_piso_step": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
+}
+
+
+def lib():
+    """Load libdifvm.so (built in place by paper_2603_15920_amd/build.py).  Fails loudly if absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2603_15920_amd/build.py`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status, name):
+    if status < 0:
+        raise DifvmError(status, f"{name}: {lib().difvm_last_error().decode()}")
+    return status
+
+
+def _ptr(t):
+    """data pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+# ------------------------------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points
+# ------------------------------------------------------------------------------------------------
+def difvm_abi_version():
+    return lib().difvm_abi_version()
+
+
+def difvm_ctx_create(device=0, hip_stream=None):
+    out = _vp()
+    _check(lib().difvm_ctx_create(int(device), hip_stream, C.byref(out)), "difvm_ctx_create")
+    return out
+
+
+def difvm_ctx_set_stream(ctx, hip_stream):
+    _check(lib().difvm_ctx_set_stream(ctx, hip_stream), "difvm_ctx_set_stream")
+
+
+def difvm_ctx_destroy(ctx):
+    _check(lib().difvm_ctx_destroy(ctx), "difvm_ctx_destroy")
+
+
+def difvm_ctx_profile(ctx, enable):
+    _check(lib().difvm_ctx_profile(ctx, int(enable)), "difvm_ctx_profile")
+
+
+def difvm_ctx_profile_read(ctx):
+    """{kernel name: (launches, total ms)} since the last read (synchronises)."""
+    buf = (KernelTime * 64)()
+    n = C.c_int32(0)
+    _check(lib().difvm_ctx_profile_read(ctx, buf, 64, C.byref(n)), "difvm_ctx_profile_read")
+    return {buf[k].name.decode(): (buf[k].launches, buf[k].total_ms) for k in range(min(n.value, 64))}
+
+
+class _DescHolder:
+    pass
+
+
+def mesh_desc(mesh):
+    """difvm_mesh_desc over a meshgen.Mesh (host arrays kept alive by the returned holder)."""
+    h = _DescHolder()
+    h.owner = np.ascontiguousarray(mesh.owner, dtype=np.int32)
+    h.nbr = np.ascontiguousarray(mesh.neighbour, dtype=np.int32)
+    h.Sf = np.ascontiguousarray(mesh.Sf, dtype=np.float64)
+    h.Cf = np.ascontiguousarray(mesh.Cf, dtype=np.float64)
+    h.C = np.ascontiguousarray(mesh.C, dtype=np.float64)
+    h.V = np.ascontiguousarray(mesh.V, dtype=np.float64)
+    h.w = None if mesh.w is None else np.ascontiguousarray(mesh.w, dtype=np.float64)
+    h.patches = (Patch * max(1, len(mesh.patches)))(*[Patch(p.start, p.size, p.u_type, p.p_type, p.wk_id)
+                                                       for p in mesh.patches])
+    h.desc = MeshDesc(C.sizeof(MeshDesc), mesh.n_cells, mesh.n_internal_faces, mesh.n_boundary_faces,
+                      len(mesh.patches), h.owner.ctypes.data_as(_i32p), h.nbr.ctypes.data_as(_i32p),
+                      h.Sf.ctypes.data_as(_f64p), h.Cf.ctypes.data_as(_f64p), h.C.ctypes.data_as(_f64p),
+                      h.V.ctypes.data_as(_f64p), None if h.w is None else h.w.ctypes.data_as(_f64p), h.patches)
+    return h
+
+
+def difvm_mesh_renumber_host(mesh, flags=RENUMBER_RCM, geometry=False):
+    """Host-only renumbering; returns a dict of numpy arrays (no device used)."""
+    h = mesh_desc(mesh)
+    nc, nfi, nfb = mesh.n_cells, mesh.n_internal_faces, mesh.n_boundary_faces
+    out = dict(cell_perm=np.empty(nc, np.int32), face_perm=np.empty(nfi, np.int32), face_flip=np.empty(nfi, np.uint8),
+               owner=np.empty(nfi, np.int32), neighbour=np.empty(nfi, np.int32), own_start=np.empty(nc + 1, np.int32),
+               losort=np.empty(nfi, np.int32), losort_start=np.empty(nc + 1, np.int32),
+               bface_perm=np.empty(nfb, np.int32), bowner=np.empty(nfb, np.int32))
+    keys = list(out)
+    if geometry:
+        out.update(S=np.empty((nfi + nfb, 3)), w=np.empty(nfi), delta=np.empty(nfi + nfb), k=np.empty((nfi, 3)))
+    ptrs = [out[k].ctypes.data_as(_vp) for k in keys]
+    g = [out[k].ctypes.data_as(_vp) if geometry else None for k in ("S", "w", "delta", "k")]
+    _check(lib().difvm_mesh_renumber_host(C.byref(h.desc), int(flags), *ptrs, *g), "difvm_mesh_renumber_host")
+    return out
+
+
+def difvm_mesh_create(ctx, mesh, flags=RENUMBER_RCM):
+    h = mesh_desc(mesh)
+    out = _vp()
+    _check(lib().difvm_mesh_create(ctx, C.byref(h.desc), int(flags), C.byref(out)), "difvm_mesh_create")
+    return out
+
+
+def difvm_mesh_get_info(m):
+    info = MeshInfo()
+    _check(lib().difvm_mesh_get_info(m, C.byref(info)), "difvm_mesh_get_info")
+    return {n: getattr(info, n) for n, _ in MeshInfo._fields_}
+
+
+def difvm_mesh_destroy(m):
+    _check(lib().difvm_mesh_destroy(m), "difvm_mesh_destroy")
+
+
+def difvm_permute(m, ncomp, kind, direction, src, dst):
+    return _check(lib().difvm_permute(m, _dtype_code(src), int(ncomp), int(kind), int(direction), _ptr(src), _ptr(dst)),
+                  "difvm_permute")
+
+
+def difvm_op_interp(m, ncomp, bc, phi, phi_b, phi_f):
+    return _check(lib().difvm_op_interp(m, _dtype_code(phi), ncomp, bc, _ptr(phi), _ptr(phi_b), _ptr(phi_f)),
+                  "difvm_op_interp")
+
+
+def difvm_op_grad(m, ncomp, bc, phi, phi_b, grad):
+    return _check(lib().difvm_op_grad(m, _dtype_code(phi), ncomp, bc, _ptr(phi), _ptr(phi_b), _ptr(grad)),
+                  "difvm_op_grad")
+
+
+def difvm_op_div(m, scheme, ncomp, bc, flux, psi, psi_b, out):
+    return _check(lib().difvm_op_div(m, _dtype_code(flux), scheme, ncomp, bc, _ptr(flux), _ptr(psi), _ptr(psi_b),
+                                     _ptr(out)), "difvm_op_div")
+
+
+def difvm_op_laplacian(m, bc, gamma_f, phi, grad_phi, phi_b, out):
+    return _check(lib().difvm_op_laplacian(m, _dtype_code(phi), bc, _ptr(gamma_f), _ptr(phi), _ptr(grad_phi),
+                                           _ptr(phi_b), _ptr(out)), "difvm_op_laplacian")
+
+
+def ldu(diag, upper, lower=None):
+    """difvm_ldu over device tensors; the returned struct keeps the tensors alive."""
+    A = Ldu(_dtype_code(diag), _ptr(diag), _ptr(upper), _ptr(lower))
+    A._keep = (diag, upper, lower)
+    return A
+
+
+def difvm_ldu_spmv(m, ncomp, transpose, A, x, y):
+    return _check(lib().difvm_ldu_spmv(m, ncomp, int(transpose), C.byref(A), _ptr(x), _ptr(y)), "difvm_ldu_spmv")
+
+
+def difvm_ldu_assemble_laplace(m, bc, gamma_f, phi_b, A, rhs_bc):
+    return _check(lib().difvm_ldu_assemble_laplace(m, bc, _ptr(gamma_f), _ptr(phi_b), C.byref(A), _ptr(rhs_bc)),
+                  "difvm_ldu_assemble_laplace")
+
+
+def difvm_ldu_assemble_momentum(m, nu, dt, flux, U, U_b, A, b):
+    return _check(lib().difvm_ldu_assemble_momentum(m, float(nu), float(dt), _ptr(flux), _ptr(U), _ptr(U_b),
+                                                    C.byref(A), _ptr(b)), "difvm_ldu_assemble_momentum")
+
+
+def difvm_solve_pcg(m, A, b, x, tol, maxit):
+    st = SolveStats()
+    status = _check(lib().difvm_solve_pcg(m, C.byref(A), _ptr(b), _ptr(x), float(tol), int(maxit), C.byref(st)),
+                    "difvm_solve_pcg")
+    return status, st.iters[0], st.residual[0]
+
+
+def difvm_solve_bicgstab(m, A, ncomp, b, x, tol, maxit):
+    st = SolveStats()
+    status = _check(lib().difvm_solve_bicgstab(m, C.byref(A), ncomp, _ptr(b), _ptr(x), float(tol), int(maxit),
+                                               C.byref(st)), "difvm_solve_bicgstab")
+    return status, list(st.iters)[:ncomp], list(st.residual)[:ncomp]
+
+
+def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0):
+    return PisoParams(C.sizeof(PisoParams), nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value)
+
+
+def difvm_piso_create(m, params):
+    out = _vp()
+    _check(lib().difvm_piso_create(m, C.byref(params), C.byref(out)), "difvm_piso_create")
+    return out
+
+
+def difvm_piso_destroy(p):
+    _check(lib().difvm_piso_destroy(p), "difvm_piso_destroy")
+
+
+def difvm_piso_set_boundary(p, U_b, p_b):
+    _check(lib().difvm_piso_set_boundary(p, _ptr(U_b), _ptr(p_b)), "difvm_piso_set_boundary")
+
+
+def difvm_piso_set_windkessel(p, wid, Rp, Cc, Rd, pc):
+    _check(lib().difvm_piso_set_windkessel(p, int(wid), float(Rp), float(Cc), float(Rd), float(pc)),
+           "difvm_piso_set_windkessel")
+
+
+def difvm_piso_set_state(p, U, pres, phi):
+    _check(lib().difvm_piso_set_state(p, _ptr(U), _ptr(pres), _ptr(phi)), "difvm_piso_set_state")
+
+
+def difvm_piso_get_state(p, U, pres, phi, n_wk=0):
+    pc = (C.c_double * max(1, n_wk))()
+    _check(lib().difvm_piso_get_state(p, _ptr(U), _ptr(pres), _ptr(phi), pc), "difvm_piso_get_state")
+    return np.array(pc[:n_wk])
+
+
+def difvm_piso_step(p, nsteps, n_corr=2):
+    stats = (StepStats * max(1, nsteps))()
+    status = _check(lib().difvm_piso_step(p, int(nsteps), stats), "difvm_piso_step")
+    it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats[:nsteps]], dtype=np.int32)
+    res = np.array([[*s.res_u, *list(s.res_p)[:n_corr]] for s in stats[:nsteps]])
+    return status, it, res
+
+
+# ------------------------------------------------------------------------------------------------
+# owning handles
+# ------------------------------------------------------------------------------------------------
+class Context:
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.h = difvm_ctx_create(device, C.c_void_p(stream.cuda_stream))
+
+    def close(self):
+        if self.h:
+            difvm_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """A mesh uploaded to the device (internal order).  Keeps the meshgen.Mesh for user-order sizes."""
+
+    def __init__(self, ctx, mesh, flags=RENUMBER_RCM):
+        self.ctx = ctx
+        self.src = mesh
+        self.h = difvm_mesh_create(ctx.h, mesh, flags)
+        self.info = difvm_mesh_get_info(self.h)
+
+    def close(self):
+        if self.h:
+            difvm_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def to_internal(self, t, kind, ncomp=None):
+        import torch
+        ncomp = ncomp if ncomp is not None else (1 if t.dim() == 1 else int(np.prod(t.shape[1:])))
+        out = torch.empty_like(t)
+        difvm_permute(self.h, ncomp, kind, TO_INTERNAL, t.contiguous(), out)
+        return out
+
+    def to_user(self, t, kind, ncomp=None):
+        import torch
+        ncomp = ncomp if ncomp is not None else (1 if t.dim() == 1 else int(np.prod(t.shape[1:])))
+        out = torch.empty_like(t)
+        difvm_permute(self.h, ncomp, kind, FROM_INTERNAL, t.contiguous(), out)
+        return out
+
+
+class Piso:
+    def __init__(self, mesh, params):
+        self.mesh = mesh
+        self.params = params
+        self.h = difvm_piso_create(mesh.h, params)
+
+    def close(self):
+        if self.h:
+            difvm_piso_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_boundary(self, U_b=None, p_b=None):
+        difvm_piso_set_boundary(self.h, U_b, p_b)
+
+    def set_windkessel(self, wid, Rp, Cc, Rd, pc):
+        difvm_piso_set_windkessel(self.h, wid, Rp, Cc, Rd, pc)
+
+    def set_state(self, U, p, phi=None):
+        difvm_piso_set_state(self.h, U, p, phi)
+
+    def get_state(self):
+        import torch
+        src = self.mesh.src
+        dev = self.mesh.ctx.device
+        U = torch.empty((src.n_cells, 3), dtype=torch.float64, device=dev)
+        p = torch.empty(src.n_cells, dtype=torch.float64, device=dev)
+        phi = torch.empty(src.n_faces, dtype=torch.float64, device=dev)
+        pc = difvm_piso_get_state(self.h, U, p, phi, self.mesh.info["n_windkessel"])
+        return U, p, phi, pc
+
+    def step(self, nsteps=1):
+        return difvm_piso_step(self.h, nsteps, self.params.n_corr)

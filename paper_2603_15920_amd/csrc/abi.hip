@@ -1,0 +1,506 @@
+// C entry points of libdifvm (declared in include/difvm.h): argument checks, object lifetimes and
+// dispatch to the kernels.  No exception crosses this boundary.
+#include <cstring>
+#include <string>
+
+#include "abi_util.h"
+#include "ops.h"
+
+namespace difvm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void* dmalloc(size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+  if (e != hipSuccess) throw Error{DIFVM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+  return p;
+}
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static hipEvent_t pool_event(Profiler& P) {
+  if (!P.pool.empty()) {
+    hipEvent_t e = P.pool.back();
+    P.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  DIFVM_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int prof_begin(Ctx& c, const char* name) {
+  Profiler& P = c.prof;
+  if (!P.on) return -1;
+  int id = -1;
+  for (size_t k = 0; k < P.names.size(); ++k)
+    if (P.names[k] == name) id = (int)k;
+  if (id < 0) {
+    id = (int)P.names.size();
+    P.names.push_back(name);
+    P.total_ms.push_back(0.0);
+    P.launches.push_back(0);
+  }
+  Profiler::Rec r{id, pool_event(P), pool_event(P)};
+  DIFVM_HIP(hipEventRecord(r.a, c.stream));
+  P.pending.push_back(r);
+  return (int)P.pending.size() - 1;
+}
+
+void prof_end(Ctx& c, int handle) {
+  if (handle < 0) return;
+  (void)hipEventRecord(c.prof.pending[handle].b, c.stream);
+}
+
+static void prof_collect(Ctx& c) {
+  Profiler& P = c.prof;
+  if (P.pending.empty()) return;
+  DIFVM_HIP(hipStreamSynchronize(c.stream));
+  for (auto& r : P.pending) {
+    float ms = 0.f;
+    DIFVM_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    P.total_ms[r.id] += ms;
+    P.launches[r.id] += 1;
+    P.pool.push_back(r.a);
+    P.pool.push_back(r.b);
+  }
+  P.pending.clear();
+}
+
+// PISO functions (piso.hip)
+void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out);
+void piso_destroy(difvm_piso* P);
+void piso_set_boundary(difvm_piso* P, const double* Ub, const double* pb);
+void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, double pc);
+void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
+void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host);
+int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats);
+
+static void check_mesh(const difvm_mesh* m) { DIFVM_CHECK(m != nullptr, DIFVM_ERR_INVALID_ARG, "mesh is NULL"); }
+static void check_dtype(int dtype) {
+  DIFVM_CHECK(dtype == DIFVM_F64 || dtype == DIFVM_F32, DIFVM_ERR_INVALID_ARG, "dtype must be DIFVM_F64 or DIFVM_F32");
+}
+static void check_ncomp(int ncomp) { DIFVM_CHECK(ncomp == 1 || ncomp == 3, DIFVM_ERR_INVALID_ARG, "ncomp must be 1 or 3"); }
+static void check_bc(int bc) { DIFVM_CHECK(bc >= 0 && bc < N_TABLES, DIFVM_ERR_INVALID_ARG, "unknown boundary table"); }
+static void check_ptr(const void* p, const char* what) {
+  DIFVM_CHECK(p != nullptr, DIFVM_ERR_INVALID_ARG, std::string(what) + " is NULL");
+}
+
+template <class T>
+static T* up_vec(difvm_mesh* m, const std::vector<T>& v) {
+  T* p = dalloc<T>(v.size());
+  m->allocs.push_back(p);
+  upload(p, v, stream_of(m));
+  return p;
+}
+
+static void upload_mesh(difvm_mesh* m) {
+  HostLayout& L = m->host;
+  DMesh& d = m->d;
+  std::memset(&d, 0, sizeof(d));
+  d.nc = L.nc; d.nfi = L.nfi; d.nfb = L.nfb; d.nslice = L.nslice; d.nslot = L.nslot; d.n_wk = L.n_wk;
+  d.has_fixed_p = L.has_fixed_p;
+  int nfi = L.nfi, nfb = L.nfb;
+  std::vector<double4> gS(nfi), gK(nfi), bg(nfb);
+  std::vector<float4> gS32(nfi), gK32(nfi), bg32(nfb);
+  std::vector<float> w32(nfi), V32(L.nc);
+  for (int f = 0; f < nfi; ++f) {
+    gS[f] = make_double4(L.S[3 * f], L.S[3 * f + 1], L.S[3 * f + 2], L.w[f]);
+    gK[f] = make_double4(L.k[3 * f], L.k[3 * f + 1], L.k[3 * f + 2], L.delta[f]);
+    gS32[f] = make_float4((float)gS[f].x, (float)gS[f].y, (float)gS[f].z, (float)gS[f].w);
+    gK32[f] = make_float4((float)gK[f].x, (float)gK[f].y, (float)gK[f].z, (float)gK[f].w);
+    w32[f] = (float)L.w[f];
+  }
+  for (int b = 0; b < nfb; ++b) {
+    int f = nfi + b;
+    bg[b] = make_double4(L.S[3 * f], L.S[3 * f + 1], L.S[3 * f + 2], L.delta[f]);
+    bg32[b] = make_float4((float)bg[b].x, (float)bg[b].y, (float)bg[b].z, (float)bg[b].w);
+  }
+  for (int i = 0; i < L.nc; ++i) V32[i] = (float)L.V[i];
+  std::vector<int8_t> codes((size_t)N_TABLES * nfb);
+  for (int t = 0; t < N_TABLES; ++t) std::copy(L.bcode[t].begin(), L.bcode[t].end(), codes.begin() + (size_t)t * nfb);
+  d.own = up_vec(m, L.owner);
+  d.nbr = up_vec(m, L.neighbour);
+  d.geomS = up_vec(m, gS);
+  d.geomK = up_vec(m, gK);
+  d.w = up_vec(m, L.w);
+  d.geomS32 = up_vec(m, gS32);
+  d.geomK32 = up_vec(m, gK32);
+  d.w32 = up_vec(m, w32);
+  d.bown = up_vec(m, L.bowner);
+  d.bgeom = up_vec(m, bg);
+  d.bgeom32 = up_vec(m, bg32);
+  d.bcode = up_vec(m, codes);
+  d.wk_start = up_vec(m, L.wk_start);
+  d.wk_faces = up_vec(m, L.wk_faces);
+  d.V = up_vec(m, L.V);
+  d.V32 = up_vec(m, V32);
+  d.slice_start = up_vec(m, L.slice_start);
+  d.slot_face = up_vec(m, L.slot_face);
+  d.slot_col = up_vec(m, L.slot_col);
+  d.cell_perm = up_vec(m, L.cell_perm);
+  d.face_perm = up_vec(m, L.face_perm);
+  d.bface_perm = up_vec(m, L.bface_perm);
+  d.face_flip = up_vec(m, L.face_flip);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+}
+
+static void free_mesh(difvm_mesh* m) {
+  if (!m) return;
+  if (m->ctx) (void)hipStreamSynchronize(stream_of(m));
+  krylov_work_free(m->krylov);
+  for (void* a : m->allocs) dfree(a);
+  delete m;
+}
+
+}  // namespace difvm
+
+using namespace difvm;
+
+extern "C" {
+
+int difvm_abi_version(void) { return DIFVM_ABI_VERSION; }
+const char* difvm_last_error(void) { return g_last_error.c_str(); }
+
+difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out) {
+  DIFVM_API_BEGIN
+  check_ptr(out, "out");
+  int n = 0;
+  DIFVM_HIP(hipGetDeviceCount(&n));
+  DIFVM_CHECK(device >= 0 && device < n, DIFVM_ERR_INVALID_ARG, "device ordinal out of range");
+  DIFVM_HIP(hipSetDevice(device));
+  difvm_ctx* c = new difvm_ctx();
+  c->c.device = device;
+  c->c.stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream) {
+  DIFVM_API_BEGIN
+  check_ptr(ctx, "ctx");
+  ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_destroy(difvm_ctx* ctx) {
+  if (!ctx) return DIFVM_OK;
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (auto& r : ctx->c.prof.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_profile(difvm_ctx* ctx, int enable) {
+  DIFVM_API_BEGIN
+  check_ptr(ctx, "ctx");
+  if (!enable) prof_collect(ctx->c);
+  ctx->c.prof.on = enable != 0;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_profile_read(difvm_ctx* ctx, difvm_kernel_time* out, int32_t max_out, int32_t* n_out) {
+  DIFVM_API_BEGIN
+  check_ptr(ctx, "ctx");
+  check_ptr(n_out, "n_out");
+  Profiler& P = ctx->c.prof;
+  prof_collect(ctx->c);
+  int n = (int)P.names.size();
+  *n_out = n;
+  for (int k = 0; k < n && k < max_out && out; ++k) {
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, P.names[k].c_str(), sizeof(out[k].name) - 1);
+    out[k].launches = (int32_t)P.launches[k];
+    out[k].total_ms = P.total_ms[k];
+  }
+  std::fill(P.total_ms.begin(), P.total_ms.end(), 0.0);
+  std::fill(P.launches.begin(), P.launches.end(), 0L);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_mesh_renumber_host(const difvm_mesh_desc* desc, uint32_t flags, int32_t* cell_perm, int32_t* face_perm,
+                                      uint8_t* face_flip, int32_t* owner, int32_t* neighbour, int32_t* own_start,
+                                      int32_t* losort, int32_t* losort_start, int32_t* bface_perm, int32_t* bowner,
+                                      double* S, double* w, double* delta, double* k) {
+  DIFVM_API_BEGIN
+  HostLayout L;
+  build_layout(desc, flags, L, false);
+  auto put = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), sizeof(v[0]) * v.size());
+  };
+  put(cell_perm, L.cell_perm); put(face_perm, L.face_perm); put(face_flip, L.face_flip); put(owner, L.owner);
+  put(neighbour, L.neighbour); put(own_start, L.own_start); put(losort, L.losort); put(losort_start, L.losort_start);
+  put(bface_perm, L.bface_perm); put(bowner, L.bowner); put(S, L.S); put(w, L.w); put(delta, L.delta); put(k, L.k);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_mesh_create(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, difvm_mesh** out) {
+  DIFVM_API_BEGIN
+  difvm_mesh* m = nullptr;
+  check_ptr(ctx, "ctx");
+  check_ptr(out, "out");
+  DIFVM_HIP(hipSetDevice(ctx->c.device));
+  m = new difvm_mesh();
+  m->ctx = ctx;
+  try {
+    build_layout(desc, flags, m->host, true);
+    upload_mesh(m);
+  } catch (...) {
+    free_mesh(m);
+    throw;
+  }
+  *out = m;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_mesh_get_info(const difvm_mesh* m, difvm_mesh_info* info) {
+  DIFVM_API_BEGIN
+  check_mesh(m);
+  check_ptr(info, "info");
+  const HostLayout& L = m->host;
+  info->n_cells = L.nc;
+  info->n_internal_faces = L.nfi;
+  info->n_boundary_faces = L.nfb;
+  info->n_patches = L.npatch;
+  info->n_slices = L.nslice;
+  info->n_slots = L.nslot;
+  info->bandwidth_in = L.bandwidth_in;
+  info->bandwidth_out = L.bandwidth_out;
+  info->n_windkessel = L.n_wk;
+  info->has_fixed_p = L.has_fixed_p ? 1 : 0;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_mesh_destroy(difvm_mesh* m) {
+  DIFVM_API_BEGIN
+  free_mesh(m);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_permute(const difvm_mesh* m, int dtype, int ncomp, int kind, int dir, const void* src, void* dst) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype);
+  DIFVM_CHECK(ncomp >= 1 && ncomp <= 9, DIFVM_ERR_INVALID_ARG, "ncomp must be in 1..9");
+  DIFVM_CHECK(kind >= DIFVM_KIND_CELL && kind <= DIFVM_KIND_BFACE, DIFVM_ERR_INVALID_ARG, "unknown kind");
+  DIFVM_CHECK(dir == DIFVM_TO_INTERNAL || dir == DIFVM_FROM_INTERNAL, DIFVM_ERR_INVALID_ARG, "unknown direction");
+  check_ptr(src, "src"); check_ptr(dst, "dst");
+  DIFVM_CHECK(src != dst, DIFVM_ERR_INVALID_ARG, "src and dst must differ");
+  permute(m, dtype, ncomp, kind, dir, src, dst);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_op_interp(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phi_b,
+                             void* phi_f) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype); check_ncomp(ncomp); check_bc(bc);
+  check_ptr(phi, "phi"); check_ptr(phi_f, "phi_f");
+  DIFVM_CHECK(phi_b || bc == DIFVM_BC_ALL_ZEROGRAD || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "phi_b is NULL");
+  op_interp(m, dtype, ncomp, bc, phi, phi_b, phi_f);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_op_grad(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phi_b,
+                           void* grad) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype); check_ncomp(ncomp); check_bc(bc);
+  check_ptr(phi, "phi"); check_ptr(grad, "grad");
+  DIFVM_CHECK(phi_b || bc == DIFVM_BC_ALL_ZEROGRAD || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "phi_b is NULL");
+  op_grad(m, dtype, ncomp, bc, phi, phi_b, grad);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_op_div(const difvm_mesh* m, int dtype, int scheme, int ncomp, int bc, const void* flux,
+                          const void* psi, const void* psi_b, void* out) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype); check_ncomp(ncomp); check_bc(bc);
+  DIFVM_CHECK(scheme >= DIFVM_SCHEME_ONE && scheme <= DIFVM_SCHEME_LINEAR, DIFVM_ERR_INVALID_ARG, "unknown scheme");
+  check_ptr(flux, "flux"); check_ptr(out, "out");
+  if (scheme != DIFVM_SCHEME_ONE) {
+    check_ptr(psi, "psi");
+    DIFVM_CHECK(psi_b || bc == DIFVM_BC_ALL_ZEROGRAD || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "psi_b is NULL");
+  }
+  op_div(m, dtype, scheme, ncomp, bc, flux, psi, psi_b, out);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_op_laplacian(const difvm_mesh* m, int dtype, int bc, const void* gamma_f, const void* phi,
+                                const void* grad_phi, const void* phi_b, void* out) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype); check_bc(bc);
+  check_ptr(phi, "phi"); check_ptr(grad_phi, "grad_phi"); check_ptr(out, "out");
+  DIFVM_CHECK(phi_b || bc == DIFVM_BC_ALL_ZEROGRAD || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "phi_b is NULL");
+  op_laplacian(m, dtype, bc, gamma_f, phi, grad_phi, phi_b, out);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ldu_spmv(const difvm_mesh* m, int ncomp, int transpose, const difvm_ldu* A, const void* x, void* y) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_ncomp(ncomp); check_ptr(A, "A");
+  check_dtype(A->dtype);
+  check_ptr(A->diag, "A->diag"); check_ptr(x, "x"); check_ptr(y, "y");
+  DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
+  DIFVM_CHECK(x != y, DIFVM_ERR_INVALID_ARG, "x and y must differ");
+  op_ldu_spmv(m, A->dtype, ncomp, transpose, A->diag, A->upper, A->lower, x, y);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ldu_assemble_laplace(const difvm_mesh* m, int bc, const void* gamma_f, const void* phi_b, difvm_ldu* A,
+                                        void* rhs_bc) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_bc(bc); check_ptr(A, "A");
+  DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "assembly is F64 only");
+  check_ptr(A->diag, "A->diag");
+  DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
+  DIFVM_CHECK(phi_b || !rhs_bc, DIFVM_ERR_INVALID_ARG, "rhs_bc needs phi_b");
+  op_assemble_laplace(m, bc, (const double*)gamma_f, (const double*)phi_b, (double*)A->diag, (double*)A->upper,
+                      (double*)rhs_bc);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double dt, const void* flux, const void* U,
+                                         const void* U_b, difvm_ldu* A, void* b) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_ptr(A, "A"); check_ptr(flux, "flux"); check_ptr(U, "U"); check_ptr(b, "b");
+  DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "assembly is F64 only");
+  check_ptr(A->diag, "A->diag");
+  DIFVM_CHECK((A->upper && A->lower) || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper or A->lower is NULL");
+  DIFVM_CHECK(dt > 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0");
+  DIFVM_CHECK(U_b || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "U_b is NULL");
+  double* gU = dalloc<double>((size_t)9 * m->d.nc);
+  try {
+    op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
+    op_assemble_momentum(m, nu, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
+                         (double*)A->upper, (double*)A->lower, nullptr, (double*)b);
+    DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+  } catch (...) {
+    dfree(gU);
+    throw;
+  }
+  dfree(gU);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+static difvm_status solve_common(const difvm_mesh* cm, const difvm_ldu* A, int ncomp, const void* b, void* x, double tol,
+                                 int32_t maxit, difvm_solve_stats* stats, bool sym) {
+  difvm_mesh* m = const_cast<difvm_mesh*>(cm);
+  check_mesh(m); check_ptr(A, "A"); check_ptr(b, "b"); check_ptr(x, "x"); check_ncomp(ncomp);
+  DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "solvers are F64 only");
+  check_ptr(A->diag, "A->diag");
+  DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
+  DIFVM_CHECK(tol >= 0 && maxit >= 0, DIFVM_ERR_INVALID_ARG, "tol and maxit must be >= 0");
+  double* val = dalloc<double>(m->d.nslot);
+  SolveResult R;
+  try {
+    sell_from_ldu(m, (const double*)A->upper, sym ? nullptr : (const double*)A->lower, val);
+    SellMatrix S{(const double*)A->diag, val};
+    if (sym) R = pcg(m, S, (const double*)b, (double*)x, tol, maxit);
+    else R = bicgstab(m, ncomp, S, (const double*)b, (double*)x, tol, maxit);
+  } catch (...) {
+    dfree(val);
+    throw;
+  }
+  dfree(val);
+  if (stats) {
+    for (int c = 0; c < 3; ++c) { stats->iters[c] = R.iters[c]; stats->residual[c] = R.res[c]; }
+    stats->status = R.status;
+  }
+  return R.status;
+}
+
+difvm_status difvm_solve_pcg(const difvm_mesh* m, const difvm_ldu* A, const void* b, void* x, double tol, int32_t maxit,
+                             difvm_solve_stats* stats) {
+  DIFVM_API_BEGIN
+  return solve_common(m, A, 1, b, x, tol, maxit, stats, true);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_solve_bicgstab(const difvm_mesh* m, const difvm_ldu* A, int ncomp, const void* b, void* x, double tol,
+                                  int32_t maxit, difvm_solve_stats* stats) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(A && (A->lower || (m && m->d.nfi == 0)), DIFVM_ERR_INVALID_ARG, "BiCGStab needs A->lower");
+  return solve_common(m, A, ncomp, b, x, tol, maxit, stats, false);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_create(const difvm_mesh* m, const difvm_piso_params* params, difvm_piso** out) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_ptr(params, "params"); check_ptr(out, "out");
+  piso_create(const_cast<difvm_mesh*>(m), params, out);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_destroy(difvm_piso* piso) {
+  DIFVM_API_BEGIN
+  piso_destroy(piso);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_set_boundary(difvm_piso* piso, const void* U_b, const void* p_b) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_set_boundary(piso, (const double*)U_b, (const double*)p_b);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_set_windkessel(difvm_piso* piso, int32_t id, double Rp, double C, double Rd, double pc) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_set_windkessel(piso, id, Rp, C, Rd, pc);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_set_state(difvm_piso* piso, const void* U, const void* p, const void* phi) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_set_state(piso, (const double*)U, (const double*)p, (const double*)phi);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi, double* pc_host) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_get_state(piso, (double*)U, (double*)p, (double*)phi, pc_host);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats* stats_host) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  DIFVM_CHECK(nsteps >= 0, DIFVM_ERR_INVALID_ARG, "nsteps must be >= 0");
+  return piso_step(piso, nsteps, stats_host);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Device helpers shared by the libdifvm kernels: XCD-aware block mapping, slot decoding, geometry
+// record types per precision, deterministic block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace difvm {
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X.  Remapping the block index
+// gives each XCD one contiguous run of tiles, so a slice's neighbours (RCM keeps them close in
+// index) are gathered through the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  int x = b & 7, k = b >> 3, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <class T>
+struct Geo;
+template <>
+struct Geo<double> {
+  using v4 = double4;
+};
+template <>
+struct Geo<float> {
+  using v4 = float4;
+};
+
+// read-only view of the device mesh passed by value to kernels
+template <class T>
+struct MeshView {
+  int nc, nfi, nfb;
+  const int32_t* __restrict__ own;
+  const int32_t* __restrict__ nbr;
+  const typename Geo<T>::v4* __restrict__ geomS;  // (S, w)
+  const typename Geo<T>::v4* __restrict__ geomK;  // (k, delta)
+  const T* __restrict__ w;
+  const int32_t* __restrict__ bown;
+  const typename Geo<T>::v4* __restrict__ bgeom;  // (S_b, delta_b)
+  const int8_t* __restrict__ bcode;               // [N_TABLES][nfb]
+  const T* __restrict__ V;
+  const int32_t* __restrict__ slice_start;
+  const int32_t* __restrict__ slot_face;
+  const int32_t* __restrict__ slot_col;
+};
+
+template <class T>
+MeshView<T> view(const DMesh& d);
+template <>
+inline MeshView<double> view<double>(const DMesh& d) {
+  return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS, d.geomK, d.w, d.bown, d.bgeom, d.bcode, d.V,
+          d.slice_start, d.slot_face, d.slot_col};
+}
+template <>
+inline MeshView<float> view<float>(const DMesh& d) {
+  return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS32, d.geomK32, d.w32, d.bown, d.bgeom32, d.bcode, d.V32,
+          d.slice_start, d.slot_face, d.slot_col};
+}
+
+// slot range of cell i: slots base + k*SLICE for k < width
+struct SlotRange {
+  int base, width;
+};
+__device__ __forceinline__ SlotRange slots_of(const int32_t* slice_start, int i) {
+  int s = i >> 6;
+  int b = slice_start[s];
+  return {b + (i & (SLICE - 1)), (slice_start[s + 1] - b) >> 6};
+}
+
+// ---------------------------------------------------------------------------------------------
+// deterministic reductions: wave64 butterfly, then the 4 waves of a 256-thread block in order
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[BLOCK / 64]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k][wid] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < BLOCK / 64; ++q) s += lds[k][q];
+    v[k] = s;
+  }
+}
+
+}  // namespace difvm

@@ -1,0 +1,135 @@
+// Internal definitions of libdifvm: mesh and context objects, error plumbing, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/difvm.h"
+#include "layout.h"
+
+namespace difvm {
+
+// ---------------------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+struct Error {
+  difvm_status code;
+  std::string msg;
+};
+
+#define DIFVM_HIP(call)                                                                              \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      throw ::difvm::Error{DIFVM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+#define DIFVM_CHECK(cond, code, msg)                     \
+  do {                                                   \
+    if (!(cond)) throw ::difvm::Error{(code), (msg)};    \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// device-side allocations
+// ---------------------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// event-pair timing of selected kernel launches (difvm_ctx_profile)
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<std::string> names;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<double> total_ms;
+  std::vector<long> launches;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Profiler prof;
+};
+
+// Brackets the next launch on `s` with events when profiling is on; returns a handle for prof_end.
+int prof_begin(Ctx& c, const char* name);
+void prof_end(Ctx& c, int handle);
+
+void* dmalloc(size_t bytes);
+void dfree(void* p);
+template <class T>
+T* dalloc(size_t n) {
+  return static_cast<T*>(dmalloc(sizeof(T) * (n ? n : 1)));
+}
+template <class T>
+void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (!src.empty()) DIFVM_HIP(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
+}
+
+// device mesh
+struct DMesh {
+  int nc, nfi, nfb, nslice, nslot, n_wk;
+  bool has_fixed_p;
+  // internal faces, owner-sorted
+  int32_t *own, *nbr;
+  double4* geomS;   // (Sx, Sy, Sz, w)
+  double4* geomK;   // (kx, ky, kz, delta)
+  double* w;
+  float4 *geomS32, *geomK32;
+  float* w32;
+  // boundary faces
+  int32_t* bown;
+  double4* bgeom;   // (Sx, Sy, Sz, delta_b)
+  float4* bgeom32;
+  int8_t* bcode;    // [N_TABLES][nfb]
+  int32_t *wk_start, *wk_faces;
+  // cells
+  double* V;
+  float* V32;
+  // cell-slot layout (SELL, slices of 64 cells, slot-major inside a slice)
+  int32_t *slice_start, *slot_face, *slot_col;
+  // permutations for user <-> internal conversions
+  int32_t *cell_perm, *face_perm, *bface_perm;
+  uint8_t* face_flip;
+};
+
+}  // namespace difvm
+
+struct difvm_ctx {
+  difvm::Ctx c;
+};
+
+namespace difvm {
+struct KrylovWork;
+}
+struct difvm_mesh {
+  difvm_ctx* ctx;
+  difvm::HostLayout host;
+  difvm::DMesh d;
+  std::vector<void*> allocs;                 // device allocations owned by the mesh
+  difvm::KrylovWork* krylov = nullptr;       // solver workspace, created on first solve
+};
+
+namespace difvm {
+inline hipStream_t stream_of(const difvm_mesh* m) { return m->ctx->c.stream; }
+inline Ctx& ctx_of(const difvm_mesh* m) { return m->ctx->c; }
+// RAII event bracket around one launch
+struct ProfScope {
+  Ctx& c;
+  int h;
+  ProfScope(const difvm_mesh* m, const char* name) : c(ctx_of(m)), h(prof_begin(ctx_of(m), name)) {}
+  ~ProfScope() { prof_end(c, h); }
+};
+inline int grid_for(int n, int per_block = BLOCK) { return (n + per_block - 1) / per_block; }
+}  // namespace difvm

@@ -1,0 +1,56 @@
+// Host-side mesh layout of libdifvm (plain C++, no HIP): renumbering, permuted geometry and the
+// cell-slot (sliced-ELL) layout every cell kernel walks.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/difvm.h"
+
+namespace difvm {
+
+struct LayoutError {
+  difvm_status code;
+  std::string msg;
+};
+
+// ---------------------------------------------------------------------------------------------
+// layout constants
+// ---------------------------------------------------------------------------------------------
+constexpr int SLICE = 64;            // cells per slice of the cell-slot layout (one wavefront)
+constexpr int CHUNK = 256;           // cells per reduction partial (fixed: results do not depend on launch shape)
+constexpr int BLOCK = 256;           // threads per block for cell and face kernels
+constexpr int SLOT_PAD = INT32_MIN;  // slot code of a padding slot
+
+// boundary codes per table
+enum : int8_t { BC_FIXED = 0, BC_ZEROGRAD = 1, BC_EMPTY = 2 };
+constexpr int N_TABLES = 4;
+
+// slot code: f >= 0 and f < nfi -> owner side of internal face f; f >= nfi -> boundary face f - nfi;
+// f < 0 (and != SLOT_PAD) -> neighbour side of internal face -f-1.
+
+// host-side renumbering result (all in new numbering)
+struct HostLayout {
+  int nc = 0, nfi = 0, nfb = 0, npatch = 0;
+  std::vector<int32_t> cell_perm, face_perm, bface_perm, owner, neighbour, own_start, losort, losort_start, bowner;
+  std::vector<uint8_t> face_flip;
+  std::vector<double> S, w, delta, k, Cf, C, V;   // permuted geometry: S[(nfi+nfb)*3], delta[nfi+nfb], k[nfi*3]
+  std::vector<difvm_patch> patches;               // unchanged (boundary ranges are kept)
+  std::vector<int8_t> bcode[N_TABLES];            // per boundary face
+  std::vector<int32_t> bwk;                       // Windkessel id per boundary face or -1
+  int n_wk = 0;
+  bool has_fixed_p = false;
+  int bandwidth_in = 0, bandwidth_out = 0;
+  // cell-slot layout
+  int nslice = 0, nslot = 0;
+  std::vector<int32_t> slice_start, slot_face, slot_col;
+  // Windkessel face lists
+  std::vector<int32_t> wk_start, wk_faces;
+};
+
+// Throws LayoutError on invalid input.
+void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots);
+
+
+}  // namespace difvm

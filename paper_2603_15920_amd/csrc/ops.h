@@ -1,0 +1,49 @@
+// Internal launchers of libdifvm (enqueue on the mesh's stream, device arrays in internal order).
+#pragma once
+
+#include "internal.h"
+
+namespace difvm {
+
+void permute(const difvm_mesh* m, int dtype, int ncomp, int kind, int dir, const void* src, void* dst);
+void op_interp(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phib, void* out);
+void op_grad(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phib, void* out);
+void op_div(const difvm_mesh* m, int dtype, int scheme, int ncomp, int bc, const void* flux, const void* psi,
+            const void* psib, void* out);
+void op_laplacian(const difvm_mesh* m, int dtype, int bc, const void* gamma, const void* phi, const void* g,
+                  const void* phib, void* out);
+void op_ldu_spmv(const difvm_mesh* m, int dtype, int ncomp, int transpose, const void* diag, const void* up,
+                 const void* lo, const void* x, void* y);
+void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const double* phib, double* diag,
+                         double* upper, double* rhs);
+
+// momentum matrix of the predictor; writes face LDU (upper/lower, may be NULL) and/or per-slot values
+void op_assemble_momentum(const difvm_mesh* m, double nu, double dt, const double* flux, const double* U,
+                          const double* gradU, const double* Ub, double* diag, double* upper, double* lower,
+                          double* slot_val, double* b);
+
+// ---- Krylov solvers on the cell-slot matrix (diag[Nc], val[n_slots]) ----
+struct SellMatrix {
+  const double* diag;
+  const double* val;
+};
+void sell_from_ldu(const difvm_mesh* m, const double* upper, const double* lower, double* val);
+void sell_spmv(const difvm_mesh* m, int ncomp, SellMatrix A, const double* x, double* y);
+
+struct SolveResult {
+  int iters[3] = {0, 0, 0};
+  double res[3] = {0, 0, 0};
+  int status = 0;
+};
+
+// Solver workspaces live with the mesh-level solver object; created lazily per mesh.
+struct KrylovWork;
+KrylovWork* krylov_work(difvm_mesh* m);
+void krylov_work_free(KrylovWork* w);
+
+// x holds the initial guess; extra_rhs (may be NULL) is subtracted from b as (b - scale_cell * extra)
+// per component: used by the predictor for b - V grad(p).
+SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit);
+SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit);
+
+}  // namespace difvm

@@ -1,0 +1,402 @@
+// Finite-volume operator kernels of libdifvm: permutation, face interpolation, Gauss gradient,
+// face-sum divergence, over-relaxed Laplacian, LDU products and assembly.
+//
+// Cell kernels walk the cell-slot layout: one thread per cell, one slot per non-empty face side of
+// that cell (owner side, neighbour side, boundary), so every aggregation of the paper's message
+// passing (eq. aggregate) is a gather in a fixed order: no atomics, bitwise deterministic, and
+// independent of the launch shape.  Face kernels (one thread per face) write per-face outputs.
+#include <cstring>
+
+#include "abi_util.h"
+#include "device.h"
+#include "ops.h"
+
+namespace difvm {
+
+// ---------------------------------------------------------------------------------------------
+// permutation between user and internal order
+// ---------------------------------------------------------------------------------------------
+// map[i] (new -> old) for each of n destination rows; sign flips where flip[i] (fluxes)
+template <class T>
+__global__ void k_permute(int n, int ncomp, const int32_t* __restrict__ map, int map_offset, const uint8_t* __restrict__ flip,
+                          int to_internal, const T* __restrict__ src, T* __restrict__ dst, int src_off, int dst_off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int old = map ? map[i] + map_offset : i + map_offset;
+  T sg = (flip && flip[i]) ? T(-1) : T(1);
+  if (to_internal) {
+    for (int c = 0; c < ncomp; ++c) dst[(size_t)(dst_off + i) * ncomp + c] = sg * src[(size_t)old * ncomp + c];
+  } else {
+    for (int c = 0; c < ncomp; ++c) dst[(size_t)old * ncomp + c] = sg * src[(size_t)(src_off + i) * ncomp + c];
+  }
+}
+
+template <class T>
+void permute_t(const difvm_mesh* m, int ncomp, int kind, int dir, const T* src, T* dst) {
+  const DMesh& d = m->d;
+  hipStream_t s = stream_of(m);
+  int to = dir == DIFVM_TO_INTERNAL;
+  if (kind == DIFVM_KIND_CELL) {
+    if (d.nc) k_permute<T><<<grid_for(d.nc), BLOCK, 0, s>>>(d.nc, ncomp, d.cell_perm, 0, nullptr, to, src, dst, 0, 0);
+  } else if (kind == DIFVM_KIND_BFACE) {
+    if (d.nfb) k_permute<T><<<grid_for(d.nfb), BLOCK, 0, s>>>(d.nfb, ncomp, d.bface_perm, 0, nullptr, to, src, dst, 0, 0);
+  } else {
+    const uint8_t* fl = kind == DIFVM_KIND_FACE_FLUX ? d.face_flip : nullptr;
+    if (d.nfi) k_permute<T><<<grid_for(d.nfi), BLOCK, 0, s>>>(d.nfi, ncomp, d.face_perm, 0, fl, to, src, dst, 0, 0);
+    // boundary block: internal row nfi+b <- user row nfi + bface_perm[b]
+    if (d.nfb) {
+      if (to)
+        k_permute<T><<<grid_for(d.nfb), BLOCK, 0, s>>>(d.nfb, ncomp, d.bface_perm, d.nfi, nullptr, 1, src, dst, 0, d.nfi);
+      else
+        k_permute<T><<<grid_for(d.nfb), BLOCK, 0, s>>>(d.nfb, ncomp, d.bface_perm, d.nfi, nullptr, 0, src, dst, d.nfi, 0);
+    }
+  }
+  DIFVM_HIP(hipGetLastError());
+}
+
+void permute(const difvm_mesh* m, int dtype, int ncomp, int kind, int dir, const void* src, void* dst) {
+  if (dtype == DIFVM_F64) permute_t<double>(m, ncomp, kind, dir, (const double*)src, (double*)dst);
+  else permute_t<float>(m, ncomp, kind, dir, (const float*)src, (float*)dst);
+}
+
+// ---------------------------------------------------------------------------------------------
+// face interpolation (face kernel)
+// ---------------------------------------------------------------------------------------------
+template <class T, int NC>
+__global__ __launch_bounds__(BLOCK) void k_interp(MeshView<T> m, int table, const T* __restrict__ phi,
+                                                  const T* __restrict__ phib, T* __restrict__ out) {
+  int f = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    T w = m.w[f];
+    int O = m.own[f], N = m.nbr[f];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[(size_t)f * NC + c] = w * phi[(size_t)O * NC + c] + (T(1) - w) * phi[(size_t)N * NC + c];
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    int8_t code = m.bcode[table * m.nfb + b];
+    int O = m.bown[b];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T v = T(0);
+      if (code == BC_FIXED) v = phib[(size_t)b * NC + c];
+      else if (code == BC_ZEROGRAD) v = phi[(size_t)O * NC + c];
+      out[(size_t)f * NC + c] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Gauss gradient (cell kernel): G_i = (1/V_i) sum_slots sigma phi_f S_f
+// ---------------------------------------------------------------------------------------------
+template <class T, int NC>
+__global__ __launch_bounds__(BLOCK) void k_grad(MeshView<T> m, int table, const T* __restrict__ phi,
+                                                const T* __restrict__ phib, T* __restrict__ out) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  T pi[NC], acc[NC][3];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    pi[c] = phi[(size_t)i * NC + c];
+    acc[c][0] = acc[c][1] = acc[c][2] = T(0);
+  }
+  const int8_t* code = m.bcode + table * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    int j = m.slot_col[at];
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      auto g = m.geomS[f];
+      T wself = nb ? T(1) - g.w : g.w;   // weight of this cell in phi_f
+      T sg = nb ? T(-1) : T(1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T pf = sg * (wself * pi[c] + (T(1) - wself) * phi[(size_t)j * NC + c]);
+        acc[c][0] += pf * g.x;
+        acc[c][1] += pf * g.y;
+        acc[c][2] += pf * g.z;
+      }
+    } else {
+      int b = sf - m.nfi;
+      auto g = m.bgeom[b];
+      bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T pf = fixed ? phib[(size_t)b * NC + c] : pi[c];
+        acc[c][0] += pf * g.x;
+        acc[c][1] += pf * g.y;
+        acc[c][2] += pf * g.z;
+      }
+    }
+  }
+  T rv = T(1) / m.V[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) out[((size_t)i * NC + c) * 3 + e] = acc[c][e] * rv;
+}
+
+// ---------------------------------------------------------------------------------------------
+// face-sum divergence (cell kernel): D_i = sum_slots sigma F_f psi_f
+// ---------------------------------------------------------------------------------------------
+template <class T, int NC, int SCHEME>
+__global__ __launch_bounds__(BLOCK) void k_div(MeshView<T> m, int table, const T* __restrict__ flux,
+                                               const T* __restrict__ psi, const T* __restrict__ psib, T* __restrict__ out) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  T pi[NC], acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    pi[c] = SCHEME == DIFVM_SCHEME_ONE ? T(0) : psi[(size_t)i * NC + c];
+    acc[c] = T(0);
+  }
+  const int8_t* code = m.bcode + table * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    int j = m.slot_col[at];
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      T F = flux[f];
+      T Fs = nb ? -F : F;                 // flux out of this cell
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T pf;
+        if (SCHEME == DIFVM_SCHEME_ONE) {
+          pf = T(1);
+        } else if (SCHEME == DIFVM_SCHEME_UPWIND) {
+          bool owner_up = F >= T(0);      // the tie F = 0 belongs to the owner
+          bool self_up = nb ? !owner_up : owner_up;
+          pf = self_up ? pi[c] : psi[(size_t)j * NC + c];
+        } else {
+          T w = m.w[f];
+          T wself = nb ? T(1) - w : w;
+          pf = wself * pi[c] + (T(1) - wself) * psi[(size_t)j * NC + c];
+        }
+        acc[c] += Fs * pf;
+      }
+    } else {
+      int b = sf - m.nfi;
+      T F = flux[m.nfi + b];
+      bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T pf = SCHEME == DIFVM_SCHEME_ONE ? T(1) : (fixed ? psib[(size_t)b * NC + c] : pi[c]);
+        acc[c] += F * pf;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Laplacian with over-relaxed correction (cell kernel)
+// ---------------------------------------------------------------------------------------------
+template <class T, bool GAMMA>
+__global__ __launch_bounds__(BLOCK) void k_laplacian(MeshView<T> m, int table, const T* __restrict__ gamma,
+                                                     const T* __restrict__ phi, const T* __restrict__ g,
+                                                     const T* __restrict__ phib, T* __restrict__ out) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  T pi = phi[i];
+  T gi0 = g[3 * (size_t)i], gi1 = g[3 * (size_t)i + 1], gi2 = g[3 * (size_t)i + 2];
+  T acc = T(0);
+  const int8_t* code = m.bcode + table * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    int j = m.slot_col[at];
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      auto kd = m.geomK[f];
+      T w = m.w[f];
+      T wself = nb ? T(1) - w : w;
+      const T* gj = g + 3 * (size_t)j;
+      // seen from this cell: delta (phi_other - phi_self) + k_out . gbar, with k_out the correction
+      // vector oriented out of this cell; the owner-side form of eq. nonortho_flux, negated for the
+      // neighbour side
+      T corr = kd.x * (wself * gi0 + (T(1) - wself) * gj[0]) + kd.y * (wself * gi1 + (T(1) - wself) * gj[1]) +
+               kd.z * (wself * gi2 + (T(1) - wself) * gj[2]);
+      T t = kd.w * (phi[j] - pi) + (nb ? -corr : corr);
+      if (GAMMA) t *= gamma[f];
+      acc += t;
+    } else {
+      int b = sf - m.nfi;
+      if (code[b] == BC_FIXED) {
+        T t = m.bgeom[b].w * (phib[b] - pi);
+        if (GAMMA) t *= gamma[m.nfi + b];
+        acc += t;
+      }
+    }
+  }
+  out[i] = acc;
+}
+
+// ---------------------------------------------------------------------------------------------
+// LDU product through the slots (owner slot: upper, neighbour slot: lower)
+// ---------------------------------------------------------------------------------------------
+template <class T, int NC>
+__global__ __launch_bounds__(BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __restrict__ diag, const T* __restrict__ up,
+                                                    const T* __restrict__ lo, const T* __restrict__ x, T* __restrict__ y) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  T acc[NC];
+  T di = diag[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    if (sf >= m.nfi) continue;
+    int j = m.slot_col[at];
+    T a = sf < 0 ? lo[-sf - 1] : up[sf];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) y[(size_t)i * NC + c] = acc[c];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Laplace assembly (cell kernel; each face's upper is written by its owner side)
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_assemble_laplace(MeshView<double> m, int table, const double* __restrict__ gamma,
+                                                            const double* __restrict__ phib, double* __restrict__ diag,
+                                                            double* __restrict__ upper, double* __restrict__ rhs) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double d = 0.0, r = 0.0;
+  const int8_t* code = m.bcode + table * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      double a = m.geomK[f].w * (gamma ? gamma[f] : 1.0);
+      d += a;
+      if (!nb) upper[f] = -a;
+    } else {
+      int b = sf - m.nfi;
+      if (code[b] == BC_FIXED) {
+        double a = m.bgeom[b].w * (gamma ? gamma[m.nfi + b] : 1.0);
+        d += a;
+        if (phib) r += a * phib[b];
+      }
+    }
+  }
+  diag[i] = d;
+  if (rhs) rhs[i] = r;
+}
+
+// ---------------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------------
+template <class T>
+void interp_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T* phib, T* out) {
+  const DMesh& d = mm->d;
+  int n = d.nfi + d.nfb;
+  if (!n) return;
+  MeshView<T> v = view<T>(d);
+  if (ncomp == 1) k_interp<T, 1><<<grid_for(n), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_interp<T, 3><<<grid_for(n), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  DIFVM_HIP(hipGetLastError());
+}
+
+template <class T>
+void grad_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T* phib, T* out) {
+  const DMesh& d = mm->d;
+  MeshView<T> v = view<T>(d);
+  if (ncomp == 1) k_grad<T, 1><<<grid_for(d.nc), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_grad<T, 3><<<grid_for(d.nc), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  DIFVM_HIP(hipGetLastError());
+}
+
+template <class T, int NC>
+void div_nc(const difvm_mesh* mm, int scheme, int table, const T* flux, const T* psi, const T* psib, T* out) {
+  const DMesh& d = mm->d;
+  MeshView<T> v = view<T>(d);
+  int G = grid_for(d.nc);
+  hipStream_t s = stream_of(mm);
+  if (scheme == DIFVM_SCHEME_ONE) k_div<T, NC, DIFVM_SCHEME_ONE><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
+  else if (scheme == DIFVM_SCHEME_UPWIND) k_div<T, NC, DIFVM_SCHEME_UPWIND><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
+  else k_div<T, NC, DIFVM_SCHEME_LINEAR><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
+  DIFVM_HIP(hipGetLastError());
+}
+
+template <class T>
+void laplacian_t(const difvm_mesh* mm, int table, const T* gamma, const T* phi, const T* g, const T* phib, T* out) {
+  const DMesh& d = mm->d;
+  MeshView<T> v = view<T>(d);
+  int G = grid_for(d.nc);
+  if (gamma) k_laplacian<T, true><<<G, BLOCK, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
+  else k_laplacian<T, false><<<G, BLOCK, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
+  DIFVM_HIP(hipGetLastError());
+}
+
+template <class T>
+void ldu_spmv_t(const difvm_mesh* mm, int ncomp, int transpose, const T* diag, const T* up, const T* lo, const T* x, T* y) {
+  const DMesh& d = mm->d;
+  MeshView<T> v = view<T>(d);
+  if (!lo) lo = up;
+  if (transpose) std::swap(up, lo);
+  int G = grid_for(d.nc);
+  if (ncomp == 1) k_ldu_spmv<T, 1><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
+  else k_ldu_spmv<T, 3><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
+  DIFVM_HIP(hipGetLastError());
+}
+
+void op_interp(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phib, void* out) {
+  if (dtype == DIFVM_F64) interp_t<double>(m, ncomp, bc, (const double*)phi, (const double*)phib, (double*)out);
+  else interp_t<float>(m, ncomp, bc, (const float*)phi, (const float*)phib, (float*)out);
+}
+void op_grad(const difvm_mesh* m, int dtype, int ncomp, int bc, const void* phi, const void* phib, void* out) {
+  if (dtype == DIFVM_F64) grad_t<double>(m, ncomp, bc, (const double*)phi, (const double*)phib, (double*)out);
+  else grad_t<float>(m, ncomp, bc, (const float*)phi, (const float*)phib, (float*)out);
+}
+void op_div(const difvm_mesh* m, int dtype, int scheme, int ncomp, int bc, const void* flux, const void* psi,
+            const void* psib, void* out) {
+  if (dtype == DIFVM_F64) {
+    if (ncomp == 1) div_nc<double, 1>(m, scheme, bc, (const double*)flux, (const double*)psi, (const double*)psib, (double*)out);
+    else div_nc<double, 3>(m, scheme, bc, (const double*)flux, (const double*)psi, (const double*)psib, (double*)out);
+  } else {
+    if (ncomp == 1) div_nc<float, 1>(m, scheme, bc, (const float*)flux, (const float*)psi, (const float*)psib, (float*)out);
+    else div_nc<float, 3>(m, scheme, bc, (const float*)flux, (const float*)psi, (const float*)psib, (float*)out);
+  }
+}
+void op_laplacian(const difvm_mesh* m, int dtype, int bc, const void* gamma, const void* phi, const void* g,
+                  const void* phib, void* out) {
+  if (dtype == DIFVM_F64)
+    laplacian_t<double>(m, bc, (const double*)gamma, (const double*)phi, (const double*)g, (const double*)phib, (double*)out);
+  else
+    laplacian_t<float>(m, bc, (const float*)gamma, (const float*)phi, (const float*)g, (const float*)phib, (float*)out);
+}
+void op_ldu_spmv(const difvm_mesh* m, int dtype, int ncomp, int transpose, const void* diag, const void* up,
+                 const void* lo, const void* x, void* y) {
+  if (dtype == DIFVM_F64)
+    ldu_spmv_t<double>(m, ncomp, transpose, (const double*)diag, (const double*)up, (const double*)lo, (const double*)x, (double*)y);
+  else
+    ldu_spmv_t<float>(m, ncomp, transpose, (const float*)diag, (const float*)up, (const float*)lo, (const float*)x, (float*)y);
+}
+void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const double* phib, double* diag,
+                         double* upper, double* rhs) {
+  const DMesh& d = m->d;
+  k_assemble_laplace<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), bc, gamma, phib, diag, upper, rhs);
+  DIFVM_HIP(hipGetLastError());
+}
+
+}  // namespace difvm

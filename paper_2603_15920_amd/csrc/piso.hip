@@ -1,0 +1,482 @@
+// PISO time step of libdifvm (paper Sec. "PISO as divergence-free constrained message passing",
+// eqs. momentum_predictor, Ap_H, pressure_poisson, velocity_correction; Windkessel outlets eqs.
+// windkessel_Q, windkessel_ode, windkessel_discrete).
+//
+// One step, all on the device:
+//   S0  Windkessel: Q_j = sum of outlet fluxes (start of step), exact exponential update of p_c,
+//       p_o = p_c + Rp Q imposed on the outlet faces
+//   S1  grad U^n; momentum matrix (implicit Euler, implicit upwind of the lagged flux, implicit
+//       orthogonal diffusion, explicit over-relaxed correction) written straight into cell-slot form
+//   S2  predictor M U* = b - V grad p^n by BiCGStab (three components, one matrix)
+//   S3  n_corr times: H = b - offdiag(U), HbyA = H / a_P, rAU = V / a_P; face flux of HbyA and the
+//       pressure matrix (negated to SPD form) with its explicit non-orthogonal source; PCG; flux
+//       and velocity correction.
+// Readings where the paper is open: implicit predictor; H of the latest velocity in every corrector;
+// Windkessel flow lagged to the start of the step; pressure reference by diagonal doubling when no
+// pressure value is fixed; no transient term in the face-flux interpolation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "abi_util.h"
+#include "device.h"
+#include "ops.h"
+
+namespace difvm {
+
+// ---------------------------------------------------------------------------------------------
+// momentum matrix (cell kernel): diag, per-slot coefficients (owner slot: upper, neighbour slot:
+// lower), optional face LDU copies, and the right-hand side b (without the pressure gradient)
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double nu, double dt,
+                                                    const double* __restrict__ flux, const double* __restrict__ U,
+                                                    const double* __restrict__ gU, const double* __restrict__ Ub,
+                                                    double* __restrict__ diag, double* __restrict__ upper,
+                                                    double* __restrict__ lower, double* __restrict__ slot_val,
+                                                    double* __restrict__ b) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double Vdt = m.V[i] / dt;
+  double d = Vdt;
+  double bi[3] = {Vdt * U[3 * (size_t)i], Vdt * U[3 * (size_t)i + 1], Vdt * U[3 * (size_t)i + 2]};
+  const double* gi = gU + 9 * (size_t)i;
+  const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    double a = 0.0;
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      int j = m.slot_col[at];
+      double F = flux[f];
+      auto kd = m.geomK[f];
+      double nd = nu * kd.w;
+      double Fp = F >= 0.0 ? F : 0.0;  // max(F,0): the tie F = 0 belongs to the owner
+      double Fm = F < 0.0 ? F : 0.0;   // min(F,0)
+      if (!nb) {
+        d += Fp + nd;
+        a = Fm - nd;                   // upper
+        if (upper) upper[f] = a;
+      } else {
+        d += -Fm + nd;
+        a = -Fp - nd;                  // lower
+        if (lower) lower[f] = a;
+      }
+      double w = m.w[f];
+      double wself = nb ? 1.0 - w : w;
+      const double* gj = gU + 9 * (size_t)j;
+      double sg = nb ? -nu : nu;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double corr = kd.x * (wself * gi[3 * c] + (1.0 - wself) * gj[3 * c]) +
+                      kd.y * (wself * gi[3 * c + 1] + (1.0 - wself) * gj[3 * c + 1]) +
+                      kd.z * (wself * gi[3 * c + 2] + (1.0 - wself) * gj[3 * c + 2]);
+        bi[c] += sg * corr;
+      }
+    } else {
+      int bf = sf - m.nfi;
+      int8_t code = codeU[bf];
+      double F = flux[m.nfi + bf];
+      if (code == BC_FIXED) {
+        double nd = nu * m.bgeom[bf].w;
+        d += nd;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bi[c] += (nd - F) * Ub[3 * (size_t)bf + c];
+      } else if (code == BC_ZEROGRAD) {
+        d += F;
+      }
+    }
+    if (slot_val) slot_val[at] = a;
+  }
+  diag[i] = d;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[3 * (size_t)i + c] = bi[c];
+}
+
+void op_assemble_momentum(const difvm_mesh* m, double nu, double dt, const double* flux, const double* U,
+                          const double* gradU, const double* Ub, double* diag, double* upper, double* lower,
+                          double* slot_val, double* b) {
+  const DMesh& d = m->d;
+  k_momentum<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), nu, dt, flux, U, gradU, Ub, diag, upper,
+                                                         lower, slot_val, b);
+  DIFVM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------------
+// step kernels
+// ---------------------------------------------------------------------------------------------
+// S0: one block per Windkessel; outlet flow summed over its faces in face order
+__global__ __launch_bounds__(BLOCK) void k_windkessel(int nfi, double dt, const int32_t* __restrict__ wk_start,
+                                                      const int32_t* __restrict__ wk_faces, const double* __restrict__ phi,
+                                                      const double* __restrict__ wk, double* __restrict__ pc,
+                                                      double* __restrict__ pbv, double* __restrict__ wk_out) {
+  int j = blockIdx.x;
+  int s0 = wk_start[j], s1 = wk_start[j + 1];
+  double v[1] = {0.0};
+  for (int q = s0 + threadIdx.x; q < s1; q += BLOCK) v[0] += phi[nfi + wk_faces[q]];
+  __shared__ double lds[1][BLOCK / 64];
+  block_sum<1>(v, lds);
+  double Q = v[0];
+  double Rp = wk[3 * j], C = wk[3 * j + 1], Rd = wk[3 * j + 2];
+  double E = exp(-dt / (Rd * C));
+  double pcn = pc[j] * E + Rd * Q * (1.0 - E);
+  double po = pcn + Rp * Q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pc[j] = pcn;
+    wk_out[2 * j] = Q;
+    wk_out[2 * j + 1] = po;
+  }
+  for (int q = s0 + threadIdx.x; q < s1; q += BLOCK) pbv[wk_faces[q]] = po;
+}
+
+// rhs = b - V grad p
+__global__ __launch_bounds__(BLOCK) void k_pred_rhs(int nc, const double* __restrict__ V, const double* __restrict__ b,
+                                                    const double* __restrict__ gp, double* __restrict__ rhs) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  double v = V[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) rhs[3 * (size_t)i + c] = b[3 * (size_t)i + c] - v * gp[3 * (size_t)i + c];
+}
+
+// H = b - sum_slots a U_j; HbyA = H / d; rAU = V / d
+__global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restrict__ slice_start,
+                                                const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                const double* __restrict__ diag, const double* __restrict__ V,
+                                                const double* __restrict__ b, const double* __restrict__ U,
+                                                double* __restrict__ HbyA, double* __restrict__ rAU) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  SlotRange R = slots_of(slice_start, i);
+  double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    double a = val[at];
+    int j = col[at];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h[c] -= a * U[3 * (size_t)j + c];
+  }
+  double d = diag[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) HbyA[3 * (size_t)i + c] = h[c] / d;
+  rAU[i] = V[i] / d;
+}
+
+// pressure face quantities: phiH (face flux of HbyA), aF = rAU_f delta_f (fixed-p boundaries only on
+// the boundary), ncorr = rAU_f k_f . grad(p_old)_f
+__global__ __launch_bounds__(BLOCK) void k_pface(MeshView<double> m, const double* __restrict__ HbyA,
+                                                 const double* __restrict__ rAU, const double* __restrict__ gp,
+                                                 const double* __restrict__ Ub, double* __restrict__ phiH,
+                                                 double* __restrict__ aF, double* __restrict__ ncorr) {
+  int f = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    int O = m.own[f], N = m.nbr[f];
+    auto g = m.geomS[f];
+    auto kd = m.geomK[f];
+    double w = g.w, wn = 1.0 - w;
+    const double* hO = HbyA + 3 * (size_t)O;
+    const double* hN = HbyA + 3 * (size_t)N;
+    phiH[f] = (w * hO[0] + wn * hN[0]) * g.x + (w * hO[1] + wn * hN[1]) * g.y + (w * hO[2] + wn * hN[2]) * g.z;
+    double rf = w * rAU[O] + wn * rAU[N];
+    aF[f] = rf * kd.w;
+    const double* gO = gp + 3 * (size_t)O;
+    const double* gN = gp + 3 * (size_t)N;
+    double kg = kd.x * (w * gO[0] + wn * gN[0]) + kd.y * (w * gO[1] + wn * gN[1]) + kd.z * (w * gO[2] + wn * gN[2]);
+    ncorr[f] = rf * kg;
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    int O = m.bown[b];
+    auto g = m.bgeom[b];
+    int8_t cu = m.bcode[DIFVM_BC_U * m.nfb + b];
+    int8_t cp = m.bcode[DIFVM_BC_P * m.nfb + b];
+    double ph = 0.0;
+    if (cu == BC_FIXED) ph = Ub[3 * (size_t)b] * g.x + Ub[3 * (size_t)b + 1] * g.y + Ub[3 * (size_t)b + 2] * g.z;
+    else if (cu == BC_ZEROGRAD)
+      ph = HbyA[3 * (size_t)O] * g.x + HbyA[3 * (size_t)O + 1] * g.y + HbyA[3 * (size_t)O + 2] * g.z;
+    phiH[f] = ph;
+    aF[f] = cp == BC_FIXED ? rAU[O] * g.w : 0.0;
+  }
+}
+
+// pressure matrix (SPD form) and right-hand side (cell kernel)
+__global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const double* __restrict__ phiH,
+                                                     const double* __restrict__ aF, const double* __restrict__ ncorr,
+                                                     const double* __restrict__ pbv, int ref, double pref,
+                                                     double* __restrict__ diag, double* __restrict__ val,
+                                                     double* __restrict__ rhs) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double d = 0.0, r = 0.0;
+  const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    double a = 0.0;
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      double af = aF[f];
+      d += af;
+      a = -af;
+      double t = -phiH[f] + ncorr[f];
+      r += nb ? -t : t;
+    } else {
+      int b = sf - m.nfi;
+      r -= phiH[m.nfi + b];
+      if (codeP[b] == BC_FIXED) {
+        double af = aF[m.nfi + b];
+        d += af;
+        r += af * pbv[b];
+      }
+    }
+    val[at] = a;
+  }
+  if (i == ref) {
+    r += d * pref;
+    d = d + d;
+  }
+  diag[i] = d;
+  rhs[i] = r;
+}
+
+// flux correction with the same explicit correction as the right-hand side
+__global__ __launch_bounds__(BLOCK) void k_flux(MeshView<double> m, const double* __restrict__ phiH,
+                                                const double* __restrict__ aF, const double* __restrict__ ncorr,
+                                                const double* __restrict__ p, const double* __restrict__ pbv,
+                                                double* __restrict__ phi) {
+  int f = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    phi[f] = phiH[f] - (aF[f] * (p[m.nbr[f]] - p[m.own[f]]) + ncorr[f]);
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    int8_t cp = m.bcode[DIFVM_BC_P * m.nfb + b];
+    double v = 0.0;
+    if (cp == BC_FIXED) v = phiH[f] - aF[f] * (pbv[b] - p[m.bown[b]]);
+    else if (cp == BC_ZEROGRAD) v = phiH[f];
+    phi[f] = v;
+  }
+}
+
+// velocity correction U = HbyA - rAU grad p (Gauss gradient of the new pressure, fused)
+__global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const double* __restrict__ p,
+                                                 const double* __restrict__ pbv, const double* __restrict__ HbyA,
+                                                 const double* __restrict__ rAU, double* __restrict__ U) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double pi = p[i];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) break;
+    int j = m.slot_col[at];
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      auto g = m.geomS[f];
+      double wself = nb ? 1.0 - g.w : g.w;
+      double pf = (nb ? -1.0 : 1.0) * (wself * pi + (1.0 - wself) * p[j]);
+      acc[0] += pf * g.x;
+      acc[1] += pf * g.y;
+      acc[2] += pf * g.z;
+    } else {
+      int b = sf - m.nfi;
+      auto g = m.bgeom[b];
+      double pf = codeP[b] == BC_FIXED ? pbv[b] : pi;
+      acc[0] += pf * g.x;
+      acc[1] += pf * g.y;
+      acc[2] += pf * g.z;
+    }
+  }
+  double s = rAU[i] / m.V[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) U[3 * (size_t)i + c] = HbyA[3 * (size_t)i + c] - s * acc[c];
+}
+
+// phi = interp(U).S with boundary values from the velocity table
+__global__ __launch_bounds__(BLOCK) void k_initial_flux(MeshView<double> m, const double* __restrict__ U,
+                                                        const double* __restrict__ Ub, double* __restrict__ phi) {
+  int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    auto g = m.geomS[f];
+    const double* uo = U + 3 * (size_t)m.own[f];
+    const double* un = U + 3 * (size_t)m.nbr[f];
+    double w = g.w, wn = 1.0 - w;
+    phi[f] = (w * uo[0] + wn * un[0]) * g.x + (w * uo[1] + wn * un[1]) * g.y + (w * uo[2] + wn * un[2]) * g.z;
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    auto g = m.bgeom[b];
+    int8_t cu = m.bcode[DIFVM_BC_U * m.nfb + b];
+    const double* u = cu == BC_FIXED ? Ub + 3 * (size_t)b : U + 3 * (size_t)m.bown[b];
+    phi[f] = cu == BC_EMPTY ? 0.0 : u[0] * g.x + u[1] * g.y + u[2] * g.z;
+  }
+}
+
+}  // namespace difvm
+
+// =============================================================================================
+// PISO object
+// =============================================================================================
+struct difvm_piso {
+  difvm_mesh* mesh = nullptr;
+  difvm_piso_params prm{};
+  int ref = -1;  // internal reference cell, -1 when a pressure value is fixed somewhere
+  double *U = nullptr, *p = nullptr, *phi = nullptr;
+  double *Ub = nullptr, *pb = nullptr, *pbv = nullptr;
+  double *wk = nullptr, *pc = nullptr, *wk_out = nullptr;
+  double *gU = nullptr, *gp = nullptr, *dM = nullptr, *valM = nullptr, *bM = nullptr, *rhs = nullptr;
+  double *HbyA = nullptr, *rAU = nullptr, *phiH = nullptr, *aF = nullptr, *ncorr = nullptr;
+  double *dK = nullptr, *valK = nullptr, *rhsK = nullptr;
+  std::vector<void*> allocs;
+  std::vector<double> wk_host;  // Rp, C, Rd per id
+};
+
+namespace difvm {
+
+static double* piso_alloc(difvm_piso* P, size_t n) {
+  double* a = dalloc<double>(n);
+  P->allocs.push_back(a);
+  DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * (n ? n : 1), stream_of(P->mesh)));
+  return a;
+}
+
+void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) {
+  DIFVM_CHECK(prm && prm->struct_size == sizeof(difvm_piso_params), DIFVM_ERR_INVALID_ARG, "difvm_piso_params mismatch");
+  DIFVM_CHECK(prm->n_corr >= 1 && prm->n_corr <= 8, DIFVM_ERR_INVALID_ARG, "n_corr must be in 1..8");
+  DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
+  const DMesh& d = m->d;
+  DIFVM_CHECK(prm->p_ref_cell >= 0 && prm->p_ref_cell < d.nc, DIFVM_ERR_INVALID_ARG, "p_ref_cell out of range");
+  difvm_piso* P = new difvm_piso();
+  try {
+    P->mesh = m;
+    P->prm = *prm;
+    if (!d.has_fixed_p) {
+      // internal index of the user reference cell
+      const std::vector<int32_t>& cp = m->host.cell_perm;
+      for (int i = 0; i < d.nc; ++i)
+        if (cp[i] == prm->p_ref_cell) P->ref = i;
+    }
+    size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+    P->U = piso_alloc(P, 3 * nc); P->p = piso_alloc(P, nc); P->phi = piso_alloc(P, nf);
+    P->Ub = piso_alloc(P, 3 * (size_t)d.nfb); P->pb = piso_alloc(P, d.nfb); P->pbv = piso_alloc(P, d.nfb);
+    int nwk = std::max(1, d.n_wk);
+    P->wk = piso_alloc(P, 3 * nwk); P->pc = piso_alloc(P, nwk); P->wk_out = piso_alloc(P, 2 * nwk);
+    P->wk_host.assign(3 * nwk, 1.0);
+    P->gU = piso_alloc(P, 9 * nc); P->gp = piso_alloc(P, 3 * nc); P->dM = piso_alloc(P, nc);
+    P->valM = piso_alloc(P, d.nslot); P->bM = piso_alloc(P, 3 * nc); P->rhs = piso_alloc(P, 3 * nc);
+    P->HbyA = piso_alloc(P, 3 * nc); P->rAU = piso_alloc(P, nc); P->phiH = piso_alloc(P, nf); P->aF = piso_alloc(P, nf);
+    P->ncorr = piso_alloc(P, std::max<size_t>(1, d.nfi));
+    P->dK = piso_alloc(P, nc); P->valK = piso_alloc(P, d.nslot); P->rhsK = piso_alloc(P, nc);
+    upload(P->wk, P->wk_host, stream_of(m));
+  } catch (...) {
+    for (void* a : P->allocs) dfree(a);
+    delete P;
+    throw;
+  }
+  *out = P;
+}
+
+void piso_destroy(difvm_piso* P) {
+  if (!P) return;
+  (void)hipStreamSynchronize(stream_of(P->mesh));
+  for (void* a : P->allocs) dfree(a);
+  delete P;
+}
+
+void piso_set_boundary(difvm_piso* P, const double* Ub_user, const double* pb_user) {
+  difvm_mesh* m = P->mesh;
+  if (Ub_user) permute(m, DIFVM_F64, 3, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, Ub_user, P->Ub);
+  if (pb_user) permute(m, DIFVM_F64, 1, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, pb_user, P->pb);
+  DIFVM_HIP(hipMemcpyAsync(P->pbv, P->pb, sizeof(double) * m->d.nfb, hipMemcpyDeviceToDevice, stream_of(m)));
+}
+
+void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, double pc) {
+  DIFVM_CHECK(id >= 0 && id < P->mesh->d.n_wk, DIFVM_ERR_INVALID_ARG, "Windkessel id out of range");
+  DIFVM_CHECK(Rp >= 0 && C > 0 && Rd > 0, DIFVM_ERR_INVALID_ARG, "Windkessel needs Rp >= 0, C > 0, Rd > 0");
+  P->wk_host[3 * id] = Rp;
+  P->wk_host[3 * id + 1] = C;
+  P->wk_host[3 * id + 2] = Rd;
+  hipStream_t s = stream_of(P->mesh);
+  DIFVM_HIP(hipMemcpyAsync(P->wk + 3 * id, &P->wk_host[3 * id], 3 * sizeof(double), hipMemcpyHostToDevice, s));
+  DIFVM_HIP(hipMemcpyAsync(P->pc + id, &pc, sizeof(double), hipMemcpyHostToDevice, s));
+  DIFVM_HIP(hipStreamSynchronize(s));  // the host scalars are on the stack
+}
+
+void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  if (U) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, U, P->U);
+  if (p) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, p, P->p);
+  if (phi) {
+    permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_TO_INTERNAL, phi, P->phi);
+  } else {
+    int nf = d.nfi + d.nfb;
+    k_initial_flux<<<grid_for(nf), BLOCK, 0, stream_of(m)>>>(view<double>(d), P->U, P->Ub, P->phi);
+    DIFVM_HIP(hipGetLastError());
+  }
+}
+
+void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host) {
+  difvm_mesh* m = P->mesh;
+  if (U) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->U, U);
+  if (p) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->p, p);
+  if (phi) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_FROM_INTERNAL, P->phi, phi);
+  if (pc_host && m->d.n_wk)
+    DIFVM_HIP(hipMemcpyAsync(pc_host, P->pc, sizeof(double) * m->d.n_wk, hipMemcpyDeviceToHost, stream_of(m)));
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+}
+
+int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  hipStream_t s = stream_of(m);
+  MeshView<double> mv = view<double>(d);
+  const difvm_piso_params& prm = P->prm;
+  int Gc = grid_for(d.nc), Gf = grid_for(d.nfi + d.nfb);
+  int worst = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    difvm_step_stats st{};
+    // S0
+    if (d.n_wk)
+      k_windkessel<<<d.n_wk, BLOCK, 0, s>>>(d.nfi, prm.dt, d.wk_start, d.wk_faces, P->phi, P->wk, P->pc, P->pbv, P->wk_out);
+    // S1
+    op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
+    op_assemble_momentum(m, prm.nu, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM, P->bM);
+    // S2
+    op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
+    k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
+    DIFVM_HIP(hipGetLastError());
+    SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u);
+    for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
+    st.status = ru.status;
+    // S3
+    for (int corr = 0; corr < prm.n_corr; ++corr) {
+      k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
+      op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
+      k_pface<<<Gf, BLOCK, 0, s>>>(mv, P->HbyA, P->rAU, P->gp, P->Ub, P->phiH, P->aF, P->ncorr);
+      k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->ref, prm.p_ref_value, P->dK, P->valK, P->rhsK);
+      DIFVM_HIP(hipGetLastError());
+      SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p);
+      st.it_p[corr] = rp.iters[0];
+      st.res_p[corr] = rp.res[0];
+      st.status = std::max(st.status, rp.status);
+      k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
+      k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
+      DIFVM_HIP(hipGetLastError());
+    }
+    worst = std::max(worst, st.status);
+    if (stats) stats[step] = st;
+  }
+  DIFVM_HIP(hipStreamSynchronize(s));
+  return worst;
+}
+
+}  // namespace difvm
