@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--n", type=int, default=56, help="hexes per side of the Kuhn cube")
     ap.add_argument("--no-ops", action="store_true", help="skip the per-operator sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing in this build uses a second GPU.",
@@ -164,6 +166,16 @@ def main():
 
     from paper_2603_15920_amd import binding as B
     from paper_2603_15920_amd import meshgen as mg
+
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_mib} MiB read + {args.copy_mib} MiB written")
+        del src, dst
 
     t0 = time.time()
     m, Ub, wk, q_in = channel_setup(mg, args.n)

@@ -77,8 +77,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[BLOCK / 64]) {
+// block of NT threads: every thread ends with the block total (fixed summation order)
+template <int NV, int NT = BLOCK>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NT / 64]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
   int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -91,7 +92,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[BLOCK /
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < BLOCK / 64; ++q) s += lds[k][q];
+    for (int q = 0; q < NT / 64; ++q) s += lds[k][q];
     v[k] = s;
   }
 }

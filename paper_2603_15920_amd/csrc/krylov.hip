@@ -91,6 +91,7 @@ __device__ __forceinline__ void sell_row(const SellView& A, int i, const double*
   double di = A.diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     double a = A.val[at];
@@ -145,16 +146,17 @@ void sell_spmv(const difvm_mesh* m, int ncomp, SellMatrix A, const double* x, do
 // ---------------------------------------------------------------------------------------------
 // PCG: two kernels per iteration and no memory fences.
 //
-// Dot products are summed per 1024-cell tile into a partial array; the NEXT kernel re-sums that
-// array in a fixed order in every block (every block obtains the same bits), so no tile ever waits
-// for another and no L2 write-back is needed.  Partials of r.r and r.z are double-buffered by
-// iteration parity so that beta = (r_k.z_k)/(r_{k-1}.z_{k-1}) can be formed from the two latest.
-// The direction update p_k = z_{k-1} + beta p_{k-1} is fused into the product q = A p_k: a cell
-// computes its own and its neighbours' p_k from z and the previous direction (ping-pong buffers).
-//   init1:  r = b - A x                         partials (b.b, r.r)
-//   init2:  stopping test at k = 0; z = r/d     partials B0 = (r.r, r.z)
-//   spmv_k: stopping test of iterate k-1, beta; p_k; q = A p_k     partials A = (p.q)
-//   upd_k:  alpha = rho/(p.q); x += alpha p; r -= alpha q; z = r/d  partials B_k = (r.r, r.z)
+// Dot products are summed per 1024-cell tile into partial arrays; the NEXT kernel re-sums an array
+// in a fixed order in every block (all blocks obtain the same bits), so no tile waits for another
+// and no L2 write-back is needed.  The direction update p_k = z_{k-1} + beta p_{k-1} is fused into
+// the product q = A p_k: each cell forms its own and its neighbours' p_k from the interleaved pair
+// (z, p) of the previous iteration, one 16-byte gather per matrix slot.  (z, p) pairs are
+// double-buffered by iteration parity, and so are the published scalars rho_k = r_k.z_k.
+//   init1:  r = b - A x                               partials (b.b, r.r)
+//   init2:  stopping test at k = 0; z0 = r/d          partials B = (r.r, r.z)
+//   spmv_k: rho_{k-1} and the stopping test of iterate k-1 (from B), beta; p_k; q = A p_k
+//                                                     partials A = (p.q); tile 0 publishes rho_{k-1}
+//   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
 // Tile 0 records iterations / residual / status; kernels after the stop return at once.
 // ---------------------------------------------------------------------------------------------
 constexpr int PCG_TILE = 1024;             // cells per reduction partial
@@ -162,6 +164,7 @@ constexpr int PCG_CPT = PCG_TILE / BLOCK;  // cells per thread
 
 struct PcgCtl {
   double tol, bn, res;
+  double rho[2];  // rho_k at index k & 1, published by tile 0 of spmv_{k+1}
   int maxit, done, iters, status;
 };
 
@@ -174,7 +177,7 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
   return f != 0;
 }
 
-// fixed-order sum of G partials (NV values each, value-major) -> identical result in every block
+// fixed-order sum of G partials (NV arrays, value-major) -> identical result in every block
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int G, double (&out)[NV]) {
   __shared__ double lds[NV][BLOCK / 64];
@@ -194,6 +197,14 @@ __device__ __forceinline__ void write_partial(double (&v)[NV], double* __restric
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < NV; ++k) part[(size_t)k * G + tile] = v[k];
+}
+
+// slice start of the wave's 64 cells, read once per wave through the scalar unit
+__device__ __forceinline__ SlotRange wave_slots(const int32_t* __restrict__ slice_start, int i) {
+  int s = __builtin_amdgcn_readfirstlane(i >> 6);
+  int b = slice_start[s];
+  int e = slice_start[s + 1];
+  return {b + (i & (SLICE - 1)), (e - b) >> 6};
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, const double* __restrict__ b, const double* __restrict__ x,
@@ -216,8 +227,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, const double* _
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, double* __restrict__ x, const double* __restrict__ r,
-                                                     double* __restrict__ z, const double* __restrict__ part_in,
-                                                     double* __restrict__ partB0, PcgCtl* ctl) {
+                                                     double2* __restrict__ zp0, const double* __restrict__ part_in,
+                                                     double* __restrict__ partB, PcgCtl* ctl) {
   int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
   double s[2];
   sum_partials<2>(part_in, G, s);
@@ -245,28 +256,28 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, double* __restr
     int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
     if (i < A.nc) {
       double ri = r[i], zi = ri / A.diag[i];
-      z[i] = zi;
+      zp0[i] = make_double2(zi, 0.0);  // p_0 = 0 so that p_1 = z_0 + 0 * p_0
       v[0] += ri * ri;
       v[1] += ri * zi;
     }
   }
-  write_partial<2>(v, partB0, G, tile);
+  write_partial<2>(v, partB, G, tile);
 }
 
-// iteration k >= 1: test iterate k-1, then p_k and q = A p_k
-__global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const double* __restrict__ z,
-                                                    const double* __restrict__ p_old, double* __restrict__ p_new,
-                                                    double* __restrict__ q, const double* __restrict__ partB_prev,
-                                                    const double* __restrict__ partB_prev2, double* __restrict__ partA,
+// iteration k >= 1: stopping test of iterate k-1, then p_k and q = A p_k
+__global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const double2* __restrict__ zp_prev,
+                                                    double2* __restrict__ zp_cur, double* __restrict__ q,
+                                                    const double* __restrict__ partB, double* __restrict__ partA,
                                                     PcgCtl* ctl) {
   if (block_flag(&ctl->done)) return;
   int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
+  double s2[2];
+  sum_partials<2>(partB, G, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+  double rho = s2[1];
+  if (tile == 0 && threadIdx.x == 0) ctl->rho[(k - 1) & 1] = rho;
   double beta = 0.0;
   if (k >= 2) {
-    double s[2], s2[2];
-    sum_partials<2>(partB_prev, G, s);    // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
-    sum_partials<2>(partB_prev2, G, s2);  // (., r_{k-2}.z_{k-2})
-    double rn = sqrt(s[0]), bn = ctl->bn;
+    double rn = sqrt(s2[0]), bn = ctl->bn;
     bool conv = rn <= ctl->tol * bn;
     if (conv || k - 1 >= ctl->maxit) {
       if (tile == 0 && threadIdx.x == 0) {
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const dou
       }
       return;
     }
-    beta = s[1] / s2[1];
+    beta = rho / ctl->rho[k & 1];  // rho_{k-1} / rho_{k-2}
   } else if (ctl->maxit <= 0) {
     if (tile == 0 && threadIdx.x == 0) {
       ctl->done = 1;
@@ -290,16 +301,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const dou
   for (int c = 0; c < PCG_CPT; ++c) {
     int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
     if (i < A.nc) {
-      double pi = k >= 2 ? z[i] + beta * p_old[i] : z[i];
-      SlotRange R = slots_of(A.slice_start, i);
+      double2 zpi = zp_prev[i];
+      double pi = zpi.x + beta * zpi.y;
+      SlotRange R = wave_slots(A.slice_start, i);
       double acc = A.diag[i] * pi;
+#pragma unroll 4
       for (int s = 0; s < R.width; ++s) {
         int at = R.base + s * SLICE;
-        int j = A.col[at];
-        double pj = k >= 2 ? z[j] + beta * p_old[j] : z[j];
-        acc += A.val[at] * pj;
+        double2 zpj = zp_prev[A.col[at]];
+        acc += A.val[at] * (zpj.x + beta * zpj.y);
       }
-      p_new[i] = pi;
+      zp_cur[i].y = pi;
       q[i] = acc;
       v[0] += pi * acc;
     }
@@ -307,28 +319,39 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const dou
   write_partial<1>(v, partA, G, tile);
 }
 
-// iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z
+// iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (loads issued before the
+// partial sum, as above)
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, double* __restrict__ x, double* __restrict__ r,
-                                                      double* __restrict__ z, const double* __restrict__ p,
-                                                      const double* __restrict__ q, const double* __restrict__ partA,
-                                                      const double* __restrict__ partB_prev, double* __restrict__ partB,
-                                                      PcgCtl* ctl) {
+                                                      double2* __restrict__ zp_cur, const double* __restrict__ q,
+                                                      const double* __restrict__ partA, double* __restrict__ partB,
+                                                      int k, PcgCtl* ctl) {
   if (block_flag(&ctl->done)) return;
   int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
-  double pq[1], s[2];
+  double xv[PCG_CPT], pv[PCG_CPT], rv[PCG_CPT], qv[PCG_CPT], dv[PCG_CPT];
+#pragma unroll
+  for (int c = 0; c < PCG_CPT; ++c) {
+    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
+    if (i < A.nc) {
+      xv[c] = x[i];
+      pv[c] = zp_cur[i].y;
+      rv[c] = r[i];
+      qv[c] = q[i];
+      dv[c] = A.diag[i];
+    }
+  }
+  double pq[1];
   sum_partials<1>(partA, G, pq);
-  sum_partials<2>(partB_prev, G, s);
-  double alpha = s[1] / pq[0];
+  double alpha = ctl->rho[(k - 1) & 1] / pq[0];
   double v[2] = {0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < PCG_CPT; ++c) {
     int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
     if (i < A.nc) {
-      x[i] += alpha * p[i];
-      double ri = r[i] - alpha * q[i];
-      double zi = ri / A.diag[i];
+      x[i] = xv[c] + alpha * pv[c];
+      double ri = rv[c] - alpha * qv[c];
+      double zi = ri / dv[c];
       r[i] = ri;
-      z[i] = zi;
+      zp_cur[i].x = zi;
       v[0] += ri * ri;
       v[1] += ri * zi;
     }
@@ -353,14 +376,14 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   init.maxit = maxit;
   DIFVM_HIP(hipMemcpyAsync(ctl, &init, sizeof(PcgCtl), hipMemcpyHostToDevice, s));
   double* r = w->r;
-  double* z = w->z;
-  double* P[2] = {w->p, w->v};
   double* q = w->q;
+  // (z, p) pairs, two parities: 2 * 2 * nc doubles in the p and v buffers (each 3 nc long)
+  double2* ZP[2] = {reinterpret_cast<double2*>(w->p), reinterpret_cast<double2*>(w->v)};
   double* partA = w->partials;
-  double* partB[2] = {w->partials + 2 * (size_t)G, w->partials + 4 * (size_t)G};
-  double* part0 = w->partials + 6 * (size_t)G;
+  double* partB = w->partials + 2 * (size_t)G;
+  double* part0 = w->partials + 4 * (size_t)G;
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, b, x, r, part0);
-  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, x, r, z, part0, partB[0], ctl);
+  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, x, r, ZP[0], part0, partB, ctl);
   DIFVM_HIP(hipGetLastError());
   // First block sized from the previous solve (iterations are similar from step to step), then
   // short polled blocks; kernels queued after the stop return at once.  Iteration k's stopping
@@ -372,12 +395,12 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     for (; k <= last; ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<G, BLOCK, 0, s>>>(V, k, z, P[(k - 1) & 1], P[k & 1], q, partB[(k - 1) & 1], partB[k & 1], partA, ctl);
+        k_pcg_spmv<<<G, BLOCK, 0, s>>>(V, k, ZP[(k - 1) & 1], ZP[k & 1], q, partB, partA, ctl);
       }
       if (k > maxit) break;
       {
         ProfScope ps(m, "pcg_update_dot");
-        k_pcg_update<<<G, BLOCK, 0, s>>>(V, x, r, z, P[k & 1], q, partA, partB[(k - 1) & 1], partB[k & 1], ctl);
+        k_pcg_update<<<G, BLOCK, 0, s>>>(V, x, r, ZP[k & 1], q, partA, partB, k, ctl);
       }
     }
     DIFVM_HIP(hipGetLastError());

@@ -101,10 +101,11 @@ __global__ __launch_bounds__(BLOCK) void k_grad(MeshView<T> m, int table, const 
     acc[c][0] = acc[c][1] = acc[c][2] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     int j = m.slot_col[at];
     if (sf < m.nfi) {
       bool nb = sf < 0;
@@ -155,10 +156,11 @@ __global__ __launch_bounds__(BLOCK) void k_div(MeshView<T> m, int table, const T
     acc[c] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     int j = m.slot_col[at];
     if (sf < m.nfi) {
       bool nb = sf < 0;
@@ -210,10 +212,11 @@ __global__ __launch_bounds__(BLOCK) void k_laplacian(MeshView<T> m, int table, c
   T gi0 = g[3 * (size_t)i], gi1 = g[3 * (size_t)i + 1], gi2 = g[3 * (size_t)i + 2];
   T acc = T(0);
   const int8_t* code = m.bcode + table * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     int j = m.slot_col[at];
     if (sf < m.nfi) {
       bool nb = sf < 0;
@@ -255,10 +258,11 @@ __global__ __launch_bounds__(BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __re
   T di = diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     if (sf >= m.nfi) continue;
     int j = m.slot_col[at];
     T a = sf < 0 ? lo[-sf - 1] : up[sf];
@@ -280,10 +284,11 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_laplace(MeshView<double> m, 
   SlotRange R = slots_of(m.slice_start, i);
   double d = 0.0, r = 0.0;
   const int8_t* code = m.bcode + table * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     if (sf < m.nfi) {
       bool nb = sf < 0;
       int f = nb ? -sf - 1 : sf;

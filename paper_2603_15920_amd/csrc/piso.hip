@@ -42,10 +42,11 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
   double bi[3] = {Vdt * U[3 * (size_t)i], Vdt * U[3 * (size_t)i + 1], Vdt * U[3 * (size_t)i + 2]};
   const double* gi = gU + 9 * (size_t)i;
   const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     double a = 0.0;
     if (sf < m.nfi) {
       bool nb = sf < 0;
@@ -153,6 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
   if (i >= nc) return;
   SlotRange R = slots_of(slice_start, i);
   double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     double a = val[at];
@@ -213,10 +215,11 @@ __global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const d
   SlotRange R = slots_of(m.slice_start, i);
   double d = 0.0, r = 0.0;
   const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     double a = 0.0;
     if (sf < m.nfi) {
       bool nb = sf < 0;
@@ -273,10 +276,11 @@ __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const doubl
   double pi = p[i];
   double acc[3] = {0.0, 0.0, 0.0};
   const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
+#pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) break;
+    if (sf == SLOT_PAD) continue;
     int j = m.slot_col[at];
     if (sf < m.nfi) {
       bool nb = sf < 0;
