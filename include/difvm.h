@@ -268,6 +268,32 @@ difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi,
  * residuals per step.  Synchronises.  Returns the worst solver status over the steps. */
 difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats* stats_host);
 
+/* ---- differentiation (paper Sec. "End-to-End Automatic Differentiation") -------------------
+ * Reverse mode through an N-step window of the PISO: a discrete adjoint of every step (transposed
+ * gathers; each linear solve differentiated implicitly with the same Krylov solver on the
+ * transposed matrix, eq. implicit_diff; upwind branches frozen at the forward's choice), with the
+ * state checkpointed every ckpt_every steps and each segment recomputed once (eq. checkpointing).
+ * The window starts from the PISO's state when difvm_piso_forward_record is called and uses the
+ * boundary values and Windkessel parameters set at that time; they must not change in between. */
+typedef struct difvm_tape difvm_tape;
+difvm_status difvm_tape_create(difvm_piso* piso, int32_t nsteps, int32_t ckpt_every, difvm_tape** out);
+difvm_status difvm_tape_destroy(difvm_tape* tape); /* NULL is a no-op */
+
+/* Runs the window's nsteps forward steps, storing checkpoints (synchronises).  stats_host[nsteps]
+ * may be NULL.  The PISO ends at the window's final state. */
+difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm_step_stats* stats_host);
+
+/* Vector-Jacobian product of the window (eq. vjp).  Cotangents of the final state in USER order
+ * (device arrays, NULL = zero): gU_N[Nc*3], gp_N[Nc], gphi_N[Fi+Fb] (user orientation), and
+ * gpc_N_host[n_windkessel] (host, NULL = zero).  Outputs: cotangents of the initial state (device,
+ * user order, NULL to skip) gU_0, gp_0, gphi_0 (the initial flux is an independent input), gpc_0_host,
+ * and of the Windkessel parameters gwk_host[n_windkessel*3] as (Rp, C, Rd) per outlet (host).
+ * adj_tol is the relative tolerance of the transposed solves.  Synchronises; the PISO is left at the
+ * window's final state. */
+difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* gU_N, const void* gp_N,
+                                const void* gphi_N, const double* gpc_N_host, double adj_tol, void* gU_0, void* gp_0,
+                                void* gphi_0, double* gpc_0_host, double* gwk_host);
+
 #ifdef __cplusplus
 }
 #endif

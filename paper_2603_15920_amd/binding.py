@@ -107,6 +107,10 @@ _SIGS = {
     "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_piso_get_state": (C.c_int32, [_vp, _vp, _vp, _vp, _f64p]),
     "difvm_piso_step": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
+    "difvm_tape_create": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(_vp)]),
+    "difvm_tape_destroy": (C.c_int32, [_vp]),
+    "difvm_piso_forward_record": (C.c_int32, [_vp, _vp, C.POINTER(StepStats)]),
+    "difvm_piso_adjoint": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _f64p, C.c_double, _vp, _vp, _vp, _f64p, _f64p]),
 }
 
 
@@ -338,6 +342,35 @@ def difvm_piso_step(p, nsteps, n_corr=2):
     it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats[:nsteps]], dtype=np.int32)
     res = np.array([[*s.res_u, *list(s.res_p)[:n_corr]] for s in stats[:nsteps]])
     return status, it, res
+
+
+def difvm_tape_create(p, nsteps, ckpt_every):
+    out = _vp()
+    _check(lib().difvm_tape_create(p, int(nsteps), int(ckpt_every), C.byref(out)), "difvm_tape_create")
+    return out
+
+
+def difvm_tape_destroy(t):
+    _check(lib().difvm_tape_destroy(t), "difvm_tape_destroy")
+
+
+def difvm_piso_forward_record(p, t, nsteps, n_corr=2):
+    stats = (StepStats * max(1, nsteps))()
+    status = _check(lib().difvm_piso_forward_record(p, t, stats), "difvm_piso_forward_record")
+    it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats[:nsteps]], dtype=np.int32)
+    return status, it
+
+
+def difvm_piso_adjoint(p, t, gU_N, gp_N, gphi_N, gpc_N, adj_tol, gU_0, gp_0, gphi_0, n_wk):
+    """Returns (status, gpc_0[n_wk], gwk[n_wk, 3]); device outputs are written in place."""
+    gpc_in = None
+    if gpc_N is not None and n_wk:
+        gpc_in = (C.c_double * n_wk)(*[float(v) for v in gpc_N])
+    gpc_out = (C.c_double * max(1, n_wk))()
+    gwk = (C.c_double * max(1, 3 * n_wk))()
+    status = _check(lib().difvm_piso_adjoint(p, t, _ptr(gU_N), _ptr(gp_N), _ptr(gphi_N), gpc_in, float(adj_tol),
+                                             _ptr(gU_0), _ptr(gp_0), _ptr(gphi_0), gpc_out, gwk), "difvm_piso_adjoint")
+    return status, np.array(gpc_out[:n_wk]), np.array(gwk[:3 * n_wk]).reshape(n_wk, 3)
 
 
 # ------------------------------------------------------------------------------------------------

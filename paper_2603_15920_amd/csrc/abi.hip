@@ -141,6 +141,8 @@ static void upload_mesh(difvm_mesh* m) {
   d.slice_start = up_vec(m, L.slice_start);
   d.slot_face = up_vec(m, L.slot_face);
   d.slot_col = up_vec(m, L.slot_col);
+  d.face_slot_own = up_vec(m, L.face_slot_own);
+  d.face_slot_nbr = up_vec(m, L.face_slot_nbr);
   d.cell_perm = up_vec(m, L.cell_perm);
   d.face_perm = up_vec(m, L.face_perm);
   d.bface_perm = up_vec(m, L.bface_perm);

@@ -1,0 +1,724 @@
+// Discrete adjoint of the PISO step and its checkpointed N-step window (paper Sec. "End-to-End
+// Automatic Differentiation": reverse mode through the time loop, eq. vjp; checkpointing, eq.
+// checkpointing; linear solves differentiated implicitly with the same solver, eq. implicit_diff;
+// Windkessel parameters as leaves, Sec. "Windkessel RCR outlet condition").
+//
+// Given the lagged flux phi^n, one step is linear in (U^n, p^n, boundary pressures); it depends
+// nonlinearly on phi^n only through the momentum coefficients (upwind branches, frozen in reverse:
+// d max(F,0)/dF = 1 for F >= 0) and on the Windkessel parameters through the exponential update.
+// The reverse step walks the forward operations backwards:
+//   gather  (cell reads neighbours)      -> transpose is a scatter, written here as a gather of
+//                                           per-face cotangents by each cell in slot order
+//   solve   A x = b                      -> A^T lambda = xbar with the same Krylov solver
+//                                           (momentum: owner/neighbour coefficients swapped;
+//                                           pressure: symmetric), then bbar += lambda and
+//                                           Abar = -lambda x^T on the sparsity pattern.
+// No atomics: every cotangent array is written by the thread owning its row, cell or face.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "abi_util.h"
+#include "device.h"
+#include "ops.h"
+#include "piso_internal.h"
+
+namespace difvm {
+
+// ---------------------------------------------------------------------------------------------
+// transposed operators
+// ---------------------------------------------------------------------------------------------
+// Adjoint of the Gauss gradient: gbar[nc][NC][3] -> phibar[nc][NC] (+=) and, on fixed-value
+// boundary faces, phib_bar[nfb][NC] (+=, may be NULL).  For an internal face the cotangent of the
+// face value is (gbar_O/V_O - gbar_N/V_N).S, shared to O and N with the interpolation weights.
+template <int NC>
+__global__ __launch_bounds__(BLOCK) void k_gradT(MeshView<double> m, int table, const double* __restrict__ gbar,
+                                                 double* __restrict__ phibar, double* __restrict__ phib_bar) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double rvi = 1.0 / m.V[i];
+  double gi[NC][3];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) gi[c][e] = gbar[((size_t)i * NC + c) * 3 + e] * rvi;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  const int8_t* code = m.bcode + table * m.nfb;
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) continue;
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      int j = m.slot_col[at];
+      auto g = m.geomS[f];
+      double wself = nb ? 1.0 - g.w : g.w;
+      double sg = nb ? -1.0 : 1.0;
+      double rvj = 1.0 / m.V[j];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double* gj = gbar + ((size_t)j * NC + c) * 3;
+        double t = (gi[c][0] - gj[0] * rvj) * g.x + (gi[c][1] - gj[1] * rvj) * g.y + (gi[c][2] - gj[2] * rvj) * g.z;
+        acc[c] += wself * sg * t;
+      }
+    } else {
+      int b = sf - m.nfi;
+      auto g = m.bgeom[b];
+      bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double t = gi[c][0] * g.x + gi[c][1] * g.y + gi[c][2] * g.z;
+        if (fixed) {
+          if (phib_bar) phib_bar[(size_t)b * NC + c] += t;
+        } else {
+          acc[c] += t;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) phibar[(size_t)i * NC + c] += acc[c];
+}
+
+// transposed momentum off-diagonals: the slot of (O,N) takes the coefficient of (N,O) and back
+__global__ __launch_bounds__(BLOCK) void k_swap_slots(int nfi, const int32_t* __restrict__ own_slot,
+                                                      const int32_t* __restrict__ nbr_slot, const double* __restrict__ val,
+                                                      double* __restrict__ valT) {
+  int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f >= nfi) return;
+  int a = own_slot[f], b = nbr_slot[f];
+  valT[a] = val[b];
+  valT[b] = val[a];
+}
+
+// ---------------------------------------------------------------------------------------------
+// reverse of the correctors
+// ---------------------------------------------------------------------------------------------
+// U = HbyA - rAU grad(p):  HbyAbar = Ubar, rAUbar -= Ubar.grad(p), gbar = -rAU Ubar
+__global__ __launch_bounds__(BLOCK) void k_adj_ucorr(int nc, const double* __restrict__ Ubar, const double* __restrict__ gpn,
+                                                     const double* __restrict__ rAU, double* __restrict__ HbyAbar,
+                                                     double* __restrict__ rAUbar, double* __restrict__ gbar) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double u = Ubar[3 * (size_t)i + c];
+    HbyAbar[3 * (size_t)i + c] = u;
+    s += u * gpn[3 * (size_t)i + c];
+    gbar[3 * (size_t)i + c] = -rAU[i] * u;
+  }
+  rAUbar[i] -= s;
+}
+
+// cotangents of the face quantities of a corrector, seeded by the step's output flux
+// (phi = phiH - aF (p_N - p_O) - ncorr; boundary: fixed p: phiH - aF_b (p_b - p_O); else phiH)
+__global__ __launch_bounds__(BLOCK) void k_adj_flux(MeshView<double> m, int seed, const double* __restrict__ phibar,
+                                                    const double* __restrict__ rAU, const double* __restrict__ p,
+                                                    const double* __restrict__ pbv, double* __restrict__ fHb,
+                                                    double* __restrict__ faF, double* __restrict__ fnc,
+                                                    double* __restrict__ g, double* __restrict__ pbvbar) {
+  int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    double fb = seed ? phibar[f] : 0.0;
+    int O = m.own[f], N = m.nbr[f];
+    double w = m.w[f];
+    double aF = (w * rAU[O] + (1.0 - w) * rAU[N]) * m.geomK[f].w;
+    fHb[f] = fb;
+    faF[f] = -fb * (p[N] - p[O]);
+    fnc[f] = -fb;
+    g[f] = aF * fb;
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    double fb = seed ? phibar[f] : 0.0;
+    int8_t cp = m.bcode[DIFVM_BC_P * m.nfb + b];
+    int O = m.bown[b];
+    fHb[f] = cp == BC_EMPTY ? 0.0 : fb;
+    faF[f] = 0.0;
+    g[f] = 0.0;
+    if (cp == BC_FIXED) {
+      double aF = rAU[O] * m.bgeom[b].w;
+      faF[f] = -fb * (pbv[b] - p[O]);
+      pbvbar[b] -= aF * fb;
+      g[f] = aF * fb;
+    }
+  }
+}
+
+// after the pressure solve: lambda = K^-1 pbar.  K pattern cotangent -lambda p^T, right-hand side
+// cotangent lambda, pushed to the face quantities (aF, phiH, ncorr) and the boundary pressures
+__global__ __launch_bounds__(BLOCK) void k_adj_psolve(MeshView<double> m, const double* __restrict__ lam,
+                                                      const double* __restrict__ p, const double* __restrict__ rAU,
+                                                      const double* __restrict__ pbv, int ref, double pref,
+                                                      double* __restrict__ fHb, double* __restrict__ faF,
+                                                      double* __restrict__ fnc, double* __restrict__ pbvbar) {
+  int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    int O = m.own[f], N = m.nbr[f];
+    double dl = lam[N] - lam[O], dp = p[N] - p[O];
+    double a = -dl * dp;
+    if (ref >= 0 && (O == ref || N == ref)) a += lam[ref] * (pref - p[ref]);
+    faF[f] += a;
+    fHb[f] += dl;
+    fnc[f] -= dl;
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    int8_t cp = m.bcode[DIFVM_BC_P * m.nfb + b];
+    if (cp == BC_EMPTY) return;
+    int O = m.bown[b];
+    double lo = lam[O];
+    fHb[f] -= lo;
+    if (cp == BC_FIXED) {
+      faF[f] += lo * (pbv[b] - p[O]);
+      pbvbar[b] += rAU[O] * m.bgeom[b].w * lo;
+    }
+  }
+}
+
+// face cotangents -> cells: rAU_f = w rAU_O + (1-w) rAU_N with rAUbar_f = aFbar delta + ncbar k.gbar,
+// phiH_f = interp(HbyA).S, ncorr_f = rAU_f k.interp(grad p_old)
+__global__ __launch_bounds__(BLOCK) void k_adj_corr_cells(MeshView<double> m, const double* __restrict__ fHb,
+                                                          const double* __restrict__ faF, const double* __restrict__ fnc,
+                                                          const double* __restrict__ rAU, const double* __restrict__ gpo,
+                                                          double* __restrict__ rAUbar, double* __restrict__ HbyAbar,
+                                                          double* __restrict__ gpobar) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double ra = 0.0, hb[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
+  const double* gi = gpo + 3 * (size_t)i;
+  const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
+  const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD) continue;
+    if (sf < m.nfi) {
+      bool nb = sf < 0;
+      int f = nb ? -sf - 1 : sf;
+      int j = m.slot_col[at];
+      auto g = m.geomS[f];
+      auto kd = m.geomK[f];
+      double wself = nb ? 1.0 - g.w : g.w;
+      const double* gj = gpo + 3 * (size_t)j;
+      double rf = wself * rAU[i] + (1.0 - wself) * rAU[j];
+      double kg = kd.x * (wself * gi[0] + (1.0 - wself) * gj[0]) + kd.y * (wself * gi[1] + (1.0 - wself) * gj[1]) +
+                  kd.z * (wself * gi[2] + (1.0 - wself) * gj[2]);
+      double nc = fnc[f];
+      ra += wself * (faF[f] * kd.w + nc * kg);
+      double h = wself * fHb[f];
+      hb[0] += h * g.x;
+      hb[1] += h * g.y;
+      hb[2] += h * g.z;
+      double t = wself * nc * rf;
+      gb[0] += t * kd.x;
+      gb[1] += t * kd.y;
+      gb[2] += t * kd.z;
+    } else {
+      int b = sf - m.nfi;
+      auto g = m.bgeom[b];
+      if (codeP[b] == BC_FIXED) ra += faF[m.nfi + b] * g.w;
+      if (codeU[b] == BC_ZEROGRAD) {
+        double h = fHb[m.nfi + b];
+        hb[0] += h * g.x;
+        hb[1] += h * g.y;
+        hb[2] += h * g.z;
+      }
+    }
+  }
+  rAUbar[i] += ra;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    HbyAbar[3 * (size_t)i + c] += hb[c];
+    gpobar[3 * (size_t)i + c] = gb[c];
+  }
+}
+
+// HbyA = H / d: Hbar = HbyAbar / d, dbar -= HbyAbar.HbyA / d, bbar += Hbar
+__global__ __launch_bounds__(BLOCK) void k_adj_hbya(int nc, const double* __restrict__ HbyAbar,
+                                                    const double* __restrict__ HbyA, const double* __restrict__ dM,
+                                                    double* __restrict__ Hbar, double* __restrict__ dbar,
+                                                    double* __restrict__ bbar) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  double d = dM[i], s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double hb = HbyAbar[3 * (size_t)i + c];
+    double h = hb / d;
+    Hbar[3 * (size_t)i + c] = h;
+    bbar[3 * (size_t)i + c] += h;
+    s += hb * HbyA[3 * (size_t)i + c];
+  }
+  dbar[i] -= s / d;
+}
+
+// H = b - offdiag(M) Uin:  valbar(i,j) -= Hbar_i.Uin_j ;  Ubar = -offdiag(M)^T Hbar  (written)
+// also used for the predictor with xbar = mu: valbar -= mu_i.U*_j (then Ubar unused)
+__global__ __launch_bounds__(BLOCK) void k_adj_offdiag(int nc, const int32_t* __restrict__ slice_start,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ valT,
+                                                       const double* __restrict__ ybar, const double* __restrict__ x,
+                                                       double* __restrict__ valbar, double* __restrict__ Ubar) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  SlotRange R = slots_of(slice_start, i);
+  double yi[3] = {ybar[3 * (size_t)i], ybar[3 * (size_t)i + 1], ybar[3 * (size_t)i + 2]};
+  double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int j = col[at];
+    const double* xj = x + 3 * (size_t)j;
+    const double* yj = ybar + 3 * (size_t)j;
+    valbar[at] -= yi[0] * xj[0] + yi[1] * xj[1] + yi[2] * xj[2];
+    double a = valT[at];
+    u[0] -= a * yj[0];
+    u[1] -= a * yj[1];
+    u[2] -= a * yj[2];
+  }
+  if (Ubar)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ubar[3 * (size_t)i + c] = u[c];
+}
+
+// predictor U* = M^-1 (b - V grad p): dbar -= mu.U*, bbar += mu, gbar = -V mu
+__global__ __launch_bounds__(BLOCK) void k_adj_pred(int nc, const double* __restrict__ mu, const double* __restrict__ Us,
+                                                    const double* __restrict__ V, double* __restrict__ dbar,
+                                                    double* __restrict__ bbar, double* __restrict__ gbar) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double m = mu[3 * (size_t)i + c];
+    s += m * Us[3 * (size_t)i + c];
+    bbar[3 * (size_t)i + c] += m;
+    gbar[3 * (size_t)i + c] = -V[i] * m;
+  }
+  dbar[i] -= s;
+}
+
+// rAU = V / d:  dbar -= rAUbar rAU / d
+__global__ __launch_bounds__(BLOCK) void k_adj_rau(int nc, const double* __restrict__ rAUbar, const double* __restrict__ rAU,
+                                                   const double* __restrict__ dM, double* __restrict__ dbar) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  dbar[i] -= rAUbar[i] * rAU[i] / dM[i];
+}
+
+// b = V/dt U^n + fixed-U boundary terms + nu sum sigma k.interp(grad U^n):
+// Ubar^n = V/dt bbar (written), gUbar_i = nu sum_slots wself sigma (bbar_i - bbar_j) (x) k
+__global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, double nu, double dt, const double* __restrict__ bbar,
+                                                    double* __restrict__ Ubar0, double* __restrict__ gUbar) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  const double* bi = bbar + 3 * (size_t)i;
+  double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD || sf >= m.nfi) continue;
+    bool nb = sf < 0;
+    int f = nb ? -sf - 1 : sf;
+    int j = m.slot_col[at];
+    auto kd = m.geomK[f];
+    double w = m.w[f];
+    double wself = nb ? 1.0 - w : w;
+    double sg = nb ? -nu : nu;
+    const double* bj = bbar + 3 * (size_t)j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double t = wself * sg * (bi[c] - bj[c]);
+      gu[c][0] += t * kd.x;
+      gu[c][1] += t * kd.y;
+      gu[c][2] += t * kd.z;
+    }
+  }
+  double vdt = m.V[i] / dt;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    Ubar0[3 * (size_t)i + c] = vdt * bi[c];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) gUbar[9 * (size_t)i + 3 * c + e] = gu[c][e];
+  }
+}
+
+// momentum coefficients -> lagged flux (upwind branch frozen at the forward's choice)
+__global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, const int32_t* __restrict__ own_slot,
+                                                   const int32_t* __restrict__ nbr_slot, const double* __restrict__ phi,
+                                                   const double* __restrict__ valbar, const double* __restrict__ dbar,
+                                                   const double* __restrict__ bbar, const double* __restrict__ Ub,
+                                                   double* __restrict__ phibar) {
+  int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f < m.nfi) {
+    int O = m.own[f], N = m.nbr[f];
+    double F = phi[f];
+    double ub = valbar[own_slot[f]], lb = valbar[nbr_slot[f]];
+    phibar[f] = F >= 0.0 ? dbar[O] - lb : ub - dbar[N];
+  } else if (f < m.nfi + m.nfb) {
+    int b = f - m.nfi;
+    int8_t cu = m.bcode[DIFVM_BC_U * m.nfb + b];
+    int O = m.bown[b];
+    double v = 0.0;
+    if (cu == BC_FIXED)
+      v = -(bbar[3 * (size_t)O] * Ub[3 * (size_t)b] + bbar[3 * (size_t)O + 1] * Ub[3 * (size_t)b + 1] +
+            bbar[3 * (size_t)O + 2] * Ub[3 * (size_t)b + 2]);
+    else if (cu == BC_ZEROGRAD)
+      v = dbar[O];
+    phibar[f] = v;
+  }
+}
+
+// Windkessel: sum of boundary-pressure cotangents over each outlet (fixed order), and the outlet flow
+// cotangent spread back to its faces
+__global__ __launch_bounds__(BLOCK) void k_adj_wk_sum(const int32_t* __restrict__ wk_start, const int32_t* __restrict__ wk_faces,
+                                                      const double* __restrict__ pbvbar, double* __restrict__ out) {
+  int j = blockIdx.x;
+  double v[1] = {0.0};
+  for (int q = wk_start[j] + threadIdx.x; q < wk_start[j + 1]; q += BLOCK) v[0] += pbvbar[wk_faces[q]];
+  __shared__ double lds[1][BLOCK / 64];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) out[j] = v[0];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_wk_spread(int nfi, const int32_t* __restrict__ wk_start,
+                                                         const int32_t* __restrict__ wk_faces, const double* __restrict__ Qbar,
+                                                         double* __restrict__ phibar) {
+  int j = blockIdx.x;
+  for (int q = wk_start[j] + threadIdx.x; q < wk_start[j + 1]; q += BLOCK) phibar[nfi + wk_faces[q]] += Qbar[j];
+}
+
+__global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+}  // namespace difvm
+
+// =============================================================================================
+// tape: checkpoints every K steps; a segment is recomputed once with full step records
+// =============================================================================================
+struct difvm_tape {
+  difvm_piso* piso = nullptr;
+  int nsteps = 0, every = 1, nseg = 0, recorded = 0;
+  std::vector<double*> ckU, ckp, ckphi;   // per checkpoint, internal order
+  std::vector<std::vector<double>> ckpc;  // host copies of the capacitor pressures
+  std::vector<difvm::StepRecord> rec;     // one per step of a segment
+  // reverse-sweep work
+  double *Ubar = nullptr, *pbar = nullptr, *phibar = nullptr, *phibar_in = nullptr, *pbvbar = nullptr;
+  double *HbyAbar = nullptr, *rAUbar = nullptr, *gbar = nullptr, *gUbar = nullptr, *Hbar = nullptr, *bbar = nullptr;
+  double *dbar = nullptr, *valbar = nullptr, *valT = nullptr, *fHb = nullptr, *faF = nullptr, *fnc = nullptr;
+  double *g = nullptr, *tmp = nullptr, *lam = nullptr, *mu = nullptr, *Ubar0 = nullptr, *wkbar = nullptr;
+  double *endU = nullptr, *endp = nullptr, *endphi = nullptr;
+  std::vector<double> endpc;
+  std::vector<void*> allocs;
+};
+
+namespace difvm {
+
+static double* tape_alloc(difvm_tape* T, size_t n) {
+  double* a = dalloc<double>(n);
+  T->allocs.push_back(a);
+  DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * (n ? n : 1), stream_of(T->piso->mesh)));
+  return a;
+}
+
+static void zero(double* a, size_t n, hipStream_t s) {
+  if (n) DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * n, s));
+}
+
+static void host_pc(difvm_piso* P, std::vector<double>& out) {
+  int nwk = P->mesh->d.n_wk;
+  out.assign(nwk, 0.0);
+  if (nwk) {
+    DIFVM_HIP(hipMemcpyAsync(out.data(), P->pc, sizeof(double) * nwk, hipMemcpyDeviceToHost, stream_of(P->mesh)));
+    DIFVM_HIP(hipStreamSynchronize(stream_of(P->mesh)));
+  }
+}
+
+static void set_pc(difvm_piso* P, const std::vector<double>& v) {
+  if (!v.empty()) {
+    DIFVM_HIP(hipMemcpyAsync(P->pc, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, stream_of(P->mesh)));
+    DIFVM_HIP(hipStreamSynchronize(stream_of(P->mesh)));
+  }
+}
+
+void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
+  DIFVM_CHECK(nsteps >= 1 && every >= 1, DIFVM_ERR_INVALID_ARG, "nsteps and ckpt_every must be >= 1");
+  difvm_tape* T = new difvm_tape();
+  try {
+    T->piso = P;
+    T->nsteps = nsteps;
+    T->every = std::min(every, nsteps);
+    T->nseg = (nsteps + T->every - 1) / T->every;
+    const DMesh& d = P->mesh->d;
+    size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+    int nwk = std::max(1, d.n_wk);
+    for (int k = 0; k < T->nseg; ++k) {
+      T->ckU.push_back(tape_alloc(T, 3 * nc));
+      T->ckp.push_back(tape_alloc(T, nc));
+      T->ckphi.push_back(tape_alloc(T, nf));
+    }
+    T->ckpc.resize(T->nseg);
+    T->rec.resize(T->every);
+    int ncorr = P->prm.n_corr;
+    for (auto& r : T->rec) {
+      r.phi_in = tape_alloc(T, nf);
+      r.pbv = tape_alloc(T, d.nfb);
+      r.dM = tape_alloc(T, nc);
+      r.valM = tape_alloc(T, d.nslot);
+      r.Ustar = tape_alloc(T, 3 * nc);
+      r.rAU = tape_alloc(T, nc);
+      r.wk_out = tape_alloc(T, 2 * nwk);
+      r.pc_in = tape_alloc(T, nwk);
+      for (int c = 0; c < ncorr; ++c) {
+        r.Uin[c] = tape_alloc(T, 3 * nc);
+        r.pold[c] = tape_alloc(T, nc);
+        r.pnew[c] = tape_alloc(T, nc);
+        r.HbyA[c] = tape_alloc(T, 3 * nc);
+        r.gpo[c] = tape_alloc(T, 3 * nc);
+        r.gpn[c] = tape_alloc(T, 3 * nc);
+      }
+    }
+    T->Ubar = tape_alloc(T, 3 * nc); T->pbar = tape_alloc(T, nc); T->phibar = tape_alloc(T, nf);
+    T->phibar_in = tape_alloc(T, nf); T->pbvbar = tape_alloc(T, d.nfb); T->HbyAbar = tape_alloc(T, 3 * nc);
+    T->rAUbar = tape_alloc(T, nc); T->gbar = tape_alloc(T, 3 * nc); T->gUbar = tape_alloc(T, 9 * nc);
+    T->Hbar = tape_alloc(T, 3 * nc); T->bbar = tape_alloc(T, 3 * nc); T->dbar = tape_alloc(T, nc);
+    T->valbar = tape_alloc(T, d.nslot); T->valT = tape_alloc(T, d.nslot); T->fHb = tape_alloc(T, nf);
+    T->faF = tape_alloc(T, nf); T->fnc = tape_alloc(T, std::max<size_t>(1, d.nfi)); T->g = tape_alloc(T, nf);
+    T->tmp = tape_alloc(T, 3 * nc); T->lam = tape_alloc(T, nc); T->mu = tape_alloc(T, 3 * nc);
+    T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk);
+    T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
+  } catch (...) {
+    for (void* a : T->allocs) dfree(a);
+    delete T;
+    throw;
+  }
+  *out = T;
+}
+
+void tape_destroy(difvm_tape* T) {
+  if (!T) return;
+  (void)hipStreamSynchronize(stream_of(T->piso->mesh));
+  for (void* a : T->allocs) dfree(a);
+  delete T;
+}
+
+static void save_state(difvm_piso* P, double* U, double* p, double* phi, std::vector<double>& pc) {
+  const DMesh& d = P->mesh->d;
+  hipStream_t s = stream_of(P->mesh);
+  dcopy(U, P->U, 3 * (size_t)d.nc, s);
+  dcopy(p, P->p, d.nc, s);
+  dcopy(phi, P->phi, (size_t)d.nfi + d.nfb, s);
+  host_pc(P, pc);
+}
+
+static void load_state(difvm_piso* P, const double* U, const double* p, const double* phi, const std::vector<double>& pc) {
+  const DMesh& d = P->mesh->d;
+  hipStream_t s = stream_of(P->mesh);
+  dcopy(P->U, U, 3 * (size_t)d.nc, s);
+  dcopy(P->p, p, d.nc, s);
+  dcopy(P->phi, phi, (size_t)d.nfi + d.nfb, s);
+  set_pc(P, pc);
+}
+
+int forward_record(difvm_piso* P, difvm_tape* T, difvm_step_stats* stats) {
+  int worst = 0;
+  for (int n = 0; n < T->nsteps; ++n) {
+    if (n % T->every == 0) {
+      int k = n / T->every;
+      save_state(P, T->ckU[k], T->ckp[k], T->ckphi[k], T->ckpc[k]);
+    }
+    difvm_step_stats st{};
+    piso_advance(P, &st, nullptr);
+    worst = std::max(worst, st.status);
+    if (stats) stats[n] = st;
+  }
+  save_state(P, T->endU, T->endp, T->endphi, T->endpc);
+  T->recorded = 1;
+  return worst;
+}
+
+// Reverse of one recorded step.  On entry T->Ubar, T->pbar, T->phibar_in (flux cotangent) and
+// pcbar (host) hold the cotangents of the step's outputs; on exit they hold those of its inputs.
+static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const double* phi_n, std::vector<double>& pcbar,
+                        std::vector<double>& wkbar, double adj_tol) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  hipStream_t s = stream_of(m);
+  MeshView<double> mv = view<double>(d);
+  const difvm_piso_params& prm = P->prm;
+  int Gc = grid_for(d.nc), Gf = grid_for(d.nfi + d.nfb);
+  size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+  int worst = 0;
+  int maxit_p = std::max(prm.maxit_p, 20000), maxit_u = std::max(prm.maxit_u, 5000);
+
+  zero(T->rAUbar, nc, s);
+  zero(T->bbar, 3 * nc, s);
+  zero(T->dbar, nc, s);
+  zero(T->valbar, d.nslot, s);
+  zero(T->pbvbar, d.nfb, s);
+  // momentum transpose (and the pressure matrix, which depends only on rAU)
+  if (d.nfi) k_swap_slots<<<grid_for(d.nfi), BLOCK, 0, s>>>(d.nfi, d.face_slot_own, d.face_slot_nbr, R.valM, T->valT);
+  piso_pressure_matrix(P, R.HbyA[0], R.rAU, R.gpo[0], R.pbv);
+  for (int c = prm.n_corr - 1; c >= 0; --c) {
+    // U = HbyA - rAU grad(p_new)
+    k_adj_ucorr<<<Gc, BLOCK, 0, s>>>(d.nc, T->Ubar, R.gpn[c], R.rAU, T->HbyAbar, T->rAUbar, T->gbar);
+    k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
+    // flux output of the last corrector
+    k_adj_flux<<<Gf, BLOCK, 0, s>>>(mv, c == prm.n_corr - 1, T->phibar_in, R.rAU, R.pnew[c], R.pbv, T->fHb, T->faF,
+                                    T->fnc, T->g, T->pbvbar);
+    op_div(m, DIFVM_F64, DIFVM_SCHEME_ONE, 1, DIFVM_BC_P, T->g, nullptr, nullptr, T->tmp);
+    k_axpy<<<Gc, BLOCK, 0, s>>>(nc, 1.0, T->tmp, T->pbar);
+    // pressure solve: lambda = K^-1 pbar (K symmetric)
+    zero(T->lam, nc, s);
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p);
+    worst = std::max(worst, rp.status);
+    k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->ref, prm.p_ref_value, T->fHb, T->faF,
+                                      T->fnc, T->pbvbar);
+    k_adj_corr_cells<<<Gc, BLOCK, 0, s>>>(mv, T->fHb, T->faF, T->fnc, R.rAU, R.gpo[c], T->rAUbar, T->HbyAbar, T->gbar);
+    // pressure entering the corrector: only through grad(p_old)
+    zero(T->pbar, nc, s);
+    k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
+    // HbyA = (b - offdiag U_in) / d
+    k_adj_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, T->HbyAbar, R.HbyA[c], R.dM, T->Hbar, T->dbar, T->bbar);
+    k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->Hbar, R.Uin[c], T->valbar, T->Ubar);
+    DIFVM_HIP(hipGetLastError());
+  }
+  // predictor: U* = M^-1 (b - V grad p^n);  mu = M^-T Ubar
+  zero(T->mu, 3 * nc, s);
+  SolveResult ru = bicgstab(m, 3, SellMatrix{R.dM, T->valT}, T->Ubar, T->mu, adj_tol, maxit_u);
+  worst = std::max(worst, ru.status);
+  k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->mu, R.Ustar, T->valbar, nullptr);
+  k_adj_pred<<<Gc, BLOCK, 0, s>>>(d.nc, T->mu, R.Ustar, d.V, T->dbar, T->bbar, T->gbar);
+  k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
+  k_adj_rau<<<Gc, BLOCK, 0, s>>>(d.nc, T->rAUbar, R.rAU, R.dM, T->dbar);
+  // momentum source and coefficients
+  k_adj_bsrc<<<Gc, BLOCK, 0, s>>>(mv, prm.nu, prm.dt, T->bbar, T->Ubar0, T->gUbar);
+  k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);
+  k_adj_phi<<<Gf, BLOCK, 0, s>>>(mv, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar, T->bbar, P->Ub,
+                                 T->phibar);
+  DIFVM_HIP(hipGetLastError());
+  // Windkessel (tiny, on the host): pbv = p_o on each outlet
+  int nwk = d.n_wk;
+  if (nwk) {
+    k_adj_wk_sum<<<nwk, BLOCK, 0, s>>>(d.wk_start, d.wk_faces, T->pbvbar, T->wkbar);
+    std::vector<double> pobar(nwk), wko(2 * nwk), pcin(nwk);
+    DIFVM_HIP(hipMemcpyAsync(pobar.data(), T->wkbar, sizeof(double) * nwk, hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipMemcpyAsync(wko.data(), R.wk_out, sizeof(double) * 2 * nwk, hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipMemcpyAsync(pcin.data(), R.pc_in, sizeof(double) * nwk, hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipStreamSynchronize(s));
+    std::vector<double> Qbar(nwk);
+    for (int j = 0; j < nwk; ++j) {
+      double Rp = P->wk_host[3 * j], Cc = P->wk_host[3 * j + 1], Rd = P->wk_host[3 * j + 2];
+      double Q = wko[2 * j], pc0 = pcin[j];
+      double E = std::exp(-prm.dt / (Rd * Cc));
+      double pc1bar = pcbar[j] + pobar[j];  // p_o = p_c1 + Rp Q
+      double Qb = pobar[j] * Rp + pc1bar * Rd * (1.0 - E);
+      double Eb = pc1bar * (pc0 - Rd * Q);
+      wkbar[3 * j] += pobar[j] * Q;
+      wkbar[3 * j + 1] += Eb * E * prm.dt / (Rd * Cc * Cc);
+      wkbar[3 * j + 2] += pc1bar * Q * (1.0 - E) + Eb * E * prm.dt / (Rd * Rd * Cc);
+      pcbar[j] = pc1bar * E;
+      Qbar[j] = Qb;
+    }
+    DIFVM_HIP(hipMemcpyAsync(T->wkbar, Qbar.data(), sizeof(double) * nwk, hipMemcpyHostToDevice, s));
+    k_adj_wk_spread<<<nwk, BLOCK, 0, s>>>(d.nfi, d.wk_start, d.wk_faces, T->wkbar, T->phibar);
+    DIFVM_HIP(hipStreamSynchronize(s));  // Qbar lives on the stack
+  }
+  // outputs become the next (earlier) step's incoming cotangents
+  dcopy(T->Ubar, T->Ubar0, 3 * nc, s);
+  dcopy(T->phibar_in, T->phibar, nf, s);
+  return worst;
+}
+
+int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, const double* gphi, const double* gpc_host,
+            double adj_tol, double* gU0, double* gp0, double* gphi0, double* gpc0_host, double* gwk_host) {
+  DIFVM_CHECK(T->recorded, DIFVM_ERR_INVALID_ARG, "tape has no forward record");
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  hipStream_t s = stream_of(m);
+  size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+  int nwk = d.n_wk;
+  // incoming cotangents (user -> internal order)
+  zero(T->Ubar, 3 * nc, s);
+  zero(T->pbar, nc, s);
+  zero(T->phibar_in, nf, s);
+  if (gU) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gU, T->Ubar);
+  if (gp) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gp, T->pbar);
+  if (gphi) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_TO_INTERNAL, gphi, T->phibar_in);
+  std::vector<double> pcbar(nwk, 0.0), wkbar(3 * nwk, 0.0);
+  if (gpc_host) for (int j = 0; j < nwk; ++j) pcbar[j] = gpc_host[j];
+  int worst = 0;
+  for (int seg = T->nseg - 1; seg >= 0; --seg) {
+    int s0 = seg * T->every, s1 = std::min(T->nsteps, s0 + T->every);
+    // recompute the segment from its checkpoint, keeping every step's intermediates
+    load_state(P, T->ckU[seg], T->ckp[seg], T->ckphi[seg], T->ckpc[seg]);
+    for (int n = s0; n < s1; ++n) piso_advance(P, nullptr, &T->rec[n - s0]);
+    for (int n = s1 - 1; n >= s0; --n)
+      worst = std::max(worst, reverse_step(P, T, T->rec[n - s0], T->rec[n - s0].phi_in, pcbar, wkbar, adj_tol));
+  }
+  // outgoing cotangents (internal -> user order)
+  if (gU0) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, T->Ubar, gU0);
+  if (gp0) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, T->pbar, gp0);
+  if (gphi0) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_FROM_INTERNAL, T->phibar_in, gphi0);
+  if (gpc0_host) for (int j = 0; j < nwk; ++j) gpc0_host[j] = pcbar[j];
+  if (gwk_host) for (int j = 0; j < 3 * nwk; ++j) gwk_host[j] = wkbar[j];
+  // leave the PISO at the end of the forward window
+  load_state(P, T->endU, T->endp, T->endphi, T->endpc);
+  DIFVM_HIP(hipStreamSynchronize(s));
+  return worst;
+}
+
+}  // namespace difvm
+
+using namespace difvm;
+
+extern "C" {
+
+difvm_status difvm_tape_create(difvm_piso* piso, int32_t nsteps, int32_t ckpt_every, difvm_tape** out) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(piso && out, DIFVM_ERR_INVALID_ARG, "piso and out must not be NULL");
+  tape_create(piso, nsteps, ckpt_every, out);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_tape_destroy(difvm_tape* tape) {
+  DIFVM_API_BEGIN
+  tape_destroy(tape);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm_step_stats* stats_host) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(piso && tape && tape->piso == piso, DIFVM_ERR_INVALID_ARG, "tape does not belong to this PISO");
+  int st = forward_record(piso, tape, stats_host);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(piso->mesh)));
+  return st;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* gU_N, const void* gp_N, const void* gphi_N,
+                                const double* gpc_N_host, double adj_tol, void* gU_0, void* gp_0, void* gphi_0,
+                                double* gpc_0_host, double* gwk_host) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(piso && tape && tape->piso == piso, DIFVM_ERR_INVALID_ARG, "tape does not belong to this PISO");
+  DIFVM_CHECK(adj_tol > 0, DIFVM_ERR_INVALID_ARG, "adj_tol must be > 0");
+  return adjoint(piso, tape, (const double*)gU_N, (const double*)gp_N, (const double*)gphi_N, gpc_N_host, adj_tol,
+                 (double*)gU_0, (double*)gp_0, (double*)gphi_0, gpc_0_host, gwk_host);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+}  // extern "C"

@@ -99,6 +99,7 @@ struct DMesh {
   float* V32;
   // cell-slot layout (SELL, slices of 64 cells, slot-major inside a slice)
   int32_t *slice_start, *slot_face, *slot_col;
+  int32_t *face_slot_own, *face_slot_nbr;
   // permutations for user <-> internal conversions
   int32_t *cell_perm, *face_perm, *bface_perm;
   uint8_t* face_flip;

@@ -345,6 +345,8 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
   L.nslot = L.slice_start[L.nslice];
   L.slot_face.assign(L.nslot, SLOT_PAD);
   L.slot_col.assign(L.nslot, 0);
+  L.face_slot_own.assign(nfi, -1);
+  L.face_slot_nbr.assign(nfi, -1);
   for (int i = 0; i < nc; ++i) {
     int s = i / SLICE, lane = i % SLICE;
     int kslot = 0;
@@ -352,6 +354,10 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
       size_t at = (size_t)L.slice_start[s] + (size_t)kslot * SLICE + lane;
       L.slot_face[at] = code;
       L.slot_col[at] = col;
+      if (code != SLOT_PAD && code < nfi) {
+        if (code >= 0) L.face_slot_own[code] = (int32_t)at;
+        else L.face_slot_nbr[-code - 1] = (int32_t)at;
+      }
       ++kslot;
     };
     for (int f = L.own_start[i]; f < L.own_start[i + 1]; ++f) put(f, L.neighbour[f]);

@@ -326,22 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_initial_flux(MeshView<double> m, cons
 
 }  // namespace difvm
 
-// =============================================================================================
-// PISO object
-// =============================================================================================
-struct difvm_piso {
-  difvm_mesh* mesh = nullptr;
-  difvm_piso_params prm{};
-  int ref = -1;  // internal reference cell, -1 when a pressure value is fixed somewhere
-  double *U = nullptr, *p = nullptr, *phi = nullptr;
-  double *Ub = nullptr, *pb = nullptr, *pbv = nullptr;
-  double *wk = nullptr, *pc = nullptr, *wk_out = nullptr;
-  double *gU = nullptr, *gp = nullptr, *dM = nullptr, *valM = nullptr, *bM = nullptr, *rhs = nullptr;
-  double *HbyA = nullptr, *rAU = nullptr, *phiH = nullptr, *aF = nullptr, *ncorr = nullptr;
-  double *dK = nullptr, *valK = nullptr, *rhsK = nullptr;
-  std::vector<void*> allocs;
-  std::vector<double> wk_host;  // Rp, C, Rd per id
-};
+#include "piso_internal.h"
 
 namespace difvm {
 
@@ -438,48 +423,94 @@ void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc
   DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
 }
 
-int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats) {
+void piso_pressure_matrix(difvm_piso* P, const double* HbyA, const double* rAU, const double* gp, const double* pbv) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  hipStream_t s = stream_of(m);
+  MeshView<double> mv = view<double>(d);
+  k_pface<<<grid_for(d.nfi + d.nfb), BLOCK, 0, s>>>(mv, HbyA, rAU, gp, P->Ub, P->phiH, P->aF, P->ncorr);
+  k_passemble<<<grid_for(d.nc), BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, pbv, P->ref, P->prm.p_ref_value, P->dK,
+                                               P->valK, P->rhsK);
+  DIFVM_HIP(hipGetLastError());
+}
+
+void dcopy(double* dst, const double* src, size_t n, hipStream_t s) {
+  DIFVM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+}
+
+void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
   difvm_mesh* m = P->mesh;
   const DMesh& d = m->d;
   hipStream_t s = stream_of(m);
   MeshView<double> mv = view<double>(d);
   const difvm_piso_params& prm = P->prm;
   int Gc = grid_for(d.nc), Gf = grid_for(d.nfi + d.nfb);
+  size_t nc = d.nc;
+  difvm_step_stats st{};
+  // S0
+  if (rec) dcopy(rec->phi_in, P->phi, (size_t)d.nfi + d.nfb, s);
+  if (rec && d.n_wk) dcopy(rec->pc_in, P->pc, d.n_wk, s);
+  if (d.n_wk)
+    k_windkessel<<<d.n_wk, BLOCK, 0, s>>>(d.nfi, prm.dt, d.wk_start, d.wk_faces, P->phi, P->wk, P->pc, P->pbv, P->wk_out);
+  if (rec) {
+    dcopy(rec->pbv, P->pbv, d.nfb, s);
+    if (d.n_wk) dcopy(rec->wk_out, P->wk_out, 2 * (size_t)d.n_wk, s);
+  }
+  // S1
+  op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
+  op_assemble_momentum(m, prm.nu, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM, P->bM);
+  // S2
+  op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
+  k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
+  DIFVM_HIP(hipGetLastError());
+  SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u);
+  for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
+  st.status = ru.status;
+  if (rec) {
+    dcopy(rec->dM, P->dM, nc, s);
+    dcopy(rec->valM, P->valM, d.nslot, s);
+    dcopy(rec->Ustar, P->U, 3 * nc, s);
+  }
+  // S3
+  for (int corr = 0; corr < prm.n_corr; ++corr) {
+    if (rec) {
+      dcopy(rec->Uin[corr], P->U, 3 * nc, s);
+      dcopy(rec->pold[corr], P->p, nc, s);
+    }
+    k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
+    op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
+    if (rec) {
+      dcopy(rec->HbyA[corr], P->HbyA, 3 * nc, s);
+      dcopy(rec->gpo[corr], P->gp, 3 * nc, s);
+      if (corr == 0) dcopy(rec->rAU, P->rAU, nc, s);
+    }
+    k_pface<<<Gf, BLOCK, 0, s>>>(mv, P->HbyA, P->rAU, P->gp, P->Ub, P->phiH, P->aF, P->ncorr);
+    k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->ref, prm.p_ref_value, P->dK, P->valK, P->rhsK);
+    DIFVM_HIP(hipGetLastError());
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p);
+    st.it_p[corr] = rp.iters[0];
+    st.res_p[corr] = rp.res[0];
+    st.status = std::max(st.status, rp.status);
+    k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
+    k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
+    DIFVM_HIP(hipGetLastError());
+    if (rec) {
+      dcopy(rec->pnew[corr], P->p, nc, s);
+      op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, rec->gpn[corr]);
+    }
+  }
+  if (stp) *stp = st;
+}
+
+int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats) {
   int worst = 0;
   for (int step = 0; step < nsteps; ++step) {
     difvm_step_stats st{};
-    // S0
-    if (d.n_wk)
-      k_windkessel<<<d.n_wk, BLOCK, 0, s>>>(d.nfi, prm.dt, d.wk_start, d.wk_faces, P->phi, P->wk, P->pc, P->pbv, P->wk_out);
-    // S1
-    op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
-    op_assemble_momentum(m, prm.nu, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM, P->bM);
-    // S2
-    op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
-    k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
-    DIFVM_HIP(hipGetLastError());
-    SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u);
-    for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
-    st.status = ru.status;
-    // S3
-    for (int corr = 0; corr < prm.n_corr; ++corr) {
-      k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
-      op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
-      k_pface<<<Gf, BLOCK, 0, s>>>(mv, P->HbyA, P->rAU, P->gp, P->Ub, P->phiH, P->aF, P->ncorr);
-      k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->ref, prm.p_ref_value, P->dK, P->valK, P->rhsK);
-      DIFVM_HIP(hipGetLastError());
-      SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p);
-      st.it_p[corr] = rp.iters[0];
-      st.res_p[corr] = rp.res[0];
-      st.status = std::max(st.status, rp.status);
-      k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
-      k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
-      DIFVM_HIP(hipGetLastError());
-    }
+    piso_advance(P, &st, nullptr);
     worst = std::max(worst, st.status);
     if (stats) stats[step] = st;
   }
-  DIFVM_HIP(hipStreamSynchronize(s));
+  DIFVM_HIP(hipStreamSynchronize(stream_of(P->mesh)));
   return worst;
 }
 

@@ -1,0 +1,48 @@
+// PISO object shared by the forward step (piso.hip) and its discrete adjoint (adjoint.hip).
+#pragma once
+
+#include "internal.h"
+
+struct difvm_piso {
+  difvm_mesh* mesh = nullptr;
+  difvm_piso_params prm{};
+  int ref = -1;  // internal reference cell, -1 when a pressure value is fixed somewhere
+  double *U = nullptr, *p = nullptr, *phi = nullptr;
+  double *Ub = nullptr, *pb = nullptr, *pbv = nullptr;
+  double *wk = nullptr, *pc = nullptr, *wk_out = nullptr;
+  double *gU = nullptr, *gp = nullptr, *dM = nullptr, *valM = nullptr, *bM = nullptr, *rhs = nullptr;
+  double *HbyA = nullptr, *rAU = nullptr, *phiH = nullptr, *aF = nullptr, *ncorr = nullptr;
+  double *dK = nullptr, *valK = nullptr, *rhsK = nullptr;
+  std::vector<void*> allocs;
+  std::vector<double> wk_host;  // Rp, C, Rd per id
+};
+
+
+namespace difvm {
+
+// Intermediates of one forward step kept for its reverse (device buffers owned by the tape).
+struct StepRecord {
+  static constexpr int MAXC = 8;
+  double* phi_in = nullptr;  // lagged flux entering the step [nfi+nfb]
+  double* pbv = nullptr;     // boundary pressure values used by the step [nfb]
+  double* dM = nullptr;      // momentum diagonal [nc]
+  double* valM = nullptr;    // momentum off-diagonals per slot [nslot]
+  double* Ustar = nullptr;   // predictor solution [nc*3]
+  double* rAU = nullptr;     // V / a_P [nc]
+  double* Uin[MAXC] = {};    // velocity entering corrector c [nc*3]
+  double* pold[MAXC] = {};   // pressure entering corrector c [nc]
+  double* pnew[MAXC] = {};   // pressure solution of corrector c [nc]
+  double* HbyA[MAXC] = {};   // [nc*3]
+  double* gpo[MAXC] = {};    // grad of the entering pressure [nc*3]
+  double* gpn[MAXC] = {};    // grad of the solved pressure [nc*3]
+  double* wk_out = nullptr;  // (Q, p_o) per Windkessel [2*n_wk]
+  double* pc_in = nullptr;   // capacitor pressures entering the step [n_wk]
+};
+
+// one PISO step of P's state; when rec != nullptr the intermediates are copied into it
+void piso_advance(difvm_piso* P, difvm_step_stats* st, StepRecord* rec);
+// pressure matrix (P->dK, P->valK) from the corrector quantities (also refreshes P->phiH, aF, ncorr, rhsK)
+void piso_pressure_matrix(difvm_piso* P, const double* HbyA, const double* rAU, const double* gp, const double* pbv);
+void dcopy(double* dst, const double* src, size_t n, hipStream_t s);
+
+}  // namespace difvm

@@ -743,3 +743,122 @@ def quad_channel(nx, ny, length, height=1.0, inlet=True):
         w = ("walls", U_FIXED, P_ZEROGRAD, -1)
         sides = {"x0": w, "x1": w, "y0": w, "y1": w, "z0": e, "z1": e}
     return hex_box(nx, ny, 1, A=A, patches=sides)
+
+
+# ----------------------------------------------------------------------------------------------
+# two-level bifurcating tube (voxelised union of swept tubes, Kuhn-split voxels)
+# ----------------------------------------------------------------------------------------------
+
+def _smoothstep(t):
+    t = np.clip(t, 0.0, 1.0)
+    return t * t * (3.0 - 2.0 * t)
+
+
+def ybif_segments(r0=0.5):
+    """Centre lines y(x) (z = 0) and radii: parent on [0,3]; branches A (up) and B (down) with
+    lateral offsets +-1 reached over 2 length units by a smoothstep; at x = 6 branch A splits into
+    A1/A2 (offsets +-0.6).  Radii follow r_child = r_parent / 2^(1/3).  All outlets lie on x = 10."""
+    rA = r0 / 2 ** (1 / 3)
+    rA1 = rA / 2 ** (1 / 3)
+    yA = lambda x: 1.0 * _smoothstep((x - 3.0) / 2.0)
+    yB = lambda x: -1.0 * _smoothstep((x - 3.0) / 2.0)
+    yA1 = lambda x: 1.0 + 0.6 * _smoothstep((x - 6.0) / 2.0)
+    yA2 = lambda x: 1.0 - 0.6 * _smoothstep((x - 6.0) / 2.0)
+    # (name, x range, centre line, radius); ranges overlap a little so the union is connected
+    return [("parent", (0.0, 3.4), lambda x: 0.0 * x, r0), ("A", (3.0, 6.3), yA, rA), ("B", (3.0, 10.0), yB, rA),
+            ("A1", (6.0, 10.0), yA1, rA1), ("A2", (6.0, 10.0), yA2, rA1)]
+
+
+def ybif(h=None, target_cells=400_000, jitter=0.15, seed=2603004, L=10.0):
+    """Bifurcating tube: voxels of size h whose centre lies in the union of the swept tubes, each
+    voxel split into 6 Kuhn tets, largest connected component kept; interior nodes jittered by
+    U[-j,j]h.  Patches: inlet (x=0), outlets A1, A2, B (x=L, Windkessel 0,1,2), wall (staircase)."""
+    from scipy import ndimage
+    segs = ybif_segments()
+    lo = np.array([0.0, -1.6, -0.55])
+    hi = np.array([L, 1.9, 0.55])
+
+    def mask_for(hh):
+        n = np.maximum(1, np.round((hi - lo) / hh).astype(int))
+        hx = (hi - lo) / n
+        xc = lo[0] + (np.arange(n[0]) + 0.5) * hx[0]
+        yc = lo[1] + (np.arange(n[1]) + 0.5) * hx[1]
+        zc = lo[2] + (np.arange(n[2]) + 0.5) * hx[2]
+        X, Y, Z = np.meshgrid(xc, yc, zc, indexing="ij")
+        inside = np.zeros(X.shape, dtype=bool)
+        for _, (x0, x1), yfun, r in segs:
+            sel = (X >= x0) & (X <= x1)
+            inside |= sel & ((Y - yfun(X)) ** 2 + Z ** 2 <= r * r)
+        lab, nl = ndimage.label(inside)
+        if nl > 1:
+            sizes = ndimage.sum(inside, lab, index=np.arange(1, nl + 1))
+            inside = lab == (1 + int(np.argmax(sizes)))
+        return inside, n, hx
+
+    if h is None:
+        # bisection on h for the target cell count (6 tets per voxel)
+        a, b = 0.01, 0.2
+        for _ in range(30):
+            mid = 0.5 * (a + b)
+            cnt = 6 * int(mask_for(mid)[0].sum())
+            if cnt > target_cells:
+                a = mid
+            else:
+                b = mid
+        h = b
+    inside, n, hx = mask_for(h)
+    idx = np.argwhere(inside)
+    # nodes of kept voxels
+    def vid(i, j, k):
+        return (i * (n[1] + 1) + j) * (n[2] + 1) + k
+    corners = []
+    for perm in _KUHN_PERMS:
+        cur = idx.copy()
+        vs = [vid(cur[:, 0], cur[:, 1], cur[:, 2])]
+        for ax in perm:
+            cur = cur.copy()
+            cur[:, ax] += 1
+            vs.append(vid(cur[:, 0], cur[:, 1], cur[:, 2]))
+        corners.append(np.stack(vs, axis=1))
+    T = np.stack(corners, axis=1).reshape(-1, 4)
+    used, Tc = np.unique(T, return_inverse=True)
+    Tc = Tc.reshape(T.shape)
+    I = used // ((n[1] + 1) * (n[2] + 1))
+    J = (used // (n[2] + 1)) % (n[1] + 1)
+    K = used % (n[2] + 1)
+    P = lo[None, :] + np.stack([I, J, K], 1) * hx[None, :]
+    # boundary nodes: nodes of faces with one adjacent kept voxel -> find via face extraction on the
+    # un-jittered mesh; jitter only the others
+    own_i, nbr_i, tri_i, own_b, tri_b = _tet_faces(P, Tc)
+    on_bnd = np.zeros(P.shape[0], dtype=bool)
+    on_bnd[np.unique(tri_b)] = True
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-jitter, jitter, size=P.shape) * hx[None, :]
+    d[on_bnd] = 0.0
+    P = P + d
+    tol = 1e-9 * L
+
+    def cls(Cf, tri):
+        x, y = Cf[:, 0], Cf[:, 1]
+        out = np.full(Cf.shape[0], 4, dtype=np.int64)          # wall
+        out[np.abs(x) < tol] = 0                                # inlet
+        at_out = np.abs(x - L) < tol
+        out[at_out & (y > 1.3)] = 1                             # A1 (centre y = 1.6)
+        out[at_out & (y <= 1.3) & (y > -0.2)] = 2               # A2 (centre y = 0.4)
+        out[at_out & (y <= -0.2)] = 3                           # B  (centre y = -1.0)
+        return out
+    specs = [("inlet", U_FIXED, P_ZEROGRAD, -1), ("A1", U_ZEROGRAD, P_WINDKESSEL, 0),
+             ("A2", U_ZEROGRAD, P_WINDKESSEL, 1), ("B", U_ZEROGRAD, P_WINDKESSEL, 2),
+             ("wall", U_FIXED, P_ZEROGRAD, -1)]
+    mesh = tet_mesh(P, Tc, cls, specs, name=f"ybif_h{h:.4f}")
+    mesh.meta.update(h=float(h), L=L, R=0.5, segments=[(s[0], s[3]) for s in segs])
+    return mesh
+
+
+def windkessel_nominal(mesh, q_in, tau=0.1, outlets=("A1", "A2", "B")):
+    """Nominal RCR per outlet: flow split by outlet area, Rd = 1/Q_ref, Rp = Rd/9, C = tau/Rd."""
+    areas = np.array([np.linalg.norm(mesh.Sf[mesh.patch(o).start:mesh.patch(o).start + mesh.patch(o).size], axis=1).sum()
+                      for o in outlets])
+    q = q_in * areas / areas.sum()
+    Rd = 1.0 / q
+    return np.stack([Rd / 9.0, tau / Rd, Rd], 1)

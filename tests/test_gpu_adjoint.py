@@ -1,0 +1,115 @@
+"""GPU discrete adjoint of the checkpointed PISO window against the oracle's forward-mode tangent:
+for every tangent direction e_k of the inputs (Windkessel Rp, C, Rd, capacitor pressure, random
+perturbations of U0, p0, phi0), <cotangent of the final state, oracle tangent_k> must equal
+<GPU cotangent of the inputs, e_k> (a dot-product test of the whole window).  Forward and
+transposed solves at tol 1e-13; bar 1e-9 relative."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15920_amd import binding as B
+from paper_2603_15920_amd import meshgen as mg
+
+from gpu_util import ctx, dev, empty, host, note, torch
+
+pytestmark = pytest.mark.gpu
+
+ADJ_BAR = 1e-9
+
+
+def channel_wk(nxyz=(6, 3, 3), seed=61):
+    m = mg.kuhn_cube(3, jitter=0.15, patches="channel", seed=seed, nxyz=nxyz, hi=(2.0, 1.0, 1.0))
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    inl = m.patch("inlet")
+    c = m.Cf[inl.start:inl.start + inl.size]
+    Ub[inl.start - Fi:inl.start - Fi + inl.size, 0] = 16 * c[:, 1] * (1 - c[:, 1]) * c[:, 2] * (1 - c[:, 2])
+    return m, Ub
+
+
+def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol=1e-13):
+    nwk = len(wk)
+    M = B.Mesh(ctx(), m)
+    prm = B.piso_params(nu, dt, tol_p=tol, tol_u=tol, maxit_p=20000, maxit_u=5000)
+    P = B.Piso(M, prm)
+    P.set_boundary(dev(Ub), dev(pb))
+    for j, (Rp, Cc, Rd) in enumerate(wk):
+        P.set_windkessel(j, Rp, Cc, Rd, pc0[j])
+    P.set_state(dev(U0), dev(p0), dev(phi0))
+    T = B.difvm_tape_create(P.h, nsteps, every)
+    st, it = B.difvm_piso_forward_record(P.h, T, nsteps)
+    assert st == 0
+    U, p, phi, pc = P.get_state()
+    gU0, gp0, gphi0 = empty((m.n_cells, 3)), empty(m.n_cells), empty(m.n_faces)
+    note("adjoint", m.name, nsteps, every)
+    st, gpc0, gwk = B.difvm_piso_adjoint(P.h, T, dev(cot["U"]), dev(cot["p"]), dev(cot["phi"]), cot["pc"], tol,
+                                         gU0, gp0, gphi0, nwk)
+    B.difvm_tape_destroy(T)
+    assert st == 0
+    return dict(U=host(U), p=host(p), phi=host(phi), pc=pc, gU0=host(gU0), gp0=host(gp0), gphi0=host(gphi0),
+                gpc0=gpc0, gwk=gwk)
+
+
+def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3):
+    rng = np.random.default_rng(seed)
+    nwk = len(wk)
+    cot = dict(U=rng.standard_normal((m.n_cells, 3)), p=rng.standard_normal(m.n_cells),
+               phi=rng.standard_normal(m.n_faces), pc=rng.standard_normal(nwk))
+    g = run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot)
+    # tangent directions
+    dirs = []
+    for j in range(nwk):
+        for k in range(3):
+            d = dict(wk=np.zeros((nwk, 3)))
+            d["wk"][j, k] = wk[j][k]          # relative perturbation of the parameter
+            dirs.append(d)
+        d = dict(pc=np.zeros(nwk)); d["pc"][j] = 1.0; dirs.append(d)
+    dirs.append(dict(U=rng.standard_normal((m.n_cells, 3))))
+    dirs.append(dict(p=rng.standard_normal(m.n_cells)))
+    dirs.append(dict(phi=rng.standard_normal(m.n_faces)))
+    nd = len(dirs)
+    assert nd <= 10
+    dwk = np.stack([d.get("wk", np.zeros((nwk, 3))) for d in dirs])
+    dU = np.stack([d.get("U", np.zeros((m.n_cells, 3))) for d in dirs])
+    dp = np.stack([d.get("p", np.zeros(m.n_cells)) for d in dirs])
+    dphi = np.stack([d.get("phi", np.zeros(m.n_faces)) for d in dirs])
+    dpc = np.stack([d.get("pc", np.zeros(nwk)) for d in dirs])
+    prm = O.piso_params(nu, dt, tol_p=1e-13, tol_u=1e-13, maxit_p=20000, maxit_u=5000, tol_tangent=1e-13)
+    t = O.piso_tangent(m, prm, U0, p0, phi0, Ub, pb, np.array(wk), pc0, nsteps, dwk=dwk, dU0=dU, dp0=dp,
+                       dphi0=dphi, dpc0=dpc)
+    # forward states agree
+    for k in ("U", "p", "phi"):
+        assert np.abs(g[k] - t[k]).max() <= 1e-10 * max(1.0, np.abs(t[k]).max()), k
+    for k in range(nd):
+        lhs = ((cot["U"] * t["tU"][k]).sum() + (cot["p"] * t["tp"][k]).sum() + (cot["phi"] * t["tphi"][k]).sum()
+               + (cot["pc"] * t["tpc"][k]).sum())
+        rhs = ((g["gU0"] * dU[k]).sum() + (g["gp0"] * dp[k]).sum() + (g["gphi0"] * dphi[k]).sum()
+               + (g["gpc0"] * dpc[k]).sum() + (g["gwk"] * dwk[k]).sum())
+        scale = max(abs(lhs), abs(rhs), 1e-30)
+        assert abs(lhs - rhs) <= ADJ_BAR * scale + 1e-14, (k, lhs, rhs)
+    return g, t
+
+
+def test_adjoint_channel_windkessel():
+    m, Ub = channel_wk()
+    rng = np.random.default_rng(9)
+    U0 = np.zeros((m.n_cells, 3)); U0[:, 0] = 0.5
+    U0 += 0.05 * rng.standard_normal(U0.shape)
+    p0 = 0.1 * rng.standard_normal(m.n_cells)
+    phi0 = O.initial_flux(m, U0, Ub)
+    check_dot(m, Ub, np.zeros(m.n_boundary_faces), [(0.4, 0.3, 1.5)], np.array([0.2]), U0, p0, phi0,
+              nu=0.05, dt=0.02, nsteps=5, every=2)
+
+
+def test_adjoint_cavity_reference_cell():
+    """closed cavity: pressure level fixed by the reference cell (diagonal doubling)"""
+    m = mg.cavity(8)
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    lid = m.patch("lid")
+    Ub[lid.start - Fi:lid.start - Fi + lid.size, 0] = 1.0
+    rng = np.random.default_rng(4)
+    U0 = 0.1 * rng.standard_normal((m.n_cells, 3)); U0[:, 2] = 0.0
+    phi0 = O.initial_flux(m, U0, Ub)
+    check_dot(m, Ub, np.zeros(m.n_boundary_faces), [], np.zeros(0), U0, np.zeros(m.n_cells), phi0,
+              nu=0.01, dt=2e-3, nsteps=4, every=3)
