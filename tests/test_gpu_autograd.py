@@ -1,0 +1,97 @@
+"""torch.autograd through the checkpointed PISO window on the bifurcating tube: gradient of a probe
+misfit with respect to the 9 Windkessel parameters (3 outlets x (Rp, C, Rd)) against central finite
+differences of the GPU forward (the workload of the adjoint configuration, at reduced size)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15920_amd import binding as B
+from paper_2603_15920_amd import meshgen as mg
+from paper_2603_15920_amd.autograd import piso_window
+
+from gpu_util import ctx, dev, note, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ysetup():
+    m = mg.ybif(h=0.2, seed=2603004)
+    Fi = m.n_internal_faces
+    inl = m.patch("inlet")
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    Ub[inl.start - Fi:inl.start - Fi + inl.size] = mg.parabolic_inlet(m.Cf[inl.start:inl.start + inl.size],
+                                                                       (0, 0, 0), 0.5, 1.0)
+    q_in = -(Ub[inl.start - Fi:inl.start - Fi + inl.size] * m.Sf[inl.start:inl.start + inl.size]).sum()
+    wk0 = mg.windkessel_nominal(m, q_in)
+    note("ybif", m.n_cells, "cells; nominal RCR", wk0.tolist())
+    M = B.Mesh(ctx(), m)
+    P = B.Piso(M, B.piso_params(0.01, 5e-3, tol_p=1e-12, tol_u=1e-12, maxit_p=20000, maxit_u=5000))
+    P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    # spin-up from rest at the nominal parameters (not differentiated)
+    for j in range(3):
+        P.set_windkessel(j, *wk0[j], 0.0)
+    P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
+    P.step(10)
+    U0, p0, phi0, pc0 = P.get_state()
+    return m, P, wk0, U0, p0, phi0, pc0
+
+
+def test_windkessel_gradient_vs_central_fd(ysetup):
+    m, P, wk0, U0, p0, phi0, pc0 = ysetup
+    t = torch()
+    rng = np.random.default_rng(2603014)
+    theta0 = wk0 * rng.uniform(0.5, 2.0, size=wk0.shape)
+    interior = np.ones(m.n_cells, bool)
+    interior[m.owner[m.n_internal_faces:]] = False
+    probes = t.as_tensor(rng.choice(np.flatnonzero(interior), 64, replace=False), device="cuda:0")
+    target_U = U0[probes] * 1.05
+    target_p = p0[probes] + 0.1
+    nsteps, every = 6, 3
+
+    def loss_of(theta, grad=False):
+        th = t.tensor(theta, dtype=t.float64, requires_grad=grad)
+        pc = t.as_tensor(pc0, dtype=t.float64)
+        U, p, phi, pcN = piso_window(P, th, U0, p0, phi0, pc, nsteps, every, adj_tol=1e-12)
+        L = ((U[probes] - target_U) ** 2).sum() + ((p[probes] - target_p) ** 2).sum()
+        if grad:
+            L.backward()
+            return float(L.detach()), th.grad.numpy().copy()
+        return float(L.detach()), None
+
+    L0, g = loss_of(theta0, grad=True)
+    fd = np.zeros_like(theta0)
+    for j in range(3):
+        for k in range(3):
+            h = 1e-5 * theta0[j, k]
+            tp = theta0.copy(); tp[j, k] += h
+            tm = theta0.copy(); tm[j, k] -= h
+            fd[j, k] = (loss_of(tp)[0] - loss_of(tm)[0]) / (2 * h)
+    note("grad", g.ravel().tolist(), "fd", fd.ravel().tolist())
+    scale = np.abs(fd).max()
+    assert scale > 0
+    assert np.abs(g - fd).max() <= 1e-6 * scale, (g, fd)
+
+
+def test_initial_state_gradient_direction(ysetup):
+    """<dL/dU0, v> against a central difference along a random velocity perturbation v"""
+    m, P, wk0, U0, p0, phi0, pc0 = ysetup
+    t = torch()
+    v = t.as_tensor(np.random.default_rng(5).standard_normal((m.n_cells, 3)), device="cuda:0")
+    theta = t.tensor(wk0, dtype=t.float64)
+    pc = t.as_tensor(pc0, dtype=t.float64)
+
+    def L(U0x, grad=False):
+        U0x = U0x.clone().requires_grad_(grad)
+        U, p, phi, pcN = piso_window(P, theta, U0x, p0, phi0, pc, 3, 2, adj_tol=1e-12)
+        val = (U ** 2).sum() + (p ** 2).sum()
+        if grad:
+            val.backward()
+            return float(val), U0x.grad
+        return float(val), None
+
+    _, gU = L(U0, True)
+    h = 1e-6
+    fd = (L(U0 + h * v)[0] - L(U0 - h * v)[0]) / (2 * h)
+    ad = float((gU * v).sum())
+    assert abs(ad - fd) <= 1e-6 * abs(fd), (ad, fd)
