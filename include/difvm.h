@@ -81,7 +81,13 @@ const char* difvm_last_error(void);
 
 /* ---- context ------------------------------------------------------------------------------
  * device: HIP device ordinal.  hip_stream: a hipStream_t (NULL = the default stream).  The context
- * owns nothing of the caller's; destroy waits for its stream. */
+ * owns nothing of the caller's; destroy waits for its stream.
+ *
+ * Lifetimes: handles are reference counted.  A mesh holds its context, a PISO object its mesh and a
+ * tape its PISO object; every *_destroy drops the caller's reference, and an object is freed (after
+ * waiting for its stream) once nothing refers to it, so handles may be destroyed in any order.  A
+ * handle must not be used after its own *_destroy.  Objects are not thread-safe: one host thread at a
+ * time per context. */
 difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out);
 difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream);
 difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
@@ -131,6 +137,7 @@ typedef struct {
   int32_t bandwidth_in, bandwidth_out; /* max |O-N| before and after renumbering */
   int32_t n_windkessel;
   int32_t has_fixed_p;              /* 1 if some face carries a fixed or Windkessel pressure */
+  int32_t n_segments;               /* independent cell ranges (1 unless made by _create_segments) */
 } difvm_mesh_info;
 
 /* Host-only renumbering (no device needed): reverse Cuthill-McKee cell order (flag
@@ -151,6 +158,17 @@ difvm_status difvm_mesh_renumber_host(const difvm_mesh_desc* desc, uint32_t flag
  * counts that do not match, patches that do not tile the boundary block, indices out of range,
  * neighbour == owner, V <= 0 or S.d <= 0 on a non-empty face. */
 difvm_status difvm_mesh_create(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, difvm_mesh** out);
+
+/* Batched form: one mesh made of n_seg independent meshes packed block-diagonally (the paper's
+ * outlook on batching many small simulations on one device).  seg_cell_start[n_seg+1] (host) gives
+ * the user cell range of each segment: 0 = start[0] < start[1] < ... < start[n_seg] = Nc.  No internal
+ * face may join two segments.  Every reduction (dot products, stopping tests) is taken per segment,
+ * so each member solves its own system with its own iteration count and results equal to those of
+ * the member run alone (same operations in the same order).  Errors as difvm_mesh_create, plus
+ * DIFVM_ERR_INVALID_ARG for bad offsets and DIFVM_ERR_INVALID_MESH for a face joining segments.
+ * difvm_mesh_create is this call with one segment. */
+difvm_status difvm_mesh_create_segments(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, int32_t n_seg,
+                                        const int32_t* seg_cell_start, difvm_mesh** out);
 difvm_status difvm_mesh_get_info(const difvm_mesh* mesh, difvm_mesh_info* info);
 difvm_status difvm_mesh_destroy(difvm_mesh* mesh); /* NULL is a no-op; waits for the stream */
 
@@ -233,7 +251,9 @@ typedef struct {
   int32_t n_corr;         /* pressure correctors per step (paper: typically 2), 1..8        */
   double tol_p, tol_u;    /* relative residual tolerances of the pressure / momentum solves  */
   int32_t maxit_p, maxit_u;
-  int32_t p_ref_cell;     /* user cell fixing the pressure level when no pressure is fixed  */
+  int32_t p_ref_cell;     /* cell fixing the pressure level where no pressure is fixed: the
+                             p_ref_cell-th user cell of each such segment (the user cell itself
+                             for a one-segment mesh)                                          */
   double p_ref_value;
 } difvm_piso_params;
 
@@ -256,6 +276,14 @@ difvm_status difvm_piso_set_boundary(difvm_piso* piso, const void* U_b, const vo
 /* Three-element Windkessel of outlet id (eqs. windkessel_ode, windkessel_discrete): proximal
  * resistance Rp, compliance C, distal resistance Rd, capacitor pressure pc. */
 difvm_status difvm_piso_set_windkessel(difvm_piso* piso, int32_t id, double Rp, double C, double Rd, double pc);
+
+/* Batched form: kinematic viscosity of each segment, nu_seg[n_seg] host (n_seg must equal the
+ * mesh's segment count; initially params.nu everywhere).  Synchronises. */
+difvm_status difvm_piso_set_viscosity(difvm_piso* piso, int32_t n_seg, const double* nu_seg);
+
+/* Solver statistics of the most recent step per segment, out_host[n_seg] (n_seg must equal the
+ * mesh's segment count).  The stats of difvm_piso_step are the maxima over segments. */
+difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, difvm_step_stats* out_host);
 
 /* State in USER order (device arrays): U[Nc*3], p[Nc], phi[Fi+Fb] (user orientation).  phi == NULL
  * in set_state computes phi = interp(U).S with boundary values from the velocity table.

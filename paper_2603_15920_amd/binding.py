@@ -49,7 +49,8 @@ class MeshDesc(C.Structure):
 
 class MeshInfo(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_cells", "n_internal_faces", "n_boundary_faces", "n_patches", "n_slices",
-                                          "n_slots", "bandwidth_in", "bandwidth_out", "n_windkessel", "has_fixed_p")]
+                                          "n_slots", "bandwidth_in", "bandwidth_out", "n_windkessel", "has_fixed_p",
+                                          "n_segments")]
 
 
 class KernelTime(C.Structure):
@@ -87,6 +88,8 @@ _SIGS = {
     "difvm_ctx_profile_read": (C.c_int32, [_vp, C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]),
     "difvm_mesh_renumber_host": (C.c_int32, [C.POINTER(MeshDesc), C.c_uint32] + [_vp] * 14),
     "difvm_mesh_create": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.POINTER(_vp)]),
+    "difvm_mesh_create_segments": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.c_int32, _i32p,
+                                               C.POINTER(_vp)]),
     "difvm_mesh_get_info": (C.c_int32, [_vp, C.POINTER(MeshInfo)]),
     "difvm_mesh_destroy": (C.c_int32, [_vp]),
     "difvm_permute": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp]),
@@ -104,6 +107,8 @@ _SIGS = {
     "difvm_piso_destroy": (C.c_int32, [_vp]),
     "difvm_piso_set_boundary": (C.c_int32, [_vp, _vp, _vp]),
     "difvm_piso_set_windkessel": (C.c_int32, [_vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "difvm_piso_set_viscosity": (C.c_int32, [_vp, C.c_int32, _f64p]),
+    "difvm_piso_segment_stats": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
     "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_piso_get_state": (C.c_int32, [_vp, _vp, _vp, _vp, _f64p]),
     "difvm_piso_step": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
@@ -233,6 +238,15 @@ def difvm_mesh_create(ctx, mesh, flags=RENUMBER_RCM):
     return out
 
 
+def difvm_mesh_create_segments(ctx, mesh, seg_cell_start, flags=RENUMBER_RCM):
+    h = mesh_desc(mesh)
+    starts = np.ascontiguousarray(seg_cell_start, dtype=np.int32)
+    out = _vp()
+    _check(lib().difvm_mesh_create_segments(ctx, C.byref(h.desc), int(flags), int(starts.size - 1),
+                                            starts.ctypes.data_as(_i32p), C.byref(out)), "difvm_mesh_create_segments")
+    return out
+
+
 def difvm_mesh_get_info(m):
     info = MeshInfo()
     _check(lib().difvm_mesh_get_info(m, C.byref(info)), "difvm_mesh_get_info")
@@ -326,6 +340,25 @@ def difvm_piso_set_windkessel(p, wid, Rp, Cc, Rd, pc):
            "difvm_piso_set_windkessel")
 
 
+def difvm_piso_set_viscosity(p, nu_seg):
+    nu = np.ascontiguousarray(nu_seg, dtype=np.float64)
+    _check(lib().difvm_piso_set_viscosity(p, int(nu.size), nu.ctypes.data_as(_f64p)), "difvm_piso_set_viscosity")
+
+
+def _stats_arrays(stats, n_corr):
+    it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats], dtype=np.int32)
+    res = np.array([[*s.res_u, *list(s.res_p)[:n_corr]] for s in stats])
+    return it, res
+
+
+def difvm_piso_segment_stats(p, n_seg, n_corr=2):
+    """Per-segment (iterations, residuals, status) of the most recent step."""
+    stats = (StepStats * n_seg)()
+    _check(lib().difvm_piso_segment_stats(p, int(n_seg), stats), "difvm_piso_segment_stats")
+    it, res = _stats_arrays(stats, n_corr)
+    return it, res, np.array([s.status for s in stats], dtype=np.int32)
+
+
 def difvm_piso_set_state(p, U, pres, phi):
     _check(lib().difvm_piso_set_state(p, _ptr(U), _ptr(pres), _ptr(phi)), "difvm_piso_set_state")
 
@@ -339,8 +372,7 @@ def difvm_piso_get_state(p, U, pres, phi, n_wk=0):
 def difvm_piso_step(p, nsteps, n_corr=2):
     stats = (StepStats * max(1, nsteps))()
     status = _check(lib().difvm_piso_step(p, int(nsteps), stats), "difvm_piso_step")
-    it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats[:nsteps]], dtype=np.int32)
-    res = np.array([[*s.res_u, *list(s.res_p)[:n_corr]] for s in stats[:nsteps]])
+    it, res = _stats_arrays(stats[:nsteps], n_corr)
     return status, it, res
 
 
@@ -400,10 +432,13 @@ class Context:
 class Mesh:
     """A mesh uploaded to the device (internal order).  Keeps the meshgen.Mesh for user-order sizes."""
 
-    def __init__(self, ctx, mesh, flags=RENUMBER_RCM):
+    def __init__(self, ctx, mesh, flags=RENUMBER_RCM, seg_cell_start=None):
         self.ctx = ctx
         self.src = mesh
-        self.h = difvm_mesh_create(ctx.h, mesh, flags)
+        if seg_cell_start is None:
+            self.h = difvm_mesh_create(ctx.h, mesh, flags)
+        else:
+            self.h = difvm_mesh_create_segments(ctx.h, mesh, seg_cell_start, flags)
         self.info = difvm_mesh_get_info(self.h)
 
     def close(self):
@@ -454,6 +489,12 @@ class Piso:
 
     def set_windkessel(self, wid, Rp, Cc, Rd, pc):
         difvm_piso_set_windkessel(self.h, wid, Rp, Cc, Rd, pc)
+
+    def set_viscosity(self, nu_seg):
+        difvm_piso_set_viscosity(self.h, nu_seg)
+
+    def segment_stats(self):
+        return difvm_piso_segment_stats(self.h, self.mesh.info["n_segments"], self.params.n_corr)
 
     def set_state(self, U, p, phi=None):
         difvm_piso_set_state(self.h, U, p, phi)

@@ -72,9 +72,11 @@ static void prof_collect(Ctx& c) {
 
 // PISO functions (piso.hip)
 void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out);
-void piso_destroy(difvm_piso* P);
 void piso_set_boundary(difvm_piso* P, const double* Ub, const double* pb);
 void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, double pc);
+void piso_set_viscosity(difvm_piso* P, int nseg, const double* nu_seg);
+void piso_release(difvm_piso* P);
+void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out);
 void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
 void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host);
 int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats);
@@ -143,6 +145,14 @@ static void upload_mesh(difvm_mesh* m) {
   d.slot_col = up_vec(m, L.slot_col);
   d.face_slot_own = up_vec(m, L.face_slot_own);
   d.face_slot_nbr = up_vec(m, L.face_slot_nbr);
+  d.nseg = L.nseg;
+  d.ntile = (int)L.tile_lo.size();
+  d.cell_seg = up_vec(m, L.cell_seg);
+  d.tile_lo = up_vec(m, L.tile_lo);
+  d.tile_hi = up_vec(m, L.tile_hi);
+  d.tile_seg = up_vec(m, L.tile_seg);
+  d.seg_tile_first = up_vec(m, L.seg_tile_first);
+  d.seg_tile_n = up_vec(m, L.seg_tile_n);
   d.cell_perm = up_vec(m, L.cell_perm);
   d.face_perm = up_vec(m, L.face_perm);
   d.bface_perm = up_vec(m, L.bface_perm);
@@ -150,12 +160,29 @@ static void upload_mesh(difvm_mesh* m) {
   DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
 }
 
+static void ctx_release(difvm_ctx* ctx) {
+  if (!ctx || --ctx->refs > 0) return;
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (auto& r : ctx->c.prof.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
 static void free_mesh(difvm_mesh* m) {
   if (!m) return;
   if (m->ctx) (void)hipStreamSynchronize(stream_of(m));
   krylov_work_free(m->krylov);
   for (void* a : m->allocs) dfree(a);
+  difvm_ctx* ctx = m->ctx;
   delete m;
+  ctx_release(ctx);
+}
+
+void mesh_release(difvm_mesh* m) {
+  if (m && --m->refs == 0) free_mesh(m);
 }
 
 }  // namespace difvm
@@ -191,14 +218,7 @@ difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream) {
 }
 
 difvm_status difvm_ctx_destroy(difvm_ctx* ctx) {
-  if (!ctx) return DIFVM_OK;
-  (void)hipStreamSynchronize(ctx->c.stream);
-  for (auto& r : ctx->c.prof.pending) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
-  }
-  for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
-  delete ctx;
+  ctx_release(ctx);
   return DIFVM_OK;
 }
 
@@ -249,15 +269,23 @@ difvm_status difvm_mesh_renumber_host(const difvm_mesh_desc* desc, uint32_t flag
 }
 
 difvm_status difvm_mesh_create(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, difvm_mesh** out) {
+  return difvm_mesh_create_segments(ctx, desc, flags, 1, nullptr, out);
+}
+
+difvm_status difvm_mesh_create_segments(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, int32_t n_seg,
+                                        const int32_t* seg_cell_start, difvm_mesh** out) {
   DIFVM_API_BEGIN
   difvm_mesh* m = nullptr;
   check_ptr(ctx, "ctx");
   check_ptr(out, "out");
+  DIFVM_CHECK(n_seg >= 1, DIFVM_ERR_INVALID_ARG, "n_seg must be >= 1");
+  DIFVM_CHECK(n_seg == 1 || seg_cell_start, DIFVM_ERR_INVALID_ARG, "seg_cell_start is NULL");
   DIFVM_HIP(hipSetDevice(ctx->c.device));
   m = new difvm_mesh();
   m->ctx = ctx;
+  ctx->refs++;  // released by free_mesh, also on the failure path below
   try {
-    build_layout(desc, flags, m->host, true);
+    build_layout(desc, flags, m->host, true, n_seg, seg_cell_start);
     upload_mesh(m);
   } catch (...) {
     free_mesh(m);
@@ -283,13 +311,14 @@ difvm_status difvm_mesh_get_info(const difvm_mesh* m, difvm_mesh_info* info) {
   info->bandwidth_out = L.bandwidth_out;
   info->n_windkessel = L.n_wk;
   info->has_fixed_p = L.has_fixed_p ? 1 : 0;
+  info->n_segments = L.nseg;
   DIFVM_API_END
   return DIFVM_OK;
 }
 
 difvm_status difvm_mesh_destroy(difvm_mesh* m) {
   DIFVM_API_BEGIN
-  free_mesh(m);
+  mesh_release(m);
   DIFVM_API_END
   return DIFVM_OK;
 }
@@ -393,7 +422,7 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
   double* gU = dalloc<double>((size_t)9 * m->d.nc);
   try {
     op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
-    op_assemble_momentum(m, nu, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
+    op_assemble_momentum(m, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
                          (double*)A->upper, (double*)A->lower, nullptr, (double*)b);
     DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
   } catch (...) {
@@ -459,7 +488,7 @@ difvm_status difvm_piso_create(const difvm_mesh* m, const difvm_piso_params* par
 
 difvm_status difvm_piso_destroy(difvm_piso* piso) {
   DIFVM_API_BEGIN
-  piso_destroy(piso);
+  piso_release(piso);
   DIFVM_API_END
   return DIFVM_OK;
 }
@@ -484,6 +513,24 @@ difvm_status difvm_piso_set_state(difvm_piso* piso, const void* U, const void* p
   DIFVM_API_BEGIN
   check_ptr(piso, "piso");
   piso_set_state(piso, (const double*)U, (const double*)p, (const double*)phi);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_set_viscosity(difvm_piso* piso, int32_t n_seg, const double* nu_seg) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  check_ptr(nu_seg, "nu_seg");
+  piso_set_viscosity(piso, n_seg, nu_seg);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, difvm_step_stats* out_host) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  check_ptr(out_host, "out_host");
+  piso_segment_stats(piso, n_seg, out_host);
   DIFVM_API_END
   return DIFVM_OK;
 }

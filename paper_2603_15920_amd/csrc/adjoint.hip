@@ -154,7 +154,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_flux(MeshView<double> m, int seed
 // cotangent lambda, pushed to the face quantities (aF, phiH, ncorr) and the boundary pressures
 __global__ __launch_bounds__(BLOCK) void k_adj_psolve(MeshView<double> m, const double* __restrict__ lam,
                                                       const double* __restrict__ p, const double* __restrict__ rAU,
-                                                      const double* __restrict__ pbv, int ref, double pref,
+                                                      const double* __restrict__ pbv,
+                                                      const int8_t* __restrict__ is_ref, double pref,
                                                       double* __restrict__ fHb, double* __restrict__ faF,
                                                       double* __restrict__ fnc, double* __restrict__ pbvbar) {
   int f = blockIdx.x * BLOCK + threadIdx.x;
@@ -162,7 +163,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_psolve(MeshView<double> m, const 
     int O = m.own[f], N = m.nbr[f];
     double dl = lam[N] - lam[O], dp = p[N] - p[O];
     double a = -dl * dp;
-    if (ref >= 0 && (O == ref || N == ref)) a += lam[ref] * (pref - p[ref]);
+    // reference row (doubled diagonal, d pref on the right): a segment holds at most one such cell
+    if (is_ref[O]) a += lam[O] * (pref - p[O]);
+    if (is_ref[N]) a += lam[N] * (pref - p[N]);
     faF[f] += a;
     fHb[f] += dl;
     fnc[f] -= dl;
@@ -314,11 +317,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_rau(int nc, const double* __restr
 
 // b = V/dt U^n + fixed-U boundary terms + nu sum sigma k.interp(grad U^n):
 // Ubar^n = V/dt bbar (written), gUbar_i = nu sum_slots wself sigma (bbar_i - bbar_j) (x) k
-__global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, double nu, double dt, const double* __restrict__ bbar,
+__global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const double* __restrict__ nu_cell, double dt,
+                                                    const double* __restrict__ bbar,
                                                     double* __restrict__ Ubar0, double* __restrict__ gUbar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
+  double nu = nu_cell[i];
   const double* bi = bbar + 3 * (size_t)i;
   double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll 4
@@ -502,6 +507,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     delete T;
     throw;
   }
+  P->refs++;
   *out = T;
 }
 
@@ -509,7 +515,9 @@ void tape_destroy(difvm_tape* T) {
   if (!T) return;
   (void)hipStreamSynchronize(stream_of(T->piso->mesh));
   for (void* a : T->allocs) dfree(a);
+  difvm_piso* P = T->piso;
   delete T;
+  piso_release(P);
 }
 
 static void save_state(difvm_piso* P, double* U, double* p, double* phi, std::vector<double>& pc) {
@@ -582,7 +590,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     zero(T->lam, nc, s);
     SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p);
     worst = std::max(worst, rp.status);
-    k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->ref, prm.p_ref_value, T->fHb, T->faF,
+    k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);
     k_adj_corr_cells<<<Gc, BLOCK, 0, s>>>(mv, T->fHb, T->faF, T->fnc, R.rAU, R.gpo[c], T->rAUbar, T->HbyAbar, T->gbar);
     // pressure entering the corrector: only through grad(p_old)
@@ -602,7 +610,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
   k_adj_rau<<<Gc, BLOCK, 0, s>>>(d.nc, T->rAUbar, R.rAU, R.dM, T->dbar);
   // momentum source and coefficients
-  k_adj_bsrc<<<Gc, BLOCK, 0, s>>>(mv, prm.nu, prm.dt, T->bbar, T->Ubar0, T->gUbar);
+  k_adj_bsrc<<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, T->bbar, T->Ubar0, T->gUbar);
   k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);
   k_adj_phi<<<Gf, BLOCK, 0, s>>>(mv, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar, T->bbar, P->Ub,
                                  T->phibar);

@@ -100,6 +100,9 @@ struct DMesh {
   // cell-slot layout (SELL, slices of 64 cells, slot-major inside a slice)
   int32_t *slice_start, *slot_face, *slot_col;
   int32_t *face_slot_own, *face_slot_nbr;
+  // segments and reduction tiles
+  int nseg, ntile;
+  int32_t *cell_seg, *tile_lo, *tile_hi, *tile_seg, *seg_tile_first, *seg_tile_n;
   // permutations for user <-> internal conversions
   int32_t *cell_perm, *face_perm, *bface_perm;
   uint8_t* face_flip;
@@ -107,8 +110,11 @@ struct DMesh {
 
 }  // namespace difvm
 
+// Handles are reference counted: a mesh holds its context, a PISO object its mesh, a tape its PISO
+// object.  *_destroy drops the caller's reference; the object is freed when none is left.
 struct difvm_ctx {
   difvm::Ctx c;
+  int refs = 1;
 };
 
 namespace difvm {
@@ -120,10 +126,12 @@ struct difvm_mesh {
   difvm::DMesh d;
   std::vector<void*> allocs;                 // device allocations owned by the mesh
   difvm::KrylovWork* krylov = nullptr;       // solver workspace, created on first solve
+  int refs = 1;
 };
 
 namespace difvm {
 inline hipStream_t stream_of(const difvm_mesh* m) { return m->ctx->c.stream; }
+void mesh_release(difvm_mesh* m);  // drops one reference (frees at zero)
 inline Ctx& ctx_of(const difvm_mesh* m) { return m->ctx->c; }
 // RAII event bracket around one launch
 struct ProfScope {

@@ -19,6 +19,7 @@ namespace difvm {
 
 struct PcgCtl;
 
+// BiCGStab state of one segment (up to three systems sharing its matrix)
 struct BiState {
   double tol;
   double bn[3], rho[3], rho1[3], alpha[3], omega[3], beta[3], res[3];
@@ -31,10 +32,9 @@ struct KrylovWork {
   double *r = nullptr, *p = nullptr, *q = nullptr, *rh = nullptr, *v = nullptr, *y = nullptr, *s = nullptr,
          *z = nullptr, *t = nullptr;
   double* partials = nullptr;
-  struct PcgCtl* pcg = nullptr;
-  BiState* bi = nullptr;
-  int* host_flag = nullptr;  // pinned
-  void* host_state = nullptr;  // pinned, sizeof(BiState)
+  struct PcgCtl* pcg = nullptr;  // [nseg]
+  BiState* bi = nullptr;         // [nseg]
+  void* host_state = nullptr;    // pinned mirror, nseg * sizeof(BiState)
   int pcg_hint = 0, bi_hint = 0;  // iterations of the previous solve: sizes the first unpolled block
 };
 
@@ -46,16 +46,16 @@ static KrylovWork* make_work(difvm_mesh* m) {
   m->krylov = w;
   int nc = m->d.nc;
   w->nc = nc;
-  w->ntile = grid_for(nc);
+  w->ntile = m->d.ntile;  // reduction tiles over all segments (at least ceil(nc / 1024))
   size_t n3 = (size_t)nc * 3;
   w->r = dalloc<double>(n3); w->p = dalloc<double>(n3); w->q = dalloc<double>(n3); w->rh = dalloc<double>(n3);
   w->v = dalloc<double>(n3); w->y = dalloc<double>(n3); w->s = dalloc<double>(n3); w->z = dalloc<double>(n3);
   w->t = dalloc<double>(n3);
-  w->partials = dalloc<double>((size_t)8 * w->ntile);  // >= 8 * ceil(nc/1024) for PCG
-  w->pcg = static_cast<PcgCtl*>(dmalloc(128));
-  w->bi = dalloc<BiState>(1);
-  DIFVM_HIP(hipHostMalloc((void**)&w->host_flag, sizeof(int), hipHostMallocDefault));
-  DIFVM_HIP(hipHostMalloc((void**)&w->host_state, sizeof(BiState), hipHostMallocDefault));
+  w->partials = dalloc<double>((size_t)8 * w->ntile);  // up to 8 values per tile (PCG uses 6, BiCGStab 6)
+  int nseg = m->d.nseg;
+  w->pcg = static_cast<PcgCtl*>(dmalloc(sizeof(BiState) * nseg));  // PcgCtl is smaller (asserted below)
+  w->bi = dalloc<BiState>(nseg);
+  DIFVM_HIP(hipHostMalloc((void**)&w->host_state, sizeof(BiState) * nseg, hipHostMallocDefault));
   return w;
 }
 
@@ -64,7 +64,6 @@ void krylov_work_free(KrylovWork* w) {
   for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->y, w->s, w->z, w->t, w->partials}) dfree(a);
   dfree(w->pcg);
   dfree(w->bi);
-  if (w->host_flag) (void)hipHostFree(w->host_flag);
   if (w->host_state) (void)hipHostFree(w->host_state);
   delete w;
 }
@@ -144,32 +143,59 @@ void sell_spmv(const difvm_mesh* m, int ncomp, SellMatrix A, const double* x, do
 }
 
 // ---------------------------------------------------------------------------------------------
-// PCG: two kernels per iteration and no memory fences.
-//
-// Dot products are summed per 1024-cell tile into partial arrays; the NEXT kernel re-sums an array
-// in a fixed order in every block (all blocks obtain the same bits), so no tile waits for another
-// and no L2 write-back is needed.  The direction update p_k = z_{k-1} + beta p_{k-1} is fused into
-// the product q = A p_k: each cell forms its own and its neighbours' p_k from the interleaved pair
-// (z, p) of the previous iteration, one 16-byte gather per matrix slot.  (z, p) pairs are
-// double-buffered by iteration parity, and so are the published scalars rho_k = r_k.z_k.
-//   init1:  r = b - A x                               partials (b.b, r.r)
-//   init2:  stopping test at k = 0; z0 = r/d          partials B = (r.r, r.z)
-//   spmv_k: rho_{k-1} and the stopping test of iterate k-1 (from B), beta; p_k; q = A p_k
-//                                                     partials A = (p.q); tile 0 publishes rho_{k-1}
-//   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
-// Tile 0 records iterations / residual / status; kernels after the stop return at once.
+// Reduction tiles: TILE = 1024 cells per block (4 per thread), listed per segment.  A segment is one
+// independent mesh of a block-diagonal batch (a single mesh is one segment); its dot products are
+// the fixed-order sums of its own tiles' partials, so a batch member computes exactly what it would
+// alone.
 // ---------------------------------------------------------------------------------------------
-constexpr int PCG_TILE = 1024;             // cells per reduction partial
-constexpr int PCG_CPT = PCG_TILE / BLOCK;  // cells per thread
+constexpr int CPT = TILE / BLOCK;  // cells per thread
 
-struct PcgCtl {
-  double tol, bn, res;
-  double rho[2];  // rho_k at index k & 1, published by tile 0 of spmv_{k+1}
-  int maxit, done, iters, status;
+struct Tiles {
+  int ntile;
+  const int32_t* __restrict__ lo;
+  const int32_t* __restrict__ hi;
+  const int32_t* __restrict__ seg;
+  const int32_t* __restrict__ first;  // per segment
+  const int32_t* __restrict__ count;  // per segment
 };
+static Tiles tiles_of(const difvm_mesh* m) {
+  const DMesh& d = m->d;
+  return {d.ntile, d.tile_lo, d.tile_hi, d.tile_seg, d.seg_tile_first, d.seg_tile_n};
+}
+
+struct TileIdx {
+  int t, s, lo, hi;
+};
+__device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
+  int t = xcd_tile(blockIdx.x, gridDim.x);
+  return {t, T.seg[t], T.lo[t], T.hi[t]};
+}
+
+// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles)
+template <int NV>
+__device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
+  __shared__ double lds[NV][BLOCK / 64];
+  int f = T.first[s], n = T.count[s];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < n; q += BLOCK) acc += part[(size_t)k * T.ntile + f + q];
+    out[k] = acc;
+  }
+  block_sum<NV>(out, lds);
+}
+
+template <int NV>
+__device__ __forceinline__ void put_partial(double (&v)[NV], double* __restrict__ part, int ntile, int t) {
+  __shared__ double lds[NV][BLOCK / 64];
+  block_sum<NV>(v, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[(size_t)k * ntile + t] = v[k];
+}
 
 // one read of a flag per block, shared through LDS, so every wave of the block takes the same branch
-// even while tile 0 of the same launch may be writing it
+// even while the segment's first tile of the same launch may be writing it
 __device__ __forceinline__ bool block_flag(const int* flag) {
   __shared__ int f;
   if (threadIdx.x == 0) f = *flag;
@@ -177,65 +203,59 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
   return f != 0;
 }
 
-// fixed-order sum of G partials (NV arrays, value-major) -> identical result in every block
-template <int NV>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int G, double (&out)[NV]) {
-  __shared__ double lds[NV][BLOCK / 64];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < G; q += BLOCK) s += part[(size_t)k * G + q];
-    out[k] = s;
-  }
-  block_sum<NV>(out, lds);
-}
+#define FOR_TILE_CELLS(I) \
+  _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) if (int I = ti.lo + c_ * BLOCK + threadIdx.x; I < ti.hi)
 
-template <int NV>
-__device__ __forceinline__ void write_partial(double (&v)[NV], double* __restrict__ part, int G, int tile) {
-  __shared__ double lds[NV][BLOCK / 64];
-  block_sum<NV>(v, lds);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[(size_t)k * G + tile] = v[k];
-}
+// ---------------------------------------------------------------------------------------------
+// PCG: two kernels per iteration and no memory fences.
+//
+// Partials of each kernel are re-summed (per segment, fixed order) at the start of the NEXT kernel
+// in every block, so no tile waits for another and no L2 write-back is needed.  The direction update
+// p_k = z_{k-1} + beta p_{k-1} is fused into the product q = A p_k: each cell forms its own and its
+// neighbours' p_k from the interleaved pair (z, p) of the previous iteration (one 16-byte gather per
+// matrix slot).  (z, p) pairs and the published rho_k = r_k.z_k are double-buffered by parity.
+//   init1:  r = b - A x                               partials (b.b, r.r)
+//   init2:  stopping test at k = 0; z0 = r/d          partials B = (r.r, r.z)
+//   spmv_k: rho_{k-1} and the stopping test of iterate k-1 (from B), beta; p_k; q = A p_k
+//                                                     partials A = (p.q); first tile publishes rho
+//   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
+// The segment's first tile records iterations / residual / status; its kernels return at once
+// after its stop.
+// ---------------------------------------------------------------------------------------------
+struct PcgCtl {
+  double tol, bn, res;
+  double rho[2];  // rho_k at index k & 1
+  int maxit, done, iters, status;
+};
+static_assert(sizeof(PcgCtl) <= sizeof(BiState), "PCG states share the BiState-sized allocation");
 
-// slice start of the wave's 64 cells, read once per wave through the scalar unit
-__device__ __forceinline__ SlotRange wave_slots(const int32_t* __restrict__ slice_start, int i) {
-  int s = __builtin_amdgcn_readfirstlane(i >> 6);
-  int b = slice_start[s];
-  int e = slice_start[s + 1];
-  return {b + (i & (SLICE - 1)), (e - b) >> 6};
-}
-
-__global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, const double* __restrict__ b, const double* __restrict__ x,
-                                                     double* __restrict__ r, double* __restrict__ part) {
-  int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
+__global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, Tiles T, const double* __restrict__ b,
+                                                     const double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ part) {
+  TileIdx ti = tile_idx(T);
   double v[2] = {0.0, 0.0};
-#pragma unroll
-  for (int c = 0; c < PCG_CPT; ++c) {
-    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-    if (i < A.nc) {
-      double ax[1];
-      sell_row<1>(A, i, x, ax);
-      double bi = b[i], ri = bi - ax[0];
-      r[i] = ri;
-      v[0] += bi * bi;
-      v[1] += ri * ri;
-    }
+  FOR_TILE_CELLS(i) {
+    double ax[1];
+    sell_row<1>(A, i, x, ax);
+    double bi = b[i], ri = bi - ax[0];
+    r[i] = ri;
+    v[0] += bi * bi;
+    v[1] += ri * ri;
   }
-  write_partial<2>(v, part, G, tile);
+  put_partial<2>(v, part, T.ntile, ti.t);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, double* __restrict__ x, const double* __restrict__ r,
+__global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double* __restrict__ x, const double* __restrict__ r,
                                                      double2* __restrict__ zp0, const double* __restrict__ part_in,
-                                                     double* __restrict__ partB, PcgCtl* ctl) {
-  int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
+                                                     double* __restrict__ partB, PcgCtl* ctls) {
+  TileIdx ti = tile_idx(T);
+  PcgCtl* ctl = ctls + ti.s;
   double s[2];
-  sum_partials<2>(part_in, G, s);
+  sum_seg<2>(part_in, T, ti.s, s);
   double bn = sqrt(s[0]), rn = sqrt(s[1]);
   bool zero_b = bn == 0.0;
   bool stop = zero_b || rn <= ctl->tol * bn;
-  if (tile == 0 && threadIdx.x == 0) {
+  if (ti.t == T.first[ti.s] && threadIdx.x == 0) {
     ctl->bn = bn;
     ctl->res = zero_b ? 0.0 : rn / bn;
     ctl->iters = 0;
@@ -243,44 +263,38 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, double* __restr
     ctl->done = stop ? 1 : 0;
   }
   if (zero_b) {
-#pragma unroll
-    for (int c = 0; c < PCG_CPT; ++c) {
-      int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-      if (i < A.nc) x[i] = 0.0;
-    }
+    FOR_TILE_CELLS(i) x[i] = 0.0;
   }
   if (stop) return;
   double v[2] = {0.0, 0.0};
-#pragma unroll
-  for (int c = 0; c < PCG_CPT; ++c) {
-    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-    if (i < A.nc) {
-      double ri = r[i], zi = ri / A.diag[i];
-      zp0[i] = make_double2(zi, 0.0);  // p_0 = 0 so that p_1 = z_0 + 0 * p_0
-      v[0] += ri * ri;
-      v[1] += ri * zi;
-    }
+  FOR_TILE_CELLS(i) {
+    double ri = r[i], zi = ri / A.diag[i];
+    zp0[i] = make_double2(zi, 0.0);  // p_0 = 0 so that p_1 = z_0 + 0 * p_0
+    v[0] += ri * ri;
+    v[1] += ri * zi;
   }
-  write_partial<2>(v, partB, G, tile);
+  put_partial<2>(v, partB, T.ntile, ti.t);
 }
 
 // iteration k >= 1: stopping test of iterate k-1, then p_k and q = A p_k
-__global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const double2* __restrict__ zp_prev,
+__global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, Tiles T, int k, const double2* __restrict__ zp_prev,
                                                     double2* __restrict__ zp_cur, double* __restrict__ q,
                                                     const double* __restrict__ partB, double* __restrict__ partA,
-                                                    PcgCtl* ctl) {
+                                                    PcgCtl* ctls) {
+  TileIdx ti = tile_idx(T);
+  PcgCtl* ctl = ctls + ti.s;
   if (block_flag(&ctl->done)) return;
-  int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
+  bool lead = ti.t == T.first[ti.s] && threadIdx.x == 0;
   double s2[2];
-  sum_partials<2>(partB, G, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+  sum_seg<2>(partB, T, ti.s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
   double rho = s2[1];
-  if (tile == 0 && threadIdx.x == 0) ctl->rho[(k - 1) & 1] = rho;
+  if (lead) ctl->rho[(k - 1) & 1] = rho;
   double beta = 0.0;
   if (k >= 2) {
     double rn = sqrt(s2[0]), bn = ctl->bn;
     bool conv = rn <= ctl->tol * bn;
     if (conv || k - 1 >= ctl->maxit) {
-      if (tile == 0 && threadIdx.x == 0) {
+      if (lead) {
         ctl->done = 1;
         ctl->iters = k - 1;
         ctl->res = rn / bn;
@@ -290,48 +304,45 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, int k, const dou
     }
     beta = rho / ctl->rho[k & 1];  // rho_{k-1} / rho_{k-2}
   } else if (ctl->maxit <= 0) {
-    if (tile == 0 && threadIdx.x == 0) {
+    if (lead) {
       ctl->done = 1;
       ctl->status = DIFVM_WARN_NOT_CONVERGED;
     }
     return;
   }
   double v[1] = {0.0};
-#pragma unroll
-  for (int c = 0; c < PCG_CPT; ++c) {
-    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-    if (i < A.nc) {
-      double2 zpi = zp_prev[i];
-      double pi = zpi.x + beta * zpi.y;
-      SlotRange R = wave_slots(A.slice_start, i);
-      double acc = A.diag[i] * pi;
+  FOR_TILE_CELLS(i) {
+    double2 zpi = zp_prev[i];
+    double pi = zpi.x + beta * zpi.y;
+    SlotRange R = slots_of(A.slice_start, i);
+    double acc = A.diag[i] * pi;
 #pragma unroll 4
-      for (int s = 0; s < R.width; ++s) {
-        int at = R.base + s * SLICE;
-        double2 zpj = zp_prev[A.col[at]];
-        acc += A.val[at] * (zpj.x + beta * zpj.y);
-      }
-      zp_cur[i].y = pi;
-      q[i] = acc;
-      v[0] += pi * acc;
+    for (int sl = 0; sl < R.width; ++sl) {
+      int at = R.base + sl * SLICE;
+      double2 zpj = zp_prev[A.col[at]];
+      acc += A.val[at] * (zpj.x + beta * zpj.y);
     }
+    zp_cur[i].y = pi;
+    q[i] = acc;
+    v[0] += pi * acc;
   }
-  write_partial<1>(v, partA, G, tile);
+  put_partial<1>(v, partA, T.ntile, ti.t);
 }
 
-// iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (loads issued before the
-// partial sum, as above)
-__global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, double* __restrict__ x, double* __restrict__ r,
+// iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (streaming loads issued
+// before the partial sum so they overlap its latency)
+__global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
                                                       double2* __restrict__ zp_cur, const double* __restrict__ q,
                                                       const double* __restrict__ partA, double* __restrict__ partB,
-                                                      int k, PcgCtl* ctl) {
+                                                      int k, PcgCtl* ctls) {
+  TileIdx ti = tile_idx(T);
+  PcgCtl* ctl = ctls + ti.s;
   if (block_flag(&ctl->done)) return;
-  int G = gridDim.x, tile = xcd_tile(blockIdx.x, G);
-  double xv[PCG_CPT], pv[PCG_CPT], rv[PCG_CPT], qv[PCG_CPT], dv[PCG_CPT];
+  double xv[CPT], pv[CPT], rv[CPT], qv[CPT], dv[CPT];
 #pragma unroll
-  for (int c = 0; c < PCG_CPT; ++c) {
-    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-    if (i < A.nc) {
+  for (int c = 0; c < CPT; ++c) {
+    int i = ti.lo + c * BLOCK + threadIdx.x;
+    if (i < ti.hi) {
       xv[c] = x[i];
       pv[c] = zp_cur[i].y;
       rv[c] = r[i];
@@ -340,13 +351,13 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, double* __rest
     }
   }
   double pq[1];
-  sum_partials<1>(partA, G, pq);
+  sum_seg<1>(partA, T, ti.s, pq);
   double alpha = ctl->rho[(k - 1) & 1] / pq[0];
   double v[2] = {0.0, 0.0};
 #pragma unroll
-  for (int c = 0; c < PCG_CPT; ++c) {
-    int i = tile * PCG_TILE + c * BLOCK + threadIdx.x;
-    if (i < A.nc) {
+  for (int c = 0; c < CPT; ++c) {
+    int i = ti.lo + c * BLOCK + threadIdx.x;
+    if (i < ti.hi) {
       x[i] = xv[c] + alpha * pv[c];
       double ri = rv[c] - alpha * qv[c];
       double zi = ri / dv[c];
@@ -356,103 +367,95 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, double* __rest
       v[1] += ri * zi;
     }
   }
-  write_partial<2>(v, partB, G, tile);
+  put_partial<2>(v, partB, T.ntile, ti.t);
 }
 
-static int poll_flag(difvm_mesh* m, KrylovWork* w, const int* dflag) {
-  DIFVM_HIP(hipMemcpyAsync(w->host_flag, dflag, sizeof(int), hipMemcpyDeviceToHost, stream_of(m)));
+// copies the per-segment states to the pinned mirror and waits
+template <class S>
+static const S* fetch_states(difvm_mesh* m, KrylovWork* w, const S* dstate) {
+  int nseg = m->d.nseg;
+  DIFVM_HIP(hipMemcpyAsync(w->host_state, dstate, sizeof(S) * nseg, hipMemcpyDeviceToHost, stream_of(m)));
   DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
-  return *w->host_flag;
+  return static_cast<const S*>(w->host_state);
 }
 
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit) {
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
-  int G = (V.nc + PCG_TILE - 1) / PCG_TILE;
-  PcgCtl* ctl = w->pcg;
-  PcgCtl init{};
-  init.tol = tol;
-  init.maxit = maxit;
-  DIFVM_HIP(hipMemcpyAsync(ctl, &init, sizeof(PcgCtl), hipMemcpyHostToDevice, s));
+  Tiles T = tiles_of(m);
+  int G = T.ntile, nseg = m->d.nseg;
+  std::vector<PcgCtl> init(nseg);
+  for (auto& c : init) {
+    c = PcgCtl{};
+    c.tol = tol;
+    c.maxit = maxit;
+  }
+  DIFVM_HIP(hipMemcpyAsync(w->pcg, init.data(), sizeof(PcgCtl) * nseg, hipMemcpyHostToDevice, s));
   double* r = w->r;
   double* q = w->q;
-  // (z, p) pairs, two parities: 2 * 2 * nc doubles in the p and v buffers (each 3 nc long)
+  // (z, p) pairs, two parities, in the p and v buffers (each 3 nc long)
   double2* ZP[2] = {reinterpret_cast<double2*>(w->p), reinterpret_cast<double2*>(w->v)};
   double* partA = w->partials;
   double* partB = w->partials + 2 * (size_t)G;
   double* part0 = w->partials + 4 * (size_t)G;
-  k_pcg_init1<<<G, BLOCK, 0, s>>>(V, b, x, r, part0);
-  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, x, r, ZP[0], part0, partB, ctl);
+  k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
+  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, T, x, r, ZP[0], part0, partB, w->pcg);
   DIFVM_HIP(hipGetLastError());
-  // First block sized from the previous solve (iterations are similar from step to step), then
-  // short polled blocks; kernels queued after the stop return at once.  Iteration k's stopping
-  // test runs at the start of iteration k+1, so the host always queues up to iteration maxit+1.
+  // First block sized from the previous solve, then short polled blocks; iteration k's stopping test
+  // runs at the start of iteration k+1, so the host queues up to iteration maxit+1.
   int k = 1;
   int nb = std::max(4, w->pcg_hint - 2);
+  const PcgCtl* hs = nullptr;
   while (true) {
     int last = std::min(k + nb - 1, maxit + 1);
     for (; k <= last; ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<G, BLOCK, 0, s>>>(V, k, ZP[(k - 1) & 1], ZP[k & 1], q, partB, partA, ctl);
+        k_pcg_spmv<<<G, BLOCK, 0, s>>>(V, T, k, ZP[(k - 1) & 1], ZP[k & 1], q, partB, partA, w->pcg);
       }
       if (k > maxit) break;
       {
         ProfScope ps(m, "pcg_update_dot");
-        k_pcg_update<<<G, BLOCK, 0, s>>>(V, x, r, ZP[k & 1], q, partA, partB, k, ctl);
+        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, ZP[k & 1], q, partA, partB, k, w->pcg);
       }
     }
     DIFVM_HIP(hipGetLastError());
-    if (k > maxit || poll_flag(m, w, &ctl->done)) break;
+    hs = fetch_states<PcgCtl>(m, w, w->pcg);
+    bool all = true;
+    for (int g = 0; g < nseg; ++g) all = all && hs[g].done;
+    if (k > maxit || all) break;
     nb = 4;
   }
-  PcgCtl out;
-  DIFVM_HIP(hipMemcpyAsync(w->host_state, ctl, sizeof(PcgCtl), hipMemcpyDeviceToHost, s));
-  DIFVM_HIP(hipStreamSynchronize(s));
-  std::memcpy(&out, w->host_state, sizeof(PcgCtl));
-  if (!out.done) out.status = DIFVM_WARN_NOT_CONVERGED;
-  w->pcg_hint = out.iters;
   SolveResult R;
-  R.iters[0] = out.iters;
-  R.res[0] = out.res;
-  R.status = out.status;
+  R.seg.resize(nseg);
+  w->pcg_hint = 0;
+  for (int g = 0; g < nseg; ++g) {
+    const PcgCtl& c = hs[g];
+    int st = c.done ? c.status : (int)DIFVM_WARN_NOT_CONVERGED;
+    R.seg[g] = {{c.iters, 0, 0}, {c.res, 0, 0}, st};
+    R.iters[0] = std::max(R.iters[0], c.iters);
+    R.res[0] = std::max(R.res[0], c.res);
+    R.status = std::max(R.status, st);
+    w->pcg_hint = std::max(w->pcg_hint, c.iters);
+  }
   return R;
 }
 
 // ---------------------------------------------------------------------------------------------
-// BiCGStab kernels (NC systems sharing one matrix, interleaved vectors).  Each reduction kernel
-// writes per-tile partials; a one-block finalize kernel sums them in a fixed order and advances the
-// scalar recurrences in device memory (the kernel boundary orders everything, no fences).
+// BiCGStab kernels (NC systems sharing one matrix per segment, interleaved vectors).  Each reduction
+// kernel writes per-tile partials; a finalize kernel (one block per segment) sums them in a fixed
+// order and advances the segment's scalar recurrences in device memory.
 // ---------------------------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void tile_partials(double (&v)[NV], double* __restrict__ part, int G, int tile) {
-  __shared__ double lds[NV][BLOCK / 64];
-  block_sum<NV>(v, lds);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[(size_t)k * G + tile] = v[k];
-}
-
-#define TILE_INDEX() int tile = xcd_tile(blockIdx.x, gridDim.x); int i = tile * BLOCK + threadIdx.x; bool in = i < A.nc
-
 enum BiStage { BI_INIT = 0, BI_ALPHA = 1, BI_S = 2, BI_OMEGA = 3, BI_X = 4 };
 
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __restrict__ part, int G, BiState* st) {
+__global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __restrict__ part, Tiles T, BiState* sts) {
+  BiState* st = sts + blockIdx.x;
   if (stage != BI_INIT && !st->any) return;
   constexpr int NV = 2 * NC;
-  __shared__ double lds[NV][BLOCK / 64];
   double tot[NV];
-  int nv = (stage == BI_ALPHA || stage == BI_S) ? NC : NV;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    if (k < nv)
-      for (int q = threadIdx.x; q < G; q += BLOCK) s += part[(size_t)k * G + q];
-    tot[k] = s;
-  }
-  block_sum<NV>(tot, lds);
+  sum_seg<NV>(part, T, blockIdx.x, tot);
   if (threadIdx.x != 0) return;
   int any = 0;
   for (int c = 0; c < NC; ++c) {
@@ -525,14 +528,15 @@ __global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __res
 }
 
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_init(SellView A, const double* __restrict__ b, const double* __restrict__ x,
-                                                   double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
-                                                   double* __restrict__ v, double* __restrict__ part) {
-  TILE_INDEX();
+__global__ __launch_bounds__(BLOCK) void k_bi_init(SellView A, Tiles T, const double* __restrict__ b,
+                                                   const double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ rh, double* __restrict__ p, double* __restrict__ v,
+                                                   double* __restrict__ part) {
+  TileIdx ti = tile_idx(T);
   double acc[2 * NC];
 #pragma unroll
   for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  if (in) {
+  FOR_TILE_CELLS(i) {
     double ax[NC];
     sell_row<NC>(A, i, x, ax);
 #pragma unroll
@@ -543,50 +547,55 @@ __global__ __launch_bounds__(BLOCK) void k_bi_init(SellView A, const double* __r
       rh[at] = ri;
       p[at] = 0.0;
       v[at] = 0.0;
-      acc[c] = bi * bi;
-      acc[NC + c] = ri * ri;
+      acc[c] += bi * bi;
+      acc[NC + c] += ri * ri;
     }
   }
-  tile_partials<2 * NC>(acc, part, gridDim.x, tile);
+  put_partial<2 * NC>(acc, part, T.ntile, ti.t);
 }
 
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_zero(int nc, double* __restrict__ x, const BiState* st) {
-  int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= nc) return;
+__global__ __launch_bounds__(BLOCK) void k_bi_zero(Tiles T, double* __restrict__ x, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
+  FOR_TILE_CELLS(i) {
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
-    if (st->zero_b[c]) x[(size_t)i * NC + c] = 0.0;
+    for (int c = 0; c < NC; ++c)
+      if (st->zero_b[c]) x[(size_t)i * NC + c] = 0.0;
+  }
 }
 
 // p = r + beta (p - omega v); y = p / d
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, const double* __restrict__ r, double* __restrict__ p,
-                                                  const double* __restrict__ v, double* __restrict__ y, const BiState* st) {
+__global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, Tiles T, const double* __restrict__ r, double* __restrict__ p,
+                                                  const double* __restrict__ v, double* __restrict__ y, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
   if (!st->any) return;
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  if (i >= A.nc) return;
-  double di = A.diag[i];
+  FOR_TILE_CELLS(i) {
+    double di = A.diag[i];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    if (!st->active[c]) continue;
-    size_t at = (size_t)i * NC + c;
-    double pi = r[at] + st->beta[c] * (p[at] - st->omega[c] * v[at]);
-    p[at] = pi;
-    y[at] = pi / di;
+    for (int c = 0; c < NC; ++c) {
+      if (!st->active[c]) continue;
+      size_t at = (size_t)i * NC + c;
+      double pi = r[at] + st->beta[c] * (p[at] - st->omega[c] * v[at]);
+      p[at] = pi;
+      y[at] = pi / di;
+    }
   }
 }
 
 // v = A y; partial rhat . v
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, const double* __restrict__ y, double* __restrict__ v,
-                                                const double* __restrict__ rh, double* __restrict__ part, const BiState* st) {
+__global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const double* __restrict__ y, double* __restrict__ v,
+                                                const double* __restrict__ rh, double* __restrict__ part, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
   if (!st->any) return;
-  TILE_INDEX();
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  if (in) {
+  FOR_TILE_CELLS(i) {
     double ay[NC];
     sell_row<NC>(A, i, y, ay);
 #pragma unroll
@@ -594,23 +603,24 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, const double* __rest
       if (!st->active[c]) continue;
       size_t at = (size_t)i * NC + c;
       v[at] = ay[c];
-      acc[c] = rh[at] * ay[c];
+      acc[c] += rh[at] * ay[c];
     }
   }
-  tile_partials<NC>(acc, part, gridDim.x, tile);
+  put_partial<NC>(acc, part, T.ntile, ti.t);
 }
 
 // s = r - alpha v; z = s / d; partial s.s
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_s(SellView A, const double* __restrict__ r, const double* __restrict__ v,
+__global__ __launch_bounds__(BLOCK) void k_bi_s(SellView A, Tiles T, const double* __restrict__ r, const double* __restrict__ v,
                                                 double* __restrict__ s, double* __restrict__ z, double* __restrict__ part,
-                                                const BiState* st) {
+                                                const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
   if (!st->any) return;
-  TILE_INDEX();
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  if (in) {
+  FOR_TILE_CELLS(i) {
     double di = A.diag[i];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -619,22 +629,23 @@ __global__ __launch_bounds__(BLOCK) void k_bi_s(SellView A, const double* __rest
       double si = r[at] - st->alpha[c] * v[at];
       s[at] = si;
       z[at] = si / di;
-      acc[c] = si * si;
+      acc[c] += si * si;
     }
   }
-  tile_partials<NC>(acc, part, gridDim.x, tile);
+  put_partial<NC>(acc, part, T.ntile, ti.t);
 }
 
 // t = A z; partials t.s, t.t
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, const double* __restrict__ z, const double* __restrict__ s,
-                                                double* __restrict__ t, double* __restrict__ part, const BiState* st) {
+__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const double* __restrict__ z, const double* __restrict__ s,
+                                                double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
   if (!st->any) return;
-  TILE_INDEX();
   double acc[2 * NC];
 #pragma unroll
   for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  if (in) {
+  FOR_TILE_CELLS(i) {
     double az[NC];
     sell_row<NC>(A, i, z, az);
 #pragma unroll
@@ -642,25 +653,26 @@ __global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, const double* __rest
       if (!st->active[c] || st->phase[c]) continue;
       size_t at = (size_t)i * NC + c;
       t[at] = az[c];
-      acc[c] = az[c] * s[at];
-      acc[NC + c] = az[c] * az[c];
+      acc[c] += az[c] * s[at];
+      acc[NC + c] += az[c] * az[c];
     }
   }
-  tile_partials<2 * NC>(acc, part, gridDim.x, tile);
+  put_partial<2 * NC>(acc, part, T.ntile, ti.t);
 }
 
 // x += alpha y (+ omega z); r = s - omega t; partials r.r, rhat.r
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, double* __restrict__ x, double* __restrict__ r,
+__global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ rh, const double* __restrict__ y,
                                                 const double* __restrict__ z, const double* __restrict__ s,
-                                                const double* __restrict__ t, double* __restrict__ part, const BiState* st) {
+                                                const double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
   if (!st->any) return;
-  TILE_INDEX();
   double acc[2 * NC];
 #pragma unroll
   for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  if (in) {
+  FOR_TILE_CELLS(i) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
@@ -671,12 +683,12 @@ __global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, double* __restrict__
         x[at] += st->alpha[c] * y[at] + st->omega[c] * z[at];
         double ri = s[at] - st->omega[c] * t[at];
         r[at] = ri;
-        acc[c] = ri * ri;
-        acc[NC + c] = rh[at] * ri;
+        acc[c] += ri * ri;
+        acc[NC + c] += rh[at] * ri;
       }
     }
   }
-  tile_partials<2 * NC>(acc, part, gridDim.x, tile);
+  put_partial<2 * NC>(acc, part, T.ntile, ti.t);
 }
 
 template <int NC>
@@ -684,46 +696,59 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
-  int G = grid_for(V.nc);
-  BiState init{};
-  init.tol = tol;
-  init.maxit = maxit;
-  DIFVM_HIP(hipMemcpyAsync(w->bi, &init, sizeof(BiState), hipMemcpyHostToDevice, s));
+  Tiles T = tiles_of(m);
+  int G = T.ntile, nseg = m->d.nseg;
+  std::vector<BiState> init(nseg);
+  for (auto& st : init) {
+    st = BiState{};
+    st.tol = tol;
+    st.maxit = maxit;
+  }
+  DIFVM_HIP(hipMemcpyAsync(w->bi, init.data(), sizeof(BiState) * nseg, hipMemcpyHostToDevice, s));
   double* part = w->partials;
-  k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, b, x, w->r, w->rh, w->p, w->v, part);
-  k_bi_fin<NC><<<1, BLOCK, 0, s>>>(BI_INIT, part, G, w->bi);
-  k_bi_zero<NC><<<G, BLOCK, 0, s>>>(V.nc, x, w->bi);
+  k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, T, b, x, w->r, w->rh, w->p, w->v, part);
+  k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
+  k_bi_zero<NC><<<G, BLOCK, 0, s>>>(T, x, w->bi);
   DIFVM_HIP(hipGetLastError());
   int done = 0;
   int nb = std::min(maxit, std::max(2, w->bi_hint - 1));
-  while (nb > 0) {
+  const BiState* hs = nullptr;
+  while (true) {
     for (int k = 0; k < nb; ++k) {
-      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, w->r, w->p, w->v, w->y, w->bi);
-      k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, w->y, w->v, w->rh, part, w->bi);
-      k_bi_fin<NC><<<1, BLOCK, 0, s>>>(BI_ALPHA, part, G, w->bi);
-      k_bi_s<NC><<<G, BLOCK, 0, s>>>(V, w->r, w->v, w->s, w->z, part, w->bi);
-      k_bi_fin<NC><<<1, BLOCK, 0, s>>>(BI_S, part, G, w->bi);
-      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, w->z, w->s, w->t, part, w->bi);
-      k_bi_fin<NC><<<1, BLOCK, 0, s>>>(BI_OMEGA, part, G, w->bi);
-      k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, x, w->r, w->rh, w->y, w->z, w->s, w->t, part, w->bi);
-      k_bi_fin<NC><<<1, BLOCK, 0, s>>>(BI_X, part, G, w->bi);
+      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->y, w->bi);
+      k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->y, w->v, w->rh, part, w->bi);
+      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
+      k_bi_s<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->v, w->s, w->z, part, w->bi);
+      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_S, part, T, w->bi);
+      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, T, w->z, w->s, w->t, part, w->bi);
+      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_OMEGA, part, T, w->bi);
+      k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, T, x, w->r, w->rh, w->y, w->z, w->s, w->t, part, w->bi);
+      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
     }
     DIFVM_HIP(hipGetLastError());
     done += nb;
-    if (done >= maxit || !poll_flag(m, w, &w->bi->any)) break;
+    hs = fetch_states<BiState>(m, w, w->bi);
+    bool any = false;
+    for (int g = 0; g < nseg; ++g) any = any || hs[g].any;
+    if (done >= maxit || !any) break;
     nb = std::min(2, maxit - done);
   }
-  BiState out;
-  DIFVM_HIP(hipMemcpyAsync(w->host_state, w->bi, sizeof(BiState), hipMemcpyDeviceToHost, s));
-  DIFVM_HIP(hipStreamSynchronize(s));
-  std::memcpy(&out, w->host_state, sizeof(BiState));
   SolveResult R;
+  R.seg.resize(nseg);
   w->bi_hint = 0;
-  for (int c = 0; c < NC; ++c) w->bi_hint = std::max(w->bi_hint, out.iters[c]);
-  for (int c = 0; c < NC; ++c) {
-    R.iters[c] = out.iters[c];
-    R.res[c] = out.res[c];
-    R.status = std::max(R.status, out.active[c] ? (int)DIFVM_WARN_NOT_CONVERGED : out.status[c]);
+  for (int g = 0; g < nseg; ++g) {
+    const BiState& st = hs[g];
+    SegResult& sr = R.seg[g];
+    sr.status = 0;
+    for (int c = 0; c < NC; ++c) {
+      sr.iters[c] = st.iters[c];
+      sr.res[c] = st.res[c];
+      sr.status = std::max(sr.status, st.active[c] ? (int)DIFVM_WARN_NOT_CONVERGED : st.status[c]);
+      R.iters[c] = std::max(R.iters[c], st.iters[c]);
+      R.res[c] = std::max(R.res[c], st.res[c]);
+      w->bi_hint = std::max(w->bi_hint, st.iters[c]);
+    }
+    R.status = std::max(R.status, sr.status);
   }
   return R;
 }

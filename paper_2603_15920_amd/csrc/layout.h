@@ -48,10 +48,21 @@ struct HostLayout {
   std::vector<int32_t> face_slot_own, face_slot_nbr;   // slot index of each internal face's two sides
   // Windkessel face lists
   std::vector<int32_t> wk_start, wk_faces;
+  // segments: independent meshes packed block-diagonally (one segment for a single mesh).  Segment m
+  // (user numbering) occupies internal cells [seg_lo[m], seg_hi[m]); reduction tiles of TILE cells
+  // start at each segment's first cell and are listed in internal cell order.
+  int nseg = 1;
+  std::vector<int32_t> seg_user_start, seg_lo, seg_hi, cell_seg;
+  std::vector<int32_t> tile_lo, tile_hi, tile_seg, seg_tile_first, seg_tile_n, seg_by_tile_order;
+  std::vector<int8_t> seg_has_fixed_p;
 };
 
-// Throws LayoutError on invalid input.
-void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots);
+constexpr int TILE = 1024;  // cells per reduction tile of the Krylov kernels
+
+// Throws LayoutError on invalid input.  seg_start (user cell offsets, nseg+1 entries) may be NULL for
+// a single segment; no internal face may join two segments.
+void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots, int nseg = 1,
+                  const int32_t* seg_start = nullptr);
 
 
 }  // namespace difvm

@@ -121,7 +121,8 @@ inline double dot(const double* a, const double* b) { return a[0] * b[0] + a[1] 
 
 }  // namespace
 
-void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots) {
+void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots, int nseg,
+                  const int32_t* seg_start) {
   if (!d) fail(DIFVM_ERR_INVALID_ARG, "mesh descriptor is NULL");
   if (d->struct_size != sizeof(difvm_mesh_desc)) fail(DIFVM_ERR_INVALID_ARG, "difvm_mesh_desc.struct_size mismatch");
   const int nc = d->n_cells, nfi = d->n_internal_faces, nfb = d->n_boundary_faces, np = d->n_patches;
@@ -168,8 +169,29 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
     if (!(dot(d->Sf + 3 * f, dd) > 0.0)) fail(DIFVM_ERR_INVALID_MESH, "boundary face with S.d <= 0");
   }
 
+  // segments (user cell ranges)
+  std::vector<int32_t> useg(nseg + 1);
+  if (nseg < 1) fail(DIFVM_ERR_INVALID_ARG, "need at least one segment");
+  if (seg_start) {
+    for (int s = 0; s <= nseg; ++s) useg[s] = seg_start[s];
+    if (useg[0] != 0 || useg[nseg] != nc) fail(DIFVM_ERR_INVALID_ARG, "segments must cover the cells");
+    for (int s = 0; s < nseg; ++s)
+      if (useg[s + 1] <= useg[s]) fail(DIFVM_ERR_INVALID_ARG, "empty or unordered segment");
+  } else {
+    if (nseg != 1) fail(DIFVM_ERR_INVALID_ARG, "segment offsets missing");
+    useg[0] = 0;
+    useg[1] = nc;
+  }
+  std::vector<int32_t> useg_of(nc);
+  for (int s = 0; s < nseg; ++s)
+    for (int i = useg[s]; i < useg[s + 1]; ++i) useg_of[i] = s;
+  for (int f = 0; f < nfi; ++f)
+    if (useg_of[d->owner[f]] != useg_of[d->neighbour[f]]) fail(DIFVM_ERR_INVALID_MESH, "internal face joins two segments");
+
   L = HostLayout();
   L.nc = nc; L.nfi = nfi; L.nfb = nfb; L.npatch = np;
+  L.nseg = nseg;
+  L.seg_user_start = useg;
   L.patches.assign(d->patches, d->patches + np);
   for (int f = 0; f < nfi; ++f) L.bandwidth_in = std::max(L.bandwidth_in, std::abs(d->owner[f] - d->neighbour[f]));
 
@@ -187,6 +209,37 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
   } else {
     std::iota(L.cell_perm.begin(), L.cell_perm.end(), 0);
     std::iota(newof.begin(), newof.end(), 0);
+  }
+
+  // ---- segments in internal numbering (each must stay contiguous: true for RCM, since components are
+  //      taken in order of their lowest index, and for the identity order) ----
+  L.seg_lo.assign(nseg, nc);
+  L.seg_hi.assign(nseg, 0);
+  for (int i = 0; i < nc; ++i) {
+    int s = useg_of[i];
+    L.seg_lo[s] = std::min(L.seg_lo[s], newof[i]);
+    L.seg_hi[s] = std::max(L.seg_hi[s], newof[i] + 1);
+  }
+  for (int s = 0; s < nseg; ++s)
+    if (L.seg_hi[s] - L.seg_lo[s] != useg[s + 1] - useg[s]) fail(DIFVM_ERR_INVALID_MESH, "segment not contiguous after renumbering");
+  L.cell_seg.resize(nc);
+  for (int i = 0; i < nc; ++i) L.cell_seg[newof[i]] = useg_of[i];
+  {
+    std::vector<int32_t> order(nseg);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return L.seg_lo[a] < L.seg_lo[b]; });
+    L.seg_by_tile_order = order;
+    L.seg_tile_first.assign(nseg, 0);
+    L.seg_tile_n.assign(nseg, 0);
+    for (int s : order) {
+      L.seg_tile_first[s] = (int32_t)L.tile_lo.size();
+      for (int a = L.seg_lo[s]; a < L.seg_hi[s]; a += TILE) {
+        L.tile_lo.push_back(a);
+        L.tile_hi.push_back(std::min(a + TILE, L.seg_hi[s]));
+        L.tile_seg.push_back(s);
+      }
+      L.seg_tile_n[s] = (int32_t)L.tile_lo.size() - L.seg_tile_first[s];
+    }
   }
 
   // ---- internal faces: orient owner < neighbour, sort by (owner, neighbour) keeping input order ----
@@ -296,9 +349,12 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
   // ---- boundary tables and Windkessel lists (patch ranges are unchanged by the sort) ----
   for (int t = 0; t < N_TABLES; ++t) L.bcode[t].assign(nfb, BC_ZEROGRAD);
   L.bwk.assign(nfb, -1);
+  L.seg_has_fixed_p.assign(nseg, 0);
   for (int p = 0; p < np; ++p) {
     const difvm_patch& P = d->patches[p];
     bool empty = P.u_type == DIFVM_U_EMPTY || P.p_type == DIFVM_P_EMPTY;
+    if (!empty && (P.p_type == DIFVM_P_FIXED || P.p_type == DIFVM_P_WINDKESSEL))
+      for (int b = P.start - nfi; b < P.start - nfi + P.size; ++b) L.seg_has_fixed_p[useg_of[d->owner[nfi + b]]] = 1;
     int8_t cu = empty ? BC_EMPTY : (P.u_type == DIFVM_U_FIXED ? BC_FIXED : BC_ZEROGRAD);
     int8_t cp = empty ? BC_EMPTY
                       : ((P.p_type == DIFVM_P_FIXED || P.p_type == DIFVM_P_WINDKESSEL) ? BC_FIXED : BC_ZEROGRAD);

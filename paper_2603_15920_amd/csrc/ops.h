@@ -18,9 +18,10 @@ void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const
                          double* upper, double* rhs);
 
 // momentum matrix of the predictor; writes face LDU (upper/lower, may be NULL) and/or per-slot values
-void op_assemble_momentum(const difvm_mesh* m, double nu, double dt, const double* flux, const double* U,
-                          const double* gradU, const double* Ub, double* diag, double* upper, double* lower,
-                          double* slot_val, double* b);
+// (nu_cell: per-cell viscosity, NULL for nu everywhere)
+void op_assemble_momentum(const difvm_mesh* m, double nu, const double* nu_cell, double dt, const double* flux,
+                          const double* U, const double* gradU, const double* Ub, double* diag, double* upper,
+                          double* lower, double* slot_val, double* b);
 
 // ---- Krylov solvers on the cell-slot matrix (diag[Nc], val[n_slots]) ----
 struct SellMatrix {
@@ -30,10 +31,17 @@ struct SellMatrix {
 void sell_from_ldu(const difvm_mesh* m, const double* upper, const double* lower, double* val);
 void sell_spmv(const difvm_mesh* m, int ncomp, SellMatrix A, const double* x, double* y);
 
+struct SegResult {
+  int iters[3] = {0, 0, 0};
+  double res[3] = {0, 0, 0};
+  int status = 0;
+};
+// aggregate (maximum over segments) plus per-segment results
 struct SolveResult {
   int iters[3] = {0, 0, 0};
   double res[3] = {0, 0, 0};
   int status = 0;
+  std::vector<SegResult> seg;
 };
 
 // Solver workspaces live with the mesh-level solver object; created lazily per mesh.

@@ -28,7 +28,8 @@ namespace difvm {
 // momentum matrix (cell kernel): diag, per-slot coefficients (owner slot: upper, neighbour slot:
 // lower), optional face LDU copies, and the right-hand side b (without the pressure gradient)
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double nu, double dt,
+__global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double nu_all,
+                                                    const double* __restrict__ nu_cell, double dt,
                                                     const double* __restrict__ flux, const double* __restrict__ U,
                                                     const double* __restrict__ gU, const double* __restrict__ Ub,
                                                     double* __restrict__ diag, double* __restrict__ upper,
@@ -37,6 +38,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
+  double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
   double Vdt = m.V[i] / dt;
   double d = Vdt;
   double bi[3] = {Vdt * U[3 * (size_t)i], Vdt * U[3 * (size_t)i + 1], Vdt * U[3 * (size_t)i + 2]};
@@ -97,12 +99,12 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
   for (int c = 0; c < 3; ++c) b[3 * (size_t)i + c] = bi[c];
 }
 
-void op_assemble_momentum(const difvm_mesh* m, double nu, double dt, const double* flux, const double* U,
-                          const double* gradU, const double* Ub, double* diag, double* upper, double* lower,
-                          double* slot_val, double* b) {
+void op_assemble_momentum(const difvm_mesh* m, double nu, const double* nu_cell, double dt, const double* flux,
+                          const double* U, const double* gradU, const double* Ub, double* diag, double* upper,
+                          double* lower, double* slot_val, double* b) {
   const DMesh& d = m->d;
-  k_momentum<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), nu, dt, flux, U, gradU, Ub, diag, upper,
-                                                         lower, slot_val, b);
+  k_momentum<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), nu, nu_cell, dt, flux, U, gradU, Ub, diag,
+                                                         upper, lower, slot_val, b);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -207,8 +209,8 @@ __global__ __launch_bounds__(BLOCK) void k_pface(MeshView<double> m, const doubl
 // pressure matrix (SPD form) and right-hand side (cell kernel)
 __global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const double* __restrict__ phiH,
                                                      const double* __restrict__ aF, const double* __restrict__ ncorr,
-                                                     const double* __restrict__ pbv, int ref, double pref,
-                                                     double* __restrict__ diag, double* __restrict__ val,
+                                                     const double* __restrict__ pbv, const int8_t* __restrict__ is_ref,
+                                                     double pref, double* __restrict__ diag, double* __restrict__ val,
                                                      double* __restrict__ rhs) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const d
     }
     val[at] = a;
   }
-  if (i == ref) {
+  if (is_ref[i]) {
     r += d * pref;
     d = d + d;
   }
@@ -342,18 +344,31 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
   DIFVM_CHECK(prm->n_corr >= 1 && prm->n_corr <= 8, DIFVM_ERR_INVALID_ARG, "n_corr must be in 1..8");
   DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
   const DMesh& d = m->d;
-  DIFVM_CHECK(prm->p_ref_cell >= 0 && prm->p_ref_cell < d.nc, DIFVM_ERR_INVALID_ARG, "p_ref_cell out of range");
+  const HostLayout& L = m->host;
+  int min_seg = d.nc;
+  for (int s = 0; s < d.nseg; ++s) min_seg = std::min(min_seg, L.seg_user_start[s + 1] - L.seg_user_start[s]);
+  DIFVM_CHECK(prm->p_ref_cell >= 0 && prm->p_ref_cell < min_seg, DIFVM_ERR_INVALID_ARG,
+              "p_ref_cell out of range (it indexes cells of each segment)");
   difvm_piso* P = new difvm_piso();
   try {
     P->mesh = m;
     P->prm = *prm;
-    if (!d.has_fixed_p) {
-      // internal index of the user reference cell
-      const std::vector<int32_t>& cp = m->host.cell_perm;
-      for (int i = 0; i < d.nc; ++i)
-        if (cp[i] == prm->p_ref_cell) P->ref = i;
-    }
     size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+    // reference cell of each segment that fixes no pressure value: its p_ref_cell-th user cell
+    std::vector<int8_t> ref(nc, 0);
+    const std::vector<int32_t>& cp = L.cell_perm;  // internal -> user
+    for (size_t i = 0; i < nc; ++i) {
+      int s = L.cell_seg[i];
+      if (!L.seg_has_fixed_p[s] && cp[i] == L.seg_user_start[s] + prm->p_ref_cell) ref[i] = 1;
+    }
+    P->is_ref = dalloc<int8_t>(nc);
+    P->allocs.push_back(P->is_ref);
+    upload(P->is_ref, ref, stream_of(m));
+    P->seg_nu.assign(d.nseg, prm->nu);
+    P->seg_stats.assign(d.nseg, difvm_step_stats{});
+    P->nu_cell = piso_alloc(P, nc);
+    std::vector<double> nu0(nc, prm->nu);  // kept until the synchronisation below
+    upload(P->nu_cell, nu0, stream_of(m));
     P->U = piso_alloc(P, 3 * nc); P->p = piso_alloc(P, nc); P->phi = piso_alloc(P, nf);
     P->Ub = piso_alloc(P, 3 * (size_t)d.nfb); P->pb = piso_alloc(P, d.nfb); P->pbv = piso_alloc(P, d.nfb);
     int nwk = std::max(1, d.n_wk);
@@ -365,19 +380,23 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
     P->ncorr = piso_alloc(P, std::max<size_t>(1, d.nfi));
     P->dK = piso_alloc(P, nc); P->valK = piso_alloc(P, d.nslot); P->rhsK = piso_alloc(P, nc);
     upload(P->wk, P->wk_host, stream_of(m));
+    DIFVM_HIP(hipStreamSynchronize(stream_of(m)));  // the host vectors above are temporaries
   } catch (...) {
     for (void* a : P->allocs) dfree(a);
     delete P;
     throw;
   }
+  m->refs++;
   *out = P;
 }
 
-void piso_destroy(difvm_piso* P) {
-  if (!P) return;
-  (void)hipStreamSynchronize(stream_of(P->mesh));
+void piso_release(difvm_piso* P) {
+  if (!P || --P->refs > 0) return;
+  difvm_mesh* m = P->mesh;
+  (void)hipStreamSynchronize(stream_of(m));
   for (void* a : P->allocs) dfree(a);
   delete P;
+  mesh_release(m);
 }
 
 void piso_set_boundary(difvm_piso* P, const double* Ub_user, const double* pb_user) {
@@ -385,6 +404,23 @@ void piso_set_boundary(difvm_piso* P, const double* Ub_user, const double* pb_us
   if (Ub_user) permute(m, DIFVM_F64, 3, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, Ub_user, P->Ub);
   if (pb_user) permute(m, DIFVM_F64, 1, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, pb_user, P->pb);
   DIFVM_HIP(hipMemcpyAsync(P->pbv, P->pb, sizeof(double) * m->d.nfb, hipMemcpyDeviceToDevice, stream_of(m)));
+}
+
+void piso_set_viscosity(difvm_piso* P, int nseg, const double* nu_seg) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  DIFVM_CHECK(nseg == d.nseg, DIFVM_ERR_INVALID_ARG, "one viscosity per segment expected");
+  for (int s = 0; s < nseg; ++s) DIFVM_CHECK(nu_seg[s] >= 0, DIFVM_ERR_INVALID_ARG, "viscosity must be >= 0");
+  P->seg_nu.assign(nu_seg, nu_seg + nseg);
+  std::vector<double> cell(d.nc);
+  for (int i = 0; i < d.nc; ++i) cell[i] = P->seg_nu[m->host.cell_seg[i]];
+  upload(P->nu_cell, cell, stream_of(m));
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+}
+
+void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out) {
+  DIFVM_CHECK(nseg == P->mesh->d.nseg, DIFVM_ERR_INVALID_ARG, "n_seg differs from the mesh's segment count");
+  for (int s = 0; s < nseg; ++s) out[s] = P->seg_stats[s];
 }
 
 void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, double pc) {
@@ -429,8 +465,8 @@ void piso_pressure_matrix(difvm_piso* P, const double* HbyA, const double* rAU, 
   hipStream_t s = stream_of(m);
   MeshView<double> mv = view<double>(d);
   k_pface<<<grid_for(d.nfi + d.nfb), BLOCK, 0, s>>>(mv, HbyA, rAU, gp, P->Ub, P->phiH, P->aF, P->ncorr);
-  k_passemble<<<grid_for(d.nc), BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, pbv, P->ref, P->prm.p_ref_value, P->dK,
-                                               P->valK, P->rhsK);
+  k_passemble<<<grid_for(d.nc), BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, pbv, P->is_ref, P->prm.p_ref_value,
+                                               P->dK, P->valK, P->rhsK);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -458,7 +494,8 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
   }
   // S1
   op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
-  op_assemble_momentum(m, prm.nu, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM, P->bM);
+  op_assemble_momentum(m, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM,
+                       P->bM);
   // S2
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
   k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
@@ -466,6 +503,12 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
   SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u);
   for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
   st.status = ru.status;
+  for (int g = 0; g < d.nseg; ++g) {
+    difvm_step_stats& sg = P->seg_stats[g];
+    sg = difvm_step_stats{};
+    for (int c = 0; c < 3; ++c) { sg.it_u[c] = ru.seg[g].iters[c]; sg.res_u[c] = ru.seg[g].res[c]; }
+    sg.status = ru.seg[g].status;
+  }
   if (rec) {
     dcopy(rec->dM, P->dM, nc, s);
     dcopy(rec->valM, P->valM, d.nslot, s);
@@ -485,12 +528,19 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
       if (corr == 0) dcopy(rec->rAU, P->rAU, nc, s);
     }
     k_pface<<<Gf, BLOCK, 0, s>>>(mv, P->HbyA, P->rAU, P->gp, P->Ub, P->phiH, P->aF, P->ncorr);
-    k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->ref, prm.p_ref_value, P->dK, P->valK, P->rhsK);
+    k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->is_ref, prm.p_ref_value, P->dK, P->valK,
+                                     P->rhsK);
     DIFVM_HIP(hipGetLastError());
     SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p);
     st.it_p[corr] = rp.iters[0];
     st.res_p[corr] = rp.res[0];
     st.status = std::max(st.status, rp.status);
+    for (int g = 0; g < d.nseg; ++g) {
+      difvm_step_stats& sg = P->seg_stats[g];
+      sg.it_p[corr] = rp.seg[g].iters[0];
+      sg.res_p[corr] = rp.seg[g].res[0];
+      sg.status = std::max(sg.status, rp.seg[g].status);
+    }
     k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
     k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
     DIFVM_HIP(hipGetLastError());

@@ -6,7 +6,10 @@
 struct difvm_piso {
   difvm_mesh* mesh = nullptr;
   difvm_piso_params prm{};
-  int ref = -1;  // internal reference cell, -1 when a pressure value is fixed somewhere
+  int8_t* is_ref = nullptr;  // per internal cell: 1 at the reference cell of a segment with no fixed pressure
+  double* nu_cell = nullptr;  // per internal cell kinematic viscosity (the segment's)
+  std::vector<double> seg_nu;
+  std::vector<difvm_step_stats> seg_stats;  // last step, per segment
   double *U = nullptr, *p = nullptr, *phi = nullptr;
   double *Ub = nullptr, *pb = nullptr, *pbv = nullptr;
   double *wk = nullptr, *pc = nullptr, *wk_out = nullptr;
@@ -15,10 +18,12 @@ struct difvm_piso {
   double *dK = nullptr, *valK = nullptr, *rhsK = nullptr;
   std::vector<void*> allocs;
   std::vector<double> wk_host;  // Rp, C, Rd per id
+  int refs = 1;                 // the caller's handle plus one per tape
 };
 
 
 namespace difvm {
+void piso_release(difvm_piso* P);  // drops one reference (frees at zero, then releases the mesh)
 
 // Intermediates of one forward step kept for its reverse (device buffers owned by the tape).
 struct StepRecord {

@@ -862,3 +862,54 @@ def windkessel_nominal(mesh, q_in, tau=0.1, outlets=("A1", "A2", "B")):
     q = q_in * areas / areas.sum()
     Rd = 1.0 / q
     return np.stack([Rd / 9.0, tau / Rd, Rd], 1)
+
+
+# ----------------------------------------------------------------------------------------------
+# batched form: several meshes packed block-diagonally into one
+# ----------------------------------------------------------------------------------------------
+
+def pack(meshes, name="packed"):
+    """One mesh holding the given meshes side by side: cells and internal faces concatenated, then
+    every member's boundary block in member order (its patches keep their order, named "k/name",
+    Windkessel ids shifted past the previous members').  Returns (mesh, seg_cell_start) with
+    seg_cell_start[k] the first cell of member k and seg_cell_start[-1] = total cells; the offsets of
+    each member's cells, internal faces, boundary faces and Windkessel ids are in mesh.meta["members"]."""
+    nc = [m.n_cells for m in meshes]
+    nfi = [m.n_internal_faces for m in meshes]
+    nfb = [m.n_boundary_faces for m in meshes]
+    c0 = np.concatenate([[0], np.cumsum(nc)]).astype(np.int64)
+    fi0 = np.concatenate([[0], np.cumsum(nfi)]).astype(np.int64)
+    fb0 = np.concatenate([[0], np.cumsum(nfb)]).astype(np.int64)
+    Fi = int(fi0[-1])
+    own_i, nbr, own_b, S_i, S_b, Cf_i, Cf_b, w, patches, members = [], [], [], [], [], [], [], [], [], []
+    wk0 = 0
+    for k, m in enumerate(meshes):
+        fi = m.n_internal_faces
+        own_i.append(m.owner[:fi] + c0[k])
+        nbr.append(m.neighbour + c0[k])
+        own_b.append(m.owner[fi:] + c0[k])
+        S_i.append(m.Sf[:fi])
+        S_b.append(m.Sf[fi:])
+        Cf_i.append(m.Cf[:fi])
+        Cf_b.append(m.Cf[fi:])
+        w.append(m.w)
+        n_wk = 0
+        for p in m.patches:
+            wk = p.wk_id + wk0 if p.wk_id >= 0 else -1
+            n_wk = max(n_wk, p.wk_id + 1)
+            patches.append(Patch(f"{k}/{p.name}", Fi + int(fb0[k]) + (p.start - fi), p.size, p.u_type, p.p_type, wk))
+        members.append(dict(cell_start=int(c0[k]), n_cells=nc[k], face_start=int(fi0[k]), n_internal_faces=fi,
+                            bface_start=Fi + int(fb0[k]), n_boundary_faces=nfb[k], wk_start=wk0, n_windkessel=n_wk))
+        wk0 += n_wk
+    out = Mesh(owner=np.concatenate(own_i + own_b).astype(np.int32), neighbour=np.concatenate(nbr).astype(np.int32),
+               Sf=np.concatenate(S_i + S_b), Cf=np.concatenate(Cf_i + Cf_b), C=np.concatenate([m.C for m in meshes]),
+               V=np.concatenate([m.V for m in meshes]), w=np.concatenate(w), patches=patches, name=name,
+               meta=dict(members=members))
+    return out, c0.astype(np.int32)
+
+
+def member_faces(packed, k):
+    """Face indices (in the packed mesh) of member k, in the member's own face order."""
+    mb = packed.meta["members"][k]
+    return np.concatenate([np.arange(mb["face_start"], mb["face_start"] + mb["n_internal_faces"]),
+                           np.arange(mb["bface_start"], mb["bface_start"] + mb["n_boundary_faces"])])
