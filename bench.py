@@ -133,6 +133,123 @@ def operator_sweep(B, M, m, torch, reps=30):
     return out
 
 
+def timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, r
+
+
+def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10):
+    """Differentiated form on the Y-bifurcation (~400k tets, 3 Windkessel outlets, nu 1e-3, dt 1e-3):
+    after a short spin-up from rest, the plain forward, the recorded forward (checkpoints every
+    `every` steps) and the reverse sweep (recomputation of each checkpoint segment plus its adjoint
+    steps) over the same `steps`-step window, tolerances 1e-8."""
+    import numpy as np
+    t0 = time.time()
+    m = mg.ybif(h=0.0519)
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    p = m.patch("inlet")
+    s = slice(p.start - m.n_internal_faces, p.start - m.n_internal_faces + p.size)
+    Ub[s] = mg.parabolic_inlet(m.Cf[p.start:p.start + p.size], (0.0, 0.0, 0.0), 0.5, 1.0)
+    wk = mg.windkessel_nominal(m, mg.inlet_flow(m, Ub))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    M = B.Mesh(ctx, m)
+    P = B.Piso(M, B.piso_params(1e-3, 1e-3, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000))
+    P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    for j, row in enumerate(wk):
+        P.set_windkessel(j, *row, 0.0)
+    P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
+    P.step(spinup)
+    log(f"adjoint: ybif {m.n_cells} cells ready ({time.time() - t0:.1f}s)")
+    U0, p0, phi0, pc0 = P.get_state()
+    t_fwd, (st, it, _) = timed(torch, lambda: P.step(steps))
+    P.set_state(U0, p0, phi0)
+    for j, row in enumerate(wk):
+        P.set_windkessel(j, *row, pc0[j])
+    T = B.difvm_tape_create(P.h, steps, every)
+    t_rec, (st_r, _) = timed(torch, lambda: B.difvm_piso_forward_record(P.h, T, steps))
+    rng = np.random.default_rng(2603024)
+    gU, gp, gphi = (torch.empty_like(U0), torch.empty_like(p0), torch.empty_like(phi0))
+    cot = [dev(rng.standard_normal((m.n_cells, 3))), dev(rng.standard_normal(m.n_cells)), dev(rng.standard_normal(m.n_faces)),
+           rng.standard_normal(len(wk))]
+    t_adj, (st_a, gpc, gwk) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
+    B.difvm_tape_destroy(T)
+    return {"workload": f"Y-bifurcation {m.n_cells} tets, 3 RCR outlets, nu 1e-3, dt 1e-3, {spinup}-step spin-up, "
+                        f"{steps}-step window, checkpoint every {every}, tol 1e-8",
+            "cells": m.n_cells, "steps": steps, "ckpt_every": every,
+            "forward_steps_per_s": round(steps / t_fwd, 3), "record_steps_per_s": round(steps / t_rec, 3),
+            "adjoint_steps_per_s": round(steps / t_adj, 3), "adjoint_over_forward": round(t_adj / t_fwd, 3),
+            "record_over_forward": round(t_rec / t_fwd, 3), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+            "status": [int(st), int(st_r), int(st_a)]}
+
+
+def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
+    """Batched form: n_members seeded meshes of uneven size packed block-diagonally into one mesh of
+    segments, each with its own viscosity and Windkessel; steps/s of the batch against the same members
+    advanced one after another as separate meshes, and a checkpointed window of adj_steps through the
+    batch (checkpoint every adj_steps/2)."""
+    import numpy as np
+    t0 = time.time()
+    mem = mg.batch_members(n_members)
+    Pm, starts = mg.pack([d["mesh"] for d in mem])
+    log(f"batch: {n_members} members, {Pm.n_cells} cells ({time.time() - t0:.1f}s)")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    prm = dict(dt=1e-3, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
+
+    def setup(mesh, Ub, wk, nus, seg=None):
+        M = B.Mesh(ctx, mesh, seg_cell_start=seg)
+        P = B.Piso(M, B.piso_params(float(nus[0]), **prm))
+        if seg is not None:
+            P.set_viscosity(nus)
+        P.set_boundary(dev(Ub), dev(np.zeros(mesh.n_boundary_faces)))
+        for j, row in enumerate(wk):
+            P.set_windkessel(j, *row, 0.0)
+        P.set_state(dev(np.zeros((mesh.n_cells, 3))), dev(np.zeros(mesh.n_cells)), None)
+        return M, P
+
+    Mb, Pb = setup(Pm, np.concatenate([d["Ub"] for d in mem]), np.concatenate([d["wk"] for d in mem]),
+                   np.array([d["nu"] for d in mem]), starts)
+    log(f"batch: device mesh ready ({time.time() - t0:.1f}s)")
+    Pb.step(2)
+    t_b, (st, it, _) = timed(torch, lambda: Pb.step(steps))
+    seg_it, _, seg_st = Pb.segment_stats()
+    t_seq = 0.0
+    for d in mem:
+        M, P = setup(d["mesh"], d["Ub"], d["wk"], [d["nu"]])
+        P.step(2)
+        dt_, _ = timed(torch, lambda: P.step(steps))
+        t_seq += dt_
+        P.close()
+        M.close()
+    out = {"workload": f"{n_members} seeded members (even: tubes, odd: box channels), sizes log-uniform in "
+                       f"[2e4, 3e5] cells, Re in [100, 800], one RCR each, dt 1e-3, 2 correctors, tol 1e-8",
+           "members": n_members, "cells": Pm.n_cells, "steps": steps,
+           "batch_steps_per_s": round(steps / t_b, 3),
+           "batch_cell_steps_per_s": round(steps * Pm.n_cells / t_b, 0),
+           "sequential_steps_per_s": round(steps / t_seq, 3),
+           "speedup_vs_sequential": round(t_seq / t_b, 3),
+           "pcg_iters_max_member": int(seg_it[:, 3:].max()), "pcg_iters_min_member": int(seg_it[:, 3:].min()),
+           "status": int(st)}
+    if adj_steps > 0:
+        T = B.difvm_tape_create(Pb.h, adj_steps, max(1, adj_steps // 2))
+        t_rec, _ = timed(torch, lambda: B.difvm_piso_forward_record(Pb.h, T, adj_steps))
+        rng = np.random.default_rng(2603025)
+        U0 = torch.empty((Pm.n_cells, 3), dtype=torch.float64, device="cuda:0")
+        gU, gp, gphi = U0, torch.empty(Pm.n_cells, dtype=torch.float64, device="cuda:0"), \
+            torch.empty(Pm.n_faces, dtype=torch.float64, device="cuda:0")
+        cot = [dev(rng.standard_normal((Pm.n_cells, 3))), dev(rng.standard_normal(Pm.n_cells)),
+               dev(rng.standard_normal(Pm.n_faces)), rng.standard_normal(n_members)]
+        t_adj, (st_a, _, _) = timed(torch, lambda: B.difvm_piso_adjoint(Pb.h, T, *cot, 1e-8, gU, gp, gphi, n_members))
+        B.difvm_tape_destroy(T)
+        out.update({"adjoint_window_steps": adj_steps, "record_steps_per_s": round(adj_steps / t_rec, 3),
+                    "adjoint_steps_per_s": round(adj_steps / t_adj, 3), "adjoint_status": int(st_a)})
+    Pb.close()
+    Mb.close()
+    return out
+
+
 def cpu_info():
     model = ""
     try:
@@ -153,6 +270,15 @@ def main():
     ap.add_argument("--n", type=int, default=56, help="hexes per side of the Kuhn cube")
     ap.add_argument("--no-ops", action="store_true", help="skip the per-operator sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated-window measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-mesh batch measurement")
+    ap.add_argument("--adj-steps", type=int, default=20)
+    ap.add_argument("--adj-every", type=int, default=10)
+    ap.add_argument("--batch-members", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-adj-steps", type=int, default=10)
+    ap.add_argument("--prof-every", type=int, default=16,
+                    help="time every n-th launch of each PCG kernel with HIP events in the timed region")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -204,7 +330,7 @@ def main():
             first_iters = it[0].tolist()
         log(f"warmup step {k}: {time.time() - ts:.3f}s iters {it[0].tolist()} status {st}")
 
-    B.difvm_ctx_profile(ctx.h, 1)
+    B.difvm_ctx_profile(ctx.h, args.prof_every)
     B.difvm_ctx_profile_read(ctx.h)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -221,16 +347,25 @@ def main():
 
     # dominant kernel: the PCG matrix-vector product with its p.q reduction
     name = "pcg_spmv_dot"
-    launches, total_ms = prof.get(name, (0, 0.0))
+    launches, total_ms = prof.get(name, (0, 0.0))  # every prof_every-th launch, HIP events
     avg_s = total_ms * 1e-3 / max(launches, 1)
     alg = op_bytes("spmv_sym", nfi, nfb, nc, 8)
     achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
     traffic = None
     roofline = {"bound": "hbm", "kernel": "k_pcg_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-                "active_iterations": int(pcg_iters)}
-    phase_ms = {k: round(v[1], 3) for k, v in prof.items()}
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
+                "timed_every": args.prof_every, "active_iterations": int(pcg_iters)}
+    kernel_us = {k: round(1e3 * v[1] / max(v[0], 1), 2) for k, v in prof.items()}
+
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_window(B, mg, torch, ctx, args.adj_steps, args.adj_every)
+        log("adjoint window", adjoint)
+    batched = None
+    if not args.no_batch:
+        batched = batch_run(B, mg, torch, ctx, args.batch_members, args.batch_steps, args.batch_adj_steps)
+        log("batched", batched)
 
     ops = None
     if not args.no_ops:
@@ -262,7 +397,9 @@ def main():
         "cpu_baseline": cpu,
         "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
                    "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st)},
-        "kernel_ms_timed_region": phase_ms,
+        "kernel_avg_us_timed_region": kernel_us,
+        "adjoint": adjoint,
+        "batched": batched,
         "operators": ops,
     }
     print(json.dumps(line), flush=True)

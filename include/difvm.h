@@ -92,16 +92,19 @@ difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out);
 difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream);
 difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
 
-/* Kernel timing for benchmarks.  While enabled, each launch of the library's solver kernels inside
- * difvm_solve_* and difvm_piso_step is bracketed by a pair of HIP events on the context's stream (the
- * stream the kernels run on).  difvm_ctx_profile_read synchronises, returns per-kernel launch counts
- * and summed event durations (kernel names in out[k].name), and clears the record. */
+/* Kernel timing for benchmarks.  difvm_ctx_profile(ctx, n) with n >= 1 enables it: every n-th launch
+ * of each of the library's PCG kernels inside difvm_solve_pcg and difvm_piso_step (counted per
+ * kernel name from the call that enabled it) is bracketed by a pair of HIP events on the context's
+ * stream, the stream the kernels run on (n > 1 keeps the events' own cost out of most launches);
+ * n = 0 disables it, n < 0 is DIFVM_ERR_INVALID_ARG.  difvm_ctx_profile_read synchronises, returns
+ * per-kernel counts of timed launches and their summed event durations (kernel names in out[k].name),
+ * and clears the record. */
 typedef struct {
   char name[32];
   int32_t launches;
   double total_ms;
 } difvm_kernel_time;
-difvm_status difvm_ctx_profile(difvm_ctx* ctx, int enable);
+difvm_status difvm_ctx_profile(difvm_ctx* ctx, int every_nth);
 difvm_status difvm_ctx_profile_read(difvm_ctx* ctx, difvm_kernel_time* out, int32_t max_out, int32_t* n_out);
 
 /* ---- mesh ----------------------------------------------------------------------------------

@@ -179,8 +179,9 @@ def difvm_ctx_destroy(ctx):
     _check(lib().difvm_ctx_destroy(ctx), "difvm_ctx_destroy")
 
 
-def difvm_ctx_profile(ctx, enable):
-    _check(lib().difvm_ctx_profile(ctx, int(enable)), "difvm_ctx_profile")
+def difvm_ctx_profile(ctx, every_nth):
+    """every_nth >= 1: time every n-th launch of each PCG kernel with HIP events; 0: off."""
+    _check(lib().difvm_ctx_profile(ctx, int(every_nth)), "difvm_ctx_profile")
 
 
 def difvm_ctx_profile_read(ctx):

@@ -43,7 +43,9 @@ int prof_begin(Ctx& c, const char* name) {
     P.names.push_back(name);
     P.total_ms.push_back(0.0);
     P.launches.push_back(0);
+    P.seen.push_back(0);
   }
+  if (P.seen[id]++ % P.stride != 0) return -1;
   Profiler::Rec r{id, pool_event(P), pool_event(P)};
   DIFVM_HIP(hipEventRecord(r.a, c.stream));
   P.pending.push_back(r);
@@ -225,8 +227,14 @@ difvm_status difvm_ctx_destroy(difvm_ctx* ctx) {
 difvm_status difvm_ctx_profile(difvm_ctx* ctx, int enable) {
   DIFVM_API_BEGIN
   check_ptr(ctx, "ctx");
+  DIFVM_CHECK(enable >= 0, DIFVM_ERR_INVALID_ARG, "enable must be >= 0");
   if (!enable) prof_collect(ctx->c);
-  ctx->c.prof.on = enable != 0;
+  Profiler& P = ctx->c.prof;
+  P.on = enable != 0;
+  if (enable) {
+    P.stride = enable;
+    std::fill(P.seen.begin(), P.seen.end(), 0L);
+  }
   DIFVM_API_END
   return DIFVM_OK;
 }

@@ -45,6 +45,8 @@ struct DevBuf {
 // event-pair timing of selected kernel launches (difvm_ctx_profile)
 struct Profiler {
   bool on = false;
+  int stride = 1;             // time every stride-th launch of each kernel name
+  std::vector<long> seen;     // launches per name since profiling was enabled
   struct Rec {
     int id;
     hipEvent_t a, b;

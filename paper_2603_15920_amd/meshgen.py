@@ -913,3 +913,52 @@ def member_faces(packed, k):
     mb = packed.meta["members"][k]
     return np.concatenate([np.arange(mb["face_start"], mb["face_start"] + mb["n_internal_faces"]),
                            np.arange(mb["bface_start"], mb["bface_start"] + mb["n_boundary_faces"])])
+
+
+def inlet_flow(mesh, Ub, patch="inlet"):
+    """Volume flow entering through a patch for boundary velocities Ub[Fb, 3] (positive inwards)."""
+    p = mesh.patch(patch)
+    s = slice(p.start - mesh.n_internal_faces, p.start - mesh.n_internal_faces + p.size)
+    return -float((Ub[s] * mesh.Sf[p.start:p.start + p.size]).sum())
+
+
+def box_channel_inlet(mesh, umax=1.0):
+    """Ub with u_x = 16 umax y(1-y) z(1-z) on the inlet of a unit-box channel, zero elsewhere."""
+    Ub = np.zeros((mesh.n_boundary_faces, 3))
+    p = mesh.patch("inlet")
+    c = mesh.Cf[p.start:p.start + p.size]
+    Ub[p.start - mesh.n_internal_faces:p.start - mesh.n_internal_faces + p.size, 0] = \
+        16 * umax * c[:, 1] * (1 - c[:, 1]) * c[:, 2] * (1 - c[:, 2])
+    return Ub
+
+
+def batch_members(n_members=64, seed0=2603100, n_lo=2e4, n_hi=3e5):
+    """Members of the many-mesh batch.  Member k draws from seed seed0+k: a target size
+    N = exp(U[ln n_lo, ln n_hi]) cells, a Reynolds number U[100, 800] and Windkessel factors
+    U[0.5, 2]^3 on the nominal RCR.  Even k: a straight tube (butterfly section 8 x 4, 1152 tets per
+    layer, axial spacing 0.05, parabolic inlet u_max = 1, Re on the mean velocity and D = 1); odd k: a
+    unit-box Kuhn channel (inlet 16 y(1-y) z(1-z), Re on u_max and the unit length).  Each has one
+    Windkessel outlet.  Returns dicts with mesh, nu, Ub, wk [1, 3], pc0 [1]."""
+    out = []
+    for k in range(n_members):
+        rng = np.random.default_rng(seed0 + k)
+        N = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        Re = float(rng.uniform(100.0, 800.0))
+        fac = rng.uniform(0.5, 2.0, 3)
+        if k % 2 == 0:
+            layers = max(4, int(round(N / 1152)))
+            m = tube(n=8, m=4, layers=layers, R=0.5, L=0.05 * layers, seed=seed0 + k, outlet="wk")
+            Ub = np.zeros((m.n_boundary_faces, 3))
+            p = m.patch("inlet")
+            s = slice(p.start - m.n_internal_faces, p.start - m.n_internal_faces + p.size)
+            Ub[s] = parabolic_inlet(m.Cf[p.start:p.start + p.size], (0.0, 0.0, 0.0), 0.5, 1.0)
+            nu = 0.5 * 1.0 / Re
+        else:
+            nb = max(4, int(round((N / 6.0) ** (1.0 / 3.0))))
+            m = kuhn_cube(nb, jitter=0.15, patches="channel", seed=seed0 + k)
+            Ub = box_channel_inlet(m)
+            nu = 1.0 / Re
+        wk = windkessel_nominal(m, inlet_flow(m, Ub), outlets=("outlet",)) * fac[None, :]
+        m.name = f"member{k}:{m.name}"
+        out.append(dict(mesh=m, nu=nu, Ub=Ub, wk=wk, pc0=np.zeros(1), Re=Re))
+    return out
