@@ -171,24 +171,25 @@ __device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
   return {t, T.seg[t], T.lo[t], T.hi[t]};
 }
 
-// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles)
-template <int NV>
+// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles) by a block of
+// NT threads; every thread ends with the totals
+template <int NV, int NT = BLOCK>
 __device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
-  __shared__ double lds[NV][BLOCK / 64];
+  __shared__ double lds[NV][NT / 64];
   int f = T.first[s], n = T.count[s];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double acc = 0.0;
-    for (int q = threadIdx.x; q < n; q += BLOCK) acc += part[(size_t)k * T.ntile + f + q];
+    for (int q = threadIdx.x; q < n; q += NT) acc += part[(size_t)k * T.ntile + f + q];
     out[k] = acc;
   }
-  block_sum<NV>(out, lds);
+  block_sum<NV, NT>(out, lds);
 }
 
-template <int NV>
+template <int NV, int NT = BLOCK>
 __device__ __forceinline__ void put_partial(double (&v)[NV], double* __restrict__ part, int ntile, int t) {
-  __shared__ double lds[NV][BLOCK / 64];
-  block_sum<NV>(v, lds);
+  __shared__ double lds[NV][NT / 64];
+  block_sum<NV, NT>(v, lds);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < NV; ++k) part[(size_t)k * ntile + t] = v[k];
@@ -212,15 +213,17 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
 // Partials of each kernel are re-summed (per segment, fixed order) at the start of the NEXT kernel
 // in every block, so no tile waits for another and no L2 write-back is needed.  The direction update
 // p_k = z_{k-1} + beta p_{k-1} is fused into the product q = A p_k: each cell forms its own and its
-// neighbours' p_k from the interleaved pair (z, p) of the previous iteration (one 16-byte gather per
-// matrix slot).  (z, p) pairs and the published rho_k = r_k.z_k are double-buffered by parity.
+// neighbours' p_k from z and p_{k-1} (separate arrays, so every store writes whole cache lines);
+// p and the published rho_k = r_k.z_k are double-buffered by parity.
 //   init1:  r = b - A x                               partials (b.b, r.r)
-//   init2:  stopping test at k = 0; z0 = r/d          partials B = (r.r, r.z)
+//   init2:  stopping test at k = 0; z0 = r/d; p0 = 0  partials B = (r.r, r.z)
 //   spmv_k: rho_{k-1} and the stopping test of iterate k-1 (from B), beta; p_k; q = A p_k
 //                                                     partials A = (p.q); first tile publishes rho
 //   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
 // The segment's first tile records iterations / residual / status; its kernels return at once
-// after its stop.
+// after its stop.  The product runs 512 threads x 2 cells per 1024-cell tile, the update 256 x 4
+// (measured best on gfx950 for these two memory patterns); rows of width 4, 5 or 6 are unrolled so
+// every slot's loads are in flight together.
 // ---------------------------------------------------------------------------------------------
 struct PcgCtl {
   double tol, bn, res;
@@ -228,6 +231,8 @@ struct PcgCtl {
   int maxit, done, iters, status;
 };
 static_assert(sizeof(PcgCtl) <= sizeof(BiState), "PCG states share the BiState-sized allocation");
+
+constexpr int PCG_SPMV_NT = 512;  // threads per block of the product kernel (TILE / NT cells each)
 
 __global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, Tiles T, const double* __restrict__ b,
                                                      const double* __restrict__ x, double* __restrict__ r,
@@ -246,8 +251,9 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, Tiles T, const 
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double* __restrict__ x, const double* __restrict__ r,
-                                                     double2* __restrict__ zp0, const double* __restrict__ part_in,
-                                                     double* __restrict__ partB, PcgCtl* ctls) {
+                                                     double* __restrict__ z, double* __restrict__ p0,
+                                                     const double* __restrict__ part_in, double* __restrict__ partB,
+                                                     PcgCtl* ctls) {
   TileIdx ti = tile_idx(T);
   PcgCtl* ctl = ctls + ti.s;
   double s[2];
@@ -269,24 +275,47 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double
   double v[2] = {0.0, 0.0};
   FOR_TILE_CELLS(i) {
     double ri = r[i], zi = ri / A.diag[i];
-    zp0[i] = make_double2(zi, 0.0);  // p_0 = 0 so that p_1 = z_0 + 0 * p_0
+    z[i] = zi;
+    p0[i] = 0.0;  // p_1 = z_0 + 0 * p_0
     v[0] += ri * ri;
     v[1] += ri * zi;
   }
   put_partial<2>(v, partB, T.ntile, ti.t);
 }
 
+// (A (z + beta p))_i with the slot loads of a width-W row issued together
+template <int W>
+__device__ __forceinline__ double dir_row(const SellView& A, int base, double acc, double beta,
+                                          const double* __restrict__ z, const double* __restrict__ pp) {
+  double a[W], zj[W], pj[W];
+  int j[W];
+#pragma unroll
+  for (int sl = 0; sl < W; ++sl) {
+    a[sl] = A.val[base + sl * SLICE];
+    j[sl] = A.col[base + sl * SLICE];
+  }
+#pragma unroll
+  for (int sl = 0; sl < W; ++sl) {
+    zj[sl] = z[j[sl]];
+    pj[sl] = pp[j[sl]];
+  }
+#pragma unroll
+  for (int sl = 0; sl < W; ++sl) acc += a[sl] * (zj[sl] + beta * pj[sl]);
+  return acc;
+}
+
 // iteration k >= 1: stopping test of iterate k-1, then p_k and q = A p_k
-__global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, Tiles T, int k, const double2* __restrict__ zp_prev,
-                                                    double2* __restrict__ zp_cur, double* __restrict__ q,
-                                                    const double* __restrict__ partB, double* __restrict__ partA,
-                                                    PcgCtl* ctls) {
+__global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, int k, const double* __restrict__ z,
+                                                          const double* __restrict__ p_prev, double* __restrict__ p_cur,
+                                                          double* __restrict__ q, const double* __restrict__ partB,
+                                                          double* __restrict__ partA, PcgCtl* ctls) {
+  constexpr int NT = PCG_SPMV_NT, C = TILE / NT;
   TileIdx ti = tile_idx(T);
   PcgCtl* ctl = ctls + ti.s;
   if (block_flag(&ctl->done)) return;
   bool lead = ti.t == T.first[ti.s] && threadIdx.x == 0;
   double s2[2];
-  sum_seg<2>(partB, T, ti.s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+  sum_seg<2, NT>(partB, T, ti.s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
   double rho = s2[1];
   if (lead) ctl->rho[(k - 1) & 1] = rho;
   double beta = 0.0;
@@ -311,44 +340,50 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_spmv(SellView A, Tiles T, int k, 
     return;
   }
   double v[1] = {0.0};
-  FOR_TILE_CELLS(i) {
-    double2 zpi = zp_prev[i];
-    double pi = zpi.x + beta * zpi.y;
-    SlotRange R = slots_of(A.slice_start, i);
-    double acc = A.diag[i] * pi;
-#pragma unroll 4
-    for (int sl = 0; sl < R.width; ++sl) {
-      int at = R.base + sl * SLICE;
-      double2 zpj = zp_prev[A.col[at]];
-      acc += A.val[at] * (zpj.x + beta * zpj.y);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    int i = ti.lo + c * NT + threadIdx.x;
+    if (i < ti.hi) {
+      double pi = z[i] + beta * p_prev[i];
+      SlotRange R = slots_of(A.slice_start, i);
+      double acc = A.diag[i] * pi;
+      switch (R.width) {
+        case 4: acc = dir_row<4>(A, R.base, acc, beta, z, p_prev); break;
+        case 5: acc = dir_row<5>(A, R.base, acc, beta, z, p_prev); break;
+        case 6: acc = dir_row<6>(A, R.base, acc, beta, z, p_prev); break;
+        default:
+          for (int sl = 0; sl < R.width; ++sl) {
+            int at = R.base + sl * SLICE;
+            int j = A.col[at];
+            acc += A.val[at] * (z[j] + beta * p_prev[j]);
+          }
+      }
+      p_cur[i] = pi;
+      q[i] = acc;
+      v[0] += pi * acc;
     }
-    zp_cur[i].y = pi;
-    q[i] = acc;
-    v[0] += pi * acc;
   }
-  put_partial<1>(v, partA, T.ntile, ti.t);
+  put_partial<1, NT>(v, partA, T.ntile, ti.t);
 }
 
 // iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (streaming loads issued
 // before the partial sum so they overlap its latency)
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
-                                                      double2* __restrict__ zp_cur, const double* __restrict__ q,
-                                                      const double* __restrict__ partA, double* __restrict__ partB,
-                                                      int k, PcgCtl* ctls) {
+                                                      double* __restrict__ z, const double* __restrict__ p_cur,
+                                                      const double* __restrict__ q, const double* __restrict__ partA,
+                                                      double* __restrict__ partB, int k, PcgCtl* ctls) {
   TileIdx ti = tile_idx(T);
   PcgCtl* ctl = ctls + ti.s;
   if (block_flag(&ctl->done)) return;
   double xv[CPT], pv[CPT], rv[CPT], qv[CPT], dv[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    int i = ti.lo + c * BLOCK + threadIdx.x;
-    if (i < ti.hi) {
-      xv[c] = x[i];
-      pv[c] = zp_cur[i].y;
-      rv[c] = r[i];
-      qv[c] = q[i];
-      dv[c] = A.diag[i];
-    }
+    int i = min(ti.lo + c * BLOCK + (int)threadIdx.x, ti.hi - 1);  // tiles are never empty
+    xv[c] = x[i];
+    pv[c] = p_cur[i];
+    rv[c] = r[i];
+    qv[c] = q[i];
+    dv[c] = A.diag[i];
   }
   double pq[1];
   sum_seg<1>(partA, T, ti.s, pq);
@@ -362,7 +397,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, doubl
       double ri = rv[c] - alpha * qv[c];
       double zi = ri / dv[c];
       r[i] = ri;
-      zp_cur[i].x = zi;
+      z[i] = zi;
       v[0] += ri * ri;
       v[1] += ri * zi;
     }
@@ -394,13 +429,13 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   DIFVM_HIP(hipMemcpyAsync(w->pcg, init.data(), sizeof(PcgCtl) * nseg, hipMemcpyHostToDevice, s));
   double* r = w->r;
   double* q = w->q;
-  // (z, p) pairs, two parities, in the p and v buffers (each 3 nc long)
-  double2* ZP[2] = {reinterpret_cast<double2*>(w->p), reinterpret_cast<double2*>(w->v)};
+  double* z = w->z;
+  double* Pk[2] = {w->p, w->v};  // p_k at parity k & 1
   double* partA = w->partials;
   double* partB = w->partials + 2 * (size_t)G;
   double* part0 = w->partials + 4 * (size_t)G;
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
-  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, T, x, r, ZP[0], part0, partB, w->pcg);
+  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
   DIFVM_HIP(hipGetLastError());
   // First block sized from the previous solve, then short polled blocks; iteration k's stopping test
   // runs at the start of iteration k+1, so the host queues up to iteration maxit+1.
@@ -412,12 +447,12 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     for (; k <= last; ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<G, BLOCK, 0, s>>>(V, T, k, ZP[(k - 1) & 1], ZP[k & 1], q, partB, partA, w->pcg);
+        k_pcg_spmv<<<G, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
       if (k > maxit) break;
       {
         ProfScope ps(m, "pcg_update_dot");
-        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, ZP[k & 1], q, partA, partB, k, w->pcg);
+        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[k & 1], q, partA, partB, k, w->pcg);
       }
     }
     DIFVM_HIP(hipGetLastError());
