@@ -59,9 +59,34 @@ def op_bytes(op, nfi, nfb, nc, fp):
     raise KeyError(op)
 
 
+class HipTimer:
+    """HIP events created with hipEventDisableSystemFence (timing only: no cache write-back around the
+    timed work), recorded on the given stream."""
+
+    def __init__(self, stream):
+        import ctypes
+        self.C = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.e0, self.e1 = ctypes.c_void_p(), ctypes.c_void_p()
+        for e in (self.e0, self.e1):
+            assert self.hip.hipEventCreateWithFlags(ctypes.byref(e), ctypes.c_uint(0x20000000)) == 0
+
+    def start(self):
+        assert self.hip.hipEventRecord(self.e0, self.stream) == 0
+
+    def stop_s(self):
+        assert self.hip.hipEventRecord(self.e1, self.stream) == 0
+        assert self.hip.hipEventSynchronize(self.e1) == 0
+        ms = self.C.c_float()
+        assert self.hip.hipEventElapsedTime(self.C.byref(ms), self.e0, self.e1) == 0
+        return ms.value * 1e-3
+
+
 def operator_sweep(B, M, m, torch, reps=30):
     """Per-operator kernel time with HIP events on the launch stream; the 256 MB Infinity Cache is
-    flushed by a 1 GiB write before every timed launch (cold numbers), warm numbers back to back."""
+    flushed by reading a 1 GiB buffer before every timed launch (cold numbers; a read leaves no dirty
+    lines to write back), warm numbers back to back."""
     import numpy as np
     from paper_2603_15920_amd import meshgen as mg
     nc, nfi, nfb = m.n_cells, m.n_internal_faces, m.n_boundary_faces
@@ -71,9 +96,30 @@ def operator_sweep(B, M, m, torch, reps=30):
     phib_u = f(m.Cf[nfi:])
     U_u = np.stack([mg.sinusoid_field(2603013 + k)(m.C) for k in range(3)], 1)
     Ub_u = np.stack([mg.sinusoid_field(2603013 + k)(m.Cf[nfi:]) for k in range(3)], 1)
-    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+    flush = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    sink = torch.empty((), dtype=torch.float32, device="cuda:0")
     out = {}
     s = torch.cuda.current_stream()
+    tm = HipTimer(s)
+    # reference: a plain device copy of 64 MiB (128 MiB moved), timed the same way
+    src = torch.ones(1 << 23, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    cold = []
+    for _ in range(reps):
+        sink = flush.sum()
+        tm.start()
+        dst.copy_(src)
+        cold.append(tm.stop_s())
+    tm.start()
+    for _ in range(reps):
+        dst.copy_(src)
+    warm = tm.stop_s() / reps
+    tc = sorted(cold)[len(cold) // 2]
+    out["copy_64MiB_reference"] = {"us_cold": round(tc * 1e6, 2), "us_warm": round(warm * 1e6, 2),
+                                   "GBps_cold": round(2 * src.numel() * 8 / tc / 1e9, 1),
+                                   "GBps_warm": round(2 * src.numel() * 8 / warm / 1e9, 1)}
+    log("copy reference", out["copy_64MiB_reference"])
+    del src, dst
     for dt, tag, fp in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
         phi = M.to_internal(dev(phi_u, dt), B.KIND_CELL)
         phib = M.to_internal(dev(phib_u, dt), B.KIND_BFACE)
@@ -107,20 +153,14 @@ def operator_sweep(B, M, m, torch, reps=30):
                 fn()
             cold = []
             for _ in range(reps):
-                flush.zero_()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(s)
+                sink = flush.sum()
+                tm.start()
                 fn()
-                e1.record(s)
-                e1.synchronize()
-                cold.append(e0.elapsed_time(e1) * 1e-3)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
+                cold.append(tm.stop_s())
+            tm.start()
             for _ in range(reps):
                 fn()
-            e1.record(s)
-            e1.synchronize()
-            warm = e0.elapsed_time(e1) * 1e-3 / reps
+            warm = tm.stop_s() / reps
             tc = sorted(cold)[len(cold) // 2]
             nbytes = op_bytes(name, nfi, nfb, nc, fp)
             out[f"{name}_{tag}"] = {

@@ -28,7 +28,8 @@ static hipEvent_t pool_event(Profiler& P) {
     return e;
   }
   hipEvent_t e;
-  DIFVM_HIP(hipEventCreate(&e));
+  // timing-only events: no system-scope fence (cache write-back) around the timed launch
+  DIFVM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 
@@ -145,6 +146,7 @@ static void upload_mesh(difvm_mesh* m) {
   d.slice_start = up_vec(m, L.slice_start);
   d.slot_face = up_vec(m, L.slot_face);
   d.slot_col = up_vec(m, L.slot_col);
+  d.cell_nslot = up_vec(m, L.cell_nslot);
   d.face_slot_own = up_vec(m, L.face_slot_own);
   d.face_slot_nbr = up_vec(m, L.face_slot_nbr);
   d.nseg = L.nseg;

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace difvm {
@@ -43,6 +45,7 @@ struct MeshView {
   const int32_t* __restrict__ slice_start;
   const int32_t* __restrict__ slot_face;
   const int32_t* __restrict__ slot_col;
+  const uint8_t* __restrict__ nslot;  // slots of each cell (255: use the slice width)
 };
 
 template <class T>
@@ -50,15 +53,16 @@ MeshView<T> view(const DMesh& d);
 template <>
 inline MeshView<double> view<double>(const DMesh& d) {
   return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS, d.geomK, d.w, d.bown, d.bgeom, d.bcode, d.V,
-          d.slice_start, d.slot_face, d.slot_col};
+          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot};
 }
 template <>
 inline MeshView<float> view<float>(const DMesh& d) {
   return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS32, d.geomK32, d.w32, d.bown, d.bgeom32, d.bcode, d.V32,
-          d.slice_start, d.slot_face, d.slot_col};
+          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot};
 }
 
-// slot range of cell i: slots base + k*SLICE for k < width
+// slot range of cell i: slots base + k*SLICE for k < width (the slice's width: trailing pads
+// possible)
 struct SlotRange {
   int base, width;
 };
@@ -66,6 +70,27 @@ __device__ __forceinline__ SlotRange slots_of(const int32_t* slice_start, int i)
   int s = i >> 6;
   int b = slice_start[s];
   return {b + (i & (SLICE - 1)), (slice_start[s + 1] - b) >> 6};
+}
+
+// number of slots a row walker visits for cell i: the cell's own count, so that a cell's arithmetic
+// never depends on the other cells of its slice (cells of one mesh packed beside another compute the
+// same bits as alone); 255 marks a count too large for the byte, then the slice width is used
+__device__ __forceinline__ int row_len(const uint8_t* __restrict__ nslot, int i, const SlotRange& R) {
+  int n = nslot[i];
+  return n == 255 ? R.width : n;
+}
+
+// calls body(W) for a row of n slots: W in {3, 4, 5, 6} unrolled with all slot loads issued
+// together, W = 0 for any other n (one slot per pass)
+template <class F>
+__device__ __forceinline__ void by_width(int n, F&& body) {
+  switch (n) {
+    case 3: body(std::integral_constant<int, 3>{}); break;
+    case 4: body(std::integral_constant<int, 4>{}); break;
+    case 5: body(std::integral_constant<int, 5>{}); break;
+    case 6: body(std::integral_constant<int, 6>{}); break;
+    default: body(std::integral_constant<int, 0>{});
+  }
 }
 
 // ---------------------------------------------------------------------------------------------

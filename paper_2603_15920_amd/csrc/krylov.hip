@@ -73,6 +73,7 @@ void krylov_work_free(KrylovWork* w) {
 // ---------------------------------------------------------------------------------------------
 struct SellView {
   int nc;
+  const uint8_t* __restrict__ nslot;
   const int32_t* __restrict__ slice_start;
   const int32_t* __restrict__ col;
   const double* __restrict__ val;
@@ -80,7 +81,7 @@ struct SellView {
 };
 
 static SellView sview(const difvm_mesh* m, SellMatrix A) {
-  return {m->d.nc, m->d.slice_start, m->d.slot_col, A.val, A.diag};
+  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag};
 }
 
 // (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
@@ -222,7 +223,7 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
 //   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
 // The segment's first tile records iterations / residual / status; its kernels return at once
 // after its stop.  The product runs 512 threads x 2 cells per 1024-cell tile, the update 256 x 4
-// (measured best on gfx950 for these two memory patterns); rows of width 4, 5 or 6 are unrolled so
+// (measured best on gfx950 for these two memory patterns); rows of 3 to 6 slots are unrolled so
 // every slot's loads are in flight together.
 // ---------------------------------------------------------------------------------------------
 struct PcgCtl {
@@ -346,13 +347,15 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
     if (i < ti.hi) {
       double pi = z[i] + beta * p_prev[i];
       SlotRange R = slots_of(A.slice_start, i);
+      const int nrow = row_len(A.nslot, i, R);
       double acc = A.diag[i] * pi;
-      switch (R.width) {
+      switch (nrow) {
+        case 3: acc = dir_row<3>(A, R.base, acc, beta, z, p_prev); break;
         case 4: acc = dir_row<4>(A, R.base, acc, beta, z, p_prev); break;
         case 5: acc = dir_row<5>(A, R.base, acc, beta, z, p_prev); break;
         case 6: acc = dir_row<6>(A, R.base, acc, beta, z, p_prev); break;
         default:
-          for (int sl = 0; sl < R.width; ++sl) {
+          for (int sl = 0; sl < nrow; ++sl) {
             int at = R.base + sl * SLICE;
             int j = A.col[at];
             acc += A.val[at] * (z[j] + beta * p_prev[j]);

@@ -45,6 +45,7 @@ struct HostLayout {
   // cell-slot layout
   int nslice = 0, nslot = 0;
   std::vector<int32_t> slice_start, slot_face, slot_col;
+  std::vector<uint8_t> cell_nslot;  // slots of each cell (its own, pads excluded), 255 = 255 or more
   std::vector<int32_t> face_slot_own, face_slot_nbr;   // slot index of each internal face's two sides
   // Windkessel face lists
   std::vector<int32_t> wk_start, wk_faces;

@@ -393,6 +393,8 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
   auto count = [&](int i) {
     return (L.own_start[i + 1] - L.own_start[i]) + (L.losort_start[i + 1] - L.losort_start[i]) + (bstart[i + 1] - bstart[i]);
   };
+  L.cell_nslot.resize(nc);
+  for (int i = 0; i < nc; ++i) L.cell_nslot[i] = (uint8_t)std::min(count(i), 255);
   for (int s = 0; s < L.nslice; ++s) {
     int wmax = 0;
     for (int i = s * SLICE; i < std::min(nc, (s + 1) * SLICE); ++i) wmax = std::max(wmax, count(i));

@@ -6,6 +6,7 @@
 // passing (eq. aggregate) is a gather in a fixed order: no atomics, bitwise deterministic, and
 // independent of the launch shape.  Face kernels (one thread per face) write per-face outputs.
 #include <cstring>
+#include <type_traits>
 
 #include "abi_util.h"
 #include "device.h"
@@ -86,6 +87,16 @@ __global__ __launch_bounds__(BLOCK) void k_interp(MeshView<T> m, int table, cons
 }
 
 // ---------------------------------------------------------------------------------------------
+// Row walkers.  A cell's own slots are visited in layout order; rows of 3 to 6 slots (2D prisms,
+// tets, prisms, hexes) are unrolled with every slot's loads issued before any is used (indices
+// clamped so each load is in bounds whatever the slot holds), other counts take the same code one
+// slot at a time.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool slot_internal(int sf, int nfi) { return sf != SLOT_PAD && sf < nfi; }
+__device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_internal(sf, nfi) ? (sf < 0 ? -sf - 1 : sf) : 0; }
+
+
+// ---------------------------------------------------------------------------------------------
 // Gauss gradient (cell kernel): G_i = (1/V_i) sum_slots sigma phi_f S_f
 // ---------------------------------------------------------------------------------------------
 template <class T, int NC>
@@ -101,38 +112,56 @@ __global__ __launch_bounds__(BLOCK) void k_grad(MeshView<T> m, int table, const 
     acc[c][0] = acc[c][1] = acc[c][2] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    int j = m.slot_col[at];
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      auto g = m.geomS[f];
-      T wself = nb ? T(1) - g.w : g.w;   // weight of this cell in phi_f
-      T sg = nb ? T(-1) : T(1);
+  const int nrow = row_len(m.nslot, i, R);
+  by_width(nrow, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    constexpr int N = W > 0 ? W : 1;
+    const int n = W > 0 ? W : nrow;
+    for (int k0 = 0; k0 < n; k0 += N) {
+      int sf[N], j[N];
+      typename Geo<T>::v4 g[N];
+      T pj[N][NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T pf = sg * (wself * pi[c] + (T(1) - wself) * phi[(size_t)j * NC + c]);
-        acc[c][0] += pf * g.x;
-        acc[c][1] += pf * g.y;
-        acc[c][2] += pf * g.z;
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        sf[k] = m.slot_face[at];
+        j[k] = m.slot_col[at];
       }
-    } else {
-      int b = sf - m.nfi;
-      auto g = m.bgeom[b];
-      bool fixed = code[b] == BC_FIXED;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T pf = fixed ? phib[(size_t)b * NC + c] : pi[c];
-        acc[c][0] += pf * g.x;
-        acc[c][1] += pf * g.y;
-        acc[c][2] += pf * g.z;
+      for (int k = 0; k < N; ++k) {
+        g[k] = m.geomS[slot_face_index(sf[k], m.nfi)];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pj[k][c] = phi[(size_t)j[k] * NC + c];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (sf[k] == SLOT_PAD) continue;
+        if (sf[k] < m.nfi) {
+          bool nb = sf[k] < 0;
+          T wself = nb ? T(1) - g[k].w : g[k].w;   // weight of this cell in phi_f
+          T sg = nb ? T(-1) : T(1);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            T pf = sg * (wself * pi[c] + (T(1) - wself) * pj[k][c]);
+            acc[c][0] += pf * g[k].x;
+            acc[c][1] += pf * g[k].y;
+            acc[c][2] += pf * g[k].z;
+          }
+        } else {
+          int b = sf[k] - m.nfi;
+          auto gb = m.bgeom[b];
+          bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            T pf = fixed ? phib[(size_t)b * NC + c] : pi[c];
+            acc[c][0] += pf * gb.x;
+            acc[c][1] += pf * gb.y;
+            acc[c][2] += pf * gb.z;
+          }
+        }
       }
     }
-  }
+  });
   T rv = T(1) / m.V[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
@@ -156,44 +185,62 @@ __global__ __launch_bounds__(BLOCK) void k_div(MeshView<T> m, int table, const T
     acc[c] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    int j = m.slot_col[at];
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      T F = flux[f];
-      T Fs = nb ? -F : F;                 // flux out of this cell
+  const int nrow = row_len(m.nslot, i, R);
+  by_width(nrow, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    constexpr int N = W > 0 ? W : 1;
+    const int n = W > 0 ? W : nrow;
+    for (int k0 = 0; k0 < n; k0 += N) {
+      int sf[N], j[N];
+      T F[N], wf[N], pj[N][NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T pf;
-        if (SCHEME == DIFVM_SCHEME_ONE) {
-          pf = T(1);
-        } else if (SCHEME == DIFVM_SCHEME_UPWIND) {
-          bool owner_up = F >= T(0);      // the tie F = 0 belongs to the owner
-          bool self_up = nb ? !owner_up : owner_up;
-          pf = self_up ? pi[c] : psi[(size_t)j * NC + c];
-        } else {
-          T w = m.w[f];
-          T wself = nb ? T(1) - w : w;
-          pf = wself * pi[c] + (T(1) - wself) * psi[(size_t)j * NC + c];
-        }
-        acc[c] += Fs * pf;
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        sf[k] = m.slot_face[at];
+        j[k] = m.slot_col[at];
       }
-    } else {
-      int b = sf - m.nfi;
-      T F = flux[m.nfi + b];
-      bool fixed = code[b] == BC_FIXED;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T pf = SCHEME == DIFVM_SCHEME_ONE ? T(1) : (fixed ? psib[(size_t)b * NC + c] : pi[c]);
-        acc[c] += F * pf;
+      for (int k = 0; k < N; ++k) {
+        // internal face, or the boundary face's own flux entry (pad slots read entry 0)
+        int fi = slot_internal(sf[k], m.nfi) ? (sf[k] < 0 ? -sf[k] - 1 : sf[k]) : (sf[k] == SLOT_PAD ? 0 : sf[k]);
+        F[k] = flux[fi];
+        wf[k] = SCHEME == DIFVM_SCHEME_LINEAR ? m.w[slot_face_index(sf[k], m.nfi)] : T(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pj[k][c] = SCHEME == DIFVM_SCHEME_ONE ? T(0) : psi[(size_t)j[k] * NC + c];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (sf[k] == SLOT_PAD) continue;
+        if (sf[k] < m.nfi) {
+          bool nb = sf[k] < 0;
+          T Fs = nb ? -F[k] : F[k];  // flux out of this cell
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            T pf;
+            if (SCHEME == DIFVM_SCHEME_ONE) {
+              pf = T(1);
+            } else if (SCHEME == DIFVM_SCHEME_UPWIND) {
+              bool owner_up = F[k] >= T(0);  // the tie F = 0 belongs to the owner
+              bool self_up = nb ? !owner_up : owner_up;
+              pf = self_up ? pi[c] : pj[k][c];
+            } else {
+              T wself = nb ? T(1) - wf[k] : wf[k];
+              pf = wself * pi[c] + (T(1) - wself) * pj[k][c];
+            }
+            acc[c] += Fs * pf;
+          }
+        } else {
+          int b = sf[k] - m.nfi;
+          bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            T pf = SCHEME == DIFVM_SCHEME_ONE ? T(1) : (fixed ? psib[(size_t)b * NC + c] : pi[c]);
+            acc[c] += F[k] * pf;
+          }
+        }
       }
     }
-  }
+  });
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
 }
@@ -212,36 +259,57 @@ __global__ __launch_bounds__(BLOCK) void k_laplacian(MeshView<T> m, int table, c
   T gi0 = g[3 * (size_t)i], gi1 = g[3 * (size_t)i + 1], gi2 = g[3 * (size_t)i + 2];
   T acc = T(0);
   const int8_t* code = m.bcode + table * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    int j = m.slot_col[at];
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      auto kd = m.geomK[f];
-      T w = m.w[f];
-      T wself = nb ? T(1) - w : w;
-      const T* gj = g + 3 * (size_t)j;
-      // seen from this cell: delta (phi_other - phi_self) + k_out . gbar, with k_out the correction
-      // vector oriented out of this cell; the owner-side form of eq. nonortho_flux, negated for the
-      // neighbour side
-      T corr = kd.x * (wself * gi0 + (T(1) - wself) * gj[0]) + kd.y * (wself * gi1 + (T(1) - wself) * gj[1]) +
-               kd.z * (wself * gi2 + (T(1) - wself) * gj[2]);
-      T t = kd.w * (phi[j] - pi) + (nb ? -corr : corr);
-      if (GAMMA) t *= gamma[f];
-      acc += t;
-    } else {
-      int b = sf - m.nfi;
-      if (code[b] == BC_FIXED) {
-        T t = m.bgeom[b].w * (phib[b] - pi);
-        if (GAMMA) t *= gamma[m.nfi + b];
-        acc += t;
+  const int nrow = row_len(m.nslot, i, R);
+  by_width(nrow, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    constexpr int N = W > 0 ? W : 1;
+    const int n = W > 0 ? W : nrow;
+    for (int k0 = 0; k0 < n; k0 += N) {
+      int sf[N], j[N];
+      typename Geo<T>::v4 kd[N];
+      T wf[N], pj[N], gj[N][3], gm[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        sf[k] = m.slot_face[at];
+        j[k] = m.slot_col[at];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        int f = slot_face_index(sf[k], m.nfi);
+        kd[k] = m.geomK[f];
+        wf[k] = m.w[f];
+        gm[k] = GAMMA ? gamma[f] : T(1);
+        pj[k] = phi[j[k]];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) gj[k][e] = g[3 * (size_t)j[k] + e];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (sf[k] == SLOT_PAD) continue;
+        if (sf[k] < m.nfi) {
+          bool nb = sf[k] < 0;
+          T wself = nb ? T(1) - wf[k] : wf[k];
+          // seen from this cell: delta (phi_other - phi_self) + k_out . gbar, with k_out the
+          // correction vector oriented out of this cell; the owner-side form of eq. nonortho_flux,
+          // negated for the neighbour side
+          T corr = kd[k].x * (wself * gi0 + (T(1) - wself) * gj[k][0]) +
+                   kd[k].y * (wself * gi1 + (T(1) - wself) * gj[k][1]) +
+                   kd[k].z * (wself * gi2 + (T(1) - wself) * gj[k][2]);
+          T t = kd[k].w * (pj[k] - pi) + (nb ? -corr : corr);
+          if (GAMMA) t *= gm[k];
+          acc += t;
+        } else {
+          int b = sf[k] - m.nfi;
+          if (code[b] == BC_FIXED) {
+            T t = m.bgeom[b].w * (phib[b] - pi);
+            if (GAMMA) t *= gamma[m.nfi + b];
+            acc += t;
+          }
+        }
       }
     }
-  }
+  });
   out[i] = acc;
 }
 
@@ -258,17 +326,37 @@ __global__ __launch_bounds__(BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __re
   T di = diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    if (sf >= m.nfi) continue;
-    int j = m.slot_col[at];
-    T a = sf < 0 ? lo[-sf - 1] : up[sf];
+  const int nrow = row_len(m.nslot, i, R);
+  by_width(nrow, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    constexpr int N = W > 0 ? W : 1;
+    const int n = W > 0 ? W : nrow;
+    for (int k0 = 0; k0 < n; k0 += N) {
+      int sf[N], j[N];
+      T a[N], xj[N][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
-  }
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        sf[k] = m.slot_face[at];
+        j[k] = m.slot_col[at];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        bool in = slot_internal(sf[k], m.nfi);
+        int f = in ? (sf[k] < 0 ? -sf[k] - 1 : sf[k]) : 0;
+        T v = (in && sf[k] < 0) ? lo[f] : up[f];
+        a[k] = in ? v : T(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xj[k][c] = x[(size_t)j[k] * NC + c];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (!slot_internal(sf[k], m.nfi)) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += a[k] * xj[k][c];
+      }
+    }
+  });
 #pragma unroll
   for (int c = 0; c < NC; ++c) y[(size_t)i * NC + c] = acc[c];
 }
@@ -359,6 +447,9 @@ void ldu_spmv_t(const difvm_mesh* mm, int ncomp, int transpose, const T* diag, c
   MeshView<T> v = view<T>(d);
   if (!lo) lo = up;
   if (transpose) std::swap(up, lo);
+  // the kernel reads entry 0 of up / lo on non-internal slots (value unused): with no internal faces
+  // the caller may pass NULL, so point both at diag (nc >= 1 entries)
+  if (d.nfi == 0) up = lo = diag;
   int G = grid_for(d.nc);
   if (ncomp == 1) k_ldu_spmv<T, 1><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
   else k_ldu_spmv<T, 3><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
