@@ -21,6 +21,25 @@ sys.path.insert(0, ROOT)
 METRIC = "PISO steps/s & faces/s/operator at 1M cells FP64 (% HBM peak); adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
 
+# HBM-side bytes per launch of k_pcg_spmv on this workload from two rocprofv3 --pmc runs (TCC
+# FETCH_SIZE and WRITE_SIZE medians in KiB, scaled by what the counters read for a 256 MiB device
+# copy), valid only for the kernel source they were taken with.
+PCG_SPMV_COUNTERS = {"source": "paper_2603_15920_amd/csrc/krylov.hip",
+                     "sha256": "e96cab643c2246b5a266fd8dd4eb9ef0e4c2e4da439e09ec6770407b5145c83a",
+                     "fetch_kib": 39050.875, "write_kib": 16472.875, "fetch_scale": 1.99974, "write_scale": 1.0}
+
+
+def counter_traffic(c):
+    """Scaled counter bytes per launch, or None once the kernel source differs from the one measured."""
+    import hashlib
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, c["source"]), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if h != c["sha256"]:
+        return None
+    return int(round(1024 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])))
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -391,7 +410,7 @@ def main():
     avg_s = total_ms * 1e-3 / max(launches, 1)
     alg = op_bytes("spmv_sym", nfi, nfb, nc, 8)
     achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
-    traffic = None
+    traffic = counter_traffic(PCG_SPMV_COUNTERS)
     roofline = {"bound": "hbm", "kernel": "k_pcg_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
