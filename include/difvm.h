@@ -295,6 +295,22 @@ difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, dif
 difvm_status difvm_piso_set_state(difvm_piso* piso, const void* U, const void* p, const void* phi);
 difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi, double* pc_host);
 
+/* Graph mode (the paper runs its time loop as one compiled scan, Sec. 2.4; here the step is a
+ * replayed hipGraph).  With enable != 0, the first difvm_piso_step step after this call runs eagerly
+ * and records its Krylov iteration counts; the whole step (Windkessel, assembly, BiCGStab, every
+ * corrector) is then captured once on a private stream with a budget per solve of those counts plus
+ * extra_iters (>= 0), and each later step is one hipGraphLaunch on the context's stream followed by
+ * one read of the solvers' states.  Iterations past a solve's stop are predicated no-ops, so results
+ * are bitwise those of eager stepping.  A step in which some solve had not stopped within its budget
+ * is discarded (its starting state, saved by the graph, is restored on the device) and run eagerly;
+ * the graph is then recaptured with the larger counts.  enable = 0 returns to eager stepping.
+ * Changing boundary values, Windkessel parameters, viscosity or the state between steps is allowed
+ * (the graph reads the device buffers).  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */
+difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extra_iters);
+
+/* Graph-mode counters since creation: replayed steps, discarded-and-redone steps, captures. */
+difvm_status difvm_piso_graph_info(const difvm_piso* piso, int64_t* replays, int64_t* redos, int64_t* captures);
+
 /* Advances nsteps time steps.  stats_host[nsteps] (may be NULL) receives solver iterations and
  * residuals per step.  Synchronises.  Returns the worst solver status over the steps. */
 difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats* stats_host);

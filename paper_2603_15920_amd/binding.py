@@ -109,6 +109,8 @@ _SIGS = {
     "difvm_piso_set_windkessel": (C.c_int32, [_vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]),
     "difvm_piso_set_viscosity": (C.c_int32, [_vp, C.c_int32, _f64p]),
     "difvm_piso_segment_stats": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
+    "difvm_piso_set_graph": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "difvm_piso_graph_info": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_piso_get_state": (C.c_int32, [_vp, _vp, _vp, _vp, _f64p]),
     "difvm_piso_step": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
@@ -360,6 +362,17 @@ def difvm_piso_segment_stats(p, n_seg, n_corr=2):
     return it, res, np.array([s.status for s in stats], dtype=np.int32)
 
 
+def difvm_piso_set_graph(p, enable, extra_iters=16):
+    _check(lib().difvm_piso_set_graph(p, int(enable), int(extra_iters)), "difvm_piso_set_graph")
+
+
+def difvm_piso_graph_info(p):
+    """(replays, redos, captures) of graph mode."""
+    v = [C.c_int64(0) for _ in range(3)]
+    _check(lib().difvm_piso_graph_info(p, *[C.byref(x) for x in v]), "difvm_piso_graph_info")
+    return tuple(x.value for x in v)
+
+
 def difvm_piso_set_state(p, U, pres, phi):
     _check(lib().difvm_piso_set_state(p, _ptr(U), _ptr(pres), _ptr(phi)), "difvm_piso_set_state")
 
@@ -490,6 +503,12 @@ class Piso:
 
     def set_windkessel(self, wid, Rp, Cc, Rd, pc):
         difvm_piso_set_windkessel(self.h, wid, Rp, Cc, Rd, pc)
+
+    def set_graph(self, enable=True, extra_iters=16):
+        difvm_piso_set_graph(self.h, enable, extra_iters)
+
+    def graph_info(self):
+        return difvm_piso_graph_info(self.h)
 
     def set_viscosity(self, nu_seg):
         difvm_piso_set_viscosity(self.h, nu_seg)

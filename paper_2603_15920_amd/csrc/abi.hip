@@ -35,7 +35,7 @@ static hipEvent_t pool_event(Profiler& P) {
 
 int prof_begin(Ctx& c, const char* name) {
   Profiler& P = c.prof;
-  if (!P.on) return -1;
+  if (!P.on || c.capturing) return -1;
   int id = -1;
   for (size_t k = 0; k < P.names.size(); ++k)
     if (P.names[k] == name) id = (int)k;
@@ -79,6 +79,8 @@ void piso_set_boundary(difvm_piso* P, const double* Ub, const double* pb);
 void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, double pc);
 void piso_set_viscosity(difvm_piso* P, int nseg, const double* nu_seg);
 void piso_release(difvm_piso* P);
+void piso_set_graph(difvm_piso* P, int enable, int extra);
+void piso_graph_info(const difvm_piso* P, long long* replays, long long* redos, long long* captures);
 void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out);
 void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
 void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host);
@@ -541,6 +543,26 @@ difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, dif
   check_ptr(piso, "piso");
   check_ptr(out_host, "out_host");
   piso_segment_stats(piso, n_seg, out_host);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extra_iters) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_set_graph(piso, enable, extra_iters);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_graph_info(const difvm_piso* piso, int64_t* replays, int64_t* redos, int64_t* captures) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  long long r = 0, d = 0, c = 0;
+  piso_graph_info(piso, &r, &d, &c);
+  if (replays) *replays = r;
+  if (redos) *redos = d;
+  if (captures) *captures = c;
   DIFVM_API_END
   return DIFVM_OK;
 }

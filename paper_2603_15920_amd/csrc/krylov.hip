@@ -408,6 +408,48 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, doubl
   put_partial<2>(v, partB, T.ntile, ti.t);
 }
 
+// per-segment control state set on the device (no host buffer, so the launch can be captured)
+__global__ void k_pcg_ctl_init(PcgCtl* ctls, int nseg, double tol, int maxit) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  PcgCtl c{};
+  c.tol = tol;
+  c.maxit = maxit;
+  ctls[g] = c;
+}
+
+// copies n doubles (solver states are made of doubles and ints, 8-byte multiples)
+__global__ void k_copy_words(double* __restrict__ dst, const double* __restrict__ src, int n) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[q];
+}
+static void copy_state(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  int n = (int)(bytes / sizeof(double));
+  k_copy_words<<<(n + 255) / 256, 256, 0, s>>>(static_cast<double*>(dst), static_cast<const double*>(src), n);
+  DIFVM_HIP(hipGetLastError());
+}
+
+size_t pcg_state_bytes(const difvm_mesh* m) { return sizeof(PcgCtl) * m->d.nseg; }
+
+SolveResult pcg_result(const difvm_mesh* m, const void* host_state, bool* complete) {
+  const PcgCtl* hs = static_cast<const PcgCtl*>(host_state);
+  int nseg = m->d.nseg;
+  SolveResult R;
+  R.seg.resize(nseg);
+  bool all = true;
+  for (int g = 0; g < nseg; ++g) {
+    const PcgCtl& c = hs[g];
+    all = all && c.done;
+    int st = c.done ? c.status : (int)DIFVM_WARN_NOT_CONVERGED;
+    R.seg[g] = {{c.iters, 0, 0}, {c.res, 0, 0}, st};
+    R.iters[0] = std::max(R.iters[0], c.iters);
+    R.res[0] = std::max(R.res[0], c.res);
+    R.status = std::max(R.status, st);
+  }
+  if (complete) *complete = all;
+  return R;
+}
+
 // copies the per-segment states to the pinned mirror and waits
 template <class S>
 static const S* fetch_states(difvm_mesh* m, KrylovWork* w, const S* dstate) {
@@ -417,19 +459,13 @@ static const S* fetch_states(difvm_mesh* m, KrylovWork* w, const S* dstate) {
   return static_cast<const S*>(w->host_state);
 }
 
-SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit) {
+SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit, const QueueOnly* qo) {
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
   Tiles T = tiles_of(m);
   int G = T.ntile, nseg = m->d.nseg;
-  std::vector<PcgCtl> init(nseg);
-  for (auto& c : init) {
-    c = PcgCtl{};
-    c.tol = tol;
-    c.maxit = maxit;
-  }
-  DIFVM_HIP(hipMemcpyAsync(w->pcg, init.data(), sizeof(PcgCtl) * nseg, hipMemcpyHostToDevice, s));
+  k_pcg_ctl_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->pcg, nseg, tol, maxit);
   double* r = w->r;
   double* q = w->q;
   double* z = w->z;
@@ -440,6 +476,17 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
   k_pcg_init2<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
   DIFVM_HIP(hipGetLastError());
+  if (qo) {
+    // queue-only: iterations 1..K and the stopping test of iterate K, no read-back
+    int K = std::min(qo->budget, maxit);
+    for (int kk = 1; kk <= K + 1; ++kk) {
+      k_pcg_spmv<<<G, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
+      if (kk <= K) k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
+    }
+    DIFVM_HIP(hipGetLastError());
+    copy_state(qo->state_out, w->pcg, pcg_state_bytes(m), s);
+    return SolveResult{};
+  }
   // First block sized from the previous solve, then short polled blocks; iteration k's stopping test
   // runs at the start of iteration k+1, so the host queues up to iteration maxit+1.
   int k = 1;
@@ -465,18 +512,8 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     if (k > maxit || all) break;
     nb = 4;
   }
-  SolveResult R;
-  R.seg.resize(nseg);
-  w->pcg_hint = 0;
-  for (int g = 0; g < nseg; ++g) {
-    const PcgCtl& c = hs[g];
-    int st = c.done ? c.status : (int)DIFVM_WARN_NOT_CONVERGED;
-    R.seg[g] = {{c.iters, 0, 0}, {c.res, 0, 0}, st};
-    R.iters[0] = std::max(R.iters[0], c.iters);
-    R.res[0] = std::max(R.res[0], c.res);
-    R.status = std::max(R.status, st);
-    w->pcg_hint = std::max(w->pcg_hint, c.iters);
-  }
+  SolveResult R = pcg_result(m, hs, nullptr);
+  w->pcg_hint = R.iters[0];
   return R;
 }
 
@@ -729,27 +766,57 @@ __global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, Tiles T, double* __r
   put_partial<2 * NC>(acc, part, T.ntile, ti.t);
 }
 
+__global__ void k_bi_state_init(BiState* sts, int nseg, double tol, int maxit) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  BiState st{};
+  st.tol = tol;
+  st.maxit = maxit;
+  sts[g] = st;
+}
+
+size_t bicgstab_state_bytes(const difvm_mesh* m) { return sizeof(BiState) * m->d.nseg; }
+
+SolveResult bicgstab_result(const difvm_mesh* m, int ncomp, const void* host_state, bool* complete) {
+  const BiState* hs = static_cast<const BiState*>(host_state);
+  int nseg = m->d.nseg;
+  SolveResult R;
+  R.seg.resize(nseg);
+  bool all = true;
+  for (int g = 0; g < nseg; ++g) {
+    const BiState& st = hs[g];
+    all = all && !st.any;
+    SegResult& sr = R.seg[g];
+    sr.status = 0;
+    for (int c = 0; c < ncomp; ++c) {
+      sr.iters[c] = st.iters[c];
+      sr.res[c] = st.res[c];
+      sr.status = std::max(sr.status, st.active[c] ? (int)DIFVM_WARN_NOT_CONVERGED : st.status[c]);
+      R.iters[c] = std::max(R.iters[c], st.iters[c]);
+      R.res[c] = std::max(R.res[c], st.res[c]);
+    }
+    R.status = std::max(R.status, sr.status);
+  }
+  if (complete) *complete = all;
+  return R;
+}
+
 template <int NC>
-static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit) {
+static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
+                               const QueueOnly* qo) {
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
   Tiles T = tiles_of(m);
   int G = T.ntile, nseg = m->d.nseg;
-  std::vector<BiState> init(nseg);
-  for (auto& st : init) {
-    st = BiState{};
-    st.tol = tol;
-    st.maxit = maxit;
-  }
-  DIFVM_HIP(hipMemcpyAsync(w->bi, init.data(), sizeof(BiState) * nseg, hipMemcpyHostToDevice, s));
+  k_bi_state_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->bi, nseg, tol, maxit);
   double* part = w->partials;
   k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, T, b, x, w->r, w->rh, w->p, w->v, part);
   k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
   k_bi_zero<NC><<<G, BLOCK, 0, s>>>(T, x, w->bi);
   DIFVM_HIP(hipGetLastError());
   int done = 0;
-  int nb = std::min(maxit, std::max(2, w->bi_hint - 1));
+  int nb = qo ? std::min(qo->budget, maxit) : std::min(maxit, std::max(2, w->bi_hint - 1));
   const BiState* hs = nullptr;
   while (true) {
     for (int k = 0; k < nb; ++k) {
@@ -764,6 +831,10 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
       k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
     }
     DIFVM_HIP(hipGetLastError());
+    if (qo) {
+      copy_state(qo->state_out, w->bi, bicgstab_state_bytes(m), s);
+      return SolveResult{};
+    }
     done += nb;
     hs = fetch_states<BiState>(m, w, w->bi);
     bool any = false;
@@ -771,29 +842,15 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
     if (done >= maxit || !any) break;
     nb = std::min(2, maxit - done);
   }
-  SolveResult R;
-  R.seg.resize(nseg);
-  w->bi_hint = 0;
-  for (int g = 0; g < nseg; ++g) {
-    const BiState& st = hs[g];
-    SegResult& sr = R.seg[g];
-    sr.status = 0;
-    for (int c = 0; c < NC; ++c) {
-      sr.iters[c] = st.iters[c];
-      sr.res[c] = st.res[c];
-      sr.status = std::max(sr.status, st.active[c] ? (int)DIFVM_WARN_NOT_CONVERGED : st.status[c]);
-      R.iters[c] = std::max(R.iters[c], st.iters[c]);
-      R.res[c] = std::max(R.res[c], st.res[c]);
-      w->bi_hint = std::max(w->bi_hint, st.iters[c]);
-    }
-    R.status = std::max(R.status, sr.status);
-  }
+  SolveResult R = bicgstab_result(m, NC, hs, nullptr);
+  w->bi_hint = std::max(R.iters[0], std::max(R.iters[1], R.iters[2]));
   return R;
 }
 
-SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit) {
-  if (ncomp == 1) return bicgstab_nc<1>(m, A, b, x, tol, maxit);
-  return bicgstab_nc<3>(m, A, b, x, tol, maxit);
+SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
+                     const QueueOnly* qo) {
+  if (ncomp == 1) return bicgstab_nc<1>(m, A, b, x, tol, maxit, qo);
+  return bicgstab_nc<3>(m, A, b, x, tol, maxit, qo);
 }
 
 }  // namespace difvm

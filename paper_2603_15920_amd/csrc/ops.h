@@ -51,7 +51,22 @@ void krylov_work_free(KrylovWork* w);
 
 // x holds the initial guess; extra_rhs (may be NULL) is subtracted from b as (b - scale_cell * extra)
 // per component: used by the predictor for b - V grad(p).
-SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit);
-SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit);
+// Queue-only solves (for a captured step): min(budget, maxit) iterations are queued with no host
+// synchronisation (iterations after a segment's stop are predicated no-ops) and the per-segment
+// solver state is copied to state_out (device, *_state_bytes(m) bytes) at the end; the caller reads
+// it back later and turns it into results with *_result, whose `complete` is false when some segment
+// had not stopped within the budget.
+struct QueueOnly {
+  int budget;
+  void* state_out;
+};
+SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
+                const QueueOnly* qo = nullptr);
+SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
+                     const QueueOnly* qo = nullptr);
+size_t pcg_state_bytes(const difvm_mesh* m);
+size_t bicgstab_state_bytes(const difvm_mesh* m);
+SolveResult pcg_result(const difvm_mesh* m, const void* host_state, bool* complete);
+SolveResult bicgstab_result(const difvm_mesh* m, int ncomp, const void* host_state, bool* complete);
 
 }  // namespace difvm

@@ -390,10 +390,13 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
   *out = P;
 }
 
+void piso_graph_free(difvm_piso* P);
+
 void piso_release(difvm_piso* P) {
   if (!P || --P->refs > 0) return;
   difvm_mesh* m = P->mesh;
   (void)hipStreamSynchronize(stream_of(m));
+  piso_graph_free(P);
   for (void* a : P->allocs) dfree(a);
   delete P;
   mesh_release(m);
@@ -474,7 +477,40 @@ void dcopy(double* dst, const double* src, size_t n, hipStream_t s) {
   DIFVM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
 }
 
-void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
+static void set_seg_stats_u(difvm_piso* P, const SolveResult& ru) {
+  for (size_t g = 0; g < P->seg_stats.size(); ++g) {
+    difvm_step_stats& sg = P->seg_stats[g];
+    sg = difvm_step_stats{};
+    for (int c = 0; c < 3; ++c) {
+      sg.it_u[c] = ru.seg[g].iters[c];
+      sg.res_u[c] = ru.seg[g].res[c];
+    }
+    sg.status = ru.seg[g].status;
+  }
+}
+
+static void set_seg_stats_p(difvm_piso* P, int corr, const SolveResult& rp) {
+  for (size_t g = 0; g < P->seg_stats.size(); ++g) {
+    difvm_step_stats& sg = P->seg_stats[g];
+    sg.it_p[corr] = rp.seg[g].iters[0];
+    sg.res_p[corr] = rp.seg[g].res[0];
+    sg.status = std::max(sg.status, rp.seg[g].status);
+  }
+}
+
+struct StepQueue;
+void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const StepQueue* qu);
+
+// Queue-only variant of a step for capture: solves queue fixed budgets and leave their states in
+// P->g.state_dev; nothing is read back.
+struct StepQueue {
+  QueueOnly u;
+  QueueOnly p[StepRecord::MAXC];
+};
+
+void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) { piso_advance_q(P, stp, rec, nullptr); }
+
+void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const StepQueue* qu) {
   difvm_mesh* m = P->mesh;
   const DMesh& d = m->d;
   hipStream_t s = stream_of(m);
@@ -500,15 +536,10 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
   k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
   DIFVM_HIP(hipGetLastError());
-  SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u);
+  SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u, qu ? &qu->u : nullptr);
   for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
   st.status = ru.status;
-  for (int g = 0; g < d.nseg; ++g) {
-    difvm_step_stats& sg = P->seg_stats[g];
-    sg = difvm_step_stats{};
-    for (int c = 0; c < 3; ++c) { sg.it_u[c] = ru.seg[g].iters[c]; sg.res_u[c] = ru.seg[g].res[c]; }
-    sg.status = ru.seg[g].status;
-  }
+  if (!qu) set_seg_stats_u(P, ru);
   if (rec) {
     dcopy(rec->dM, P->dM, nc, s);
     dcopy(rec->valM, P->valM, d.nslot, s);
@@ -531,16 +562,11 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
     k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->is_ref, prm.p_ref_value, P->dK, P->valK,
                                      P->rhsK);
     DIFVM_HIP(hipGetLastError());
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p);
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p, qu ? &qu->p[corr] : nullptr);
     st.it_p[corr] = rp.iters[0];
     st.res_p[corr] = rp.res[0];
     st.status = std::max(st.status, rp.status);
-    for (int g = 0; g < d.nseg; ++g) {
-      difvm_step_stats& sg = P->seg_stats[g];
-      sg.it_p[corr] = rp.seg[g].iters[0];
-      sg.res_p[corr] = rp.seg[g].res[0];
-      sg.status = std::max(sg.status, rp.seg[g].status);
-    }
+    if (!qu) set_seg_stats_p(P, corr, rp);
     k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
     k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
     DIFVM_HIP(hipGetLastError());
@@ -552,11 +578,183 @@ void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) {
   if (stp) *stp = st;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Graph mode.  The step (Windkessel, assembly, BiCGStab, correctors) is captured once on a private
+// stream with a fixed iteration budget per solve and replayed with one hipGraphLaunch per step; the
+// host reads the solver states once per step.  Iterations past a solve's stop are predicated no-ops,
+// so a replay computes what the eager step computes.  A replay in which some solve had not stopped
+// within its budget is discarded: the state saved by the graph's first node is restored and the
+// step is run eagerly, then the graph is recaptured with budgets from the new counts.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_dcopy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[q];
+}
+static void dcopy_k(double* dst, const double* src, size_t n, hipStream_t s) {
+  if (!n) return;
+  k_dcopy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n);
+  DIFVM_HIP(hipGetLastError());
+}
+
+static size_t state_words(const DMesh& d) { return 4 * (size_t)d.nc + d.nfi + d.nfb + std::max(1, d.n_wk); }
+
+// save (to backup) or restore (from backup) U, p, phi, pc
+static void backup_state(difvm_piso* P, bool save, hipStream_t s) {
+  const DMesh& d = P->mesh->d;
+  double* b = P->g.backup;
+  size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb, nw = std::max(1, d.n_wk);
+  double* dev[4] = {P->U, P->p, P->phi, P->pc};
+  size_t len[4] = {3 * nc, nc, nf, nw};
+  for (int k = 0; k < 4; ++k) {
+    if (save) dcopy_k(b, dev[k], len[k], s);
+    else dcopy_k(dev[k], b, len[k], s);
+    b += len[k];
+  }
+}
+
+static void graph_drop(PisoGraph& G) {
+  if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  if (G.graph) (void)hipGraphDestroy(G.graph);
+  G.exec = nullptr;
+  G.graph = nullptr;
+}
+
+void piso_graph_free(difvm_piso* P) {
+  PisoGraph& G = P->g;
+  graph_drop(G);
+  if (G.cap) (void)hipStreamDestroy(G.cap);
+  if (G.state_host) (void)hipHostFree(G.state_host);
+  G.cap = nullptr;
+  G.state_host = nullptr;
+  // state_dev and backup are in P->allocs
+}
+
+static void graph_capture(difvm_piso* P) {
+  PisoGraph& G = P->g;
+  difvm_mesh* m = P->mesh;
+  Ctx& c = ctx_of(m);
+  StepQueue qu;
+  char* st = static_cast<char*>(G.state_dev);
+  qu.u = QueueOnly{G.budget_u, st};
+  for (int k = 0; k < P->prm.n_corr; ++k) qu.p[k] = QueueOnly{G.budget_p[k], st + G.bytes_u + k * G.bytes_p};
+  hipStream_t orig = c.stream;
+  c.stream = G.cap;
+  c.capturing = true;
+  DIFVM_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+  try {
+    backup_state(P, true, G.cap);
+    piso_advance_q(P, nullptr, nullptr, &qu);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(G.cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c.stream = orig;
+    c.capturing = false;
+    throw;
+  }
+  hipError_t e = hipStreamEndCapture(G.cap, &G.graph);
+  c.stream = orig;
+  c.capturing = false;
+  DIFVM_HIP(e);
+  DIFVM_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+  G.captures++;
+}
+
+static void set_budgets(difvm_piso* P, const difvm_step_stats& st, bool grow_only) {
+  PisoGraph& G = P->g;
+  int bu = std::max(st.it_u[0], std::max(st.it_u[1], st.it_u[2])) + G.extra;
+  G.budget_u = grow_only ? std::max(G.budget_u, bu) : bu;
+  for (int k = 0; k < P->prm.n_corr; ++k) {
+    int bp = st.it_p[k] + G.extra;
+    G.budget_p[k] = grow_only ? std::max(G.budget_p[k], bp) : bp;
+  }
+}
+
+static void graph_step(difvm_piso* P, difvm_step_stats* out) {
+  PisoGraph& G = P->g;
+  difvm_mesh* m = P->mesh;
+  hipStream_t s = stream_of(m);
+  difvm_step_stats st{};
+  if (!G.exec) {
+    // learn the iteration counts eagerly, then capture with budgets from them
+    piso_advance(P, &st, nullptr);
+    set_budgets(P, st, false);
+    graph_capture(P);
+    *out = st;
+    return;
+  }
+  DIFVM_HIP(hipGraphLaunch(G.exec, s));
+  size_t bytes = G.bytes_u + (size_t)P->prm.n_corr * G.bytes_p;
+  DIFVM_HIP(hipMemcpyAsync(G.state_host, G.state_dev, bytes, hipMemcpyDeviceToHost, s));
+  DIFVM_HIP(hipStreamSynchronize(s));
+  G.replays++;
+  const char* hs = static_cast<const char*>(G.state_host);
+  bool ok = true, c1 = true;
+  SolveResult ru = bicgstab_result(m, 3, hs, &c1);
+  ok = ok && c1;
+  SolveResult rp[StepRecord::MAXC];
+  for (int k = 0; k < P->prm.n_corr; ++k) {
+    rp[k] = pcg_result(m, hs + G.bytes_u + k * G.bytes_p, &c1);
+    ok = ok && c1;
+  }
+  if (!ok) {
+    // some solve needed more than its budget: discard the replay, redo the step eagerly
+    backup_state(P, false, s);
+    piso_advance(P, &st, nullptr);
+    set_budgets(P, st, true);
+    graph_drop(G);
+    graph_capture(P);
+    G.redos++;
+    *out = st;
+    return;
+  }
+  for (int c = 0; c < 3; ++c) {
+    st.it_u[c] = ru.iters[c];
+    st.res_u[c] = ru.res[c];
+  }
+  st.status = ru.status;
+  set_seg_stats_u(P, ru);
+  for (int k = 0; k < P->prm.n_corr; ++k) {
+    st.it_p[k] = rp[k].iters[0];
+    st.res_p[k] = rp[k].res[0];
+    st.status = std::max(st.status, rp[k].status);
+    set_seg_stats_p(P, k, rp[k]);
+  }
+  *out = st;
+}
+
+void piso_set_graph(difvm_piso* P, int enable, int extra) {
+  DIFVM_CHECK(extra >= 0, DIFVM_ERR_INVALID_ARG, "extra_iters must be >= 0");
+  PisoGraph& G = P->g;
+  graph_drop(G);
+  G.on = enable != 0;
+  G.extra = extra;
+  if (!G.on) return;
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  if (!G.cap) DIFVM_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  G.bytes_u = bicgstab_state_bytes(m);
+  G.bytes_p = pcg_state_bytes(m);
+  size_t bytes = G.bytes_u + (size_t)StepRecord::MAXC * G.bytes_p;
+  if (!G.state_dev) {
+    G.state_dev = piso_alloc(P, (bytes + 7) / 8);
+    G.backup = piso_alloc(P, state_words(d));
+    DIFVM_HIP(hipHostMalloc(&G.state_host, bytes, hipHostMallocDefault));
+  }
+}
+
+void piso_graph_info(const difvm_piso* P, long long* replays, long long* redos, long long* captures) {
+  if (replays) *replays = P->g.replays;
+  if (redos) *redos = P->g.redos;
+  if (captures) *captures = P->g.captures;
+}
+
 int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats) {
   int worst = 0;
   for (int step = 0; step < nsteps; ++step) {
     difvm_step_stats st{};
-    piso_advance(P, &st, nullptr);
+    if (P->g.on) graph_step(P, &st);
+    else piso_advance(P, &st, nullptr);
     worst = std::max(worst, st.status);
     if (stats) stats[step] = st;
   }

@@ -3,6 +3,21 @@
 
 #include "internal.h"
 
+// Captured step (graph mode): the whole step as one hipGraph with a fixed iteration budget per solve
+struct PisoGraph {
+  bool on = false;
+  int extra = 16;                       // iterations added to the last counts to form the budgets
+  int budget_u = 0, budget_p[8] = {};
+  hipStream_t cap = nullptr;            // private stream the step is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* state_dev = nullptr;            // solver states after each solve (BiCGStab, then each PCG)
+  void* state_host = nullptr;           // pinned copy
+  size_t bytes_u = 0, bytes_p = 0;
+  double* backup = nullptr;             // U, p, phi, pc before the step
+  long long replays = 0, redos = 0, captures = 0;
+};
+
 struct difvm_piso {
   difvm_mesh* mesh = nullptr;
   difvm_piso_params prm{};
@@ -19,6 +34,7 @@ struct difvm_piso {
   std::vector<void*> allocs;
   std::vector<double> wk_host;  // Rp, C, Rd per id
   int refs = 1;                 // the caller's handle plus one per tape
+  PisoGraph g;
 };
 
 

@@ -1,0 +1,140 @@
+"""Graph mode of the PISO step: the captured step replayed with hipGraphLaunch must give, after every
+step, bitwise the state and solver statistics of eager stepping from the same start, with the
+program's own eager work and synchronisations between replays; also when a solve outruns its
+iteration budget (the replay is discarded and the step redone), when boundary or Windkessel values
+change between steps, and for a packed batch of meshes."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15920_amd import binding as B
+from paper_2603_15920_amd import meshgen as mg
+
+from gpu_util import ctx, dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def lid(m, u=1.0):
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    p = m.patch("lid")
+    Ub[p.start - m.n_internal_faces:p.start - m.n_internal_faces + p.size, 0] = u
+    return Ub
+
+
+def make(m, Ub, nu, dt, wk=(), pc0=(), seg=None, nus=None):
+    M = B.Mesh(ctx(), m, seg_cell_start=seg)
+    P = B.Piso(M, B.piso_params(nu, dt))
+    if nus is not None:
+        P.set_viscosity(nus)
+    P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    for j, row in enumerate(wk):
+        P.set_windkessel(j, *row, pc0[j])
+    U0 = np.zeros((m.n_cells, 3))
+    P.set_state(dev(U0), dev(np.zeros(m.n_cells)), dev(O.initial_flux(m, U0, Ub)))
+    return M, P
+
+
+def same_state(Pa, Pb):
+    a, b = Pa.get_state(), Pb.get_state()
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(host(x), host(y))
+    np.testing.assert_array_equal(a[3], b[3])
+
+
+def run_pair(Pe, Pg, nsteps, between=None):
+    for s in range(nsteps):
+        if between:
+            between(s, Pe)
+            between(s, Pg)
+        ste, ite, rese = Pe.step(1)
+        stg, itg, resg = Pg.step(1)
+        assert ste == stg == 0
+        np.testing.assert_array_equal(itg, ite)
+        np.testing.assert_array_equal(resg, rese)
+        same_state(Pe, Pg)
+
+
+def test_cavity_graph_equals_eager():
+    m = mg.cavity(16)
+    Ub = lid(m)
+    _, Pe = make(m, Ub, 0.01, 1e-3)
+    _, Pg = make(m, Ub, 0.01, 1e-3)
+    Pg.set_graph(True, 16)
+    note("graph cavity", m.n_cells)
+    run_pair(Pe, Pg, 10)
+    replays, redos, captures = Pg.graph_info()
+    assert captures >= 1 and replays + redos == 9, (replays, redos, captures)
+    assert replays >= 5
+
+
+def test_graph_redo_when_budget_exceeded():
+    """Zero extra iterations and a rough random state set mid-run (a far worse initial guess than any
+    step before): the replay must exceed its budget, be discarded and redone, and the states still
+    match eager stepping."""
+    m = mg.cavity(16)
+    Ub = lid(m)
+    _, Pe = make(m, Ub, 0.01, 1e-3)
+    _, Pg = make(m, Ub, 0.01, 1e-3)
+    Pg.set_graph(True, 0)
+    rng = np.random.default_rng(9)
+    Ur = rng.standard_normal((m.n_cells, 3))
+    Ur[:, 2] = 0.0
+    pr = 100.0 * rng.standard_normal(m.n_cells)
+
+    def between(s, P):
+        if s == 4:
+            P.set_state(dev(Ur), dev(pr), None)
+    note("graph redo", m.n_cells)
+    run_pair(Pe, Pg, 8, between)
+    replays, redos, captures = Pg.graph_info()
+    assert redos >= 1 and captures == 1 + redos, (replays, redos, captures)
+
+
+def test_windkessel_channel_graph_with_parameter_change():
+    m = mg.kuhn_cube(3, jitter=0.15, patches="channel", seed=61, nxyz=(6, 3, 3), hi=(2.0, 1.0, 1.0))
+    Ub = mg.box_channel_inlet(m)
+    wk = np.array([[0.4, 0.3, 1.5]])
+    _, Pe = make(m, Ub, 0.01, 5e-3, wk, [0.1])
+    _, Pg = make(m, Ub, 0.01, 5e-3, wk, [0.1])
+    Pg.set_graph(True, 8)
+
+    def between(s, P):
+        if s == 3:
+            P.set_windkessel(0, 0.8, 0.2, 2.5, 0.05)
+    note("graph windkessel", m.n_cells)
+    run_pair(Pe, Pg, 7, between)
+    assert Pg.graph_info()[0] >= 3
+
+
+def test_packed_batch_graph_equals_eager():
+    ms = [mg.cavity(8), mg.kuhn_cube(3, jitter=0.15, patches="channel", seed=61, nxyz=(6, 3, 3), hi=(2.0, 1.0, 1.0)),
+          mg.cavity(8, seed=77)]
+    P, starts = mg.pack(ms)
+    Ub = np.concatenate([lid(ms[0]), mg.box_channel_inlet(ms[1]), lid(ms[2])])
+    wk, pc0, nus = np.array([[0.4, 0.3, 1.5]]), [0.1], np.array([0.01, 0.01, 0.02])
+    _, Pe = make(P, Ub, 0.01, 2e-3, wk, pc0, starts, nus)
+    _, Pg = make(P, Ub, 0.01, 2e-3, wk, pc0, starts, nus)
+    Pg.set_graph(True, 8)
+    note("graph packed", P.n_cells)
+    for s in range(6):
+        Pe.step(1)
+        Pg.step(1)
+        same_state(Pe, Pg)
+        for a, b in zip(Pe.segment_stats(), Pg.segment_stats()):
+            np.testing.assert_array_equal(a, b)
+    assert Pg.graph_info()[0] >= 3
+
+
+def test_graph_errors_and_off():
+    m = mg.cavity(8)
+    _, P = make(m, lid(m), 0.01, 1e-3)
+    with pytest.raises(B.DifvmError) as e:
+        P.set_graph(True, -1)
+    assert e.value.status == B.ERR_INVALID_ARG
+    P.set_graph(True, 4)
+    P.step(3)
+    P.set_graph(False)
+    r0 = P.graph_info()[0]
+    P.step(2)
+    assert P.graph_info()[0] == r0
