@@ -175,6 +175,37 @@ difvm_status difvm_mesh_create_segments(difvm_ctx* ctx, const difvm_mesh_desc* d
 difvm_status difvm_mesh_get_info(const difvm_mesh* mesh, difvm_mesh_info* info);
 difvm_status difvm_mesh_destroy(difvm_mesh* mesh); /* NULL is a no-op; waits for the stream */
 
+/* ---- launch tuning (autotuner) ------------------------------------------------------------
+ * Knobs that change how work is spread over the GPU but not what any output computes: threads per
+ * block of the operator kernels (one cell or face per thread, no reductions), and the grid of the
+ * PCG product kernel (one block per 1024-cell tile, or a persistent grid whose blocks walk several
+ * tiles; every tile's partial sum is formed the same way).  Outputs are bitwise identical for every
+ * value.  Each mesh starts with 256 threads and one block per tile. */
+enum {
+  DIFVM_TUNE_INTERP_F64 = 0, DIFVM_TUNE_INTERP_F32 = 1,
+  DIFVM_TUNE_GRAD_F64 = 2, DIFVM_TUNE_GRAD_F32 = 3,
+  DIFVM_TUNE_DIV_F64 = 4, DIFVM_TUNE_DIV_F32 = 5,
+  DIFVM_TUNE_LAPLACIAN_F64 = 6, DIFVM_TUNE_LAPLACIAN_F32 = 7,
+  DIFVM_TUNE_LDU_SPMV_F64 = 8, DIFVM_TUNE_LDU_SPMV_F32 = 9,
+  DIFVM_TUNE_PCG_GRID = 10,
+  DIFVM_TUNE_COUNT = 11
+};
+
+/* Sets one knob: operator knobs take 64, 128, 256 or 512 (threads per block); DIFVM_TUNE_PCG_GRID
+ * takes 0 (one block per tile) or a multiple of 8 (persistent grid; values >= the tile count mean
+ * one block per tile).  Other values or knobs: DIFVM_ERR_INVALID_ARG. */
+difvm_status difvm_mesh_set_launch(difvm_mesh* mesh, int32_t knob, int32_t value);
+difvm_status difvm_mesh_get_launch(const difvm_mesh* mesh, int32_t knob, int32_t* value);
+
+/* Autotuner: for every knob, times each candidate value on this mesh (HIP events on the context's
+ * stream, scratch inputs allocated and freed here, one warm-up and repeated launches) and keeps the
+ * fastest.  cache_path (may be NULL) names a JSON file of choices keyed by GPU architecture, knob and
+ * mesh size bucket (floor(log2(cells)), and whether the mesh has one or several segments): knobs
+ * found there are applied without timing, the others are timed and the file is rewritten with them
+ * added.  n_timed (may be NULL) receives the number of knobs timed.  Synchronises.  Errors:
+ * DIFVM_ERR_INVALID_ARG for an unreadable or unwritable cache file. */
+difvm_status difvm_tune(difvm_mesh* mesh, const char* cache_path, int32_t* n_timed);
+
 /* Reorders a field between user and internal order (device arrays, src != dst). */
 difvm_status difvm_permute(const difvm_mesh* mesh, int dtype, int ncomp, int kind, int dir, const void* src,
                            void* dst);

@@ -22,6 +22,9 @@ KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
 TO_INTERNAL, FROM_INTERNAL = 0, 1
 RENUMBER_RCM = 1
 OK, WARN_NOT_CONVERGED, WARN_BREAKDOWN = 0, 1, 2
+TUNE_KNOBS = ["interp_f64", "interp_f32", "grad_f64", "grad_f32", "div_f64", "div_f32", "laplacian_f64",
+              "laplacian_f32", "ldu_spmv_f64", "ldu_spmv_f32", "pcg_grid"]
+TUNE_PCG_GRID = 10
 ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED, ERR_NONFINITE = -1, -2, -3, -4, -5, -6
 
 _i32p = C.POINTER(C.c_int32)
@@ -91,6 +94,9 @@ _SIGS = {
     "difvm_mesh_create_segments": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.c_int32, _i32p,
                                                C.POINTER(_vp)]),
     "difvm_mesh_get_info": (C.c_int32, [_vp, C.POINTER(MeshInfo)]),
+    "difvm_mesh_set_launch": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "difvm_mesh_get_launch": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "difvm_tune": (C.c_int32, [_vp, C.c_char_p, C.POINTER(C.c_int32)]),
     "difvm_mesh_destroy": (C.c_int32, [_vp]),
     "difvm_permute": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp]),
     "difvm_op_interp": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
@@ -248,6 +254,24 @@ def difvm_mesh_create_segments(ctx, mesh, seg_cell_start, flags=RENUMBER_RCM):
     _check(lib().difvm_mesh_create_segments(ctx, C.byref(h.desc), int(flags), int(starts.size - 1),
                                             starts.ctypes.data_as(_i32p), C.byref(out)), "difvm_mesh_create_segments")
     return out
+
+
+def difvm_mesh_set_launch(m, knob, value):
+    _check(lib().difvm_mesh_set_launch(m, int(knob), int(value)), "difvm_mesh_set_launch")
+
+
+def difvm_mesh_get_launch(m, knob):
+    v = C.c_int32(0)
+    _check(lib().difvm_mesh_get_launch(m, int(knob), C.byref(v)), "difvm_mesh_get_launch")
+    return v.value
+
+
+def difvm_tune(m, cache_path=None):
+    """Autotunes the mesh's launch knobs (cache_path: JSON cache file or None); returns knobs timed."""
+    n = C.c_int32(0)
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().difvm_tune(m, path, C.byref(n)), "difvm_tune")
+    return n.value
 
 
 def difvm_mesh_get_info(m):

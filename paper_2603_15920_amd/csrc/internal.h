@@ -131,6 +131,7 @@ struct difvm_mesh {
   std::vector<void*> allocs;                 // device allocations owned by the mesh
   difvm::KrylovWork* krylov = nullptr;       // solver workspace, created on first solve
   int refs = 1;
+  int tune[DIFVM_TUNE_COUNT] = {256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 0};  // launch knobs
 };
 
 namespace difvm {

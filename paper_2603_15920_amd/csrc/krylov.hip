@@ -200,6 +200,7 @@ __device__ __forceinline__ void put_partial(double (&v)[NV], double* __restrict_
 // even while the segment's first tile of the same launch may be writing it
 __device__ __forceinline__ bool block_flag(const int* flag) {
   __shared__ int f;
+  __syncthreads();  // a previous call's readers are done with f
   if (threadIdx.x == 0) f = *flag;
   __syncthreads();
   return f != 0;
@@ -305,68 +306,101 @@ __device__ __forceinline__ double dir_row(const SellView& A, int base, double ac
   return acc;
 }
 
+// Tiles of this block: one tile per block when the grid has one block per tile (XCD-aware order),
+// otherwise (a grid of G < ntile blocks, G a multiple of 8) block b walks tiles lo + b/8, lo + b/8 +
+// G/8, ... of the contiguous eighth of the tiles that its XCD (b mod 8) owns.  Which block computes a
+// tile does not change the tile's arithmetic or its partial.
+struct TileWalk {
+  int t, step, end;
+};
+__device__ __forceinline__ TileWalk tile_walk(int ntile) {
+  int b = blockIdx.x, G = gridDim.x;
+  if (G >= ntile) {
+    int t = xcd_tile(b, G);
+    return {t, 1, t + 1};
+  }
+  int x = b & 7, per = G >> 3;
+  int lo = (int)((long long)ntile * x / 8), hi = (int)((long long)ntile * (x + 1) / 8);
+  return {lo + (b >> 3), per, hi};
+}
+
 // iteration k >= 1: stopping test of iterate k-1, then p_k and q = A p_k
 __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, int k, const double* __restrict__ z,
                                                           const double* __restrict__ p_prev, double* __restrict__ p_cur,
                                                           double* __restrict__ q, const double* __restrict__ partB,
                                                           double* __restrict__ partA, PcgCtl* ctls) {
   constexpr int NT = PCG_SPMV_NT, C = TILE / NT;
-  TileIdx ti = tile_idx(T);
-  PcgCtl* ctl = ctls + ti.s;
-  if (block_flag(&ctl->done)) return;
-  bool lead = ti.t == T.first[ti.s] && threadIdx.x == 0;
-  double s2[2];
-  sum_seg<2, NT>(partB, T, ti.s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
-  double rho = s2[1];
-  if (lead) ctl->rho[(k - 1) & 1] = rho;
+  TileWalk tw = tile_walk(T.ntile);
+  int cur = -1;
+  bool skip = true;
   double beta = 0.0;
-  if (k >= 2) {
-    double rn = sqrt(s2[0]), bn = ctl->bn;
-    bool conv = rn <= ctl->tol * bn;
-    if (conv || k - 1 >= ctl->maxit) {
-      if (lead) {
-        ctl->done = 1;
-        ctl->iters = k - 1;
-        ctl->res = rn / bn;
-        ctl->status = conv ? 0 : DIFVM_WARN_NOT_CONVERGED;
-      }
-      return;
-    }
-    beta = rho / ctl->rho[k & 1];  // rho_{k-1} / rho_{k-2}
-  } else if (ctl->maxit <= 0) {
-    if (lead) {
-      ctl->done = 1;
-      ctl->status = DIFVM_WARN_NOT_CONVERGED;
-    }
-    return;
-  }
-  double v[1] = {0.0};
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    int i = ti.lo + c * NT + threadIdx.x;
-    if (i < ti.hi) {
-      double pi = z[i] + beta * p_prev[i];
-      SlotRange R = slots_of(A.slice_start, i);
-      const int nrow = row_len(A.nslot, i, R);
-      double acc = A.diag[i] * pi;
-      switch (nrow) {
-        case 3: acc = dir_row<3>(A, R.base, acc, beta, z, p_prev); break;
-        case 4: acc = dir_row<4>(A, R.base, acc, beta, z, p_prev); break;
-        case 5: acc = dir_row<5>(A, R.base, acc, beta, z, p_prev); break;
-        case 6: acc = dir_row<6>(A, R.base, acc, beta, z, p_prev); break;
-        default:
-          for (int sl = 0; sl < nrow; ++sl) {
-            int at = R.base + sl * SLICE;
-            int j = A.col[at];
-            acc += A.val[at] * (z[j] + beta * p_prev[j]);
+  for (int t = tw.t; t < tw.end; t += tw.step) {
+    int s = T.seg[t];
+    if (s != cur) {
+      // first tile of segment s for this block: the segment's stopping test and beta
+      cur = s;
+      PcgCtl* ctl = ctls + s;
+      skip = block_flag(&ctl->done);
+      if (!skip) {
+        bool lead = t == T.first[s] && threadIdx.x == 0;  // the block holding the segment's first tile
+        double s2[2];
+        sum_seg<2, NT>(partB, T, s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+        double rho = s2[1];
+        if (lead) ctl->rho[(k - 1) & 1] = rho;
+        beta = 0.0;
+        if (k >= 2) {
+          double rn = sqrt(s2[0]), bn = ctl->bn;
+          bool conv = rn <= ctl->tol * bn;
+          if (conv || k - 1 >= ctl->maxit) {
+            if (lead) {
+              ctl->done = 1;
+              ctl->iters = k - 1;
+              ctl->res = rn / bn;
+              ctl->status = conv ? 0 : DIFVM_WARN_NOT_CONVERGED;
+            }
+            skip = true;
+          } else {
+            beta = rho / ctl->rho[k & 1];  // rho_{k-1} / rho_{k-2}
           }
+        } else if (ctl->maxit <= 0) {
+          if (lead) {
+            ctl->done = 1;
+            ctl->status = DIFVM_WARN_NOT_CONVERGED;
+          }
+          skip = true;
+        }
       }
-      p_cur[i] = pi;
-      q[i] = acc;
-      v[0] += pi * acc;
     }
+    if (skip) continue;
+    int lo = T.lo[t], hi = T.hi[t];
+    double v[1] = {0.0};
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int i = lo + c * NT + threadIdx.x;
+      if (i < hi) {
+        double pi = z[i] + beta * p_prev[i];
+        SlotRange R = slots_of(A.slice_start, i);
+        const int nrow = row_len(A.nslot, i, R);
+        double acc = A.diag[i] * pi;
+        switch (nrow) {
+          case 3: acc = dir_row<3>(A, R.base, acc, beta, z, p_prev); break;
+          case 4: acc = dir_row<4>(A, R.base, acc, beta, z, p_prev); break;
+          case 5: acc = dir_row<5>(A, R.base, acc, beta, z, p_prev); break;
+          case 6: acc = dir_row<6>(A, R.base, acc, beta, z, p_prev); break;
+          default:
+            for (int sl = 0; sl < nrow; ++sl) {
+              int at = R.base + sl * SLICE;
+              int j = A.col[at];
+              acc += A.val[at] * (z[j] + beta * p_prev[j]);
+            }
+        }
+        p_cur[i] = pi;
+        q[i] = acc;
+        v[0] += pi * acc;
+      }
+    }
+    put_partial<1, NT>(v, partA, T.ntile, t);
   }
-  put_partial<1, NT>(v, partA, T.ntile, ti.t);
 }
 
 // iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (streaming loads issued
@@ -431,6 +465,13 @@ static void copy_state(void* dst, const void* src, size_t bytes, hipStream_t s) 
 
 size_t pcg_state_bytes(const difvm_mesh* m) { return sizeof(PcgCtl) * m->d.nseg; }
 
+// grid of the product kernel: one block per tile, or the tuned persistent grid (a multiple of 8)
+int pcg_spmv_grid(const difvm_mesh* m) {
+  int nt = m->d.ntile, g = m->tune[DIFVM_TUNE_PCG_GRID];
+  if (g <= 0 || g >= nt) return nt;
+  return std::max(8, g & ~7);
+}
+
 SolveResult pcg_result(const difvm_mesh* m, const void* host_state, bool* complete) {
   const PcgCtl* hs = static_cast<const PcgCtl*>(host_state);
   int nseg = m->d.nseg;
@@ -466,6 +507,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   Tiles T = tiles_of(m);
   int G = T.ntile, nseg = m->d.nseg;
   k_pcg_ctl_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->pcg, nseg, tol, maxit);
+  const int GS = pcg_spmv_grid(m);
   double* r = w->r;
   double* q = w->q;
   double* z = w->z;
@@ -480,7 +522,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     // queue-only: iterations 1..K and the stopping test of iterate K, no read-back
     int K = std::min(qo->budget, maxit);
     for (int kk = 1; kk <= K + 1; ++kk) {
-      k_pcg_spmv<<<G, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
+      k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
       if (kk <= K) k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
     }
     DIFVM_HIP(hipGetLastError());
@@ -497,7 +539,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     for (; k <= last; ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<G, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
+        k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
       if (k > maxit) break;
       {
@@ -851,6 +893,78 @@ SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, do
                      const QueueOnly* qo) {
   if (ncomp == 1) return bicgstab_nc<1>(m, A, b, x, tol, maxit, qo);
   return bicgstab_nc<3>(m, A, b, x, tol, maxit, qo);
+}
+
+// ---------------------------------------------------------------------------------------------
+// timing of the product kernel for the autotuner: `reps` launches at iteration 2 on scratch data
+// (matrix values, vectors and partials set to constants, a control state that never stops), so no
+// solve state is involved; returns seconds per launch
+// ---------------------------------------------------------------------------------------------
+__global__ void k_fill_const(double* __restrict__ a, size_t n, double v) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) a[q] = v;
+}
+__global__ void k_tune_ctl(PcgCtl* ctls, int nseg) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  PcgCtl c{};
+  c.tol = 0.0;
+  c.bn = 1.0;
+  c.rho[0] = c.rho[1] = 1.0;
+  c.maxit = 1 << 30;
+  ctls[g] = c;
+}
+
+double time_pcg_spmv(difvm_mesh* m, int grid, int reps, hipEvent_t e0, hipEvent_t e1) {
+  KrylovWork* w = make_work(m);
+  hipStream_t s = stream_of(m);
+  const DMesh& d = m->d;
+  double* val = dalloc<double>(d.nslot);
+  double* diag = nullptr;
+  PcgCtl* ctl = nullptr;
+  double t = 0.0;
+  try {
+    diag = dalloc<double>(d.nc);
+    ctl = static_cast<PcgCtl*>(dmalloc(sizeof(PcgCtl) * d.nseg));
+    auto fill = [&](double* a, size_t n, double v) {
+      k_fill_const<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, n, v);
+    };
+    fill(val, d.nslot, -0.25);
+    fill(diag, d.nc, 4.0);
+    fill(w->z, d.nc, 1.0);
+    fill(w->p, d.nc, 1.0);
+    fill(w->partials, (size_t)8 * w->ntile, 1.0);
+    k_tune_ctl<<<(d.nseg + 63) / 64, 64, 0, s>>>(ctl, d.nseg);
+    DIFVM_HIP(hipGetLastError());
+    int old = m->tune[DIFVM_TUNE_PCG_GRID];
+    m->tune[DIFVM_TUNE_PCG_GRID] = grid;
+    int GS = pcg_spmv_grid(m);
+    m->tune[DIFVM_TUNE_PCG_GRID] = old;
+    SellView V{d.nc, d.cell_nslot, d.slice_start, d.slot_col, val, diag};
+    Tiles T = tiles_of(m);
+    double* partA = w->partials;
+    double* partB = w->partials + 2 * (size_t)T.ntile;
+    k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
+    DIFVM_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r)
+      k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
+    DIFVM_HIP(hipEventRecord(e1, s));
+    DIFVM_HIP(hipGetLastError());
+    DIFVM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DIFVM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    t = ms * 1e-3 / reps;
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    dfree(val);
+    dfree(diag);
+    dfree(ctl);
+    throw;
+  }
+  dfree(val);
+  dfree(diag);
+  dfree(ctl);
+  return t;
 }
 
 }  // namespace difvm

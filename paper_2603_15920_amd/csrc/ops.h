@@ -65,6 +65,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
 SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
                      const QueueOnly* qo = nullptr);
 size_t pcg_state_bytes(const difvm_mesh* m);
+int pcg_spmv_grid(const difvm_mesh* m);
 size_t bicgstab_state_bytes(const difvm_mesh* m);
 SolveResult pcg_result(const difvm_mesh* m, const void* host_state, bool* complete);
 SolveResult bicgstab_result(const difvm_mesh* m, int ncomp, const void* host_state, bool* complete);

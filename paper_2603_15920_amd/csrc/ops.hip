@@ -60,13 +60,18 @@ void permute(const difvm_mesh* m, int dtype, int ncomp, int kind, int dir, const
   else permute_t<float>(m, ncomp, kind, dir, (const float*)src, (float*)dst);
 }
 
+// largest threads-per-block a tuned operator kernel may be launched with (the knobs of
+// difvm_mesh_set_launch); one cell or face per thread, so the outputs do not depend on it
+constexpr int OP_MAX_BLOCK = 512;
+static int op_block(const difvm_mesh* m, int knob_f64, int dtype_is_f32) { return m->tune[knob_f64 + dtype_is_f32]; }
+
 // ---------------------------------------------------------------------------------------------
 // face interpolation (face kernel)
 // ---------------------------------------------------------------------------------------------
 template <class T, int NC>
-__global__ __launch_bounds__(BLOCK) void k_interp(MeshView<T> m, int table, const T* __restrict__ phi,
+__global__ __launch_bounds__(OP_MAX_BLOCK) void k_interp(MeshView<T> m, int table, const T* __restrict__ phi,
                                                   const T* __restrict__ phib, T* __restrict__ out) {
-  int f = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  int f = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (f < m.nfi) {
     T w = m.w[f];
     int O = m.own[f], N = m.nbr[f];
@@ -100,9 +105,9 @@ __device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_in
 // Gauss gradient (cell kernel): G_i = (1/V_i) sum_slots sigma phi_f S_f
 // ---------------------------------------------------------------------------------------------
 template <class T, int NC>
-__global__ __launch_bounds__(BLOCK) void k_grad(MeshView<T> m, int table, const T* __restrict__ phi,
+__global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table, const T* __restrict__ phi,
                                                 const T* __restrict__ phib, T* __restrict__ out) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
   T pi[NC], acc[NC][3];
@@ -173,9 +178,9 @@ __global__ __launch_bounds__(BLOCK) void k_grad(MeshView<T> m, int table, const 
 // face-sum divergence (cell kernel): D_i = sum_slots sigma F_f psi_f
 // ---------------------------------------------------------------------------------------------
 template <class T, int NC, int SCHEME>
-__global__ __launch_bounds__(BLOCK) void k_div(MeshView<T> m, int table, const T* __restrict__ flux,
+__global__ __launch_bounds__(OP_MAX_BLOCK) void k_div(MeshView<T> m, int table, const T* __restrict__ flux,
                                                const T* __restrict__ psi, const T* __restrict__ psib, T* __restrict__ out) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
   T pi[NC], acc[NC];
@@ -249,10 +254,10 @@ __global__ __launch_bounds__(BLOCK) void k_div(MeshView<T> m, int table, const T
 // Laplacian with over-relaxed correction (cell kernel)
 // ---------------------------------------------------------------------------------------------
 template <class T, bool GAMMA>
-__global__ __launch_bounds__(BLOCK) void k_laplacian(MeshView<T> m, int table, const T* __restrict__ gamma,
+__global__ __launch_bounds__(OP_MAX_BLOCK) void k_laplacian(MeshView<T> m, int table, const T* __restrict__ gamma,
                                                      const T* __restrict__ phi, const T* __restrict__ g,
                                                      const T* __restrict__ phib, T* __restrict__ out) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
   T pi = phi[i];
@@ -317,9 +322,9 @@ __global__ __launch_bounds__(BLOCK) void k_laplacian(MeshView<T> m, int table, c
 // LDU product through the slots (owner slot: upper, neighbour slot: lower)
 // ---------------------------------------------------------------------------------------------
 template <class T, int NC>
-__global__ __launch_bounds__(BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __restrict__ diag, const T* __restrict__ up,
+__global__ __launch_bounds__(OP_MAX_BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __restrict__ diag, const T* __restrict__ up,
                                                     const T* __restrict__ lo, const T* __restrict__ x, T* __restrict__ y) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
   T acc[NC];
@@ -405,8 +410,9 @@ void interp_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T*
   int n = d.nfi + d.nfb;
   if (!n) return;
   MeshView<T> v = view<T>(d);
-  if (ncomp == 1) k_interp<T, 1><<<grid_for(n), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
-  else k_interp<T, 3><<<grid_for(n), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  int nb = op_block(mm, DIFVM_TUNE_INTERP_F64, sizeof(T) == 4);
+  if (ncomp == 1) k_interp<T, 1><<<grid_for(n, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_interp<T, 3><<<grid_for(n, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -414,8 +420,9 @@ template <class T>
 void grad_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T* phib, T* out) {
   const DMesh& d = mm->d;
   MeshView<T> v = view<T>(d);
-  if (ncomp == 1) k_grad<T, 1><<<grid_for(d.nc), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
-  else k_grad<T, 3><<<grid_for(d.nc), BLOCK, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  int nb = op_block(mm, DIFVM_TUNE_GRAD_F64, sizeof(T) == 4);
+  if (ncomp == 1) k_grad<T, 1><<<grid_for(d.nc, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_grad<T, 3><<<grid_for(d.nc, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -423,11 +430,12 @@ template <class T, int NC>
 void div_nc(const difvm_mesh* mm, int scheme, int table, const T* flux, const T* psi, const T* psib, T* out) {
   const DMesh& d = mm->d;
   MeshView<T> v = view<T>(d);
-  int G = grid_for(d.nc);
+  int nb = op_block(mm, DIFVM_TUNE_DIV_F64, sizeof(T) == 4);
+  int G = grid_for(d.nc, nb);
   hipStream_t s = stream_of(mm);
-  if (scheme == DIFVM_SCHEME_ONE) k_div<T, NC, DIFVM_SCHEME_ONE><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
-  else if (scheme == DIFVM_SCHEME_UPWIND) k_div<T, NC, DIFVM_SCHEME_UPWIND><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
-  else k_div<T, NC, DIFVM_SCHEME_LINEAR><<<G, BLOCK, 0, s>>>(v, table, flux, psi, psib, out);
+  if (scheme == DIFVM_SCHEME_ONE) k_div<T, NC, DIFVM_SCHEME_ONE><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
+  else if (scheme == DIFVM_SCHEME_UPWIND) k_div<T, NC, DIFVM_SCHEME_UPWIND><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
+  else k_div<T, NC, DIFVM_SCHEME_LINEAR><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -435,9 +443,10 @@ template <class T>
 void laplacian_t(const difvm_mesh* mm, int table, const T* gamma, const T* phi, const T* g, const T* phib, T* out) {
   const DMesh& d = mm->d;
   MeshView<T> v = view<T>(d);
-  int G = grid_for(d.nc);
-  if (gamma) k_laplacian<T, true><<<G, BLOCK, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
-  else k_laplacian<T, false><<<G, BLOCK, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
+  int nb = op_block(mm, DIFVM_TUNE_LAPLACIAN_F64, sizeof(T) == 4);
+  int G = grid_for(d.nc, nb);
+  if (gamma) k_laplacian<T, true><<<G, nb, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
+  else k_laplacian<T, false><<<G, nb, 0, stream_of(mm)>>>(v, table, gamma, phi, g, phib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -450,9 +459,10 @@ void ldu_spmv_t(const difvm_mesh* mm, int ncomp, int transpose, const T* diag, c
   // the kernel reads entry 0 of up / lo on non-internal slots (value unused): with no internal faces
   // the caller may pass NULL, so point both at diag (nc >= 1 entries)
   if (d.nfi == 0) up = lo = diag;
-  int G = grid_for(d.nc);
-  if (ncomp == 1) k_ldu_spmv<T, 1><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
-  else k_ldu_spmv<T, 3><<<G, BLOCK, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
+  int nb = op_block(mm, DIFVM_TUNE_LDU_SPMV_F64, sizeof(T) == 4);
+  int G = grid_for(d.nc, nb);
+  if (ncomp == 1) k_ldu_spmv<T, 1><<<G, nb, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
+  else k_ldu_spmv<T, 3><<<G, nb, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
   DIFVM_HIP(hipGetLastError());
 }
 
