@@ -200,6 +200,47 @@ def timed(torch, fn):
     return time.perf_counter() - t, r
 
 
+def graph_rate(P, torch, steps, extra=16):
+    """Steps/s of the same PISO object in graph mode (one hipGraphLaunch per step; the first step
+    after enabling runs eagerly and captures, two more replays warm up)."""
+    P.set_graph(True, extra)
+    P.step(3)
+    t, (st, it, _) = timed(torch, lambda: P.step(steps))
+    replays, redos, captures = P.graph_info()
+    P.set_graph(False)
+    return {"steps_per_s": round(steps / t, 4), "steps": steps, "status": int(st), "replays": replays,
+            "redos": redos, "captures": captures, "extra_iters": extra}
+
+
+def small_case(B, mg, torch, ctx, steps=50):
+    """The small PISO case (lid-driven cavity, 2048 jittered triangle prisms, Re 100, nu 0.01,
+    dt 1e-3): launch-bound, so eager stepping against graph mode."""
+    import numpy as np
+    m = mg.cavity()
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    p = m.patch("lid")
+    Ub[p.start - m.n_internal_faces:p.start - m.n_internal_faces + p.size, 0] = 1.0
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    out = {"workload": f"cavity {m.n_cells} prisms, nu 0.01, dt 1e-3, 2 correctors, tol 1e-8", "cells": m.n_cells}
+    M = B.Mesh(ctx, m)
+    for mode in ("eager", "graph"):
+        P = B.Piso(M, B.piso_params(0.01, 1e-3))
+        P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+        P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
+        if mode == "graph":
+            P.set_graph(True, 16)
+        P.step(3)
+        t, (st, it, _) = timed(torch, lambda: P.step(steps))
+        out[f"{mode}_steps_per_s"] = round(steps / t, 2)
+        out[f"{mode}_status"] = int(st)
+        if mode == "graph":
+            out["graph_replays"], out["graph_redos"], _ = P.graph_info()
+        P.close()
+    out["pcg_iters_per_solve"] = round(float(it[:, 3:].mean()), 1)
+    out["graph_speedup"] = round(out["graph_steps_per_s"] / out["eager_steps_per_s"], 3)
+    return out
+
+
 def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10):
     """Differentiated form on the Y-bifurcation (~400k tets, 3 Windkessel outlets, nu 1e-3, dt 1e-3):
     after a short spin-up from rest, the plain forward, the recorded forward (checkpoints every
@@ -274,6 +315,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
     Pb.step(2)
     t_b, (st, it, _) = timed(torch, lambda: Pb.step(steps))
     seg_it, _, seg_st = Pb.segment_stats()
+    gr = graph_rate(Pb, torch, steps)
     t_seq = 0.0
     for d in mem:
         M, P = setup(d["mesh"], d["Ub"], d["wk"], [d["nu"]])
@@ -289,6 +331,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
            "batch_cell_steps_per_s": round(steps * Pm.n_cells / t_b, 0),
            "sequential_steps_per_s": round(steps / t_seq, 3),
            "speedup_vs_sequential": round(t_seq / t_b, 3),
+           "batch_graph_steps_per_s": gr["steps_per_s"], "batch_graph_redos": gr["redos"],
            "pcg_iters_max_member": int(seg_it[:, 3:].max()), "pcg_iters_min_member": int(seg_it[:, 3:].min()),
            "status": int(st)}
     if adj_steps > 0:
@@ -331,6 +374,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated-window measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-mesh batch measurement")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
     ap.add_argument("--adj-steps", type=int, default=20)
     ap.add_argument("--adj-every", type=int, default=10)
     ap.add_argument("--batch-members", type=int, default=64)
@@ -378,6 +423,12 @@ def main():
     U0, p0 = np.zeros((nc, 3)), np.zeros(nc)
     P.set_state(dev(U0), dev(p0), None)
     torch.cuda.synchronize()
+    tuned = None
+    if not args.no_tune:
+        tt = time.time()
+        B.difvm_tune(M.h, None)
+        tuned = {name: B.difvm_mesh_get_launch(M.h, k) for k, name in enumerate(B.TUNE_KNOBS)}
+        log(f"tuned launch shapes ({time.time() - tt:.2f}s)", tuned)
 
     first_step_s = None
     for k in range(args.warmup):
@@ -416,6 +467,14 @@ def main():
                 "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
                 "timed_every": args.prof_every, "active_iterations": int(pcg_iters)}
     kernel_us = {k: round(1e3 * v[1] / max(v[0], 1), 2) for k, v in prof.items()}
+
+    graph = None
+    small = None
+    if not args.no_graph:
+        graph = graph_rate(P, torch, args.steps)
+        log("graph mode", graph)
+        small = small_case(B, mg, torch, ctx)
+        log("small case", small)
 
     adjoint = None
     if not args.no_adjoint:
@@ -457,6 +516,9 @@ def main():
         "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
                    "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st)},
         "kernel_avg_us_timed_region": kernel_us,
+        "tuned_launch": tuned,
+        "graph_mode": graph,
+        "small_case": small,
         "adjoint": adjoint,
         "batched": batched,
         "operators": ops,
