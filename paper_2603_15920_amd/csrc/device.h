@@ -80,17 +80,22 @@ __device__ __forceinline__ int row_len(const uint8_t* __restrict__ nslot, int i,
   return n == 255 ? R.width : n;
 }
 
-// calls body(W) for a row of n slots: W in {3, 4, 5, 6} unrolled with all slot loads issued
-// together, W = 0 for any other n (one slot per pass)
-template <class F>
-__device__ __forceinline__ void by_width(int n, F&& body) {
-  switch (n) {
-    case 3: body(std::integral_constant<int, 3>{}); break;
-    case 4: body(std::integral_constant<int, 4>{}); break;
-    case 5: body(std::integral_constant<int, 5>{}); break;
-    case 6: body(std::integral_constant<int, 6>{}); break;
-    default: body(std::integral_constant<int, 0>{});
+// Walks a row of n slots in order: body(W, k0) handles slots k0 .. k0+W-1 with W a compile-time
+// count; the first min(n, CH) slots go in one unrolled chunk (all their loads issued together), the
+// rest one at a time.  CH bounds the registers a kernel allocates (its widest chunk sets them).
+template <int CH, class F>
+__device__ __forceinline__ void walk_row(int n, F&& body) {
+  int k0 = 0;
+  if (n >= CH) {
+    body(std::integral_constant<int, CH>{}, 0);
+    k0 = CH;
+  } else if constexpr (CH > 3) {
+    if (n == 3) {
+      body(std::integral_constant<int, 3>{}, 0);
+      k0 = 3;
+    }
   }
+  for (; k0 < n; ++k0) body(std::integral_constant<int, 1>{}, k0);
 }
 
 // ---------------------------------------------------------------------------------------------

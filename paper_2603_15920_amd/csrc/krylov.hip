@@ -224,8 +224,8 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
 //   upd_k:  alpha = rho_{k-1}/(p.q); x += alpha p; r -= alpha q; z = r/d   partials B
 // The segment's first tile records iterations / residual / status; its kernels return at once
 // after its stop.  The product runs 512 threads x 2 cells per 1024-cell tile, the update 256 x 4
-// (measured best on gfx950 for these two memory patterns); rows of 3 to 6 slots are unrolled so
-// every slot's loads are in flight together.
+// (measured best on gfx950 for these two memory patterns); the first four slots of a row are
+// unrolled so their loads are in flight together.
 // ---------------------------------------------------------------------------------------------
 struct PcgCtl {
   double tol, bn, res;
@@ -382,18 +382,9 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
         SlotRange R = slots_of(A.slice_start, i);
         const int nrow = row_len(A.nslot, i, R);
         double acc = A.diag[i] * pi;
-        switch (nrow) {
-          case 3: acc = dir_row<3>(A, R.base, acc, beta, z, p_prev); break;
-          case 4: acc = dir_row<4>(A, R.base, acc, beta, z, p_prev); break;
-          case 5: acc = dir_row<5>(A, R.base, acc, beta, z, p_prev); break;
-          case 6: acc = dir_row<6>(A, R.base, acc, beta, z, p_prev); break;
-          default:
-            for (int sl = 0; sl < nrow; ++sl) {
-              int at = R.base + sl * SLICE;
-              int j = A.col[at];
-              acc += A.val[at] * (z[j] + beta * p_prev[j]);
-            }
-        }
+        walk_row<4>(nrow, [&](auto Wc, int k0) {
+          acc = dir_row<decltype(Wc)::value>(A, R.base + k0 * SLICE, acc, beta, z, p_prev);
+        });
         p_cur[i] = pi;
         q[i] = acc;
         v[0] += pi * acc;

@@ -92,10 +92,11 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_interp(MeshView<T> m, int tabl
 }
 
 // ---------------------------------------------------------------------------------------------
-// Row walkers.  A cell's own slots are visited in layout order; rows of 3 to 6 slots (2D prisms,
-// tets, prisms, hexes) are unrolled with every slot's loads issued before any is used (indices
-// clamped so each load is in bounds whatever the slot holds), other counts take the same code one
-// slot at a time.
+// Row walkers.  A cell's own slots are visited in layout order; the first four (two for the vector
+// gradient, whose slots carry more values) go in one unrolled chunk with every slot's loads issued
+// before any is used (indices clamped so each load is in bounds whatever the slot holds), the rest
+// one at a time.  (Two-slot chunks in the Laplacian raise occupancy but were slower: the second
+// chunk's loads wait for the first's.)
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ bool slot_internal(int sf, int nfi) { return sf != SLOT_PAD && sf < nfi; }
 __device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_internal(sf, nfi) ? (sf < 0 ? -sf - 1 : sf) : 0; }
@@ -117,12 +118,9 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
     acc[c][0] = acc[c][1] = acc[c][2] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-  const int nrow = row_len(m.nslot, i, R);
-  by_width(nrow, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
-    constexpr int N = W > 0 ? W : 1;
-    const int n = W > 0 ? W : nrow;
-    for (int k0 = 0; k0 < n; k0 += N) {
+  walk_row<(NC == 3 ? 2 : 4)>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    {
       int sf[N], j[N];
       typename Geo<T>::v4 g[N];
       T pj[N][NC];
@@ -190,12 +188,9 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_div(MeshView<T> m, int table, 
     acc[c] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-  const int nrow = row_len(m.nslot, i, R);
-  by_width(nrow, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
-    constexpr int N = W > 0 ? W : 1;
-    const int n = W > 0 ? W : nrow;
-    for (int k0 = 0; k0 < n; k0 += N) {
+  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    {
       int sf[N], j[N];
       T F[N], wf[N], pj[N][NC];
 #pragma unroll
@@ -264,53 +259,48 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_laplacian(MeshView<T> m, int t
   T gi0 = g[3 * (size_t)i], gi1 = g[3 * (size_t)i + 1], gi2 = g[3 * (size_t)i + 2];
   T acc = T(0);
   const int8_t* code = m.bcode + table * m.nfb;
-  const int nrow = row_len(m.nslot, i, R);
-  by_width(nrow, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
-    constexpr int N = W > 0 ? W : 1;
-    const int n = W > 0 ? W : nrow;
-    for (int k0 = 0; k0 < n; k0 += N) {
-      int sf[N], j[N];
-      typename Geo<T>::v4 kd[N];
-      T wf[N], pj[N], gj[N][3], gm[N];
+  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    int sf[N], j[N];
+    typename Geo<T>::v4 kd[N];
+    T wf[N], pj[N], gj[N][3], gm[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        int at = R.base + (k0 + k) * SLICE;
-        sf[k] = m.slot_face[at];
-        j[k] = m.slot_col[at];
-      }
+    for (int k = 0; k < N; ++k) {
+      int at = R.base + (k0 + k) * SLICE;
+      sf[k] = m.slot_face[at];
+      j[k] = m.slot_col[at];
+    }
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        int f = slot_face_index(sf[k], m.nfi);
-        kd[k] = m.geomK[f];
-        wf[k] = m.w[f];
-        gm[k] = GAMMA ? gamma[f] : T(1);
-        pj[k] = phi[j[k]];
+    for (int k = 0; k < N; ++k) {
+      int f = slot_face_index(sf[k], m.nfi);
+      kd[k] = m.geomK[f];
+      wf[k] = m.w[f];
+      gm[k] = GAMMA ? gamma[f] : T(1);
+      pj[k] = phi[j[k]];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) gj[k][e] = g[3 * (size_t)j[k] + e];
-      }
+      for (int e = 0; e < 3; ++e) gj[k][e] = g[3 * (size_t)j[k] + e];
+    }
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        if (sf[k] == SLOT_PAD) continue;
-        if (sf[k] < m.nfi) {
-          bool nb = sf[k] < 0;
-          T wself = nb ? T(1) - wf[k] : wf[k];
-          // seen from this cell: delta (phi_other - phi_self) + k_out . gbar, with k_out the
-          // correction vector oriented out of this cell; the owner-side form of eq. nonortho_flux,
-          // negated for the neighbour side
-          T corr = kd[k].x * (wself * gi0 + (T(1) - wself) * gj[k][0]) +
-                   kd[k].y * (wself * gi1 + (T(1) - wself) * gj[k][1]) +
-                   kd[k].z * (wself * gi2 + (T(1) - wself) * gj[k][2]);
-          T t = kd[k].w * (pj[k] - pi) + (nb ? -corr : corr);
-          if (GAMMA) t *= gm[k];
+    for (int k = 0; k < N; ++k) {
+      if (sf[k] == SLOT_PAD) continue;
+      if (sf[k] < m.nfi) {
+        bool nb = sf[k] < 0;
+        T wself = nb ? T(1) - wf[k] : wf[k];
+        // seen from this cell: delta (phi_other - phi_self) + k_out . gbar, with k_out the
+        // correction vector oriented out of this cell; the owner-side form of eq. nonortho_flux,
+        // negated for the neighbour side
+        T corr = kd[k].x * (wself * gi0 + (T(1) - wself) * gj[k][0]) +
+                 kd[k].y * (wself * gi1 + (T(1) - wself) * gj[k][1]) +
+                 kd[k].z * (wself * gi2 + (T(1) - wself) * gj[k][2]);
+        T t = kd[k].w * (pj[k] - pi) + (nb ? -corr : corr);
+        if (GAMMA) t *= gm[k];
+        acc += t;
+      } else {
+        int b = sf[k] - m.nfi;
+        if (code[b] == BC_FIXED) {
+          T t = m.bgeom[b].w * (phib[b] - pi);
+          if (GAMMA) t *= gamma[m.nfi + b];
           acc += t;
-        } else {
-          int b = sf[k] - m.nfi;
-          if (code[b] == BC_FIXED) {
-            T t = m.bgeom[b].w * (phib[b] - pi);
-            if (GAMMA) t *= gamma[m.nfi + b];
-            acc += t;
-          }
         }
       }
     }
@@ -331,12 +321,9 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_ldu_spmv(MeshView<T> m, const 
   T di = diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
-  const int nrow = row_len(m.nslot, i, R);
-  by_width(nrow, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
-    constexpr int N = W > 0 ? W : 1;
-    const int n = W > 0 ? W : nrow;
-    for (int k0 = 0; k0 < n; k0 += N) {
+  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    {
       int sf[N], j[N];
       T a[N], xj[N][NC];
 #pragma unroll
