@@ -218,3 +218,40 @@ def test_handles_destroy_in_any_order():
     assert st == 0
     B.difvm_piso_destroy(ph)
     B.difvm_tape_destroy(th)  # last reference: frees tape, PISO object, mesh and context
+
+
+def single_tet(shift=0.0):
+    P = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]]) + 0.1 + shift
+    return mg.tet_mesh(P, np.array([[0, 1, 2, 3]]), lambda Cf, tri: np.zeros(Cf.shape[0], int),
+                       [("walls", mg.U_FIXED, mg.P_FIXED, -1)], name="tet1")
+
+
+def test_packed_with_faceless_member_solves_per_segment():
+    """A one-cell member (no internal face, its tile holds one cell) packed between two meshes: each
+    segment's Laplace solve equals the member's own solve bit for bit, iteration counts included."""
+    from gpu_util import empty
+    ms = [mg.kuhn_cube(5, jitter=0.15, patches="channel", seed=41), single_tet(),
+          mg.kuhn_cube(4, jitter=0.15, patches="channel", seed=42)]
+    Pm, starts = mg.pack(ms)
+    pbs = [np.linspace(0.0, 1.0, m.n_boundary_faces) for m in ms]
+    rhs_extra = [np.random.default_rng(k).standard_normal(m.n_cells) for k, m in enumerate(ms)]
+
+    def solve(mesh, pb, extra, seg):
+        M = B.Mesh(ctx(), mesh, seg_cell_start=seg)
+        d, u, rhs = empty(mesh.n_cells), empty(max(1, mesh.n_internal_faces)), empty(mesh.n_cells)
+        A = B.ldu(d, u)
+        B.difvm_ldu_assemble_laplace(M.h, B.BC_P, None, M.to_internal(dev(pb), B.KIND_BFACE), A, rhs)
+        b = rhs + M.to_internal(dev(extra), B.KIND_CELL)
+        x = empty(mesh.n_cells).zero_()
+        st = B.difvm_solve_pcg(M.h, A, b, x, 1e-11, 5000)
+        return st, host(M.to_user(x, B.KIND_CELL))
+
+    st, x = solve(Pm, np.concatenate(pbs), np.concatenate(rhs_extra), starts)
+    assert st[0] == 0
+    its = []
+    for k, m in enumerate(ms):
+        sk, xk = solve(m, pbs[k], rhs_extra[k], None)
+        assert sk[0] == 0
+        its.append(sk[1])
+        np.testing.assert_array_equal(x[starts[k]:starts[k + 1]], xk)
+    assert st[1] == max(its)

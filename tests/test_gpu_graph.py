@@ -138,3 +138,31 @@ def test_graph_errors_and_off():
     r0 = P.graph_info()[0]
     P.step(2)
     assert P.graph_info()[0] == r0
+
+
+def test_graph_with_iteration_cap():
+    """Every pressure solve stops at its cap (not converged): the budgets equal the cap, replays are
+    complete, and states and warnings match eager stepping."""
+    m = mg.cavity(16)
+    Ub = lid(m)
+    Ms, Ps = [], []
+    for k in range(2):
+        M = B.Mesh(ctx(), m)
+        P = B.Piso(M, B.piso_params(0.01, 1e-3, maxit_p=7))
+        P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+        U0 = np.zeros((m.n_cells, 3))
+        P.set_state(dev(U0), dev(np.zeros(m.n_cells)), dev(O.initial_flux(m, U0, Ub)))
+        Ms.append(M)
+        Ps.append(P)
+    Pe, Pg = Ps
+    Pg.set_graph(True, 4)
+    for s in range(5):
+        ste, ite, rese = Pe.step(1)
+        stg, itg, resg = Pg.step(1)
+        assert ste == stg == B.WARN_NOT_CONVERGED
+        np.testing.assert_array_equal(itg, ite)
+        np.testing.assert_array_equal(resg, rese)
+        assert (itg[0, 3:] == 7).all()
+        same_state(Pe, Pg)
+    replays, redos, _ = Pg.graph_info()
+    assert replays == 4 and redos == 0
