@@ -200,16 +200,30 @@ def timed(torch, fn):
     return time.perf_counter() - t, r
 
 
-def graph_rate(P, torch, steps, extra=16):
-    """Steps/s of the same PISO object in graph mode (one hipGraphLaunch per step; the first step
-    after enabling runs eagerly and captures, two more replays warm up)."""
+def graph_rate(P, torch, steps, wk, extra=16):
+    """Eager against graph mode over the same window: the state (U, p, phi, capacitor pressures with
+    Windkessel rows wk) is saved, `steps` eager steps are timed, the state is restored, one step
+    captures the graph, the state is restored again and the same `steps` are timed as replays."""
+    U0, p0, phi0, pc0 = P.get_state()
+
+    def restore():
+        P.set_state(U0, p0, phi0)
+        for j, row in enumerate(wk):
+            P.set_windkessel(j, *row, pc0[j])
+
+    te, (ste, ite, _) = timed(torch, lambda: P.step(steps))
+    restore()
     P.set_graph(True, extra)
-    P.step(3)
-    t, (st, it, _) = timed(torch, lambda: P.step(steps))
-    replays, redos, captures = P.graph_info()
+    P.step(1)
+    restore()
+    r0 = P.graph_info()
+    tg, (stg, itg, _) = timed(torch, lambda: P.step(steps))
+    r1 = P.graph_info()
     P.set_graph(False)
-    return {"steps_per_s": round(steps / t, 4), "steps": steps, "status": int(st), "replays": replays,
-            "redos": redos, "captures": captures, "extra_iters": extra}
+    return {"steps": steps, "eager_steps_per_s": round(steps / te, 4), "graph_steps_per_s": round(steps / tg, 4),
+            "speedup": round(te / tg, 4), "same_iterations": bool((ite == itg).all()), "status": [int(ste), int(stg)],
+            "replays": r1[0] - r0[0], "redos": r1[1] - r0[1], "extra_iters": extra,
+            "pcg_iters_per_solve": round(float(itg[:, 3:].mean()), 1)}
 
 
 def small_case(B, mg, torch, ctx, steps=50):
@@ -315,7 +329,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
     Pb.step(2)
     t_b, (st, it, _) = timed(torch, lambda: Pb.step(steps))
     seg_it, _, seg_st = Pb.segment_stats()
-    gr = graph_rate(Pb, torch, steps)
+    gr = graph_rate(Pb, torch, steps, np.concatenate([d["wk"] for d in mem]))
     t_seq = 0.0
     for d in mem:
         M, P = setup(d["mesh"], d["Ub"], d["wk"], [d["nu"]])
@@ -331,7 +345,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
            "batch_cell_steps_per_s": round(steps * Pm.n_cells / t_b, 0),
            "sequential_steps_per_s": round(steps / t_seq, 3),
            "speedup_vs_sequential": round(t_seq / t_b, 3),
-           "batch_graph_steps_per_s": gr["steps_per_s"], "batch_graph_redos": gr["redos"],
+           "batch_graph": gr,
            "pcg_iters_max_member": int(seg_it[:, 3:].max()), "pcg_iters_min_member": int(seg_it[:, 3:].min()),
            "status": int(st)}
     if adj_steps > 0:
@@ -381,7 +395,7 @@ def main():
     ap.add_argument("--batch-members", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-adj-steps", type=int, default=10)
-    ap.add_argument("--prof-every", type=int, default=16,
+    ap.add_argument("--prof-every", type=int, default=256,
                     help="time every n-th launch of each PCG kernel with HIP events in the timed region")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
@@ -440,6 +454,7 @@ def main():
             first_iters = it[0].tolist()
         log(f"warmup step {k}: {time.time() - ts:.3f}s iters {it[0].tolist()} status {st}")
 
+    # timed region: eager steps, HIP events around every prof_every-th launch of each PCG kernel
     B.difvm_ctx_profile(ctx.h, args.prof_every)
     B.difvm_ctx_profile_read(ctx.h)
     torch.cuda.synchronize()
@@ -471,7 +486,7 @@ def main():
     graph = None
     small = None
     if not args.no_graph:
-        graph = graph_rate(P, torch, args.steps)
+        graph = graph_rate(P, torch, args.steps, [wk])
         log("graph mode", graph)
         small = small_case(B, mg, torch, ctx)
         log("small case", small)

@@ -96,9 +96,10 @@ difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
  * of each of the library's PCG kernels inside difvm_solve_pcg and difvm_piso_step (counted per
  * kernel name from the call that enabled it) is bracketed by a pair of HIP events on the context's
  * stream, the stream the kernels run on (n > 1 keeps the events' own cost out of most launches);
- * n = 0 disables it, n < 0 is DIFVM_ERR_INVALID_ARG.  difvm_ctx_profile_read synchronises, returns
- * per-kernel counts of timed launches and their summed event durations (kernel names in out[k].name),
- * and clears the record. */
+ * n = 0 disables it, n < 0 is DIFVM_ERR_INVALID_ARG.  Launches inside a captured step (graph mode,
+ * difvm_piso_set_graph) are not timed.  difvm_ctx_profile_read
+ * synchronises, returns per-kernel counts of timed launches and their summed event durations
+ * (kernel names in out[k].name), and clears the record. */
 typedef struct {
   char name[32];
   int32_t launches;
@@ -329,8 +330,9 @@ difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi,
 /* Graph mode (the paper runs its time loop as one compiled scan, Sec. 2.4; here the step is a
  * replayed hipGraph).  With enable != 0, the first difvm_piso_step step after this call runs eagerly
  * and records its Krylov iteration counts; the whole step (Windkessel, assembly, BiCGStab, every
- * corrector) is then captured once on a private stream with a budget per solve of those counts plus
- * extra_iters (>= 0), and each later step is one hipGraphLaunch on the context's stream followed by
+ * corrector) is then captured once on a private stream with a budget per solve of the largest count
+ * of its kind (BiCGStab components, or pressure correctors) plus extra_iters (>= 0) plus 1/16 of that
+ * count, and each later step is one hipGraphLaunch on the context's stream followed by
  * one read of the solvers' states.  Iterations past a solve's stop are predicated no-ops, so results
  * are bitwise those of eager stepping.  A step in which some solve had not stopped within its budget
  * is discarded (its starting state, saved by the graph, is restored on the device) and run eagerly;

@@ -62,7 +62,7 @@ struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   Profiler prof;
-  bool capturing = false;  // a step is being captured: no event timing
+  bool capturing = false;  // a step is being captured: launches are not timed
 };
 
 // Brackets the next launch on `s` with events when profiling is on; returns a handle for prof_end.

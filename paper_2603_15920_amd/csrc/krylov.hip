@@ -34,7 +34,8 @@ struct KrylovWork {
   double* partials = nullptr;
   struct PcgCtl* pcg = nullptr;  // [nseg]
   BiState* bi = nullptr;         // [nseg]
-  void* host_state = nullptr;    // pinned mirror, nseg * sizeof(BiState)
+  void* host_state[2] = {nullptr, nullptr};  // pinned mirrors of the solver states (two polls in flight)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   int pcg_hint = 0, bi_hint = 0;  // iterations of the previous solve: sizes the first unpolled block
 };
 
@@ -55,7 +56,10 @@ static KrylovWork* make_work(difvm_mesh* m) {
   int nseg = m->d.nseg;
   w->pcg = static_cast<PcgCtl*>(dmalloc(sizeof(BiState) * nseg));  // PcgCtl is smaller (asserted below)
   w->bi = dalloc<BiState>(nseg);
-  DIFVM_HIP(hipHostMalloc((void**)&w->host_state, sizeof(BiState) * nseg, hipHostMallocDefault));
+  for (int q = 0; q < 2; ++q) {
+    DIFVM_HIP(hipHostMalloc((void**)&w->host_state[q], sizeof(BiState) * nseg, hipHostMallocDefault));
+    DIFVM_HIP(hipEventCreateWithFlags(&w->poll_ev[q], hipEventDisableTiming));
+  }
   return w;
 }
 
@@ -64,7 +68,10 @@ void krylov_work_free(KrylovWork* w) {
   for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->y, w->s, w->z, w->t, w->partials}) dfree(a);
   dfree(w->pcg);
   dfree(w->bi);
-  if (w->host_state) (void)hipHostFree(w->host_state);
+  for (int q = 0; q < 2; ++q) {
+    if (w->host_state[q]) (void)hipHostFree(w->host_state[q]);
+    if (w->poll_ev[q]) (void)hipEventDestroy(w->poll_ev[q]);
+  }
   delete w;
 }
 
@@ -482,13 +489,18 @@ SolveResult pcg_result(const difvm_mesh* m, const void* host_state, bool* comple
   return R;
 }
 
-// copies the per-segment states to the pinned mirror and waits
-template <class S>
-static const S* fetch_states(difvm_mesh* m, KrylovWork* w, const S* dstate) {
-  int nseg = m->d.nseg;
-  DIFVM_HIP(hipMemcpyAsync(w->host_state, dstate, sizeof(S) * nseg, hipMemcpyDeviceToHost, stream_of(m)));
-  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
-  return static_cast<const S*>(w->host_state);
+// Polling without draining the queue: the host copies the per-segment states into one of two pinned
+// buffers after a block of iterations and records an event, queues the next block, and only then
+// waits for the earlier copy; iterations queued past a segment's stop are predicated no-ops, so the
+// extra block changes nothing.
+static void post_poll(difvm_mesh* m, KrylovWork* w, const void* dstate, size_t bytes, int slot) {
+  hipStream_t s = stream_of(m);
+  DIFVM_HIP(hipMemcpyAsync(w->host_state[slot], dstate, bytes, hipMemcpyDeviceToHost, s));
+  DIFVM_HIP(hipEventRecord(w->poll_ev[slot], s));
+}
+static const void* wait_poll(KrylovWork* w, int slot) {
+  DIFVM_HIP(hipEventSynchronize(w->poll_ev[slot]));
+  return w->host_state[slot];
 }
 
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit, const QueueOnly* qo) {
@@ -513,37 +525,52 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     // queue-only: iterations 1..K and the stopping test of iterate K, no read-back
     int K = std::min(qo->budget, maxit);
     for (int kk = 1; kk <= K + 1; ++kk) {
-      k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
-      if (kk <= K) k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
+      {
+        ProfScope ps(m, "pcg_spmv_dot");
+        k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
+      }
+      if (kk <= K) {
+        ProfScope ps(m, "pcg_update_dot");
+        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
+      }
     }
     DIFVM_HIP(hipGetLastError());
     copy_state(qo->state_out, w->pcg, pcg_state_bytes(m), s);
     return SolveResult{};
   }
-  // First block sized from the previous solve, then short polled blocks; iteration k's stopping test
-  // runs at the start of iteration k+1, so the host queues up to iteration maxit+1.
-  int k = 1;
-  int nb = std::max(4, w->pcg_hint - 2);
-  const PcgCtl* hs = nullptr;
-  while (true) {
-    int last = std::min(k + nb - 1, maxit + 1);
-    for (; k <= last; ++k) {
+  // First block sized from the previous solve, then short blocks, each queued before the host waits
+  // for the state copied after the block before it; iteration k's stopping test runs at the start of
+  // iteration k+1, so the host queues up to iteration maxit+1.
+  int k = 1;  // next iteration to queue
+  auto queue_block = [&](int nb) {
+    for (int n = 0; n < nb && k <= maxit + 1; ++n, ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
         k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
-      if (k > maxit) break;
-      {
+      if (k <= maxit) {
         ProfScope ps(m, "pcg_update_dot");
         k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[k & 1], q, partA, partB, k, w->pcg);
       }
     }
     DIFVM_HIP(hipGetLastError());
-    hs = fetch_states<PcgCtl>(m, w, w->pcg);
+  };
+  const size_t bytes = pcg_state_bytes(m);
+  queue_block(std::max(4, w->pcg_hint - 2));
+  int slot = 0;
+  post_poll(m, w, w->pcg, bytes, slot);
+  const PcgCtl* hs = nullptr;
+  while (true) {
+    bool more = k <= maxit + 1;
+    if (more) {
+      queue_block(4);
+      post_poll(m, w, w->pcg, bytes, slot ^ 1);
+    }
+    hs = static_cast<const PcgCtl*>(wait_poll(w, slot));
     bool all = true;
     for (int g = 0; g < nseg; ++g) all = all && hs[g].done;
-    if (k > maxit || all) break;
-    nb = 4;
+    if (all || !more) break;
+    slot ^= 1;
   }
   SolveResult R = pcg_result(m, hs, nullptr);
   w->pcg_hint = R.iters[0];
@@ -848,11 +875,9 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
   k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
   k_bi_zero<NC><<<G, BLOCK, 0, s>>>(T, x, w->bi);
   DIFVM_HIP(hipGetLastError());
-  int done = 0;
-  int nb = qo ? std::min(qo->budget, maxit) : std::min(maxit, std::max(2, w->bi_hint - 1));
-  const BiState* hs = nullptr;
-  while (true) {
-    for (int k = 0; k < nb; ++k) {
+  int done = 0;  // iterations queued
+  auto queue_iters = [&](int nb) {
+    for (int it = 0; it < nb; ++it) {
       k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->y, w->bi);
       k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->y, w->v, w->rh, part, w->bi);
       k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
@@ -863,17 +888,30 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
       k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, T, x, w->r, w->rh, w->y, w->z, w->s, w->t, part, w->bi);
       k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
     }
-    DIFVM_HIP(hipGetLastError());
-    if (qo) {
-      copy_state(qo->state_out, w->bi, bicgstab_state_bytes(m), s);
-      return SolveResult{};
-    }
     done += nb;
-    hs = fetch_states<BiState>(m, w, w->bi);
+    DIFVM_HIP(hipGetLastError());
+  };
+  if (qo) {
+    queue_iters(std::min(qo->budget, maxit));
+    copy_state(qo->state_out, w->bi, bicgstab_state_bytes(m), s);
+    return SolveResult{};
+  }
+  const size_t bytes = bicgstab_state_bytes(m);
+  queue_iters(std::min(maxit, std::max(2, w->bi_hint - 1)));
+  int slot = 0;
+  post_poll(m, w, w->bi, bytes, slot);
+  const BiState* hs = nullptr;
+  while (true) {
+    bool more = done < maxit;
+    if (more) {
+      queue_iters(std::min(2, maxit - done));
+      post_poll(m, w, w->bi, bytes, slot ^ 1);
+    }
+    hs = static_cast<const BiState*>(wait_poll(w, slot));
     bool any = false;
     for (int g = 0; g < nseg; ++g) any = any || hs[g].any;
-    if (done >= maxit || !any) break;
-    nb = std::min(2, maxit - done);
+    if (!any || !more) break;
+    slot ^= 1;
   }
   SolveResult R = bicgstab_result(m, NC, hs, nullptr);
   w->bi_hint = std::max(R.iters[0], std::max(R.iters[1], R.iters[2]));

@@ -660,14 +660,17 @@ static void graph_capture(difvm_piso* P) {
   G.captures++;
 }
 
+// budgets: the largest count of the step (over components or correctors) plus the margin and 1/16 of
+// that count, since later steps' counts drift a little around the first one's
 static void set_budgets(difvm_piso* P, const difvm_step_stats& st, bool grow_only) {
   PisoGraph& G = P->g;
-  int bu = std::max(st.it_u[0], std::max(st.it_u[1], st.it_u[2])) + G.extra;
+  int mu = std::max(st.it_u[0], std::max(st.it_u[1], st.it_u[2]));
+  int bu = mu + G.extra + mu / 16;
   G.budget_u = grow_only ? std::max(G.budget_u, bu) : bu;
-  for (int k = 0; k < P->prm.n_corr; ++k) {
-    int bp = st.it_p[k] + G.extra;
-    G.budget_p[k] = grow_only ? std::max(G.budget_p[k], bp) : bp;
-  }
+  int mp = 0;
+  for (int k = 0; k < P->prm.n_corr; ++k) mp = std::max(mp, st.it_p[k]);
+  int bp = mp + G.extra + mp / 16;
+  for (int k = 0; k < P->prm.n_corr; ++k) G.budget_p[k] = grow_only ? std::max(G.budget_p[k], bp) : bp;
 }
 
 static void graph_step(difvm_piso* P, difvm_step_stats* out) {

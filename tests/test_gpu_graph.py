@@ -166,3 +166,27 @@ def test_graph_with_iteration_cap():
         same_state(Pe, Pg)
     replays, redos, _ = Pg.graph_info()
     assert replays == 4 and redos == 0
+
+
+def test_graph_replays_are_not_timed():
+    """Kernel timing counts eager launches only: replays of a captured step add nothing, and turning
+    profiling on or off changes no result."""
+    m = mg.cavity(16)
+    Ub = lid(m)
+    _, Pe = make(m, Ub, 0.01, 1e-3)
+    cx = B.Context(0)
+    Mg = B.Mesh(cx, m)
+    Pg = B.Piso(Mg, B.piso_params(0.01, 1e-3))
+    Pg.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    U0 = np.zeros((m.n_cells, 3))
+    Pg.set_state(dev(U0), dev(np.zeros(m.n_cells)), dev(O.initial_flux(m, U0, Ub)))
+    Pg.set_graph(True, 8)
+    B.difvm_ctx_profile(cx.h, 4)
+    run_pair(Pe, Pg, 1)          # eager step (timed) + capture
+    first = B.difvm_ctx_profile_read(cx.h)
+    assert first["pcg_spmv_dot"][0] > 0
+    run_pair(Pe, Pg, 3)          # replays
+    prof = B.difvm_ctx_profile_read(cx.h)
+    B.difvm_ctx_profile(cx.h, 0)
+    assert all(v[0] == 0 for v in prof.values()), prof
+    assert Pg.graph_info()[0] == 3
