@@ -22,6 +22,13 @@ class PisoWindow(torch.autograd.Function):
         for j in range(n_wk):
             piso.set_windkessel(j, th[j, 0], th[j, 1], th[j, 2], pcv[j])
         piso.set_state(U0.detach().contiguous(), p0.detach().contiguous(), phi0.detach().contiguous())
+        ctx.tape = None
+        if not any(ctx.needs_input_grad[:5]):
+            # nothing to differentiate: plain steps, no tape (the same arithmetic)
+            status, iters, _ = piso.step(nsteps)
+            U, p, phi, pc = piso.get_state()
+            ctx.status, ctx.iters = status, iters
+            return U, p, phi, torch.as_tensor(pc, dtype=torch.float64, device=pc0.device)
         tape = B.difvm_tape_create(piso.h, nsteps, ckpt_every)
         try:
             status, iters = B.difvm_piso_forward_record(piso.h, tape, nsteps, piso.params.n_corr)
@@ -36,6 +43,8 @@ class PisoWindow(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gU, gp, gphi, gpc):
+        if ctx.tape is None:
+            raise RuntimeError("PisoWindow: this window was run without a tape (no input required grad)")
         piso, n_wk = ctx.piso, ctx.n_wk
         src = piso.mesh.src
         dev = piso.mesh.ctx.device
