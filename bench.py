@@ -226,6 +226,47 @@ def graph_rate(P, torch, steps, wk, extra=16):
             "pcg_iters_per_solve": round(float(itg[:, 3:].mean()), 1)}
 
 
+def poisson_run(B, mg, torch, ctx, sizes=(12, 18, 25, 56)):
+    """The paper's 3D Poisson verification workload (manufactured solution on jittered Kuhn cubes of
+    10,368 / 34,992 / 93,750 cells, plus the 1,053,696-cell cube): Dirichlet data from the exact field,
+    over-relaxed correction from the exact gradient, Jacobi-PCG to 1e-12.  Times assembly + solve and
+    reports the L2 error against the exact field and its order between sizes."""
+    import math
+    import numpy as np
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    out = []
+    for n in sizes:
+        m = mg.kuhn_cube(n, jitter=0.15, patches="walls", seed=2603007 if n != 56 else 2603002)
+        M = B.Mesh(ctx, m)
+        B.difvm_tune(M.h, None)
+        phib = M.to_internal(dev(mg.poisson_mms_solution(m.Cf[m.n_internal_faces:])), B.KIND_BFACE)
+        g = M.to_internal(dev(mg.poisson_mms_gradient(m.C)), B.KIND_CELL)
+        src = M.to_internal(dev(m.V * mg.poisson_mms_source(m.C)), B.KIND_CELL)
+        e = lambda k: torch.empty(k, dtype=torch.float64, device="cuda:0")
+        d, u, rbc, lap0, zero, x = e(m.n_cells), e(m.n_internal_faces), e(m.n_cells), e(m.n_cells), e(m.n_cells), e(m.n_cells)
+        zero.zero_()
+        A = B.ldu(d, u)
+
+        def solve():
+            B.difvm_ldu_assemble_laplace(M.h, B.BC_ALL_FIXED, None, phib, A, rbc)
+            B.difvm_op_laplacian(M.h, B.BC_ALL_FIXED, None, zero, g, phib, lap0)
+            torch.sub(lap0, src, out=lap0)
+            x.zero_()
+            return B.difvm_solve_pcg(M.h, A, lap0, x, 1e-12, 20000)
+        solve()
+        t, (st, it, res) = timed(torch, solve)
+        phi = M.to_user(x, B.KIND_CELL).cpu().numpy()
+        err = phi - mg.poisson_mms_solution(m.C)
+        l2 = math.sqrt((m.V * err * err).sum() / m.V.sum())
+        out.append({"cells": m.n_cells, "pcg_iters": it, "status": st, "solve_ms": round(1e3 * t, 3),
+                    "us_per_iteration": round(1e6 * t / max(it, 1), 2), "l2_error": l2})
+        M.close()
+    for a, b in zip(out, out[1:]):
+        b["order"] = round(math.log(a["l2_error"] / b["l2_error"]) / math.log((b["cells"] / a["cells"]) ** (1 / 3)), 3)
+    return {"workload": "manufactured 3D Poisson solution, jittered Kuhn cubes, exact-gradient correction, "
+                        "Jacobi-PCG tol 1e-12", "runs": out}
+
+
 def small_case(B, mg, torch, ctx, steps=50):
     """The small PISO case (lid-driven cavity, 2048 jittered triangle prisms, Re 100, nu 0.01,
     dt 1e-3): launch-bound, so eager stepping against graph mode."""
@@ -389,6 +430,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated-window measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-mesh batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson verification workload")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
     ap.add_argument("--adj-steps", type=int, default=20)
     ap.add_argument("--adj-every", type=int, default=10)
@@ -491,6 +533,10 @@ def main():
         small = small_case(B, mg, torch, ctx)
         log("small case", small)
 
+    poisson = None
+    if not args.no_poisson:
+        poisson = poisson_run(B, mg, torch, ctx)
+        log("poisson", poisson)
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_window(B, mg, torch, ctx, args.adj_steps, args.adj_every)
@@ -534,6 +580,7 @@ def main():
         "tuned_launch": tuned,
         "graph_mode": graph,
         "small_case": small,
+        "poisson": poisson,
         "adjoint": adjoint,
         "batched": batched,
         "operators": ops,

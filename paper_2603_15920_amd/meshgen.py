@@ -962,3 +962,27 @@ def batch_members(n_members=64, seed0=2603100, n_lo=2e4, n_hi=3e5):
         m.name = f"member{k}:{m.name}"
         out.append(dict(mesh=m, nu=nu, Ub=Ub, wk=wk, pc0=np.zeros(1), Re=Re))
     return out
+
+
+# ----------------------------------------------------------------------------------------------
+# manufactured Poisson solution on the unit cube (inputs of the Poisson verification workload)
+# ----------------------------------------------------------------------------------------------
+
+def poisson_mms_solution(x):
+    """phi(x) = 2 sin(pi x) (y^4 - y) sin(2 pi z) + 10 (the paper's 3D Poisson verification field)."""
+    return 2 * np.sin(math.pi * x[:, 0]) * (x[:, 1] ** 4 - x[:, 1]) * np.sin(2 * math.pi * x[:, 2]) + 10.0
+
+
+def poisson_mms_source(x):
+    """f = lap(phi) of poisson_mms_solution."""
+    s = np.sin(math.pi * x[:, 0]) * np.sin(2 * math.pi * x[:, 2])
+    return -10 * math.pi ** 2 * s * (x[:, 1] ** 4 - x[:, 1]) + 24 * s * x[:, 1] ** 2
+
+
+def poisson_mms_gradient(x):
+    """grad(phi) of poisson_mms_solution, [n, 3]."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    pi = math.pi
+    return np.stack([2 * pi * np.cos(pi * X) * (Y ** 4 - Y) * np.sin(2 * pi * Z),
+                     2 * np.sin(pi * X) * (4 * Y ** 3 - 1) * np.sin(2 * pi * Z),
+                     4 * pi * np.sin(pi * X) * (Y ** 4 - Y) * np.cos(2 * pi * Z)], 1)
