@@ -267,6 +267,36 @@ def poisson_run(B, mg, torch, ctx, sizes=(12, 18, 25, 56)):
                         "Jacobi-PCG tol 1e-12", "runs": out}
 
 
+def tube_run(B, mg, torch, ctx, steps):
+    """The full PISO configuration on the straight tube (1,999,872 tets, L/D 10, parabolic inlet at
+    Re 500, p = 0 outlet, nu 1e-3, dt 1e-3, 2 correctors, PCG tol 1e-8), from rest: the first step
+    untimed, then `steps` timed steps (graph mode off, tuned launch shapes)."""
+    import numpy as np
+    t0 = time.time()
+    m = mg.tube()
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    p = m.patch("inlet")
+    Ub[p.start - Fi:p.start - Fi + p.size] = mg.parabolic_inlet(m.Cf[p.start:p.start + p.size], (0, 0, 0), 0.5, 1.0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    M = B.Mesh(ctx, m)
+    B.difvm_tune(M.h, None)
+    P = B.Piso(M, B.piso_params(1e-3, 1e-3, tol_p=1e-8, tol_u=1e-8, maxit_p=20000, maxit_u=2000))
+    P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
+    log(f"tube: {m.n_cells} cells ready ({time.time() - t0:.1f}s)")
+    P.step(1)
+    t, (st, it, _) = timed(torch, lambda: P.step(steps))
+    out = {"workload": f"tube {m.n_cells} tets, L/D 10, Re 500, p = 0 outlet, nu 1e-3, dt 1e-3, 2 correctors, "
+                       f"PCG tol 1e-8, steps 2-{steps + 1} from rest",
+           "cells": m.n_cells, "steps": steps, "steps_per_s": round(steps / t, 4),
+           "cell_steps_per_s": round(steps * m.n_cells / t, 0), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+           "status": int(st)}
+    P.close()
+    M.close()
+    return out
+
+
 def small_case(B, mg, torch, ctx, steps=50):
     """The small PISO case (lid-driven cavity, 2048 jittered triangle prisms, Re 100, nu 0.01,
     dt 1e-3): launch-bound, so eager stepping against graph mode."""
@@ -366,6 +396,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
 
     Mb, Pb = setup(Pm, np.concatenate([d["Ub"] for d in mem]), np.concatenate([d["wk"] for d in mem]),
                    np.array([d["nu"] for d in mem]), starts)
+    B.difvm_tune(Mb.h, None)
     log(f"batch: device mesh ready ({time.time() - t0:.1f}s)")
     Pb.step(2)
     t_b, (st, it, _) = timed(torch, lambda: Pb.step(steps))
@@ -431,6 +462,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-mesh batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson verification workload")
+    ap.add_argument("--no-tube", action="store_true", help="skip the 2M-cell tube PISO run")
+    ap.add_argument("--tube-steps", type=int, default=10)
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
     ap.add_argument("--adj-steps", type=int, default=20)
     ap.add_argument("--adj-every", type=int, default=10)
@@ -533,6 +566,10 @@ def main():
         small = small_case(B, mg, torch, ctx)
         log("small case", small)
 
+    tube = None
+    if not args.no_tube:
+        tube = tube_run(B, mg, torch, ctx, args.tube_steps)
+        log("tube", tube)
     poisson = None
     if not args.no_poisson:
         poisson = poisson_run(B, mg, torch, ctx)
@@ -580,6 +617,7 @@ def main():
         "tuned_launch": tuned,
         "graph_mode": graph,
         "small_case": small,
+        "tube": tube,
         "poisson": poisson,
         "adjoint": adjoint,
         "batched": batched,
