@@ -6,8 +6,8 @@
 //
 // Every operator is the plain finite-volume definition evaluated face by face, in face order, on the
 // mesh exactly as given (user numbering):  for f: acc[owner f] += t_f; acc[neighbour f] -= t_f.
-// The paper states its graph form reaches exactly these operators (Sec. "Graph-Based Reformulation",
-// "mapping is exact and lossless"), so the definition is the oracle.
+// The paper's graph form (Sec. "Graph-Based Reformulation") computes exactly these sums, only
+// reorganised as per-edge messages and per-node aggregation, so the definition is the oracle.
 //
 // Notation (paper Sec. "Mesh data structure"): internal faces f in [0,Fi) with owner O_f, neighbour
 // N_f; boundary faces b in [Fi, Fi+Fb) with owner O_b; S outward from the owner; d_f = C_N - C_O,
