@@ -327,6 +327,19 @@ difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, dif
 difvm_status difvm_piso_set_state(difvm_piso* piso, const void* U, const void* p, const void* phi);
 difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi, double* pc_host);
 
+/* Passive scalar transport over one time step with the PISO object's current face flux (the
+ * paper's convection-diffusion discretisation, Sec. "Spatial discretization", applied to one scalar
+ * c): (V/dt)(c' - c) + sum_f F_f c'_upwind - D sum_f (delta_f (c'_N - c'_O) + k_f . grad(c)_f) = 0,
+ * i.e. the momentum predictor's matrix with one component and diffusivity D >= 0: implicit Euler,
+ * implicit upwind of the flux (tie F = 0 to the owner), implicit orthogonal diffusion, explicit
+ * over-relaxed correction from the Gauss gradient of c.  bc selects the boundary table (DIFVM_BC_*);
+ * c_b[Fb] (device, user boundary order) gives the values on its fixed faces; c[Nc] (device, user order)
+ * holds c on entry and c' on return.  Right-Jacobi BiCGStab from c with the PISO object's tol_u and
+ * maxit_u; stats (host, may be NULL) receives iterations and residual in component 0.  Synchronises.
+ * Returns a warning (c' still written) when the solve did not converge or broke down. */
+difvm_status difvm_piso_transport_scalar(difvm_piso* piso, double D, int32_t bc, const void* c_b, void* c,
+                                         difvm_solve_stats* stats);
+
 /* Graph mode (the paper runs its time loop as one compiled scan, Sec. 2.4; here the step is a
  * replayed hipGraph).  With enable != 0, the first difvm_piso_step step after this call runs eagerly
  * and records its Krylov iteration counts; the whole step (Windkessel, assembly, BiCGStab, every

@@ -13,6 +13,7 @@ _LIB = None
 
 TABLE_U, TABLE_P, TABLE_ALL_FIXED, TABLE_ALL_ZEROGRAD = 0, 1, 2, 3
 SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
+OK, WARN_NOT_CONVERGED, WARN_BREAKDOWN = 0, 1, 2
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -190,6 +191,15 @@ def bicgstab(mesh, diag, upper, lower, b, x0=None, tol=1e-8, maxit=500):
     st = lib().oracle_bicgstab(om(mesh), ncomp, _p(_f(diag)), _p(_f(upper)), _p(_f(lower)), _p(b), _p(x),
                                C.c_double(tol), int(maxit), _p(it, _i32p), _p(res))
     return x, it, res, st
+
+
+def transport_scalar(mesh, phi, c, cb, D, dt, table=TABLE_U, tol=1e-8, maxit=500):
+    """One implicit step of a passive scalar with face flux phi; returns (c_new, iters, res, status)."""
+    x = np.array(c, dtype=np.float64, copy=True)
+    it, rs = C.c_int32(0), C.c_double(0.0)
+    st = lib().oracle_transport_scalar(om(mesh), int(table), C.c_double(D), C.c_double(dt), _p(_f(phi)), _p(_f(cb)),
+                                       _p(x), C.c_double(tol), int(maxit), C.byref(it), C.byref(rs))
+    return x, it.value, rs.value, st
 
 
 def initial_flux(mesh, U, Ub):

@@ -115,6 +115,7 @@ _SIGS = {
     "difvm_piso_set_windkessel": (C.c_int32, [_vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]),
     "difvm_piso_set_viscosity": (C.c_int32, [_vp, C.c_int32, _f64p]),
     "difvm_piso_segment_stats": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
+    "difvm_piso_transport_scalar": (C.c_int32, [_vp, C.c_double, C.c_int32, _vp, _vp, C.POINTER(SolveStats)]),
     "difvm_piso_set_graph": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
     "difvm_piso_graph_info": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
@@ -386,6 +387,14 @@ def difvm_piso_segment_stats(p, n_seg, n_corr=2):
     return it, res, np.array([s.status for s in stats], dtype=np.int32)
 
 
+def difvm_piso_transport_scalar(p, D, bc, c_b, c):
+    """One passive-scalar step in place on c (device, user order); returns (status, iters, residual)."""
+    st = SolveStats()
+    status = _check(lib().difvm_piso_transport_scalar(p, float(D), int(bc), _ptr(c_b), _ptr(c), C.byref(st)),
+                    "difvm_piso_transport_scalar")
+    return status, st.iters[0], st.residual[0]
+
+
 def difvm_piso_set_graph(p, enable, extra_iters=16):
     _check(lib().difvm_piso_set_graph(p, int(enable), int(extra_iters)), "difvm_piso_set_graph")
 
@@ -527,6 +536,9 @@ class Piso:
 
     def set_windkessel(self, wid, Rp, Cc, Rd, pc):
         difvm_piso_set_windkessel(self.h, wid, Rp, Cc, Rd, pc)
+
+    def transport_scalar(self, D, bc, c_b, c):
+        return difvm_piso_transport_scalar(self.h, D, bc, c_b, c)
 
     def set_graph(self, enable=True, extra_iters=16):
         difvm_piso_set_graph(self.h, enable, extra_iters)

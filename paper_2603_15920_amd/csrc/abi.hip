@@ -80,6 +80,7 @@ void piso_set_windkessel(difvm_piso* P, int id, double Rp, double C, double Rd, 
 void piso_set_viscosity(difvm_piso* P, int nseg, const double* nu_seg);
 void piso_release(difvm_piso* P);
 void piso_set_graph(difvm_piso* P, int enable, int extra);
+SolveResult piso_transport_scalar(difvm_piso* P, double D, int table, const double* cb_user, double* c_user);
 void piso_graph_info(const difvm_piso* P, long long* replays, long long* redos, long long* captures);
 void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out);
 void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
@@ -545,6 +546,24 @@ difvm_status difvm_piso_segment_stats(const difvm_piso* piso, int32_t n_seg, dif
   piso_segment_stats(piso, n_seg, out_host);
   DIFVM_API_END
   return DIFVM_OK;
+}
+
+difvm_status difvm_piso_transport_scalar(difvm_piso* piso, double D, int32_t bc, const void* c_b, void* c,
+                                         difvm_solve_stats* stats) {
+  int status = 0;
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  check_ptr(c, "c");
+  SolveResult r = piso_transport_scalar(piso, D, bc, (const double*)c_b, (double*)c);
+  if (stats) {
+    *stats = difvm_solve_stats{};
+    stats->iters[0] = r.iters[0];
+    stats->residual[0] = r.res[0];
+    stats->status = r.status;
+  }
+  status = r.status;
+  DIFVM_API_END
+  return (difvm_status)status;
 }
 
 difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extra_iters) {

@@ -28,7 +28,8 @@ namespace difvm {
 // momentum matrix (cell kernel): diag, per-slot coefficients (owner slot: upper, neighbour slot:
 // lower), optional face LDU copies, and the right-hand side b (without the pressure gradient)
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double nu_all,
+template <int NC>
+__global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int table, double nu_all,
                                                     const double* __restrict__ nu_cell, double dt,
                                                     const double* __restrict__ flux, const double* __restrict__ U,
                                                     const double* __restrict__ gU, const double* __restrict__ Ub,
@@ -41,9 +42,11 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
   double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
   double Vdt = m.V[i] / dt;
   double d = Vdt;
-  double bi[3] = {Vdt * U[3 * (size_t)i], Vdt * U[3 * (size_t)i + 1], Vdt * U[3 * (size_t)i + 2]};
-  const double* gi = gU + 9 * (size_t)i;
-  const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
+  double bi[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) bi[c] = Vdt * U[NC * (size_t)i + c];
+  const double* gi = gU + 3 * NC * (size_t)i;
+  const int8_t* codeU = m.bcode + table * m.nfb;
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
@@ -70,10 +73,10 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
       }
       double w = m.w[f];
       double wself = nb ? 1.0 - w : w;
-      const double* gj = gU + 9 * (size_t)j;
+      const double* gj = gU + 3 * NC * (size_t)j;
       double sg = nb ? -nu : nu;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < NC; ++c) {
         double corr = kd.x * (wself * gi[3 * c] + (1.0 - wself) * gj[3 * c]) +
                       kd.y * (wself * gi[3 * c + 1] + (1.0 - wself) * gj[3 * c + 1]) +
                       kd.z * (wself * gi[3 * c + 2] + (1.0 - wself) * gj[3 * c + 2]);
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
         double nd = nu * m.bgeom[bf].w;
         d += nd;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bi[c] += (nd - F) * Ub[3 * (size_t)bf + c];
+        for (int c = 0; c < NC; ++c) bi[c] += (nd - F) * Ub[NC * (size_t)bf + c];
       } else if (code == BC_ZEROGRAD) {
         d += F;
       }
@@ -96,15 +99,15 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, double n
   }
   diag[i] = d;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) b[3 * (size_t)i + c] = bi[c];
+  for (int c = 0; c < NC; ++c) b[NC * (size_t)i + c] = bi[c];
 }
 
 void op_assemble_momentum(const difvm_mesh* m, double nu, const double* nu_cell, double dt, const double* flux,
                           const double* U, const double* gradU, const double* Ub, double* diag, double* upper,
                           double* lower, double* slot_val, double* b) {
   const DMesh& d = m->d;
-  k_momentum<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), nu, nu_cell, dt, flux, U, gradU, Ub, diag,
-                                                         upper, lower, slot_val, b);
+  k_momentum<3><<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), DIFVM_BC_U, nu, nu_cell, dt, flux, U,
+                                                            gradU, Ub, diag, upper, lower, slot_val, b);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -419,6 +422,31 @@ void piso_set_viscosity(difvm_piso* P, int nseg, const double* nu_seg) {
   for (int i = 0; i < d.nc; ++i) cell[i] = P->seg_nu[m->host.cell_seg[i]];
   upload(P->nu_cell, cell, stream_of(m));
   DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+}
+
+// Passive scalar over one step with the current face flux: the momentum predictor's discretisation
+// with one component, diffusivity D in place of the viscosity and the given boundary table.
+SolveResult piso_transport_scalar(difvm_piso* P, double D, int table, const double* cb_user, double* c_user) {
+  DIFVM_CHECK(D >= 0, DIFVM_ERR_INVALID_ARG, "D must be >= 0");
+  DIFVM_CHECK(table >= 0 && table < N_TABLES, DIFVM_ERR_INVALID_ARG, "unknown boundary table");
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  DIFVM_CHECK(cb_user || d.nfb == 0, DIFVM_ERR_INVALID_ARG, "c_b is NULL");
+  hipStream_t s = stream_of(m);
+  if (!P->sc) {
+    P->sc = piso_alloc(P, d.nc); P->scb = piso_alloc(P, d.nfb); P->sg = piso_alloc(P, 3 * (size_t)d.nc);
+    P->sd = piso_alloc(P, d.nc); P->sval = piso_alloc(P, d.nslot); P->sb = piso_alloc(P, d.nc);
+  }
+  permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, c_user, P->sc);
+  if (d.nfb) permute(m, DIFVM_F64, 1, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, cb_user, P->scb);
+  op_grad(m, DIFVM_F64, 1, table, P->sc, P->scb, P->sg);
+  k_momentum<1><<<grid_for(d.nc), BLOCK, 0, s>>>(view<double>(d), table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg,
+                                                 P->scb, P->sd, nullptr, nullptr, P->sval, P->sb);
+  DIFVM_HIP(hipGetLastError());
+  SolveResult r = bicgstab(m, 1, SellMatrix{P->sd, P->sval}, P->sb, P->sc, P->prm.tol_u, P->prm.maxit_u);
+  permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->sc, c_user);
+  DIFVM_HIP(hipStreamSynchronize(s));
+  return r;
 }
 
 void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out) {

@@ -31,6 +31,7 @@ struct difvm_piso {
   double *gU = nullptr, *gp = nullptr, *dM = nullptr, *valM = nullptr, *bM = nullptr, *rhs = nullptr;
   double *HbyA = nullptr, *rAU = nullptr, *phiH = nullptr, *aF = nullptr, *ncorr = nullptr;
   double *dK = nullptr, *valK = nullptr, *rhsK = nullptr;
+  double *sc = nullptr, *scb = nullptr, *sg = nullptr, *sd = nullptr, *sval = nullptr, *sb = nullptr;  // scalar step
   std::vector<void*> allocs;
   std::vector<double> wk_host;  // Rp, C, Rd per id
   int refs = 1;                 // the caller's handle plus one per tape
