@@ -558,6 +558,18 @@ def main():
                 "timed_every": args.prof_every, "active_iterations": int(pcg_iters)}
     kernel_us = {k: round(1e3 * v[1] / max(v[0], 1), 2) for k, v in prof.items()}
 
+    # passive scalar carried by the flow of the last step (D = 1e-4, zeroGradient walls and outlet)
+    scalar = None
+    if not args.no_poisson:
+        c = torch.from_numpy(np.exp(-((m.C - np.array([0.3, 0.5, 0.5])) ** 2).sum(1) / 0.05)).to("cuda:0")
+        cb = torch.zeros(nfb, dtype=torch.float64, device="cuda:0")
+        P.transport_scalar(1e-4, B.BC_U, cb, c)
+        ts_, (sts, its, _) = timed(torch, lambda: P.transport_scalar(1e-4, B.BC_U, cb, c))
+        scalar = {"workload": "passive scalar blob in the channel's last flux, D 1e-4, implicit Euler, upwind, "
+                              "BiCGStab tol 1e-8", "cells": nc, "step_ms": round(1e3 * ts_, 3), "bicgstab_iters": its,
+                  "status": sts}
+        log("scalar", scalar)
+
     graph = None
     small = None
     if not args.no_graph:
@@ -617,6 +629,7 @@ def main():
         "tuned_launch": tuned,
         "graph_mode": graph,
         "small_case": small,
+        "scalar_transport": scalar,
         "tube": tube,
         "poisson": poisson,
         "adjoint": adjoint,
