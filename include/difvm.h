@@ -70,7 +70,22 @@ enum {
 };
 enum { DIFVM_TO_INTERNAL = 0, DIFVM_FROM_INTERNAL = 1 };
 
+/* Mesh flags.  DIFVM_RENUMBER_RCM: reverse Cuthill-McKee cell order.  DIFVM_NONORTH_*: the split of a
+ * face vector S = Delta + k used by every diffusion-type flux (Laplacian, momentum viscous term,
+ * pressure equation, face-flux correction, adjoint), Sec. "Diffusive flux discretization", eq.
+ * nonortho_flux.  Delta = delta d lies along the cell-to-cell vector d (boundary: d = Cf - C_O, where
+ * k is dropped) and the orthogonal part of S.grad(phi) is delta (phi_N - phi_O):
+ *   OVERRELAXED (default)  delta = |S|^2 / (S.d)      k = S - delta d   (k perpendicular to S)
+ *   MINIMUM                delta = (S.d) / |d|^2      k = S - delta d   (k perpendicular to d)
+ *   ORTHOGONAL             delta = |S| / |d|          k = S - delta d   (|Delta| = |S|)
+ *   NONE                   delta = |S| / |d|          k = 0             (two-point stencil, eq. diff_ortho)
+ * The four are values of a two-bit field (DIFVM_NONORTH_MASK); all coincide when S is parallel to d. */
 #define DIFVM_RENUMBER_RCM 1u
+#define DIFVM_NONORTH_OVERRELAXED 0u
+#define DIFVM_NONORTH_MINIMUM 2u
+#define DIFVM_NONORTH_ORTHOGONAL 4u
+#define DIFVM_NONORTH_NONE 6u
+#define DIFVM_NONORTH_MASK 6u
 
 typedef struct difvm_ctx difvm_ctx;
 typedef struct difvm_mesh difvm_mesh;
@@ -151,16 +166,18 @@ typedef struct {
  * (new -> old where a permutation): cell_perm[Nc], face_perm[Fi], face_flip[Fi], owner[Fi],
  * neighbour[Fi], own_start[Nc+1], losort[Fi], losort_start[Nc+1], bface_perm[Fb] (indices within the
  * boundary block), bowner[Fb].  Optional (NULL to skip) permuted geometry: S[(Fi+Fb)*3], w[Fi],
- * delta[Fi+Fb] (|S|^2/(S.d), boundary d = Cf - C_O), k[Fi*3] (S - delta d, eq. nonortho_flux). */
+ * delta[Fi+Fb] and k[Fi*3] of the DIFVM_NONORTH_* scheme in flags (boundary d = Cf - C_O).  Unknown
+ * flag bits: DIFVM_ERR_INVALID_ARG. */
 difvm_status difvm_mesh_renumber_host(const difvm_mesh_desc* desc, uint32_t flags, int32_t* cell_perm,
                                       int32_t* face_perm, uint8_t* face_flip, int32_t* owner, int32_t* neighbour,
                                       int32_t* own_start, int32_t* losort, int32_t* losort_start,
                                       int32_t* bface_perm, int32_t* bowner, double* S, double* w, double* delta,
                                       double* k);
 
-/* Validates, renumbers and uploads a mesh (synchronises).  Errors: DIFVM_ERR_INVALID_MESH for
- * counts that do not match, patches that do not tile the boundary block, indices out of range,
- * neighbour == owner, V <= 0 or S.d <= 0 on a non-empty face. */
+/* Validates, renumbers and uploads a mesh (synchronises).  flags: DIFVM_RENUMBER_RCM or 0, or-ed with
+ * one DIFVM_NONORTH_* scheme.  Errors: DIFVM_ERR_INVALID_ARG for unknown flag bits;
+ * DIFVM_ERR_INVALID_MESH for counts that do not match, patches that do not tile the boundary block,
+ * indices out of range, neighbour == owner, V <= 0 or S.d <= 0 on a non-empty face. */
 difvm_status difvm_mesh_create(difvm_ctx* ctx, const difvm_mesh_desc* desc, uint32_t flags, difvm_mesh** out);
 
 /* Batched form: one mesh made of n_seg independent meshes packed block-diagonally (the paper's

@@ -11,8 +11,9 @@
 //
 // Notation (paper Sec. "Mesh data structure"): internal faces f in [0,Fi) with owner O_f, neighbour
 // N_f; boundary faces b in [Fi, Fi+Fb) with owner O_b; S outward from the owner; d_f = C_N - C_O,
-// d_b = Cf_b - C_O; delta_f = |S|^2/(S.d) and k_f = S - delta_f d_f (over-relaxed split, eq.
-// nonortho_flux); delta_b likewise with d_b, k_b = 0.  Empty faces are skipped everywhere.
+// d_b = Cf_b - C_O; the face vector is split as S = Delta + k with Delta = delta d along d (eq.
+// nonortho_flux); delta_f follows the chosen correction scheme (over-relaxed by default, see
+// face_split), delta_b likewise with d_b and k_b = 0.  Empty faces are skipped everywhere.
 //
 // Parity pins live in tests/test_oracle_*.py.  Readings of points the paper leaves open are listed in
 // the repository's design notes; the ones used here are restated at each function.
@@ -76,6 +77,7 @@ typedef struct {
   const int32_t* putype;     // 0 fixed, 1 zeroGradient, 2 empty
   const int32_t* pptype;     // 0 zeroGradient, 1 fixed, 2 Windkessel, 3 empty
   const int32_t* pwk;        // Windkessel id or -1
+  int32_t nonorth;           // correction scheme: 0 over-relaxed, 1 minimum, 2 orthogonal, 3 none
 } om_mesh;
 
 typedef struct {
@@ -112,23 +114,41 @@ std::vector<int> bc_codes(const om_mesh& m, int table) {
 
 inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-// d_f, delta_f, k_f of an internal face (over-relaxed split, eq. nonortho_flux)
+enum { NONORTH_OVERRELAXED = 0, NONORTH_MINIMUM = 1, NONORTH_ORTHOGONAL = 2, NONORTH_NONE = 3 };
+
+// Split of the face vector S into Delta = delta d (along the cell-to-cell vector d) and k = S - Delta
+// (Sec. "Diffusive flux discretization", eq. nonortho_flux), so that the orthogonal part of the
+// face-normal gradient is delta (phi_N - phi_O).  The schemes differ only in |Delta|:
+//   over-relaxed  |Delta| = |S| / |S^ . d^|   ->  delta = |S|^2 / (S.d)
+//   minimum       Delta = (S . d^) d^         ->  delta = (S.d) / |d|^2
+//   orthogonal    |Delta| = |S|               ->  delta = |S| / |d|
+//   none          two-point stencil of eq. diff_ortho: delta = |S| / |d| and no correction (k = 0)
+double face_split(int scheme, const double S[3], const double d[3], double k[3]) {
+  double delta;
+  if (scheme == NONORTH_MINIMUM) delta = dot3(S, d) / dot3(d, d);
+  else if (scheme == NONORTH_ORTHOGONAL || scheme == NONORTH_NONE) delta = std::sqrt(dot3(S, S)) / std::sqrt(dot3(d, d));
+  else delta = dot3(S, S) / dot3(S, d);
+  for (int c = 0; c < 3; ++c) k[c] = (scheme == NONORTH_NONE) ? 0.0 : S[c] - delta * d[c];
+  return delta;
+}
+
+// d_f, delta_f, k_f of an internal face
 void face_geom(const om_mesh& m, int f, double d[3], double& delta, double k[3]) {
   const double* S = m.Sf + 3 * f;
   const double* CO = m.C + 3 * m.owner[f];
   const double* CN = m.C + 3 * m.nbr[f];
   for (int c = 0; c < 3; ++c) d[c] = CN[c] - CO[c];
-  delta = dot3(S, S) / dot3(S, d);
-  for (int c = 0; c < 3; ++c) k[c] = S[c] - delta * d[c];
+  delta = face_split(m.nonorth, S, d, k);
 }
 
-// delta_b of a boundary face: d_b = Cf - C_O, no non-orthogonal part on boundaries
+// delta_b of a boundary face: the same scheme with d_b = Cf - C_O; the correction k_b is dropped
 double bface_delta(const om_mesh& m, int f) {
   const double* S = m.Sf + 3 * f;
   const double* CO = m.C + 3 * m.owner[f];
   const double* Cf = m.Cf + 3 * f;
   double d[3] = {Cf[0] - CO[0], Cf[1] - CO[1], Cf[2] - CO[2]};
-  return dot3(S, S) / dot3(S, d);
+  double k[3];
+  return face_split(m.nonorth, S, d, k);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -218,7 +238,7 @@ void div(const om_mesh& m, int scheme, int ncomp, const std::vector<int>& code, 
   }
 }
 
-// Laplacian with over-relaxed non-orthogonal correction (eqs. diff_ortho, nonortho_flux):
+// Laplacian with non-orthogonal correction (scheme of face_split) (eqs. diff_ortho, nonortho_flux):
 // L_i = sum_f sigma G_f [delta_f (phi_N - phi_O) + k_f . (w g_O + (1-w) g_N)]
 //       + sum_{b fixed} G_b delta_b (phi_b - phi_O);  zeroGradient boundaries add nothing.
 // The face gradient in the correction is the linear interpolate of the given cell gradients.
@@ -708,7 +728,7 @@ std::vector<int> rcm_order(const om_mesh& m) {
 // ================================================================================================
 extern "C" {
 
-int oracle_version(void) { return 1; }
+int oracle_version(void) { return 2; }  // 2: om_mesh carries the correction scheme
 
 // Renumbering.  rcm = 0 keeps the cell order.  Outputs (new -> old where a permutation):
 //  cell_perm[nc], face_perm[nfi], face_flip[nfi], owner[nfi], nbr[nfi], own_start[nc+1],

@@ -23,7 +23,12 @@ class OmMesh(C.Structure):
     _fields_ = [("nc", C.c_int32), ("nfi", C.c_int32), ("nfb", C.c_int32), ("npatch", C.c_int32),
                 ("owner", _i32p), ("nbr", _i32p), ("Sf", _f64p), ("Cf", _f64p), ("C", _f64p),
                 ("V", _f64p), ("w", _f64p), ("pstart", _i32p), ("psize", _i32p), ("putype", _i32p),
-                ("pptype", _i32p), ("pwk", _i32p)]
+                ("pptype", _i32p), ("pwk", _i32p), ("nonorth", C.c_int32)]
+
+
+# Non-orthogonal correction schemes (Sec. "Diffusive flux discretization"); a mesh selects one through
+# mesh.meta["nonorth"] (default: over-relaxed).
+NONORTH = {"overrelaxed": 0, "minimum": 1, "orthogonal": 2, "none": 3}
 
 
 class OmPisoParams(C.Structure):
@@ -41,6 +46,8 @@ def lib():
             _b.build()
         _LIB = C.CDLL(path)
         _LIB.oracle_version.restype = C.c_int
+        if _LIB.oracle_version() != 2:
+            raise RuntimeError(f"{path} is stale (version {_LIB.oracle_version()}); rebuild the oracle")
     return _LIB
 
 
@@ -53,9 +60,11 @@ class _Hold:
 
 
 def om(mesh):
-    """Build (and cache on the mesh object) the C view of a meshgen.Mesh."""
+    """Build (and cache on the mesh object) the C view of a meshgen.Mesh, with the correction scheme
+    named by mesh.meta["nonorth"]."""
+    scheme = NONORTH[mesh.meta.get("nonorth", "overrelaxed")]
     cached = getattr(mesh, "_om", None)
-    if cached is not None:
+    if cached is not None and cached[3] == scheme:
         return cached[0]
     h = _Hold()
     h.owner = np.ascontiguousarray(mesh.owner, dtype=np.int32)
@@ -73,8 +82,8 @@ def om(mesh):
     s = OmMesh(mesh.n_cells, mesh.n_internal_faces, mesh.n_boundary_faces, len(mesh.patches),
                _p(h.owner, _i32p), _p(h.nbr, _i32p), _p(h.Sf), _p(h.Cf), _p(h.C), _p(h.V), _p(h.w),
                _p(h.pstart, _i32p), _p(h.psize, _i32p), _p(h.putype, _i32p), _p(h.pptype, _i32p),
-               _p(h.pwk, _i32p))
-    mesh._om = (C.byref(s), s, h)
+               _p(h.pwk, _i32p), scheme)
+    mesh._om = (C.byref(s), s, h, scheme)
     return mesh._om[0]
 
 

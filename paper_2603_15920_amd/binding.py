@@ -21,6 +21,8 @@ SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
 KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
 TO_INTERNAL, FROM_INTERNAL = 0, 1
 RENUMBER_RCM = 1
+# non-orthogonal correction schemes (a two-bit field of the mesh flags), keyed like mesh.meta["nonorth"]
+NONORTH = {"overrelaxed": 0, "minimum": 2, "orthogonal": 4, "none": 6}
 OK, WARN_NOT_CONVERGED, WARN_BREAKDOWN = 0, 1, 2
 TUNE_KNOBS = ["interp_f64", "interp_f32", "grad_f64", "grad_f32", "div_f64", "div_f32", "laplacian_f64",
               "laplacian_f32", "ldu_spmv_f64", "ldu_spmv_f32", "pcg_grid"]
@@ -477,11 +479,15 @@ class Context:
 
 
 class Mesh:
-    """A mesh uploaded to the device (internal order).  Keeps the meshgen.Mesh for user-order sizes."""
+    """A mesh uploaded to the device (internal order).  Keeps the meshgen.Mesh for user-order sizes.
+    flags=None: RCM order and the correction scheme named by mesh.meta["nonorth"] (over-relaxed if
+    absent)."""
 
-    def __init__(self, ctx, mesh, flags=RENUMBER_RCM, seg_cell_start=None):
+    def __init__(self, ctx, mesh, flags=None, seg_cell_start=None):
         self.ctx = ctx
         self.src = mesh
+        if flags is None:
+            flags = RENUMBER_RCM | NONORTH[mesh.meta.get("nonorth", "overrelaxed")]
         if seg_cell_start is None:
             self.h = difvm_mesh_create(ctx.h, mesh, flags)
         else:

@@ -121,6 +121,21 @@ inline double dot(const double* a, const double* b) { return a[0] * b[0] + a[1] 
 
 }  // namespace
 
+// S = Delta + k with Delta = delta d along the cell-to-cell vector d (eq. nonortho_flux); the scheme
+// fixes |Delta|: over-relaxed |S|/|S^.d^|, minimum S.d^, orthogonal |S|; "none" keeps the two-point
+// stencil of eq. diff_ortho (|Delta| = |S|) and drops k.  Returns delta, writes k.
+static double split_face(uint32_t scheme, const double* S, const double* dv, double* k) {
+  double delta;
+  if (scheme == DIFVM_NONORTH_MINIMUM)
+    delta = dot(S, dv) / dot(dv, dv);
+  else if (scheme == DIFVM_NONORTH_ORTHOGONAL || scheme == DIFVM_NONORTH_NONE)
+    delta = std::sqrt(dot(S, S)) / std::sqrt(dot(dv, dv));
+  else
+    delta = dot(S, S) / dot(S, dv);
+  for (int c = 0; c < 3; ++c) k[c] = scheme == DIFVM_NONORTH_NONE ? 0.0 : S[c] - delta * dv[c];
+  return delta;
+}
+
 void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots, int nseg,
                   const int32_t* seg_start) {
   if (!d) fail(DIFVM_ERR_INVALID_ARG, "mesh descriptor is NULL");
@@ -129,6 +144,8 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
   if (nc <= 0 || nfi < 0 || nfb < 0 || np < 0) fail(DIFVM_ERR_INVALID_MESH, "negative or zero counts");
   if (!d->owner || (nfi && !d->neighbour) || !d->Sf || !d->Cf || !d->C || !d->V || (np && !d->patches))
     fail(DIFVM_ERR_INVALID_ARG, "NULL mesh array");
+  if (flags & ~(DIFVM_RENUMBER_RCM | DIFVM_NONORTH_MASK)) fail(DIFVM_ERR_INVALID_ARG, "unknown mesh flag bits");
+  const uint32_t scheme = flags & DIFVM_NONORTH_MASK;
   const int nf = nfi + nfb;
   for (int f = 0; f < nf; ++f)
     if (d->owner[f] < 0 || d->owner[f] >= nc) fail(DIFVM_ERR_INVALID_MESH, "owner index out of range");
@@ -329,9 +346,7 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
     const double* CO = &L.C[3 * L.owner[f]];
     const double* CN = &L.C[3 * L.neighbour[f]];
     double dv[3] = {CN[0] - CO[0], CN[1] - CO[1], CN[2] - CO[2]};
-    double delta = dot(S, S) / dot(S, dv);
-    L.delta[f] = delta;
-    for (int c = 0; c < 3; ++c) L.k[3 * f + c] = S[c] - delta * dv[c];
+    L.delta[f] = split_face(scheme, S, dv, &L.k[3 * f]);
   }
   for (int b = 0; b < nfb; ++b) {
     int g = nfi + L.bface_perm[b];
@@ -343,7 +358,8 @@ void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool 
     const double* CO = &L.C[3 * L.bowner[b]];
     double dv[3] = {L.Cf[3 * f] - CO[0], L.Cf[3 * f + 1] - CO[1], L.Cf[3 * f + 2] - CO[2]};
     const double* S = &L.S[3 * f];
-    L.delta[f] = dot(S, S) / dot(S, dv);
+    double kb[3];
+    L.delta[f] = split_face(scheme, S, dv, kb);  // no correction on boundary faces: kb is unused
   }
 
   // ---- boundary tables and Windkessel lists (patch ranges are unchanged by the sort) ----

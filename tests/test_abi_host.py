@@ -63,11 +63,13 @@ def shuffled(m, seed):
 
 @pytest.mark.parametrize("name", sorted(MESHES))
 @pytest.mark.parametrize("shuffle", [False, True])
-def test_renumbering_bit_exact(name, shuffle):
+@pytest.mark.parametrize("scheme", sorted(B.NONORTH))
+def test_renumbering_bit_exact(name, shuffle, scheme):
     m = MESHES[name]()
     if shuffle:
         m = shuffled(m, 7)
-    lib = B.difvm_mesh_renumber_host(m, geometry=True)
+    m.meta["nonorth"] = scheme
+    lib = B.difvm_mesh_renumber_host(m, flags=B.RENUMBER_RCM | B.NONORTH[scheme], geometry=True)
     ora = O.renumber(m)
     for k in ("cell_perm", "face_perm", "face_flip", "owner", "neighbour", "own_start", "losort", "losort_start",
               "bface_perm", "bowner"):
@@ -95,6 +97,14 @@ def test_identity_order_flag():
     r = B.difvm_mesh_renumber_host(m, flags=0)
     assert np.array_equal(r["cell_perm"], np.arange(m.n_cells))
     assert np.array_equal(r["cell_perm"], O.renumber(m, rcm=False)["cell_perm"])
+
+
+def test_unknown_flag_bits_rejected():
+    m = mg.kuhn_cube(3, patches="walls")
+    for flags in (8, 16, 1 << 31):
+        with pytest.raises(B.DifvmError) as e:
+            B.difvm_mesh_renumber_host(m, flags=B.RENUMBER_RCM | flags)
+        assert e.value.status == B.ERR_INVALID_ARG
 
 
 def _expect_invalid(m, code=B.ERR_INVALID_MESH):
