@@ -88,6 +88,7 @@ typedef struct {
   int32_t p_ref_cell;        // user numbering
   double p_ref_value;
   double tol_tangent;        // tolerance of the tangent (implicitly differentiated) solves
+  int32_t conv;              // convection scheme: 0 upwind, 1 linear, 2 SOU, 3 QUICK (see deferred_correction)
 } om_piso_params;
 }
 
@@ -234,6 +235,51 @@ void div(const om_mesh& m, int scheme, int ncomp, const std::vector<int>& code, 
       if (scheme == 0) pf = T(1.0);
       else pf = (code[b] == BC_FIXED) ? psib[b * ncomp + c] : psi[O * ncomp + c];
       out[O * ncomp + c] += flux[f] * pf;
+    }
+  }
+}
+
+enum { CONV_UPWIND = 0, CONV_LINEAR = 1, CONV_SOU = 2, CONV_QUICK = 3 };
+
+// Deferred correction of the convection term (eq. deferred_correction): the upwind face value stays
+// implicit and F_f (phi_f^HO - phi_f^U) is added explicitly, i.e. as a source on the right-hand side:
+//   src_i += - sum_f sigma F_f (phi_f^HO - phi_f^U)          (internal faces; sigma = +1 owner, -1 neighbour)
+// with C the upwind cell of f (the owner when F >= 0, eq. upwind), D the other cell, g the given
+// cell gradients and phi_f^U = phi_C.  The higher-order face values:
+//   linear  phi^HO = w phi_O + (1-w) phi_N                     (central, Table "schemes")
+//   SOU     phi^HO = phi_C + g_C . (x_f - x_C)                 (eq. sou)
+//   QUICK   phi^HO = phi_C + (phi_D - phi_C)/4 + g_C . (x_D - x_C)/4
+// QUICK here is the classical upwind-biased quadratic 3/8 phi_D + 6/8 phi_C - 1/8 phi_U of a uniform
+// line of cells with the far-upwind value, which an unstructured mesh does not have, replaced by
+// phi_U = phi_D - 2 g_C . (x_D - x_C); on a uniform line with the central-difference gradient it is the
+// classical stencil exactly.  Boundary faces carry no correction (their face value is the boundary
+// value or the owner value for every scheme).  Upwind adds nothing.
+template <class T>
+void deferred_correction(const om_mesh& m, int conv, int ncomp, const T* F, const T* phi, const T* g, T* src) {
+  if (conv == CONV_UPWIND) return;
+  for (int f = 0; f < m.nfi; ++f) {
+    int O = m.owner[f], N = m.nbr[f];
+    bool own_up = val(F[f]) >= 0.0;
+    int Cc = own_up ? O : N, Dc = own_up ? N : O;
+    const double* xf = m.Cf + 3 * f;
+    const double* xC = m.C + 3 * Cc;
+    const double* xD = m.C + 3 * Dc;
+    double w = m.w[f];
+    for (int c = 0; c < ncomp; ++c) {
+      const T* gC = g + ((size_t)Cc * ncomp + c) * 3;
+      T pC = phi[(size_t)Cc * ncomp + c], pD = phi[(size_t)Dc * ncomp + c];
+      T ho;
+      if (conv == CONV_LINEAR) {
+        ho = w * phi[(size_t)O * ncomp + c] + (1.0 - w) * phi[(size_t)N * ncomp + c];
+      } else if (conv == CONV_SOU) {
+        ho = pC + (gC[0] * (xf[0] - xC[0]) + gC[1] * (xf[1] - xC[1]) + gC[2] * (xf[2] - xC[2]));
+      } else {
+        T gd = gC[0] * (xD[0] - xC[0]) + gC[1] * (xD[1] - xC[1]) + gC[2] * (xD[2] - xC[2]);
+        ho = pC + 0.25 * (pD - pC) + 0.25 * gd;
+      }
+      T t = F[f] * (ho - pC);
+      src[(size_t)O * ncomp + c] -= t;
+      src[(size_t)N * ncomp + c] += t;
     }
   }
 }
@@ -491,7 +537,8 @@ struct Piso {
       for (int b = 0; b < nfb; ++b) if (wk_of_face[b] == j) pbv[b] = po;
     }
     // S1: momentum LDU from the lagged flux: implicit Euler + implicit upwind + implicit orthogonal
-    // diffusion; the non-orthogonal diffusion part is explicit from grad(U^n).
+    // diffusion; the non-orthogonal diffusion part and the deferred correction of a higher-order
+    // convection scheme are explicit from U^n and grad(U^n).
     std::vector<T> gU((size_t)nc * 9);
     grad(m, 3, codeU, U.data(), Ub.data(), gU.data());
     std::vector<T> dM(nc), uM(nfi), lM(nfi), bM((size_t)nc * 3);
@@ -527,6 +574,8 @@ struct Piso {
         dM[O] += phi[nfi + b];
       }
     }
+    // higher-order convection as an explicit source from U^n (part of b, hence of H in every corrector)
+    deferred_correction(m, prm.conv, 3, phi.data(), U.data(), gU.data(), bM.data());
     // S2: predictor M U* = b - V grad(p^n), BiCGStab per component from U^n
     std::vector<T> gp((size_t)nc * 3);
     grad(m, 1, codeP, p.data(), pbv.data(), gp.data());
@@ -728,7 +777,7 @@ std::vector<int> rcm_order(const om_mesh& m) {
 // ================================================================================================
 extern "C" {
 
-int oracle_version(void) { return 2; }  // 2: om_mesh carries the correction scheme
+int oracle_version(void) { return 3; }  // 3: convection scheme in the PISO parameters
 
 // Renumbering.  rcm = 0 keeps the cell order.  Outputs (new -> old where a permutation):
 //  cell_perm[nc], face_perm[nfi], face_flip[nfi], owner[nfi], nbr[nfi], own_start[nc+1],
@@ -859,6 +908,14 @@ int oracle_spmv(const om_mesh* m, int ncomp, int transpose, const double* diag, 
   return 0;
 }
 
+// Deferred-correction source alone (see deferred_correction): src[nc*ncomp] = - sum_f sigma F (phi^HO - phi^U)
+int oracle_deferred_correction(const om_mesh* m, int conv, int ncomp, const double* flux, const double* phi,
+                               const double* g, double* src) {
+  std::fill(src, src + (size_t)m->nc * ncomp, 0.0);
+  deferred_correction(*m, conv, ncomp, flux, phi, g, src);
+  return 0;
+}
+
 // Orthogonal (implicit) part of -div(G grad phi) as an SPD LDU matrix K with boundary source:
 // upper_f = -G_f delta_f; diag_i = sum G_f delta_f + sum_{b fixed} G_b delta_b;
 // rhs_bc_i = sum_{b fixed} G_b delta_b phi_b.
@@ -950,12 +1007,13 @@ int oracle_bicgstab(const om_mesh* m, int ncomp, const double* diag, const doubl
 // Passive scalar over one time step with a given face flux (the momentum predictor's discretisation
 // applied to one transported scalar c with diffusivity D, Sec. "Spatial discretization"):
 //   (V/dt)(c^{n+1} - c^n) + sum_f F_f c_f^upwind - D sum_f (delta_f (c_N - c_O) + k_f . grad c^n_f) = 0,
-// convection implicit upwind of the given flux (tie F = 0 to the owner), diffusion implicit in its
-// orthogonal part and explicit in the over-relaxed correction from the Gauss gradient of c^n;
+// convection implicit upwind of the given flux (tie F = 0 to the owner) plus the deferred correction
+// of the scheme conv from c^n, diffusion implicit in its orthogonal part and explicit in the
+// non-orthogonal correction from the Gauss gradient of c^n;
 // boundary faces by the table's codes with values cb (fixed) or c of the owner (zeroGradient).
 // Solved by BiCGStab from c^n; c is overwritten.
-int oracle_transport_scalar(const om_mesh* m, int table, double D, double dt, const double* phi, const double* cb,
-                            double* c, double tol, int maxit, int32_t* iters, double* res) {
+int oracle_transport_scalar(const om_mesh* m, int table, int conv, double D, double dt, const double* phi,
+                            const double* cb, double* c, double tol, int maxit, int32_t* iters, double* res) {
   std::vector<int> code = bc_codes(*m, table);
   std::vector<double> g((size_t)m->nc * 3);
   grad<double>(*m, 1, code, c, cb, g.data());
@@ -989,6 +1047,7 @@ int oracle_transport_scalar(const om_mesh* m, int table, double D, double dt, co
       diag[O] += phi[f];
     }
   }
+  deferred_correction(*m, conv, 1, phi, c, g.data(), b.data());
   SolveInfo si = bicgstab(*m, diag.data(), upper.data(), lower.data(), b.data(), c, tol, maxit);
   *iters = si.iters;
   *res = si.res;
