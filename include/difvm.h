@@ -60,6 +60,10 @@ enum { DIFVM_BC_U = 0, DIFVM_BC_P = 1, DIFVM_BC_ALL_FIXED = 2, DIFVM_BC_ALL_ZERO
 
 /* face value used by the divergence operator (eqs. conv_face_flux, upwind) */
 enum { DIFVM_SCHEME_ONE = 0, DIFVM_SCHEME_UPWIND = 1, DIFVM_SCHEME_LINEAR = 2 };
+/* convection schemes of the momentum predictor and scalar transport (Sec. "Spatial discretization",
+ * scheme table): upwind is implicit; the others add the deferred correction of eq.
+ * deferred_correction to an implicit upwind matrix (see difvm_op_deferred_correction) */
+enum { DIFVM_CONV_UPWIND = 0, DIFVM_CONV_LINEAR = 1, DIFVM_CONV_SOU = 2, DIFVM_CONV_QUICK = 3 };
 
 /* array kinds for difvm_permute */
 enum {
@@ -247,7 +251,22 @@ difvm_status difvm_op_grad(const difvm_mesh* mesh, int dtype, int ncomp, int bc,
 difvm_status difvm_op_div(const difvm_mesh* mesh, int dtype, int scheme, int ncomp, int bc, const void* flux,
                           const void* psi, const void* psi_b, void* out);
 
-/* Laplacian with over-relaxed non-orthogonal correction (eqs. diff_ortho, nonortho_flux):
+/* Deferred-correction source of a convection scheme (eq. deferred_correction): the explicit part
+ * F_f (phi_f^HO - phi_f^U) of every internal face moved to the right-hand side,
+ *   out_i = - sum_f sigma F_f (phi_f^HO - phi_f^U),   sigma = +1 for the owner, -1 for the neighbour,
+ * with C the upwind cell (the owner when F >= 0), D the other cell, phi^U = phi_C and
+ *   DIFVM_CONV_LINEAR  phi^HO = w phi_O + (1-w) phi_N
+ *   DIFVM_CONV_SOU     phi^HO = phi_C + g_C . (x_f - x_C)                  (eq. sou)
+ *   DIFVM_CONV_QUICK   phi^HO = phi_C + (phi_D - phi_C)/4 + g_C . (x_D - x_C)/4
+ *   DIFVM_CONV_UPWIND  no correction (out = 0).
+ * (QUICK: the uniform-grid 3/8 phi_D + 6/8 phi_C - 1/8 phi_U with the far-upwind value taken as
+ * phi_D - 2 g_C . (x_D - x_C).)  Boundary faces carry no correction.  dtype F64 only (F32:
+ * DIFVM_ERR_UNSUPPORTED).  flux[Fi+Fb] (internal orientation), phi[Nc*ncomp], grad[Nc*ncomp*3] (the
+ * cell gradients, e.g. difvm_op_grad) -> out[Nc*ncomp]. */
+difvm_status difvm_op_deferred_correction(const difvm_mesh* mesh, int dtype, int conv, int ncomp, const void* flux,
+                                          const void* phi, const void* grad, void* out);
+
+/* Laplacian with non-orthogonal correction (the mesh's DIFVM_NONORTH_* scheme; eqs. diff_ortho, nonortho_flux):
  * L_i = sum_f sigma G_f [delta_f (phi_N - phi_O) + k_f . (w g_O + (1-w) g_N)]
  *       + sum_{b fixed} G_b delta_b (phi_b - phi_O).
  * gamma_f[Fi+Fb] or NULL (= 1), phi[Nc], grad_phi[Nc*3] (given), phi_b[Fb] -> out[Nc]. */
@@ -307,6 +326,10 @@ typedef struct {
                              p_ref_cell-th user cell of each such segment (the user cell itself
                              for a one-segment mesh)                                          */
   double p_ref_value;
+  int32_t conv;           /* convection scheme (DIFVM_CONV_*) of the predictor and of scalar
+                             transport; the deferred correction is evaluated once per step from
+                             U^n and its Gauss gradient and is part of the momentum source b, so
+                             it also enters H in every corrector                               */
 } difvm_piso_params;
 
 typedef struct {
@@ -348,8 +371,9 @@ difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi,
  * paper's convection-diffusion discretisation, Sec. "Spatial discretization", applied to one scalar
  * c): (V/dt)(c' - c) + sum_f F_f c'_upwind - D sum_f (delta_f (c'_N - c'_O) + k_f . grad(c)_f) = 0,
  * i.e. the momentum predictor's matrix with one component and diffusivity D >= 0: implicit Euler,
- * implicit upwind of the flux (tie F = 0 to the owner), implicit orthogonal diffusion, explicit
- * over-relaxed correction from the Gauss gradient of c.  bc selects the boundary table (DIFVM_BC_*);
+ * implicit upwind of the flux (tie F = 0 to the owner) plus the deferred correction of the PISO
+ * object's convection scheme (params.conv) from c, implicit orthogonal diffusion, explicit
+ * non-orthogonal correction from the Gauss gradient of c.  bc selects the boundary table (DIFVM_BC_*);
  * c_b[Fb] (device, user boundary order) gives the values on its fixed faces; c[Nc] (device, user order)
  * holds c on entry and c' on return.  Right-Jacobi BiCGStab from c with the PISO object's tol_u and
  * maxit_u; stats (host, may be NULL) receives iterations and residual in component 0.  Synchronises.

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libdifvm.so")
 F64, F32 = 0, 1
 BC_U, BC_P, BC_ALL_FIXED, BC_ALL_ZEROGRAD = 0, 1, 2, 3
 SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
+# convection schemes of the PISO predictor and scalar transport (deferred correction beyond upwind)
+CONV = {"upwind": 0, "linear": 1, "sou": 2, "quick": 3}
 KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
 TO_INTERNAL, FROM_INTERNAL = 0, 1
 RENUMBER_RCM = 1
@@ -73,7 +75,7 @@ class SolveStats(C.Structure):
 class PisoParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("nu", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
                 ("tol_p", C.c_double), ("tol_u", C.c_double), ("maxit_p", C.c_int32), ("maxit_u", C.c_int32),
-                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double)]
+                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("conv", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -104,6 +106,7 @@ _SIGS = {
     "difvm_op_interp": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
     "difvm_op_grad": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
     "difvm_op_div": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
+    "difvm_op_deferred_correction": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "difvm_op_laplacian": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "difvm_ldu_spmv": (C.c_int32, [_vp, C.c_int, C.c_int, C.POINTER(Ldu), _vp, _vp]),
     "difvm_ldu_assemble_laplace": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.POINTER(Ldu), _vp]),
@@ -302,6 +305,12 @@ def difvm_op_grad(m, ncomp, bc, phi, phi_b, grad):
                   "difvm_op_grad")
 
 
+def difvm_op_deferred_correction(m, conv, ncomp, flux, phi, grad, out):
+    return _check(lib().difvm_op_deferred_correction(m, _dtype_code(out), CONV[conv] if isinstance(conv, str) else conv,
+                                                     ncomp, _ptr(flux), _ptr(phi), _ptr(grad), _ptr(out)),
+                  "difvm_op_deferred_correction")
+
+
 def difvm_op_div(m, scheme, ncomp, bc, flux, psi, psi_b, out):
     return _check(lib().difvm_op_div(m, _dtype_code(flux), scheme, ncomp, bc, _ptr(flux), _ptr(psi), _ptr(psi_b),
                                      _ptr(out)), "difvm_op_div")
@@ -347,8 +356,10 @@ def difvm_solve_bicgstab(m, A, ncomp, b, x, tol, maxit):
     return status, list(st.iters)[:ncomp], list(st.residual)[:ncomp]
 
 
-def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0):
-    return PisoParams(C.sizeof(PisoParams), nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value)
+def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0,
+                conv="upwind"):
+    return PisoParams(C.sizeof(PisoParams), nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value,
+                      CONV[conv])
 
 
 def difvm_piso_create(m, params):

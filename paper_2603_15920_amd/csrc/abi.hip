@@ -164,6 +164,16 @@ static void upload_mesh(difvm_mesh* m) {
   d.face_perm = up_vec(m, L.face_perm);
   d.bface_perm = up_vec(m, L.bface_perm);
   d.face_flip = up_vec(m, L.face_flip);
+  std::vector<double4> rO(nfi), rN(nfi);
+  for (int f = 0; f < nfi; ++f) {
+    const double* xf = &L.Cf[3 * f];
+    const double* xO = &L.C[3 * L.owner[f]];
+    const double* xN = &L.C[3 * L.neighbour[f]];
+    rO[f] = make_double4(xf[0] - xO[0], xf[1] - xO[1], xf[2] - xO[2], 0.0);
+    rN[f] = make_double4(xf[0] - xN[0], xf[1] - xN[1], xf[2] - xN[2], 0.0);
+  }
+  d.face_rO = up_vec(m, rO);
+  d.face_rN = up_vec(m, rN);
   DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
 }
 
@@ -386,6 +396,19 @@ difvm_status difvm_op_div(const difvm_mesh* m, int dtype, int scheme, int ncomp,
   return DIFVM_OK;
 }
 
+difvm_status difvm_op_deferred_correction(const difvm_mesh* m, int dtype, int conv, int ncomp, const void* flux,
+                                          const void* phi, const void* grad, void* out) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_dtype(dtype); check_ncomp(ncomp);
+  DIFVM_CHECK(dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "deferred correction is F64 only");
+  DIFVM_CHECK(conv >= DIFVM_CONV_UPWIND && conv <= DIFVM_CONV_QUICK, DIFVM_ERR_INVALID_ARG, "unknown convection scheme");
+  check_ptr(out, "out");
+  if (conv != DIFVM_CONV_UPWIND) { check_ptr(flux, "flux"); check_ptr(phi, "phi"); check_ptr(grad, "grad"); }
+  op_deferred_correction(m, conv, ncomp, (const double*)flux, (const double*)phi, (const double*)grad, (double*)out);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
 difvm_status difvm_op_laplacian(const difvm_mesh* m, int dtype, int bc, const void* gamma_f, const void* phi,
                                 const void* grad_phi, const void* phi_b, void* out) {
   DIFVM_API_BEGIN
@@ -435,7 +458,7 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
   double* gU = dalloc<double>((size_t)9 * m->d.nc);
   try {
     op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
-    op_assemble_momentum(m, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
+    op_assemble_momentum(m, DIFVM_CONV_UPWIND, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
                          (double*)A->upper, (double*)A->lower, nullptr, (double*)b);
     DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
   } catch (...) {

@@ -19,6 +19,7 @@
 #include <cstring>
 
 #include "abi_util.h"
+#include "dc.h"
 #include "device.h"
 #include "ops.h"
 #include "piso_internal.h"
@@ -315,10 +316,15 @@ __global__ __launch_bounds__(BLOCK) void k_adj_rau(int nc, const double* __restr
   dbar[i] -= rAUbar[i] * rAU[i] / dM[i];
 }
 
-// b = V/dt U^n + fixed-U boundary terms + nu sum sigma k.interp(grad U^n):
-// Ubar^n = V/dt bbar (written), gUbar_i = nu sum_slots wself sigma (bbar_i - bbar_j) (x) k
+// b = V/dt U^n + fixed-U boundary terms + nu sum sigma k.interp(grad U^n) + deferred correction:
+// Ubar^n = V/dt bbar (written), gUbar_i = nu sum_slots wself sigma (bbar_i - bbar_j) (x) k; the
+// deferred correction t_f = F_f Delta_f(U^n, grad U^n) (b_O -= t, b_N += t) adds, with
+// Deltabar = sF (bbar_i - bbar_j) seen from cell i (sF = -F owner side, +F neighbour side), the
+// cell's own partial derivatives of Delta (upwind branch frozen)
+template <int CONV>
 __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const double* __restrict__ nu_cell, double dt,
-                                                    const double* __restrict__ bbar,
+                                                    const double* __restrict__ bbar, const double* __restrict__ flux,
+                                                    const double4* __restrict__ rO, const double4* __restrict__ rN,
                                                     double* __restrict__ Ubar0, double* __restrict__ gUbar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
@@ -326,6 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
   double nu = nu_cell[i];
   const double* bi = bbar + 3 * (size_t)i;
   double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double ub[3] = {0, 0, 0};
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
@@ -346,28 +353,70 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
       gu[c][1] += t * kd.y;
       gu[c][2] += t * kd.z;
     }
+    if constexpr (CONV != DIFVM_CONV_UPWIND) {
+      double F = flux[f];
+      bool up = dc_self_up(F, nb);
+      double sF = nb ? F : -F;
+      double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double Db = sF * (bi[c] - bj[c]);
+        if constexpr (CONV == DIFVM_CONV_LINEAR) {
+          ub[c] += Db * (wself - (up ? 1.0 : 0.0));
+        } else if constexpr (CONV == DIFVM_CONV_SOU) {
+          if (up) {
+            gu[c][0] += Db * rs.x;
+            gu[c][1] += Db * rs.y;
+            gu[c][2] += Db * rs.z;
+          }
+        } else {
+          ub[c] += up ? -0.25 * Db : 0.25 * Db;
+          if (up) {
+            gu[c][0] += 0.25 * Db * (rs.x - ro.x);
+            gu[c][1] += 0.25 * Db * (rs.y - ro.y);
+            gu[c][2] += 0.25 * Db * (rs.z - ro.z);
+          }
+        }
+      }
+    }
   }
   double vdt = m.V[i] / dt;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    Ubar0[3 * (size_t)i + c] = vdt * bi[c];
+    Ubar0[3 * (size_t)i + c] = vdt * bi[c] + ub[c];
 #pragma unroll
     for (int e = 0; e < 3; ++e) gUbar[9 * (size_t)i + 3 * c + e] = gu[c][e];
   }
 }
 
-// momentum coefficients -> lagged flux (upwind branch frozen at the forward's choice)
+// momentum coefficients (and the deferred correction t_f = F_f Delta_f, whose Delta is taken from
+// U^n and its gradient) -> lagged flux (upwind branch frozen at the forward's choice)
+template <int CONV>
 __global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, const int32_t* __restrict__ own_slot,
                                                    const int32_t* __restrict__ nbr_slot, const double* __restrict__ phi,
                                                    const double* __restrict__ valbar, const double* __restrict__ dbar,
                                                    const double* __restrict__ bbar, const double* __restrict__ Ub,
+                                                   const double* __restrict__ Un, const double* __restrict__ gUn,
+                                                   const double4* __restrict__ rO, const double4* __restrict__ rN,
                                                    double* __restrict__ phibar) {
   int f = blockIdx.x * BLOCK + threadIdx.x;
   if (f < m.nfi) {
     int O = m.own[f], N = m.nbr[f];
     double F = phi[f];
     double ub = valbar[own_slot[f]], lb = valbar[nbr_slot[f]];
-    phibar[f] = F >= 0.0 ? dbar[O] - lb : ub - dbar[N];
+    double v = F >= 0.0 ? dbar[O] - lb : ub - dbar[N];
+    if constexpr (CONV != DIFVM_CONV_UPWIND) {
+      bool up = dc_self_up(F, false);
+      double4 ro_ = rO[f], rn_ = rN[f];
+      double w = m.w[f];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double D = dc_delta<CONV>(up, w, Un[3 * (size_t)O + c], Un[3 * (size_t)N + c], gUn + 9 * (size_t)O + 3 * c,
+                                  gUn + 9 * (size_t)N + 3 * c, ro_, rn_);
+        v -= D * (bbar[3 * (size_t)O + c] - bbar[3 * (size_t)N + c]);
+      }
+    }
+    phibar[f] = v;
   } else if (f < m.nfi + m.nfb) {
     int b = f - m.nfi;
     int8_t cu = m.bcode[DIFVM_BC_U * m.nfb + b];
@@ -422,6 +471,7 @@ struct difvm_tape {
   double *HbyAbar = nullptr, *rAUbar = nullptr, *gbar = nullptr, *gUbar = nullptr, *Hbar = nullptr, *bbar = nullptr;
   double *dbar = nullptr, *valbar = nullptr, *valT = nullptr, *fHb = nullptr, *faF = nullptr, *fnc = nullptr;
   double *g = nullptr, *tmp = nullptr, *lam = nullptr, *mu = nullptr, *Ubar0 = nullptr, *wkbar = nullptr;
+  double* gUn = nullptr;  // grad U^n of the step being reversed (deferred-correction schemes)
   double *endU = nullptr, *endp = nullptr, *endphi = nullptr;
   std::vector<double> endpc;
   std::vector<void*> allocs;
@@ -484,6 +534,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
       r.rAU = tape_alloc(T, nc);
       r.wk_out = tape_alloc(T, 2 * nwk);
       r.pc_in = tape_alloc(T, nwk);
+      if (P->prm.conv != DIFVM_CONV_UPWIND) r.Un = tape_alloc(T, 3 * nc);
       for (int c = 0; c < ncorr; ++c) {
         r.Uin[c] = tape_alloc(T, 3 * nc);
         r.pold[c] = tape_alloc(T, nc);
@@ -501,6 +552,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     T->faF = tape_alloc(T, nf); T->fnc = tape_alloc(T, std::max<size_t>(1, d.nfi)); T->g = tape_alloc(T, nf);
     T->tmp = tape_alloc(T, 3 * nc); T->lam = tape_alloc(T, nc); T->mu = tape_alloc(T, 3 * nc);
     T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk);
+    if (P->prm.conv != DIFVM_CONV_UPWIND) T->gUn = tape_alloc(T, 9 * nc);
     T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
   } catch (...) {
     for (void* a : T->allocs) dfree(a);
@@ -610,10 +662,22 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
   k_adj_rau<<<Gc, BLOCK, 0, s>>>(d.nc, T->rAUbar, R.rAU, R.dM, T->dbar);
   // momentum source and coefficients
-  k_adj_bsrc<<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, T->bbar, T->Ubar0, T->gUbar);
-  k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);
-  k_adj_phi<<<Gf, BLOCK, 0, s>>>(mv, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar, T->bbar, P->Ub,
-                                 T->phibar);
+  if (prm.conv != DIFVM_CONV_UPWIND) op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, R.Un, P->Ub, T->gUn);
+  switch (prm.conv) {
+#define DIFVM_ADJ_SRC(CV)                                                                                            \
+  case CV:                                                                                                            \
+    k_adj_bsrc<CV><<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, T->bbar, phi_n, d.face_rO, d.face_rN, T->Ubar0,       \
+                                        T->gUbar);                                                                    \
+    k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);                                      \
+    k_adj_phi<CV><<<Gf, BLOCK, 0, s>>>(mv, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar, T->bbar,      \
+                                       P->Ub, R.Un, T->gUn, d.face_rO, d.face_rN, T->phibar);                         \
+    break;
+    DIFVM_ADJ_SRC(DIFVM_CONV_UPWIND)
+    DIFVM_ADJ_SRC(DIFVM_CONV_LINEAR)
+    DIFVM_ADJ_SRC(DIFVM_CONV_SOU)
+    DIFVM_ADJ_SRC(DIFVM_CONV_QUICK)
+#undef DIFVM_ADJ_SRC
+  }
   DIFVM_HIP(hipGetLastError());
   // Windkessel (tiny, on the host): pbv = p_o on each outlet
   int nwk = d.n_wk;

@@ -110,6 +110,8 @@ struct DMesh {
   // permutations for user <-> internal conversions
   int32_t *cell_perm, *face_perm, *bface_perm;
   uint8_t* face_flip;
+  // internal faces: x_f - x_O and x_f - x_N (w unused), for the higher-order convection schemes
+  double4 *face_rO, *face_rN;
 };
 
 }  // namespace difvm

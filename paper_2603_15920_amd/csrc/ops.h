@@ -18,10 +18,13 @@ void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const
                          double* upper, double* rhs);
 
 // momentum matrix of the predictor; writes face LDU (upper/lower, may be NULL) and/or per-slot values
-// (nu_cell: per-cell viscosity, NULL for nu everywhere)
-void op_assemble_momentum(const difvm_mesh* m, double nu, const double* nu_cell, double dt, const double* flux,
-                          const double* U, const double* gradU, const double* Ub, double* diag, double* upper,
-                          double* lower, double* slot_val, double* b);
+// (nu_cell: per-cell viscosity, NULL for nu everywhere); conv adds its deferred correction to b
+void op_assemble_momentum(const difvm_mesh* m, int conv, double nu, const double* nu_cell, double dt,
+                          const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
+                          double* upper, double* lower, double* slot_val, double* b);
+// deferred-correction source alone (F64): out = - sum_f sigma F (phi^HO - phi^U)
+void op_deferred_correction(const difvm_mesh* m, int conv, int ncomp, const double* flux, const double* phi,
+                            const double* grad, double* out);
 
 // ---- Krylov solvers on the cell-slot matrix (diag[Nc], val[n_slots]) ----
 struct SellMatrix {

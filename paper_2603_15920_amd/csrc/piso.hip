@@ -6,7 +6,8 @@
 //   S0  Windkessel: Q_j = sum of outlet fluxes (start of step), exact exponential update of p_c,
 //       p_o = p_c + Rp Q imposed on the outlet faces
 //   S1  grad U^n; momentum matrix (implicit Euler, implicit upwind of the lagged flux, implicit
-//       orthogonal diffusion, explicit over-relaxed correction) written straight into cell-slot form
+//       orthogonal diffusion, explicit non-orthogonal correction, explicit deferred correction of a
+//       higher-order convection scheme) written straight into cell-slot form
 //   S2  predictor M U* = b - V grad p^n by BiCGStab (three components, one matrix)
 //   S3  n_corr times: H = b - offdiag(U), HbyA = H / a_P, rAU = V / a_P; face flux of HbyA and the
 //       pressure matrix (negated to SPD form) with its explicit non-orthogonal source; PCG; flux
@@ -19,6 +20,7 @@
 #include <cstring>
 
 #include "abi_util.h"
+#include "dc.h"
 #include "device.h"
 #include "ops.h"
 
@@ -26,13 +28,15 @@ namespace difvm {
 
 // ---------------------------------------------------------------------------------------------
 // momentum matrix (cell kernel): diag, per-slot coefficients (owner slot: upper, neighbour slot:
-// lower), optional face LDU copies, and the right-hand side b (without the pressure gradient)
+// lower), optional face LDU copies, and the right-hand side b (without the pressure gradient),
+// including the deferred correction of convection scheme CONV (rO/rN: x_f - x_O, x_f - x_N)
 // ---------------------------------------------------------------------------------------------
-template <int NC>
+template <int NC, int CONV>
 __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int table, double nu_all,
                                                     const double* __restrict__ nu_cell, double dt,
                                                     const double* __restrict__ flux, const double* __restrict__ U,
                                                     const double* __restrict__ gU, const double* __restrict__ Ub,
+                                                    const double4* __restrict__ rO, const double4* __restrict__ rN,
                                                     double* __restrict__ diag, double* __restrict__ upper,
                                                     double* __restrict__ lower, double* __restrict__ slot_val,
                                                     double* __restrict__ b) {
@@ -42,9 +46,12 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
   double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
   double Vdt = m.V[i] / dt;
   double d = Vdt;
-  double bi[NC];
+  double bi[NC], ui[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) bi[c] = Vdt * U[NC * (size_t)i + c];
+  for (int c = 0; c < NC; ++c) {
+    ui[c] = U[NC * (size_t)i + c];
+    bi[c] = Vdt * ui[c];
+  }
   const double* gi = gU + 3 * NC * (size_t)i;
   const int8_t* codeU = m.bcode + table * m.nfb;
 #pragma unroll 4
@@ -82,6 +89,15 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
                       kd.z * (wself * gi[3 * c + 2] + (1.0 - wself) * gj[3 * c + 2]);
         bi[c] += sg * corr;
       }
+      if constexpr (CONV != DIFVM_CONV_UPWIND) {
+        double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
+        bool up = dc_self_up(F, nb);
+        double sF = nb ? F : -F;  // owner side: b -= F delta; neighbour side: b += F delta
+        const double* uj = U + NC * (size_t)j;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          bi[c] += sF * dc_delta<CONV>(up, wself, ui[c], uj[c], gi + 3 * c, gj + 3 * c, rs, ro);
+      }
     } else {
       int bf = sf - m.nfi;
       int8_t code = codeU[bf];
@@ -102,13 +118,107 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
   for (int c = 0; c < NC; ++c) b[NC * (size_t)i + c] = bi[c];
 }
 
-void op_assemble_momentum(const difvm_mesh* m, double nu, const double* nu_cell, double dt, const double* flux,
-                          const double* U, const double* gradU, const double* Ub, double* diag, double* upper,
-                          double* lower, double* slot_val, double* b) {
+// deferred-correction source alone: out_i = - sum_f sigma F_f (phi^HO - phi^U), internal faces
+template <int NC, int CONV>
+__global__ __launch_bounds__(BLOCK) void k_dc(MeshView<double> m, const double* __restrict__ flux,
+                                              const double* __restrict__ phi, const double* __restrict__ g,
+                                              const double4* __restrict__ rO, const double4* __restrict__ rN,
+                                              double* __restrict__ out) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  if (i >= m.nc) return;
+  SlotRange R = slots_of(m.slice_start, i);
+  double pi_[NC], acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    pi_[c] = phi[NC * (size_t)i + c];
+    acc[c] = 0.0;
+  }
+  const double* gi = g + 3 * NC * (size_t)i;
+  int n = row_len(m.nslot, i, R);
+  for (int k = 0; k < n; ++k) {
+    int at = R.base + k * SLICE;
+    int sf = m.slot_face[at];
+    if (sf == SLOT_PAD || sf >= m.nfi) continue;
+    bool nb = sf < 0;
+    int f = nb ? -sf - 1 : sf;
+    int j = m.slot_col[at];
+    double F = flux[f];
+    double w = m.w[f];
+    double wself = nb ? 1.0 - w : w;
+    double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
+    bool up = dc_self_up(F, nb);
+    double sF = nb ? F : -F;
+    const double* pj = phi + NC * (size_t)j;
+    const double* gj = g + 3 * NC * (size_t)j;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += sF * dc_delta<CONV>(up, wself, pi_[c], pj[c], gi + 3 * c, gj + 3 * c, rs, ro);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[NC * (size_t)i + c] = acc[c];
+}
+
+template <int NC>
+static void launch_dc(const difvm_mesh* m, int conv, const double* flux, const double* phi, const double* g,
+                      double* out) {
   const DMesh& d = m->d;
-  k_momentum<3><<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(view<double>(d), DIFVM_BC_U, nu, nu_cell, dt, flux, U,
-                                                            gradU, Ub, diag, upper, lower, slot_val, b);
+  MeshView<double> v = view<double>(d);
+  dim3 G(grid_for(d.nc)), B(BLOCK);
+  hipStream_t s = stream_of(m);
+  if (conv == DIFVM_CONV_LINEAR)
+    k_dc<NC, DIFVM_CONV_LINEAR><<<G, B, 0, s>>>(v, flux, phi, g, d.face_rO, d.face_rN, out);
+  else if (conv == DIFVM_CONV_SOU)
+    k_dc<NC, DIFVM_CONV_SOU><<<G, B, 0, s>>>(v, flux, phi, g, d.face_rO, d.face_rN, out);
+  else
+    k_dc<NC, DIFVM_CONV_QUICK><<<G, B, 0, s>>>(v, flux, phi, g, d.face_rO, d.face_rN, out);
   DIFVM_HIP(hipGetLastError());
+}
+
+void op_deferred_correction(const difvm_mesh* m, int conv, int ncomp, const double* flux, const double* phi,
+                            const double* grad, double* out) {
+  DIFVM_CHECK(conv >= DIFVM_CONV_UPWIND && conv <= DIFVM_CONV_QUICK, DIFVM_ERR_INVALID_ARG, "unknown convection scheme");
+  if (conv == DIFVM_CONV_UPWIND) {
+    DIFVM_HIP(hipMemsetAsync(out, 0, sizeof(double) * ncomp * (size_t)m->d.nc, stream_of(m)));
+    return;
+  }
+  if (ncomp == 1) launch_dc<1>(m, conv, flux, phi, grad, out);
+  else launch_dc<3>(m, conv, flux, phi, grad, out);
+}
+
+template <int NC>
+static void launch_momentum(const difvm_mesh* m, int conv, int table, double nu, const double* nu_cell, double dt,
+                            const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
+                            double* upper, double* lower, double* slot_val, double* b) {
+  const DMesh& d = m->d;
+  MeshView<double> v = view<double>(d);
+  dim3 G(grid_for(d.nc)), B(BLOCK);
+  hipStream_t s = stream_of(m);
+  switch (conv) {
+    case DIFVM_CONV_UPWIND:
+      k_momentum<NC, DIFVM_CONV_UPWIND><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+                                                        d.face_rN, diag, upper, lower, slot_val, b);
+      break;
+    case DIFVM_CONV_LINEAR:
+      k_momentum<NC, DIFVM_CONV_LINEAR><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+                                                        d.face_rN, diag, upper, lower, slot_val, b);
+      break;
+    case DIFVM_CONV_SOU:
+      k_momentum<NC, DIFVM_CONV_SOU><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+                                                     d.face_rN, diag, upper, lower, slot_val, b);
+      break;
+    case DIFVM_CONV_QUICK:
+      k_momentum<NC, DIFVM_CONV_QUICK><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+                                                       d.face_rN, diag, upper, lower, slot_val, b);
+      break;
+    default:
+      throw Error{DIFVM_ERR_INVALID_ARG, "unknown convection scheme"};
+  }
+  DIFVM_HIP(hipGetLastError());
+}
+
+void op_assemble_momentum(const difvm_mesh* m, int conv, double nu, const double* nu_cell, double dt,
+                          const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
+                          double* upper, double* lower, double* slot_val, double* b) {
+  launch_momentum<3>(m, conv, DIFVM_BC_U, nu, nu_cell, dt, flux, U, gradU, Ub, diag, upper, lower, slot_val, b);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -345,6 +455,8 @@ static double* piso_alloc(difvm_piso* P, size_t n) {
 void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) {
   DIFVM_CHECK(prm && prm->struct_size == sizeof(difvm_piso_params), DIFVM_ERR_INVALID_ARG, "difvm_piso_params mismatch");
   DIFVM_CHECK(prm->n_corr >= 1 && prm->n_corr <= 8, DIFVM_ERR_INVALID_ARG, "n_corr must be in 1..8");
+  DIFVM_CHECK(prm->conv >= DIFVM_CONV_UPWIND && prm->conv <= DIFVM_CONV_QUICK, DIFVM_ERR_INVALID_ARG,
+              "unknown convection scheme");
   DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
   const DMesh& d = m->d;
   const HostLayout& L = m->host;
@@ -440,9 +552,8 @@ SolveResult piso_transport_scalar(difvm_piso* P, double D, int table, const doub
   permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, c_user, P->sc);
   if (d.nfb) permute(m, DIFVM_F64, 1, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, cb_user, P->scb);
   op_grad(m, DIFVM_F64, 1, table, P->sc, P->scb, P->sg);
-  k_momentum<1><<<grid_for(d.nc), BLOCK, 0, s>>>(view<double>(d), table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg,
-                                                 P->scb, P->sd, nullptr, nullptr, P->sval, P->sb);
-  DIFVM_HIP(hipGetLastError());
+  launch_momentum<1>(m, P->prm.conv, table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg, P->scb, P->sd, nullptr,
+                     nullptr, P->sval, P->sb);
   SolveResult r = bicgstab(m, 1, SellMatrix{P->sd, P->sval}, P->sb, P->sc, P->prm.tol_u, P->prm.maxit_u);
   permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->sc, c_user);
   DIFVM_HIP(hipStreamSynchronize(s));
@@ -558,8 +669,9 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   }
   // S1
   op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
-  op_assemble_momentum(m, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr, P->valM,
-                       P->bM);
+  if (rec && rec->Un) dcopy(rec->Un, P->U, 3 * nc, s);
+  op_assemble_momentum(m, prm.conv, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr,
+                       P->valM, P->bM);
   // S2
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
   k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);

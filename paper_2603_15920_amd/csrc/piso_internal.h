@@ -59,6 +59,7 @@ struct StepRecord {
   double* gpn[MAXC] = {};    // grad of the solved pressure [nc*3]
   double* wk_out = nullptr;  // (Q, p_o) per Windkessel [2*n_wk]
   double* pc_in = nullptr;   // capacitor pressures entering the step [n_wk]
+  double* Un = nullptr;      // velocity entering the step [nc*3] (kept for a deferred-correction scheme)
 };
 
 // one PISO step of P's state; when rec != nullptr the intermediates are copied into it

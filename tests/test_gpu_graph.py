@@ -22,9 +22,9 @@ def lid(m, u=1.0):
     return Ub
 
 
-def make(m, Ub, nu, dt, wk=(), pc0=(), seg=None, nus=None):
+def make(m, Ub, nu, dt, wk=(), pc0=(), seg=None, nus=None, conv="upwind"):
     M = B.Mesh(ctx(), m, seg_cell_start=seg)
-    P = B.Piso(M, B.piso_params(nu, dt))
+    P = B.Piso(M, B.piso_params(nu, dt, conv=conv))
     if nus is not None:
         P.set_viscosity(nus)
     P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
