@@ -89,6 +89,7 @@ typedef struct {
   double p_ref_value;
   double tol_tangent;        // tolerance of the tangent (implicitly differentiated) solves
   int32_t conv;              // convection scheme: 0 upwind, 1 linear, 2 SOU, 3 QUICK (see deferred_correction)
+  int32_t time;              // time scheme: 0 backward Euler, 1 forward Euler, 2 Crank-Nicolson (see time_theta)
 } om_piso_params;
 }
 
@@ -237,6 +238,22 @@ void div(const om_mesh& m, int scheme, int ncomp, const std::vector<int>& code, 
       out[O * ncomp + c] += flux[f] * pf;
     }
   }
+}
+
+enum { TIME_BACKWARD_EULER = 0, TIME_FORWARD_EULER = 1, TIME_CRANK_NICOLSON = 2 };
+
+// The three time schemes of the scheme table as one theta-method on the matrix part of the transport
+// operator A (convection of the lagged flux, orthogonal diffusion):
+//   (V/dt)(u' - u^n) + theta A u' + (1 - theta) A u^n = explicit terms,
+// theta = 1 backward Euler, 1/2 Crank-Nicolson, 0 forward Euler (then the matrix is V/dt alone and
+// the predictor is the explicit update of eq. momentum_predictor).  One set of boundary values serves
+// both halves; the caller gives them at t^n + theta dt (new level, mid-step, old level).  The explicit
+// terms (non-orthogonal and deferred corrections, pressure gradient) are taken whole from the old
+// level.
+double time_theta(int scheme) {
+  if (scheme == TIME_FORWARD_EULER) return 0.0;
+  if (scheme == TIME_CRANK_NICOLSON) return 0.5;
+  return 1.0;
 }
 
 enum { CONV_UPWIND = 0, CONV_LINEAR = 1, CONV_SOU = 2, CONV_QUICK = 3 };
@@ -536,9 +553,10 @@ struct Piso {
       T po = pc[j] + Rp * Q;
       for (int b = 0; b < nfb; ++b) if (wk_of_face[b] == j) pbv[b] = po;
     }
-    // S1: momentum LDU from the lagged flux: implicit Euler + implicit upwind + implicit orthogonal
-    // diffusion; the non-orthogonal diffusion part and the deferred correction of a higher-order
-    // convection scheme are explicit from U^n and grad(U^n).
+    // S1: momentum LDU from the lagged flux: the time scheme's theta-weighted upwind convection and
+    // orthogonal diffusion (implicit Euler at theta = 1); the non-orthogonal diffusion part and the
+    // deferred correction of a higher-order convection scheme are explicit from U^n and grad(U^n).
+    const double th = time_theta(prm.time);
     std::vector<T> gU((size_t)nc * 9);
     grad(m, 3, codeU, U.data(), Ub.data(), gU.data());
     std::vector<T> dM(nc), uM(nfi), lM(nfi), bM((size_t)nc * 3);
@@ -552,10 +570,17 @@ struct Piso {
       T Fp = (val(F) >= 0.0) ? F : T(0.0);   // max(F, 0); the tie F = 0 belongs to the owner side
       T Fm = (val(F) < 0.0) ? F : T(0.0);    // min(F, 0)
       double nd = nu * delta[f];
-      dM[O] += Fp + nd;
-      dM[N] += (-Fm) + nd;                   // max(-F, 0) = -min(F, 0)
-      uM[f] = Fm - nd;
-      lM[f] = -Fp - nd;
+      T aO = Fp + nd, aN = (-Fm) + nd;       // max(-F, 0) = -min(F, 0)
+      T up = Fm - nd, lo = -Fp - nd;
+      dM[O] += th * aO;
+      dM[N] += th * aN;
+      uM[f] = th * up;
+      lM[f] = th * lo;
+      if (th != 1.0)
+        for (int c = 0; c < 3; ++c) {
+          bM[O * 3 + c] -= (1.0 - th) * (aO * U[O * 3 + c] + up * U[N * 3 + c]);
+          bM[N * 3 + c] -= (1.0 - th) * (aN * U[N * 3 + c] + lo * U[O * 3 + c]);
+        }
       double w = m.w[f];
       for (int c = 0; c < 3; ++c) {
         T corr = T(0.0);
@@ -568,10 +593,12 @@ struct Piso {
       int O = m.owner[nfi + b];
       if (codeU[b] == BC_FIXED) {
         double nd = nu * deltab[b];
-        dM[O] += T(nd);
+        dM[O] += T(th * nd);
         for (int c = 0; c < 3; ++c) bM[O * 3 + c] += (nd - phi[nfi + b]) * Ub[b * 3 + c];
+        if (th != 1.0) for (int c = 0; c < 3; ++c) bM[O * 3 + c] -= (1.0 - th) * nd * U[O * 3 + c];
       } else if (codeU[b] == BC_ZEROGRAD) {
-        dM[O] += phi[nfi + b];
+        dM[O] += th * phi[nfi + b];
+        if (th != 1.0) for (int c = 0; c < 3; ++c) bM[O * 3 + c] -= (1.0 - th) * phi[nfi + b] * U[O * 3 + c];
       }
     }
     // higher-order convection as an explicit source from U^n (part of b, hence of H in every corrector)
@@ -777,7 +804,7 @@ std::vector<int> rcm_order(const om_mesh& m) {
 // ================================================================================================
 extern "C" {
 
-int oracle_version(void) { return 3; }  // 3: convection scheme in the PISO parameters
+int oracle_version(void) { return 4; }  // 4: time scheme in the PISO parameters
 
 // Renumbering.  rcm = 0 keeps the cell order.  Outputs (new -> old where a permutation):
 //  cell_perm[nc], face_perm[nfi], face_flip[nfi], owner[nfi], nbr[nfi], own_start[nc+1],
@@ -1007,13 +1034,15 @@ int oracle_bicgstab(const om_mesh* m, int ncomp, const double* diag, const doubl
 // Passive scalar over one time step with a given face flux (the momentum predictor's discretisation
 // applied to one transported scalar c with diffusivity D, Sec. "Spatial discretization"):
 //   (V/dt)(c^{n+1} - c^n) + sum_f F_f c_f^upwind - D sum_f (delta_f (c_N - c_O) + k_f . grad c^n_f) = 0,
-// convection implicit upwind of the given flux (tie F = 0 to the owner) plus the deferred correction
-// of the scheme conv from c^n, diffusion implicit in its orthogonal part and explicit in the
-// non-orthogonal correction from the Gauss gradient of c^n;
+// convection upwind of the given flux (tie F = 0 to the owner) plus the deferred correction of the
+// scheme conv from c^n, diffusion in its orthogonal part and explicit in the non-orthogonal correction
+// from the Gauss gradient of c^n, the matrix part weighted by the time scheme (time_theta; implicit
+// Euler by default);
 // boundary faces by the table's codes with values cb (fixed) or c of the owner (zeroGradient).
 // Solved by BiCGStab from c^n; c is overwritten.
-int oracle_transport_scalar(const om_mesh* m, int table, int conv, double D, double dt, const double* phi,
+int oracle_transport_scalar(const om_mesh* m, int table, int conv, int time, double D, double dt, const double* phi,
                             const double* cb, double* c, double tol, int maxit, int32_t* iters, double* res) {
+  const double th = time_theta(time);
   std::vector<int> code = bc_codes(*m, table);
   std::vector<double> g((size_t)m->nc * 3);
   grad<double>(*m, 1, code, c, cb, g.data());
@@ -1028,10 +1057,15 @@ int oracle_transport_scalar(const om_mesh* m, int table, int conv, double D, dou
     face_geom(*m, f, d, delta, k);
     double F = phi[f], nd = D * delta, w = m->w[f];
     double Fp = F >= 0 ? F : 0.0, Fm = F < 0 ? F : 0.0;
-    diag[O] += Fp + nd;
-    diag[N] += -Fm + nd;
-    upper[f] = Fm - nd;
-    lower[f] = -Fp - nd;
+    double aO = Fp + nd, aN = -Fm + nd, up = Fm - nd, lo = -Fp - nd;
+    diag[O] += th * aO;
+    diag[N] += th * aN;
+    upper[f] = th * up;
+    lower[f] = th * lo;
+    if (th != 1.0) {
+      b[O] -= (1.0 - th) * (aO * c[O] + up * c[N]);
+      b[N] -= (1.0 - th) * (aN * c[N] + lo * c[O]);
+    }
     double corr = 0.0;
     for (int e = 0; e < 3; ++e) corr += k[e] * (w * g[O * 3 + e] + (1 - w) * g[N * 3 + e]);
     b[O] += D * corr;
@@ -1041,10 +1075,12 @@ int oracle_transport_scalar(const om_mesh* m, int table, int conv, double D, dou
     int f = m->nfi + bb, O = m->owner[f];
     if (code[bb] == BC_FIXED) {
       double nd = D * bface_delta(*m, f);
-      diag[O] += nd;
+      diag[O] += th * nd;
       b[O] += (nd - phi[f]) * cb[bb];
+      if (th != 1.0) b[O] -= (1.0 - th) * nd * c[O];
     } else if (code[bb] == BC_ZEROGRAD) {
-      diag[O] += phi[f];
+      diag[O] += th * phi[f];
+      if (th != 1.0) b[O] -= (1.0 - th) * phi[f] * c[O];
     }
   }
   deferred_correction(*m, conv, 1, phi, c, g.data(), b.data());

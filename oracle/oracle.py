@@ -35,11 +35,13 @@ class OmPisoParams(C.Structure):
     _fields_ = [("nu", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32), ("tol_p", C.c_double),
                 ("tol_u", C.c_double), ("maxit_p", C.c_int32), ("maxit_u", C.c_int32),
                 ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("tol_tangent", C.c_double),
-                ("conv", C.c_int32)]
+                ("conv", C.c_int32), ("time", C.c_int32)]
 
 
 # convection schemes (upwind implicit; the others by deferred correction, eq. deferred_correction)
 CONV = {"upwind": 0, "linear": 1, "sou": 2, "quick": 3}
+# time schemes (theta-method on the matrix part: 1, 0, 1/2)
+TIME = {"backward_euler": 0, "forward_euler": 1, "crank_nicolson": 2}
 
 
 def lib():
@@ -51,7 +53,7 @@ def lib():
             _b.build()
         _LIB = C.CDLL(path)
         _LIB.oracle_version.restype = C.c_int
-        if _LIB.oracle_version() != 3:
+        if _LIB.oracle_version() != 4:
             raise RuntimeError(f"{path} is stale (version {_LIB.oracle_version()}); rebuild the oracle")
     return _LIB
 
@@ -207,12 +209,14 @@ def bicgstab(mesh, diag, upper, lower, b, x0=None, tol=1e-8, maxit=500):
     return x, it, res, st
 
 
-def transport_scalar(mesh, phi, c, cb, D, dt, table=TABLE_U, tol=1e-8, maxit=500, conv="upwind"):
-    """One implicit step of a passive scalar with face flux phi; returns (c_new, iters, res, status)."""
+def transport_scalar(mesh, phi, c, cb, D, dt, table=TABLE_U, tol=1e-8, maxit=500, conv="upwind",
+                     time="backward_euler"):
+    """One step of a passive scalar with face flux phi; returns (c_new, iters, res, status)."""
     x = np.array(c, dtype=np.float64, copy=True)
     it, rs = C.c_int32(0), C.c_double(0.0)
-    st = lib().oracle_transport_scalar(om(mesh), int(table), CONV[conv], C.c_double(D), C.c_double(dt), _p(_f(phi)),
-                                       _p(_f(cb)), _p(x), C.c_double(tol), int(maxit), C.byref(it), C.byref(rs))
+    st = lib().oracle_transport_scalar(om(mesh), int(table), CONV[conv], TIME[time], C.c_double(D), C.c_double(dt),
+                                       _p(_f(phi)), _p(_f(cb)), _p(x), C.c_double(tol), int(maxit), C.byref(it),
+                                       C.byref(rs))
     return x, it.value, rs.value, st
 
 
@@ -233,9 +237,9 @@ def initial_flux(mesh, U, Ub):
 
 
 def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0,
-                tol_tangent=1e-13, conv="upwind"):
+                tol_tangent=1e-13, conv="upwind", time="backward_euler"):
     return OmPisoParams(nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value, tol_tangent,
-                        CONV[conv])
+                        CONV[conv], TIME[time])
 
 
 def piso_run(mesh, prm, U, p, phi, Ub, pb, wk=None, pc=None, nsteps=1):
