@@ -64,6 +64,13 @@ enum { DIFVM_SCHEME_ONE = 0, DIFVM_SCHEME_UPWIND = 1, DIFVM_SCHEME_LINEAR = 2 };
  * scheme table): upwind is implicit; the others add the deferred correction of eq.
  * deferred_correction to an implicit upwind matrix (see difvm_op_deferred_correction) */
 enum { DIFVM_CONV_UPWIND = 0, DIFVM_CONV_LINEAR = 1, DIFVM_CONV_SOU = 2, DIFVM_CONV_QUICK = 3 };
+/* time schemes (scheme table): a theta-method on the matrix part of the predictor (upwind convection
+ * of the lagged flux and orthogonal diffusion), (V/dt)(u' - u^n) + theta A u' + (1 - theta) A u^n =
+ * explicit terms, with theta = 1 (backward Euler), 0 (forward Euler: the predictor is the explicit
+ * update of eq. momentum_predictor), 1/2 (Crank-Nicolson).  Explicit terms (non-orthogonal and
+ * deferred corrections, the pressure gradient of the predictor) come whole from the old level.  One set
+ * of boundary values serves a step: give them at t^n + theta dt. */
+enum { DIFVM_TIME_BACKWARD_EULER = 0, DIFVM_TIME_FORWARD_EULER = 1, DIFVM_TIME_CRANK_NICOLSON = 2 };
 
 /* array kinds for difvm_permute */
 enum {
@@ -330,6 +337,7 @@ typedef struct {
                              transport; the deferred correction is evaluated once per step from
                              U^n and its Gauss gradient and is part of the momentum source b, so
                              it also enters H in every corrector                               */
+  int32_t time;           /* time scheme (DIFVM_TIME_*) of the predictor and of scalar transport   */
 } difvm_piso_params;
 
 typedef struct {
@@ -370,7 +378,8 @@ difvm_status difvm_piso_get_state(difvm_piso* piso, void* U, void* p, void* phi,
 /* Passive scalar transport over one time step with the PISO object's current face flux (the
  * paper's convection-diffusion discretisation, Sec. "Spatial discretization", applied to one scalar
  * c): (V/dt)(c' - c) + sum_f F_f c'_upwind - D sum_f (delta_f (c'_N - c'_O) + k_f . grad(c)_f) = 0,
- * i.e. the momentum predictor's matrix with one component and diffusivity D >= 0: implicit Euler,
+ * i.e. the momentum predictor's matrix with one component and diffusivity D >= 0 (written here for
+ * the default backward Euler; params.time selects the theta-method of DIFVM_TIME_*): implicit Euler,
  * implicit upwind of the flux (tie F = 0 to the owner) plus the deferred correction of the PISO
  * object's convection scheme (params.conv) from c, implicit orthogonal diffusion, explicit
  * non-orthogonal correction from the Gauss gradient of c.  bc selects the boundary table (DIFVM_BC_*);

@@ -20,6 +20,8 @@ BC_U, BC_P, BC_ALL_FIXED, BC_ALL_ZEROGRAD = 0, 1, 2, 3
 SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
 # convection schemes of the PISO predictor and scalar transport (deferred correction beyond upwind)
 CONV = {"upwind": 0, "linear": 1, "sou": 2, "quick": 3}
+# time schemes (theta-method on the predictor's matrix part: 1, 0, 1/2)
+TIME = {"backward_euler": 0, "forward_euler": 1, "crank_nicolson": 2}
 KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
 TO_INTERNAL, FROM_INTERNAL = 0, 1
 RENUMBER_RCM = 1
@@ -75,7 +77,7 @@ class SolveStats(C.Structure):
 class PisoParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("nu", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
                 ("tol_p", C.c_double), ("tol_u", C.c_double), ("maxit_p", C.c_int32), ("maxit_u", C.c_int32),
-                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("conv", C.c_int32)]
+                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("conv", C.c_int32), ("time", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -357,9 +359,9 @@ def difvm_solve_bicgstab(m, A, ncomp, b, x, tol, maxit):
 
 
 def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0,
-                conv="upwind"):
+                conv="upwind", time="backward_euler"):
     return PisoParams(C.sizeof(PisoParams), nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value,
-                      CONV[conv])
+                      CONV[conv], TIME[time])
 
 
 def difvm_piso_create(m, params):

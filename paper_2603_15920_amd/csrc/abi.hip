@@ -458,7 +458,7 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
   double* gU = dalloc<double>((size_t)9 * m->d.nc);
   try {
     op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
-    op_assemble_momentum(m, DIFVM_CONV_UPWIND, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
+    op_assemble_momentum(m, DIFVM_CONV_UPWIND, DIFVM_TIME_BACKWARD_EULER, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
                          (double*)A->upper, (double*)A->lower, nullptr, (double*)b);
     DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
   } catch (...) {

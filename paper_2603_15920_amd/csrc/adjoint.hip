@@ -321,11 +321,14 @@ __global__ __launch_bounds__(BLOCK) void k_adj_rau(int nc, const double* __restr
 // deferred correction t_f = F_f Delta_f(U^n, grad U^n) (b_O -= t, b_N += t) adds, with
 // Deltabar = sF (bbar_i - bbar_j) seen from cell i (sF = -F owner side, +F neighbour side), the
 // cell's own partial derivatives of Delta (upwind branch frozen)
+// With a time scheme theta < 1, b also holds -(1 - theta) A U^n (A: the upwind convection and orthogonal
+// diffusion coefficients of the lagged flux), whose transpose adds -(1 - theta) (A^T bbar)_i.
 template <int CONV>
 __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const double* __restrict__ nu_cell, double dt,
-                                                    const double* __restrict__ bbar, const double* __restrict__ flux,
-                                                    const double4* __restrict__ rO, const double4* __restrict__ rN,
-                                                    double* __restrict__ Ubar0, double* __restrict__ gUbar) {
+                                                    double theta, const double* __restrict__ bbar,
+                                                    const double* __restrict__ flux, const double4* __restrict__ rO,
+                                                    const double4* __restrict__ rN, double* __restrict__ Ubar0,
+                                                    double* __restrict__ gUbar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m.slice_start, i);
@@ -333,11 +336,22 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
   const double* bi = bbar + 3 * (size_t)i;
   double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double ub[3] = {0, 0, 0};
+  const double ex = 1.0 - theta;  // explicit share of the matrix part
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
-    if (sf == SLOT_PAD || sf >= m.nfi) continue;
+    if (sf == SLOT_PAD) continue;
+    if (sf >= m.nfi) {
+      if (ex != 0.0) {
+        int bf = sf - m.nfi;
+        int8_t code = m.bcode[DIFVM_BC_U * m.nfb + bf];
+        double a = code == BC_FIXED ? nu * m.bgeom[bf].w : (code == BC_ZEROGRAD ? flux[m.nfi + bf] : 0.0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ub[c] -= ex * a * bi[c];
+      }
+      continue;
+    }
     bool nb = sf < 0;
     int f = nb ? -sf - 1 : sf;
     int j = m.slot_col[at];
@@ -346,6 +360,14 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
     double wself = nb ? 1.0 - w : w;
     double sg = nb ? -nu : nu;
     const double* bj = bbar + 3 * (size_t)j;
+    if (ex != 0.0) {
+      double F = flux[f], nd = nu * kd.w;
+      double Fp = F >= 0.0 ? F : 0.0, Fm = F < 0.0 ? F : 0.0;
+      double ad = nb ? -Fm + nd : Fp + nd;  // self's diagonal part
+      double aj = nb ? Fm - nd : -Fp - nd;  // the other row's coefficient of self (upper / lower)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ub[c] -= ex * (ad * bi[c] + aj * bj[c]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double t = wself * sg * (bi[c] - bj[c]);
@@ -391,8 +413,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
 
 // momentum coefficients (and the deferred correction t_f = F_f Delta_f, whose Delta is taken from
 // U^n and its gradient) -> lagged flux (upwind branch frozen at the forward's choice)
+// (theta: the stored coefficients carry theta; the explicit share 1 - theta of the matrix part acts on U^n)
 template <int CONV>
-__global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, const int32_t* __restrict__ own_slot,
+__global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, double theta, const int32_t* __restrict__ own_slot,
                                                    const int32_t* __restrict__ nbr_slot, const double* __restrict__ phi,
                                                    const double* __restrict__ valbar, const double* __restrict__ dbar,
                                                    const double* __restrict__ bbar, const double* __restrict__ Ub,
@@ -404,7 +427,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, const int
     int O = m.own[f], N = m.nbr[f];
     double F = phi[f];
     double ub = valbar[own_slot[f]], lb = valbar[nbr_slot[f]];
-    double v = F >= 0.0 ? dbar[O] - lb : ub - dbar[N];
+    double v = theta * (F >= 0.0 ? dbar[O] - lb : ub - dbar[N]);
+    if (theta != 1.0) {
+      int Cc = F >= 0.0 ? O : N;  // upwind cell
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        v -= (1.0 - theta) * (bbar[3 * (size_t)O + c] - bbar[3 * (size_t)N + c]) * Un[3 * (size_t)Cc + c];
+    }
     if constexpr (CONV != DIFVM_CONV_UPWIND) {
       bool up = dc_self_up(F, false);
       double4 ro_ = rO[f], rn_ = rN[f];
@@ -425,8 +454,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, const int
     if (cu == BC_FIXED)
       v = -(bbar[3 * (size_t)O] * Ub[3 * (size_t)b] + bbar[3 * (size_t)O + 1] * Ub[3 * (size_t)b + 1] +
             bbar[3 * (size_t)O + 2] * Ub[3 * (size_t)b + 2]);
-    else if (cu == BC_ZEROGRAD)
-      v = dbar[O];
+    else if (cu == BC_ZEROGRAD) {
+      v = theta * dbar[O];
+      if (theta != 1.0)
+        v -= (1.0 - theta) * (bbar[3 * (size_t)O] * Un[3 * (size_t)O] + bbar[3 * (size_t)O + 1] * Un[3 * (size_t)O + 1] +
+                              bbar[3 * (size_t)O + 2] * Un[3 * (size_t)O + 2]);
+    }
     phibar[f] = v;
   }
 }
@@ -534,7 +567,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
       r.rAU = tape_alloc(T, nc);
       r.wk_out = tape_alloc(T, 2 * nwk);
       r.pc_in = tape_alloc(T, nwk);
-      if (P->prm.conv != DIFVM_CONV_UPWIND) r.Un = tape_alloc(T, 3 * nc);
+      if (P->prm.conv != DIFVM_CONV_UPWIND || P->prm.time != DIFVM_TIME_BACKWARD_EULER) r.Un = tape_alloc(T, 3 * nc);
       for (int c = 0; c < ncorr; ++c) {
         r.Uin[c] = tape_alloc(T, 3 * nc);
         r.pold[c] = tape_alloc(T, nc);
@@ -663,14 +696,15 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   k_adj_rau<<<Gc, BLOCK, 0, s>>>(d.nc, T->rAUbar, R.rAU, R.dM, T->dbar);
   // momentum source and coefficients
   if (prm.conv != DIFVM_CONV_UPWIND) op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, R.Un, P->Ub, T->gUn);
+  const double theta = time_theta(prm.time);
   switch (prm.conv) {
 #define DIFVM_ADJ_SRC(CV)                                                                                            \
   case CV:                                                                                                            \
-    k_adj_bsrc<CV><<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, T->bbar, phi_n, d.face_rO, d.face_rN, T->Ubar0,       \
-                                        T->gUbar);                                                                    \
+    k_adj_bsrc<CV><<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, theta, T->bbar, phi_n, d.face_rO, d.face_rN,          \
+                                        T->Ubar0, T->gUbar);                                                          \
     k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);                                      \
-    k_adj_phi<CV><<<Gf, BLOCK, 0, s>>>(mv, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar, T->bbar,      \
-                                       P->Ub, R.Un, T->gUn, d.face_rO, d.face_rN, T->phibar);                         \
+    k_adj_phi<CV><<<Gf, BLOCK, 0, s>>>(mv, theta, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar,        \
+                                       T->bbar, P->Ub, R.Un, T->gUn, d.face_rO, d.face_rN, T->phibar);                \
     break;
     DIFVM_ADJ_SRC(DIFVM_CONV_UPWIND)
     DIFVM_ADJ_SRC(DIFVM_CONV_LINEAR)

@@ -18,8 +18,10 @@ void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const
                          double* upper, double* rhs);
 
 // momentum matrix of the predictor; writes face LDU (upper/lower, may be NULL) and/or per-slot values
-// (nu_cell: per-cell viscosity, NULL for nu everywhere); conv adds its deferred correction to b
-void op_assemble_momentum(const difvm_mesh* m, int conv, double nu, const double* nu_cell, double dt,
+// (nu_cell: per-cell viscosity, NULL for nu everywhere); conv adds its deferred correction to b; time
+// selects the theta-method (the rest of the matrix part applied to U on the right-hand side)
+double time_theta(int scheme);  // DIFVM_TIME_* -> theta of the matrix part (1, 0, 1/2)
+void op_assemble_momentum(const difvm_mesh* m, int conv, int time, double nu, const double* nu_cell, double dt,
                           const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
                           double* upper, double* lower, double* slot_val, double* b);
 // deferred-correction source alone (F64): out = - sum_f sigma F (phi^HO - phi^U)

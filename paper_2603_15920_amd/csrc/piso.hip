@@ -31,9 +31,11 @@ namespace difvm {
 // lower), optional face LDU copies, and the right-hand side b (without the pressure gradient),
 // including the deferred correction of convection scheme CONV (rO/rN: x_f - x_O, x_f - x_N)
 // ---------------------------------------------------------------------------------------------
+// theta: time scheme weight of the matrix part (1 backward Euler, 1/2 Crank-Nicolson, 0 forward
+// Euler); the remaining 1 - theta of it is applied to U^n on the right-hand side
 template <int NC, int CONV>
 __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int table, double nu_all,
-                                                    const double* __restrict__ nu_cell, double dt,
+                                                    const double* __restrict__ nu_cell, double dt, double theta,
                                                     const double* __restrict__ flux, const double* __restrict__ U,
                                                     const double* __restrict__ gU, const double* __restrict__ Ub,
                                                     const double4* __restrict__ rO, const double4* __restrict__ rN,
@@ -69,14 +71,19 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
       double nd = nu * kd.w;
       double Fp = F >= 0.0 ? F : 0.0;  // max(F,0): the tie F = 0 belongs to the owner
       double Fm = F < 0.0 ? F : 0.0;   // min(F,0)
+      double ad = nb ? -Fm + nd : Fp + nd;  // this face's part of the diagonal
+      double ao = nb ? -Fp - nd : Fm - nd;  // coefficient of the other cell (lower / upper)
+      d += theta * ad;
+      a = theta * ao;
       if (!nb) {
-        d += Fp + nd;
-        a = Fm - nd;                   // upper
         if (upper) upper[f] = a;
       } else {
-        d += -Fm + nd;
-        a = -Fp - nd;                  // lower
         if (lower) lower[f] = a;
+      }
+      const double* uj = U + NC * (size_t)j;
+      if (theta != 1.0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * (ad * ui[c] + ao * uj[c]);
       }
       double w = m.w[f];
       double wself = nb ? 1.0 - w : w;
@@ -93,7 +100,6 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
         double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
         bool up = dc_self_up(F, nb);
         double sF = nb ? F : -F;  // owner side: b -= F delta; neighbour side: b += F delta
-        const double* uj = U + NC * (size_t)j;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
           bi[c] += sF * dc_delta<CONV>(up, wself, ui[c], uj[c], gi + 3 * c, gj + 3 * c, rs, ro);
@@ -104,11 +110,19 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
       double F = flux[m.nfi + bf];
       if (code == BC_FIXED) {
         double nd = nu * m.bgeom[bf].w;
-        d += nd;
+        d += theta * nd;
 #pragma unroll
         for (int c = 0; c < NC; ++c) bi[c] += (nd - F) * Ub[NC * (size_t)bf + c];
+        if (theta != 1.0) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * nd * ui[c];
+        }
       } else if (code == BC_ZEROGRAD) {
-        d += F;
+        d += theta * F;
+        if (theta != 1.0) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * F * ui[c];
+        }
       }
     }
     if (slot_val) slot_val[at] = a;
@@ -184,29 +198,35 @@ void op_deferred_correction(const difvm_mesh* m, int conv, int ncomp, const doub
   else launch_dc<3>(m, conv, flux, phi, grad, out);
 }
 
+double time_theta(int scheme) {
+  if (scheme == DIFVM_TIME_FORWARD_EULER) return 0.0;
+  if (scheme == DIFVM_TIME_CRANK_NICOLSON) return 0.5;
+  return 1.0;
+}
+
 template <int NC>
-static void launch_momentum(const difvm_mesh* m, int conv, int table, double nu, const double* nu_cell, double dt,
-                            const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
-                            double* upper, double* lower, double* slot_val, double* b) {
+static void launch_momentum(const difvm_mesh* m, int conv, double theta, int table, double nu, const double* nu_cell,
+                            double dt, const double* flux, const double* U, const double* gradU, const double* Ub,
+                            double* diag, double* upper, double* lower, double* slot_val, double* b) {
   const DMesh& d = m->d;
   MeshView<double> v = view<double>(d);
   dim3 G(grid_for(d.nc)), B(BLOCK);
   hipStream_t s = stream_of(m);
   switch (conv) {
     case DIFVM_CONV_UPWIND:
-      k_momentum<NC, DIFVM_CONV_UPWIND><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+      k_momentum<NC, DIFVM_CONV_UPWIND><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, theta, flux, U, gradU, Ub, d.face_rO,
                                                         d.face_rN, diag, upper, lower, slot_val, b);
       break;
     case DIFVM_CONV_LINEAR:
-      k_momentum<NC, DIFVM_CONV_LINEAR><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+      k_momentum<NC, DIFVM_CONV_LINEAR><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, theta, flux, U, gradU, Ub, d.face_rO,
                                                         d.face_rN, diag, upper, lower, slot_val, b);
       break;
     case DIFVM_CONV_SOU:
-      k_momentum<NC, DIFVM_CONV_SOU><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+      k_momentum<NC, DIFVM_CONV_SOU><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, theta, flux, U, gradU, Ub, d.face_rO,
                                                      d.face_rN, diag, upper, lower, slot_val, b);
       break;
     case DIFVM_CONV_QUICK:
-      k_momentum<NC, DIFVM_CONV_QUICK><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, flux, U, gradU, Ub, d.face_rO,
+      k_momentum<NC, DIFVM_CONV_QUICK><<<G, B, 0, s>>>(v, table, nu, nu_cell, dt, theta, flux, U, gradU, Ub, d.face_rO,
                                                        d.face_rN, diag, upper, lower, slot_val, b);
       break;
     default:
@@ -215,10 +235,11 @@ static void launch_momentum(const difvm_mesh* m, int conv, int table, double nu,
   DIFVM_HIP(hipGetLastError());
 }
 
-void op_assemble_momentum(const difvm_mesh* m, int conv, double nu, const double* nu_cell, double dt,
+void op_assemble_momentum(const difvm_mesh* m, int conv, int time, double nu, const double* nu_cell, double dt,
                           const double* flux, const double* U, const double* gradU, const double* Ub, double* diag,
                           double* upper, double* lower, double* slot_val, double* b) {
-  launch_momentum<3>(m, conv, DIFVM_BC_U, nu, nu_cell, dt, flux, U, gradU, Ub, diag, upper, lower, slot_val, b);
+  launch_momentum<3>(m, conv, time_theta(time), DIFVM_BC_U, nu, nu_cell, dt, flux, U, gradU, Ub, diag, upper, lower,
+                     slot_val, b);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -457,6 +478,8 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
   DIFVM_CHECK(prm->n_corr >= 1 && prm->n_corr <= 8, DIFVM_ERR_INVALID_ARG, "n_corr must be in 1..8");
   DIFVM_CHECK(prm->conv >= DIFVM_CONV_UPWIND && prm->conv <= DIFVM_CONV_QUICK, DIFVM_ERR_INVALID_ARG,
               "unknown convection scheme");
+  DIFVM_CHECK(prm->time >= DIFVM_TIME_BACKWARD_EULER && prm->time <= DIFVM_TIME_CRANK_NICOLSON, DIFVM_ERR_INVALID_ARG,
+              "unknown time scheme");
   DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
   const DMesh& d = m->d;
   const HostLayout& L = m->host;
@@ -552,7 +575,7 @@ SolveResult piso_transport_scalar(difvm_piso* P, double D, int table, const doub
   permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, c_user, P->sc);
   if (d.nfb) permute(m, DIFVM_F64, 1, DIFVM_KIND_BFACE, DIFVM_TO_INTERNAL, cb_user, P->scb);
   op_grad(m, DIFVM_F64, 1, table, P->sc, P->scb, P->sg);
-  launch_momentum<1>(m, P->prm.conv, table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg, P->scb, P->sd, nullptr,
+  launch_momentum<1>(m, P->prm.conv, time_theta(P->prm.time), table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg, P->scb, P->sd, nullptr,
                      nullptr, P->sval, P->sb);
   SolveResult r = bicgstab(m, 1, SellMatrix{P->sd, P->sval}, P->sb, P->sc, P->prm.tol_u, P->prm.maxit_u);
   permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->sc, c_user);
@@ -670,7 +693,7 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   // S1
   op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, P->U, P->Ub, P->gU);
   if (rec && rec->Un) dcopy(rec->Un, P->U, 3 * nc, s);
-  op_assemble_momentum(m, prm.conv, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr,
+  op_assemble_momentum(m, prm.conv, prm.time, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr,
                        P->valM, P->bM);
   // S2
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);

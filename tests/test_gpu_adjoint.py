@@ -27,10 +27,11 @@ def channel_wk(nxyz=(6, 3, 3), seed=61):
     return m, Ub
 
 
-def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol=1e-13, conv="upwind"):
+def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol=1e-13, conv="upwind",
+               time="backward_euler"):
     nwk = len(wk)
     M = B.Mesh(ctx(), m)
-    prm = B.piso_params(nu, dt, tol_p=tol, tol_u=tol, maxit_p=20000, maxit_u=5000, conv=conv)
+    prm = B.piso_params(nu, dt, tol_p=tol, tol_u=tol, maxit_p=20000, maxit_u=5000, conv=conv, time=time)
     P = B.Piso(M, prm)
     P.set_boundary(dev(Ub), dev(pb))
     for j, (Rp, Cc, Rd) in enumerate(wk):
@@ -50,12 +51,12 @@ def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol
                 gpc0=gpc0, gwk=gwk)
 
 
-def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3, conv="upwind"):
+def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3, conv="upwind", time="backward_euler"):
     rng = np.random.default_rng(seed)
     nwk = len(wk)
     cot = dict(U=rng.standard_normal((m.n_cells, 3)), p=rng.standard_normal(m.n_cells),
                phi=rng.standard_normal(m.n_faces), pc=rng.standard_normal(nwk))
-    g = run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, conv=conv)
+    g = run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, conv=conv, time=time)
     # tangent directions
     dirs = []
     for j in range(nwk):
@@ -74,7 +75,8 @@ def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3, c
     dp = np.stack([d.get("p", np.zeros(m.n_cells)) for d in dirs])
     dphi = np.stack([d.get("phi", np.zeros(m.n_faces)) for d in dirs])
     dpc = np.stack([d.get("pc", np.zeros(nwk)) for d in dirs])
-    prm = O.piso_params(nu, dt, tol_p=1e-13, tol_u=1e-13, maxit_p=20000, maxit_u=5000, tol_tangent=1e-13, conv=conv)
+    prm = O.piso_params(nu, dt, tol_p=1e-13, tol_u=1e-13, maxit_p=20000, maxit_u=5000, tol_tangent=1e-13, conv=conv,
+                        time=time)
     t = O.piso_tangent(m, prm, U0, p0, phi0, Ub, pb, np.array(wk), pc0, nsteps, dwk=dwk, dU0=dU, dp0=dp,
                        dphi0=dphi, dpc0=dpc)
     # forward states agree
