@@ -437,6 +437,13 @@ difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* 
                                 const void* gphi_N, const double* gpc_N_host, double adj_tol, void* gU_0, void* gp_0,
                                 void* gphi_0, double* gpc_0_host, double* gwk_host);
 
+/* Cotangent of the fixed velocity boundary values U_b of the window from the last difvm_piso_adjoint
+ * on this tape (the boundary values are inputs of every step; their cotangent is summed over the
+ * window).  gU_b[Fb*3]: device array, USER boundary order; zero on faces whose velocity is not fixed.
+ * The lid-velocity inverse problem of Sec. "Lid velocity recovery" differentiates through it.
+ * Errors: DIFVM_ERR_INVALID_ARG before an adjoint has run.  Synchronises. */
+difvm_status difvm_tape_boundary_cotangent(const difvm_tape* tape, void* gU_b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -804,7 +804,7 @@ std::vector<int> rcm_order(const om_mesh& m) {
 // ================================================================================================
 extern "C" {
 
-int oracle_version(void) { return 4; }  // 4: time scheme in the PISO parameters
+int oracle_version(void) { return 5; }  // 5: boundary-value tangents
 
 // Renumbering.  rcm = 0 keeps the cell order.  Outputs (new -> old where a permutation):
 //  cell_perm[nc], face_perm[nfi], face_flip[nfi], owner[nfi], nbr[nfi], own_start[nc+1],
@@ -1135,13 +1135,16 @@ int oracle_piso_run(const om_mesh* m, const om_piso_params* prm, const double* U
 int oracle_piso_tangent(const om_mesh* m, const om_piso_params* prm, const double* Ub, const double* pb,
                         const double* wk, int nwk, double* pc, double* U, double* p, double* phi, int nsteps, int nd,
                         const double* dwk, const double* dU0, const double* dp0, const double* dphi0,
-                        const double* dpc0, double* tU, double* tp, double* tphi, double* tpc) {
+                        const double* dpc0, const double* dUb, double* tU, double* tp, double* tphi, double* tpc) {
   if (nd > ND || nd < 0) return -1;
   Piso<Dual> S(*m, *prm);
   int nc = m->nc, nf = m->nfi + m->nfb;
   int nw = std::max(nwk, S.nwk);
   S.Ub.resize((size_t)m->nfb * 3);
-  for (size_t i = 0; i < S.Ub.size(); ++i) S.Ub[i] = Dual(Ub[i]);
+  for (size_t i = 0; i < S.Ub.size(); ++i) {
+    S.Ub[i] = Dual(Ub[i]);
+    for (int k = 0; k < nd; ++k) S.Ub[i].d[k] = dUb ? dUb[(size_t)k * m->nfb * 3 + i] : 0.0;
+  }
   S.pb.resize(m->nfb);
   for (int i = 0; i < m->nfb; ++i) S.pb[i] = Dual(pb[i]);
   S.wk.resize(3 * nw);

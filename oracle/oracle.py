@@ -53,7 +53,7 @@ def lib():
             _b.build()
         _LIB = C.CDLL(path)
         _LIB.oracle_version.restype = C.c_int
-        if _LIB.oracle_version() != 4:
+        if _LIB.oracle_version() != 5:
             raise RuntimeError(f"{path} is stale (version {_LIB.oracle_version()}); rebuild the oracle")
     return _LIB
 
@@ -257,13 +257,14 @@ def piso_run(mesh, prm, U, p, phi, Ub, pb, wk=None, pc=None, nsteps=1):
 
 
 def piso_tangent(mesh, prm, U, p, phi, Ub, pb, wk, pc, nsteps, dwk=None, dU0=None, dp0=None, dphi0=None, dpc0=None,
-                 nd=None):
-    """Forward-mode tangents of the final state.  Seeds have a leading direction axis (nd <= 10)."""
+                 nd=None, dUb=None):
+    """Forward-mode tangents of the final state.  Seeds have a leading direction axis (nd <= 10); dUb
+    seeds the fixed velocity boundary values [nd, Fb, 3]."""
     U, p, phi = _f(U).copy(), _f(p).copy(), _f(phi).copy()
     wk = _f(wk).reshape(-1, 3)
     nwk = wk.shape[0]
     pc = _f(pc).copy() if nwk else np.zeros(1)
-    seeds = [s for s in (dwk, dU0, dp0, dphi0, dpc0) if s is not None]
+    seeds = [s for s in (dwk, dU0, dp0, dphi0, dpc0, dUb) if s is not None]
     if nd is None:
         nd = seeds[0].shape[0] if seeds else 0
     nc, nf = mesh.n_cells, mesh.n_faces
@@ -271,7 +272,8 @@ def piso_tangent(mesh, prm, U, p, phi, Ub, pb, wk, pc, nsteps, dwk=None, dU0=Non
 
     def sd(a):
         return None if a is None else _p(np.ascontiguousarray(np.asarray(a, np.float64)))
-    hold = [None if a is None else np.ascontiguousarray(np.asarray(a, np.float64)) for a in (dwk, dU0, dp0, dphi0, dpc0)]
+    hold = [None if a is None else np.ascontiguousarray(np.asarray(a, np.float64))
+            for a in (dwk, dU0, dp0, dphi0, dpc0, dUb)]
     st = lib().oracle_piso_tangent(om(mesh), C.byref(prm), _p(_f(Ub)), _p(_f(pb)),
                                    _p(np.ascontiguousarray(wk.ravel())), nwk, _p(pc), _p(U), _p(p), _p(phi),
                                    int(nsteps), int(nd), *[None if a is None else _p(a) for a in hold],

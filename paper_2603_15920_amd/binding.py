@@ -132,6 +132,7 @@ _SIGS = {
     "difvm_tape_destroy": (C.c_int32, [_vp]),
     "difvm_piso_forward_record": (C.c_int32, [_vp, _vp, C.POINTER(StepStats)]),
     "difvm_piso_adjoint": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _f64p, C.c_double, _vp, _vp, _vp, _f64p, _f64p]),
+    "difvm_tape_boundary_cotangent": (C.c_int32, [_vp, _vp]),
 }
 
 
@@ -453,6 +454,10 @@ def difvm_piso_forward_record(p, t, nsteps, n_corr=2):
     status = _check(lib().difvm_piso_forward_record(p, t, stats), "difvm_piso_forward_record")
     it = np.array([[*s.it_u, *list(s.it_p)[:n_corr]] for s in stats[:nsteps]], dtype=np.int32)
     return status, it
+
+
+def difvm_tape_boundary_cotangent(t, gU_b):
+    return _check(lib().difvm_tape_boundary_cotangent(t, _ptr(gU_b)), "difvm_tape_boundary_cotangent")
 
 
 def difvm_piso_adjoint(p, t, gU_N, gp_N, gphi_N, gpc_N, adj_tol, gU_0, gp_0, gphi_0, n_wk):

@@ -464,6 +464,31 @@ __global__ __launch_bounds__(BLOCK) void k_adj_phi(MeshView<double> m, double th
   }
 }
 
+// Fixed velocity boundary values U_b enter a step through the face flux of HbyA (phiH_b = U_b . S_b in
+// every corrector), the momentum source (b_O += (nu delta_b - F_b) U_b) and the Gauss gradient of
+// U^n (handled by k_gradT).  Both kernels add into Ubbar[nfb*3], one thread per boundary face.
+__global__ __launch_bounds__(BLOCK) void k_adj_ub_flux(MeshView<double> m, const double* __restrict__ fHb,
+                                                       double* __restrict__ Ubbar) {
+  int b = blockIdx.x * BLOCK + threadIdx.x;
+  if (b >= m.nfb || m.bcode[DIFVM_BC_U * m.nfb + b] != BC_FIXED) return;
+  auto g = m.bgeom[b];
+  double h = fHb[m.nfi + b];
+  Ubbar[3 * (size_t)b] += h * g.x;
+  Ubbar[3 * (size_t)b + 1] += h * g.y;
+  Ubbar[3 * (size_t)b + 2] += h * g.z;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_ub_src(MeshView<double> m, const double* __restrict__ nu_cell,
+                                                      const double* __restrict__ phi, const double* __restrict__ bbar,
+                                                      double* __restrict__ Ubbar) {
+  int b = blockIdx.x * BLOCK + threadIdx.x;
+  if (b >= m.nfb || m.bcode[DIFVM_BC_U * m.nfb + b] != BC_FIXED) return;
+  int O = m.bown[b];
+  double a = nu_cell[O] * m.bgeom[b].w - phi[m.nfi + b];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Ubbar[3 * (size_t)b + c] += a * bbar[3 * (size_t)O + c];
+}
+
 // Windkessel: sum of boundary-pressure cotangents over each outlet (fixed order), and the outlet flow
 // cotangent spread back to its faces
 __global__ __launch_bounds__(BLOCK) void k_adj_wk_sum(const int32_t* __restrict__ wk_start, const int32_t* __restrict__ wk_faces,
@@ -495,7 +520,7 @@ __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double*
 // =============================================================================================
 struct difvm_tape {
   difvm_piso* piso = nullptr;
-  int nsteps = 0, every = 1, nseg = 0, recorded = 0;
+  int nsteps = 0, every = 1, nseg = 0, recorded = 0, reversed = 0;
   std::vector<double*> ckU, ckp, ckphi;   // per checkpoint, internal order
   std::vector<std::vector<double>> ckpc;  // host copies of the capacitor pressures
   std::vector<difvm::StepRecord> rec;     // one per step of a segment
@@ -505,6 +530,7 @@ struct difvm_tape {
   double *dbar = nullptr, *valbar = nullptr, *valT = nullptr, *fHb = nullptr, *faF = nullptr, *fnc = nullptr;
   double *g = nullptr, *tmp = nullptr, *lam = nullptr, *mu = nullptr, *Ubar0 = nullptr, *wkbar = nullptr;
   double* gUn = nullptr;  // grad U^n of the step being reversed (deferred-correction schemes)
+  double* Ubbar = nullptr;  // cotangent of the fixed velocity boundary values, summed over the window [nfb*3]
   double *endU = nullptr, *endp = nullptr, *endphi = nullptr;
   std::vector<double> endpc;
   std::vector<void*> allocs;
@@ -584,7 +610,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     T->valbar = tape_alloc(T, d.nslot); T->valT = tape_alloc(T, d.nslot); T->fHb = tape_alloc(T, nf);
     T->faF = tape_alloc(T, nf); T->fnc = tape_alloc(T, std::max<size_t>(1, d.nfi)); T->g = tape_alloc(T, nf);
     T->tmp = tape_alloc(T, 3 * nc); T->lam = tape_alloc(T, nc); T->mu = tape_alloc(T, 3 * nc);
-    T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk);
+    T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk); T->Ubbar = tape_alloc(T, 3 * (size_t)d.nfb);
     if (P->prm.conv != DIFVM_CONV_UPWIND) T->gUn = tape_alloc(T, 9 * nc);
     T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
   } catch (...) {
@@ -678,6 +704,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);
     k_adj_corr_cells<<<Gc, BLOCK, 0, s>>>(mv, T->fHb, T->faF, T->fnc, R.rAU, R.gpo[c], T->rAUbar, T->HbyAbar, T->gbar);
+    if (d.nfb) k_adj_ub_flux<<<grid_for(d.nfb), BLOCK, 0, s>>>(mv, T->fHb, T->Ubbar);
     // pressure entering the corrector: only through grad(p_old)
     zero(T->pbar, nc, s);
     k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
@@ -702,7 +729,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   case CV:                                                                                                            \
     k_adj_bsrc<CV><<<Gc, BLOCK, 0, s>>>(mv, P->nu_cell, prm.dt, theta, T->bbar, phi_n, d.face_rO, d.face_rN,          \
                                         T->Ubar0, T->gUbar);                                                          \
-    k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, nullptr);                                      \
+    k_gradT<3><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_U, T->gUbar, T->Ubar0, T->Ubbar);                                     \
     k_adj_phi<CV><<<Gf, BLOCK, 0, s>>>(mv, theta, d.face_slot_own, d.face_slot_nbr, phi_n, T->valbar, T->dbar,        \
                                        T->bbar, P->Ub, R.Un, T->gUn, d.face_rO, d.face_rN, T->phibar);                \
     break;
@@ -712,6 +739,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     DIFVM_ADJ_SRC(DIFVM_CONV_QUICK)
 #undef DIFVM_ADJ_SRC
   }
+  if (d.nfb) k_adj_ub_src<<<grid_for(d.nfb), BLOCK, 0, s>>>(mv, P->nu_cell, phi_n, T->bbar, T->Ubbar);
   DIFVM_HIP(hipGetLastError());
   // Windkessel (tiny, on the host): pbv = p_o on each outlet
   int nwk = d.n_wk;
@@ -758,6 +786,7 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
   zero(T->Ubar, 3 * nc, s);
   zero(T->pbar, nc, s);
   zero(T->phibar_in, nf, s);
+  zero(T->Ubbar, 3 * (size_t)d.nfb, s);
   if (gU) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gU, T->Ubar);
   if (gp) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gp, T->pbar);
   if (gphi) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_TO_INTERNAL, gphi, T->phibar_in);
@@ -778,6 +807,7 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
   if (gphi0) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_FROM_INTERNAL, T->phibar_in, gphi0);
   if (gpc0_host) for (int j = 0; j < nwk; ++j) gpc0_host[j] = pcbar[j];
   if (gwk_host) for (int j = 0; j < 3 * nwk; ++j) gwk_host[j] = wkbar[j];
+  T->reversed = 1;
   // leave the PISO at the end of the forward window
   load_state(P, T->endU, T->endp, T->endphi, T->endpc);
   DIFVM_HIP(hipStreamSynchronize(s));
@@ -811,6 +841,17 @@ difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm
   int st = forward_record(piso, tape, stats_host);
   DIFVM_HIP(hipStreamSynchronize(stream_of(piso->mesh)));
   return st;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_tape_boundary_cotangent(const difvm_tape* tape, void* gU_b) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(tape && gU_b, DIFVM_ERR_INVALID_ARG, "tape and gU_b must not be NULL");
+  DIFVM_CHECK(tape->reversed, DIFVM_ERR_INVALID_ARG, "difvm_piso_adjoint has not run on this tape");
+  difvm_mesh* m = tape->piso->mesh;
+  if (m->d.nfb) permute(m, DIFVM_F64, 3, DIFVM_KIND_BFACE, DIFVM_FROM_INTERNAL, tape->Ubbar, gU_b);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
   DIFVM_API_END
   return DIFVM_OK;
 }

@@ -58,3 +58,35 @@ def fit_windkessel(piso, theta0, state0, target, n_windows, steps, observe, iter
             callback(it, history[-1])
         opt.step()
     return torch.exp(log_theta).detach(), history
+
+
+def fit_boundary_scale(piso, pattern, s0, state0, probes, target, steps, iters=30, lr=0.1, betas=(0.7, 0.999),
+                       ckpt_every=10, adj_tol=1e-10, callback=None):
+    """Recovers a scalar s that scales a fixed velocity boundary pattern, U_b = s * pattern [Fb, 3] (the
+    lid-velocity problem of Sec. 3.3.1: U_lid = (s, 0, 0) on the lid faces), from velocities probed at
+    cells `probes` after `steps` steps from state0 = (U, p, phi, pc): Adam on s itself, the loss the
+    mean squared misfit of the probed velocity components against `target` [n_probes, 3].  The initial
+    flux state0[2] is an independent input held fixed (for a lid the boundary flux U_b . S is zero
+    whatever s).  The first-moment decay 0.7 (torch's default is 0.9) damps the slow oscillation
+    of a single parameter about its optimum.  Returns (s, history) with history (loss, s) per
+    iteration."""
+    s = torch.tensor(float(s0), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([s], lr=lr, betas=betas)
+    U0, p0, phi0, pc0 = state0
+    dev = U0.device
+    pattern = torch.as_tensor(pattern, dtype=torch.float64, device=dev)
+    target = torch.as_tensor(target, dtype=torch.float64, device=dev)
+    probes = torch.as_tensor(probes, device=dev)
+    theta = torch.zeros((0, 3), dtype=torch.float64)
+    history = []
+    for it in range(iters):
+        opt.zero_grad()
+        Ub = s.to(dev) * pattern
+        U, p, phi_n, pc = piso_window(piso, theta, U0, p0, phi0, pc0, steps, ckpt_every, adj_tol, Ub=Ub)
+        loss = ((U[probes] - target) ** 2).mean()
+        loss.backward()
+        history.append((float(loss.detach()), float(s.detach())))
+        if callback:
+            callback(it, history[-1])
+        opt.step()
+    return float(s.detach()), history

@@ -91,3 +91,29 @@ def test_windkessel_scalar_derivative():
     expect = [0.0, pcn * dE_dC - Rd * Q * dE_dC, pcn * dE_dRd + Q * (1 - E) - Rd * Q * dE_dRd]
     np.testing.assert_allclose(t["tpc"][:, 0], expect, rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(t["pc"][0], pcn * E + Rd * Q * (1 - E), rtol=1e-14)
+
+
+@pytest.mark.parametrize("conv,time", [("upwind", "backward_euler"), ("sou", "crank_nicolson")])
+def test_boundary_value_tangent_matches_central_fd(conv, time):
+    """Tangent with respect to the fixed velocity boundary values (the inlet profile's amplitude and a
+    random perturbation of all fixed faces) against central differences of the forward run."""
+    m, Ub = wk_channel()
+    prm = O.piso_params(0.05, 0.02, tol_p=1e-13, tol_u=1e-13, maxit_p=5000, maxit_u=2000, tol_tangent=1e-13,
+                        conv=conv, time=time)
+    rng = np.random.default_rng(8)
+    U0 = np.zeros((m.n_cells, 3))
+    U0[:, 0] = 0.5
+    p0 = np.zeros(m.n_cells)
+    phi0 = O.initial_flux(m, U0, Ub)
+    wk = np.array([[0.4, 0.3, 1.5]])
+    pc0 = np.array([0.2])
+    dUb = np.stack([Ub, rng.standard_normal(Ub.shape)])
+    t = O.piso_tangent(m, prm, U0, p0, phi0, Ub, np.zeros(m.n_boundary_faces), wk, pc0, 3, dUb=dUb)
+    tang = np.concatenate([t["tU"].reshape(2, -1), t["tp"], t["tphi"], t["tpc"]], axis=1)
+    for k in range(2):
+        h = 1e-5
+        fd = (run_state(m, Ub + h * dUb[k], wk, pc0, U0, p0, phi0, 3, prm)
+              - run_state(m, Ub - h * dUb[k], wk, pc0, U0, p0, phi0, 3, prm)) / (2 * h)
+        scale = np.abs(fd).max()
+        assert scale > 0
+        assert np.abs(fd - tang[k]).max() / scale < 1e-6, k
