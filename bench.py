@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--no-tube", action="store_true", help="skip the 2M-cell tube PISO run")
     ap.add_argument("--tube-steps", type=int, default=10)
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
+    ap.add_argument("--precond", choices=["jacobi", "amg"], default="jacobi",
+                    help="pressure preconditioner of the timed PISO steps")
     ap.add_argument("--adj-steps", type=int, default=20)
     ap.add_argument("--adj-every", type=int, default=10)
     ap.add_argument("--batch-members", type=int, default=64)
@@ -504,7 +506,7 @@ def main():
     ctx = B.Context(0)
     M = B.Mesh(ctx, m)
     log("device mesh", M.info)
-    prm = B.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
+    prm = B.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000, precond=args.precond)
     P = B.Piso(M, prm)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
     P.set_boundary(dev(Ub), dev(np.zeros(nfb)))

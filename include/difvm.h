@@ -322,6 +322,35 @@ difvm_status difvm_solve_pcg(const difvm_mesh* mesh, const difvm_ldu* A, const v
 difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, int ncomp, const void* b, void* x,
                                   double tol, int32_t maxit, difvm_solve_stats* stats);
 
+/* ---- smoothed-aggregation AMG preconditioner for symmetric pressure systems ---------------------
+ * The paper preconditions its pressure CG with ILU.  Besides Jacobi the library offers one V-cycle of
+ * smoothed-aggregation algebraic multigrid per CG iteration: aggregates of distance-2 strong
+ * neighbourhoods on the finest level and distance-1 below (strength threshold 0.08 on the finest,
+ * 0 below), the constant vector as near-null space, prolongators smoothed by one damped-Jacobi step
+ * with weight 4/(3 rho(D^-1 A)), Galerkin coarse operators, one damped-Jacobi sweep (2/3) before and
+ * after each coarse correction, and the dense inverse of the coarsest level (at most 96 rows if the
+ * matrix coarsens that far, 1024 at most).  The hierarchy is built on the host from one matrix and
+ * kept; the finest level of each V-cycle uses the matrix being solved, so M^-1 stays symmetric
+ * positive definite while the matrix drifts.  One-segment meshes only (DIFVM_ERR_UNSUPPORTED
+ * otherwise).  CG with it converges to the same solution as with Jacobi (the preconditioner changes
+ * the iterates, not the stopping rule). */
+enum { DIFVM_PRECOND_JACOBI = 0, DIFVM_PRECOND_AMG = 1 };
+typedef struct difvm_amg difvm_amg;
+/* Builds the hierarchy of the symmetric F64 LDU matrix A (device arrays, lower ignored; synchronises).
+ * The object holds a reference to the mesh and a copy of A for difvm_amg_apply.  Errors: INVALID_ARG
+ * for a non-positive diagonal, UNSUPPORTED for a multi-segment mesh or a matrix that does not coarsen. */
+difvm_status difvm_amg_create(const difvm_mesh* mesh, const difvm_ldu* A, difvm_amg** out);
+difvm_status difvm_amg_destroy(difvm_amg* amg); /* NULL is a no-op */
+/* rows of each level, finest first, into rows[0..cap) (host); *n_levels receives the level count */
+difvm_status difvm_amg_levels(const difvm_amg* amg, int32_t* rows, int32_t cap, int32_t* n_levels);
+/* z = M^-1 r, one V-cycle with the stored copy of A as finest level (device arrays, internal order,
+ * r != z; synchronises) */
+difvm_status difvm_amg_apply(difvm_amg* amg, const void* r, void* z);
+/* CG on the symmetric F64 LDU matrix A preconditioned by the V-cycle (A as finest level, the stored
+ * hierarchy below); arguments, stopping rule and stats as difvm_solve_pcg. */
+difvm_status difvm_solve_pcg_amg(difvm_amg* amg, const difvm_ldu* A, const void* b, void* x, double tol, int32_t maxit,
+                                 difvm_solve_stats* stats);
+
 /* ---- PISO (paper Sec. "PISO as divergence-free constrained message passing") --------------- */
 typedef struct {
   size_t struct_size;     /* sizeof(difvm_piso_params) */
@@ -338,6 +367,9 @@ typedef struct {
                              U^n and its Gauss gradient and is part of the momentum source b, so
                              it also enters H in every corrector                               */
   int32_t time;           /* time scheme (DIFVM_TIME_*) of the predictor and of scalar transport   */
+  int32_t precond;        /* pressure preconditioner (DIFVM_PRECOND_*); AMG builds its hierarchy from
+                             the pressure matrix of the first solve and keeps it (see
+                             difvm_piso_rebuild_preconditioner); one-segment meshes only       */
 } difvm_piso_params;
 
 typedef struct {
@@ -406,6 +438,11 @@ difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extr
 
 /* Graph-mode counters since creation: replayed steps, discarded-and-redone steps, captures. */
 difvm_status difvm_piso_graph_info(const difvm_piso* piso, int64_t* replays, int64_t* redos, int64_t* captures);
+
+/* Drops the AMG hierarchy of the pressure preconditioner (and a captured step using it); the next
+ * pressure solve builds a new one from its own matrix (e.g. after a change of dt or viscosity).
+ * DIFVM_ERR_INVALID_ARG when the PISO object uses Jacobi. */
+difvm_status difvm_piso_rebuild_preconditioner(difvm_piso* piso);
 
 /* Advances nsteps time steps.  stats_host[nsteps] (may be NULL) receives solver iterations and
  * residuals per step.  Synchronises.  Returns the worst solver status over the steps. */

@@ -22,6 +22,8 @@ SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
 CONV = {"upwind": 0, "linear": 1, "sou": 2, "quick": 3}
 # time schemes (theta-method on the predictor's matrix part: 1, 0, 1/2)
 TIME = {"backward_euler": 0, "forward_euler": 1, "crank_nicolson": 2}
+# pressure preconditioners
+PRECOND = {"jacobi": 0, "amg": 1}
 KIND_CELL, KIND_FACE, KIND_FACE_FLUX, KIND_BFACE = 0, 1, 2, 3
 TO_INTERNAL, FROM_INTERNAL = 0, 1
 RENUMBER_RCM = 1
@@ -77,7 +79,8 @@ class SolveStats(C.Structure):
 class PisoParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("nu", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
                 ("tol_p", C.c_double), ("tol_u", C.c_double), ("maxit_p", C.c_int32), ("maxit_u", C.c_int32),
-                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("conv", C.c_int32), ("time", C.c_int32)]
+                ("p_ref_cell", C.c_int32), ("p_ref_value", C.c_double), ("conv", C.c_int32), ("time", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -114,6 +117,12 @@ _SIGS = {
     "difvm_ldu_assemble_laplace": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.POINTER(Ldu), _vp]),
     "difvm_ldu_assemble_momentum": (C.c_int32, [_vp, C.c_double, C.c_double, _vp, _vp, _vp, C.POINTER(Ldu), _vp]),
     "difvm_solve_pcg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
+    "difvm_amg_create": (C.c_int32, [_vp, C.POINTER(Ldu), C.POINTER(_vp)]),
+    "difvm_amg_destroy": (C.c_int32, [_vp]),
+    "difvm_amg_levels": (C.c_int32, [_vp, _i32p, C.c_int32, _i32p]),
+    "difvm_amg_apply": (C.c_int32, [_vp, _vp, _vp]),
+    "difvm_solve_pcg_amg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
+    "difvm_piso_rebuild_preconditioner": (C.c_int32, [_vp]),
     "difvm_solve_bicgstab": (C.c_int32, [_vp, C.POINTER(Ldu), C.c_int, _vp, _vp, C.c_double, C.c_int32,
                                          C.POINTER(SolveStats)]),
     "difvm_piso_create": (C.c_int32, [_vp, C.POINTER(PisoParams), C.POINTER(_vp)]),
@@ -352,6 +361,38 @@ def difvm_solve_pcg(m, A, b, x, tol, maxit):
     return status, st.iters[0], st.residual[0]
 
 
+def difvm_amg_create(m, A):
+    out = _vp()
+    _check(lib().difvm_amg_create(m, C.byref(A), C.byref(out)), "difvm_amg_create")
+    return out
+
+
+def difvm_amg_destroy(a):
+    _check(lib().difvm_amg_destroy(a), "difvm_amg_destroy")
+
+
+def difvm_amg_levels(a):
+    rows = np.zeros(64, np.int32)
+    n = C.c_int32(0)
+    _check(lib().difvm_amg_levels(a, rows.ctypes.data_as(_i32p), 64, C.byref(n)), "difvm_amg_levels")
+    return rows[:n.value].tolist()
+
+
+def difvm_amg_apply(a, r, z):
+    _check(lib().difvm_amg_apply(a, _ptr(r), _ptr(z)), "difvm_amg_apply")
+
+
+def difvm_solve_pcg_amg(a, A, b, x, tol, maxit):
+    st = SolveStats()
+    status = _check(lib().difvm_solve_pcg_amg(a, C.byref(A), _ptr(b), _ptr(x), float(tol), int(maxit), C.byref(st)),
+                    "difvm_solve_pcg_amg")
+    return status, st.iters[0], st.residual[0]
+
+
+def difvm_piso_rebuild_preconditioner(p):
+    _check(lib().difvm_piso_rebuild_preconditioner(p), "difvm_piso_rebuild_preconditioner")
+
+
 def difvm_solve_bicgstab(m, A, ncomp, b, x, tol, maxit):
     st = SolveStats()
     status = _check(lib().difvm_solve_bicgstab(m, C.byref(A), ncomp, _ptr(b), _ptr(x), float(tol), int(maxit),
@@ -360,9 +401,9 @@ def difvm_solve_bicgstab(m, A, ncomp, b, x, tol, maxit):
 
 
 def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=500, p_ref_cell=0, p_ref_value=0.0,
-                conv="upwind", time="backward_euler"):
+                conv="upwind", time="backward_euler", precond="jacobi"):
     return PisoParams(C.sizeof(PisoParams), nu, dt, n_corr, tol_p, tol_u, maxit_p, maxit_u, p_ref_cell, p_ref_value,
-                      CONV[conv], TIME[time])
+                      CONV[conv], TIME[time], PRECOND[precond])
 
 
 def difvm_piso_create(m, params):

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "abi_util.h"
+#include "amg_dev.h"
 #include "ops.h"
 
 namespace difvm {
@@ -86,6 +87,7 @@ void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out);
 void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
 void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host);
 int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats);
+void piso_rebuild_preconditioner(difvm_piso* P);
 
 static void check_mesh(const difvm_mesh* m) { DIFVM_CHECK(m != nullptr, DIFVM_ERR_INVALID_ARG, "mesh is NULL"); }
 static void check_dtype(int dtype) {
@@ -471,7 +473,7 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
 }
 
 static difvm_status solve_common(const difvm_mesh* cm, const difvm_ldu* A, int ncomp, const void* b, void* x, double tol,
-                                 int32_t maxit, difvm_solve_stats* stats, bool sym) {
+                                 int32_t maxit, difvm_solve_stats* stats, bool sym, const AmgDev* amg = nullptr) {
   difvm_mesh* m = const_cast<difvm_mesh*>(cm);
   check_mesh(m); check_ptr(A, "A"); check_ptr(b, "b"); check_ptr(x, "x"); check_ncomp(ncomp);
   DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "solvers are F64 only");
@@ -483,7 +485,7 @@ static difvm_status solve_common(const difvm_mesh* cm, const difvm_ldu* A, int n
   try {
     sell_from_ldu(m, (const double*)A->upper, sym ? nullptr : (const double*)A->lower, val);
     SellMatrix S{(const double*)A->diag, val};
-    if (sym) R = pcg(m, S, (const double*)b, (double*)x, tol, maxit);
+    if (sym) R = pcg(m, S, (const double*)b, (double*)x, tol, maxit, nullptr, amg);
     else R = bicgstab(m, ncomp, S, (const double*)b, (double*)x, tol, maxit);
   } catch (...) {
     dfree(val);
@@ -510,6 +512,106 @@ difvm_status difvm_solve_bicgstab(const difvm_mesh* m, const difvm_ldu* A, int n
   DIFVM_API_BEGIN
   DIFVM_CHECK(A && (A->lower || (m && m->d.nfi == 0)), DIFVM_ERR_INVALID_ARG, "BiCGStab needs A->lower");
   return solve_common(m, A, ncomp, b, x, tol, maxit, stats, false);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+}  // extern "C"
+
+struct difvm_amg {
+  difvm_mesh* mesh = nullptr;
+  AmgDev* dev = nullptr;
+  double *diag = nullptr, *val = nullptr;  // the matrix the hierarchy was built from (cell-slot form)
+};
+
+static void amg_release(difvm_amg* a) {
+  if (!a) return;
+  amg_free(a->dev);
+  dfree(a->diag);
+  dfree(a->val);
+  difvm_mesh* m = a->mesh;
+  delete a;
+  mesh_release(m);
+}
+
+static void check_sym_ldu(const difvm_mesh* m, const difvm_ldu* A) {
+  check_ptr(A, "A");
+  DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "solvers are F64 only");
+  check_ptr(A->diag, "A->diag");
+  DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
+}
+
+extern "C" {
+
+difvm_status difvm_amg_create(const difvm_mesh* cm, const difvm_ldu* A, difvm_amg** out) {
+  DIFVM_API_BEGIN
+  check_mesh(cm); check_ptr(out, "out");
+  difvm_mesh* m = const_cast<difvm_mesh*>(cm);
+  check_sym_ldu(m, A);
+  DIFVM_CHECK(m->d.nseg == 1, DIFVM_ERR_UNSUPPORTED, "the AMG preconditioner needs a one-segment mesh");
+  difvm_amg* a = new difvm_amg();
+  try {
+    a->diag = dalloc<double>(m->d.nc);
+    a->val = dalloc<double>(m->d.nslot);
+    DIFVM_HIP(hipMemcpyAsync(a->diag, A->diag, sizeof(double) * m->d.nc, hipMemcpyDeviceToDevice, stream_of(m)));
+    sell_from_ldu(m, (const double*)A->upper, nullptr, a->val);
+    a->dev = amg_create(m, SellMatrix{a->diag, a->val}, AmgOptions{});
+  } catch (...) {
+    amg_free(a->dev);
+    dfree(a->diag);
+    dfree(a->val);
+    delete a;
+    throw;
+  }
+  a->mesh = m;
+  m->refs++;
+  *out = a;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_amg_destroy(difvm_amg* amg) {
+  DIFVM_API_BEGIN
+  amg_release(amg);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_amg_levels(const difvm_amg* amg, int32_t* rows, int32_t cap, int32_t* n_levels) {
+  DIFVM_API_BEGIN
+  check_ptr(amg, "amg");
+  DIFVM_CHECK(cap >= 0 && (rows || cap == 0), DIFVM_ERR_INVALID_ARG, "rows is NULL");
+  std::vector<int> r(64);
+  int n = amg_levels(amg->dev, r.data(), 64);
+  for (int l = 0; l < n && l < cap; ++l) rows[l] = r[l];
+  if (n_levels) *n_levels = n;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_amg_apply(difvm_amg* amg, const void* r, void* z) {
+  DIFVM_API_BEGIN
+  check_ptr(amg, "amg"); check_ptr(r, "r"); check_ptr(z, "z");
+  DIFVM_CHECK(r != z, DIFVM_ERR_INVALID_ARG, "r and z must differ");
+  amg_vcycle(amg->dev, SellMatrix{amg->diag, amg->val}, (const double*)r, (double*)z, nullptr, nullptr);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(amg->mesh)));
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_solve_pcg_amg(difvm_amg* amg, const difvm_ldu* A, const void* b, void* x, double tol, int32_t maxit,
+                                 difvm_solve_stats* stats) {
+  DIFVM_API_BEGIN
+  check_ptr(amg, "amg");
+  return solve_common(amg->mesh, A, 1, b, x, tol, maxit, stats, true, amg->dev);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_rebuild_preconditioner(difvm_piso* piso) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  piso_rebuild_preconditioner(piso);
   DIFVM_API_END
   return DIFVM_OK;
 }

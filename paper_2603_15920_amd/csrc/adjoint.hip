@@ -699,7 +699,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     k_axpy<<<Gc, BLOCK, 0, s>>>(nc, 1.0, T->tmp, T->pbar);
     // pressure solve: lambda = K^-1 pbar (K symmetric)
     zero(T->lam, nc, s);
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p);
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, nullptr, P->amg);
     worst = std::max(worst, rp.status);
     k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);

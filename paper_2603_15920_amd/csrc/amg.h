@@ -1,0 +1,49 @@
+// Smoothed-aggregation AMG: host-side hierarchy (amg_host.cpp) and its device form (amg.hip).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace difvm {
+
+struct AmgError {
+  std::string msg;
+};
+
+// Square CSR matrix with n rows.  For operators, diag holds the diagonal and ptr/col/val the
+// off-diagonal entries only; for transfer operators (P, R) diag is unused and every entry is in CSR.
+struct AmgCsr {
+  int n = 0;
+  std::vector<int32_t> ptr, col;
+  std::vector<double> val, diag;
+};
+
+// Transfer between level l (fine) and l+1: P (rows of level l, columns of level l+1) and R = P^T.
+struct AmgLevel {
+  AmgCsr P, R;
+};
+
+struct AmgOptions {
+  double theta = 0.0;        // strength-of-connection threshold on coarse levels (0: every coupling)
+  double theta_fine = 0.08;  // ... and on the finest
+  int radius_fine = 2;       // aggregation over distance-1 or distance-2 strong neighbourhoods
+  int radius = 1;
+  int max_levels = 12;
+  int coarsest = 96;         // stop coarsening at or below this many rows
+  int max_dense = 1024;      // largest coarsest level solved by its dense inverse
+};
+
+// levels[l] maps level l to l+1; coarse[l] is the operator of level l+1; the coarsest operator's dense
+// inverse (row-major, n_coarsest^2) closes the V-cycle.
+struct AmgHierarchy {
+  std::vector<AmgLevel> levels;
+  std::vector<AmgCsr> coarse;
+  int n_coarsest = 0;
+  std::vector<double> coarsest_inv;
+};
+
+// Builds the hierarchy of a symmetric positive definite matrix A0 (diagonal apart).  Throws AmgError.
+void amg_build(const AmgCsr& A0, const AmgOptions& opt, AmgHierarchy& H);
+
+}  // namespace difvm

@@ -2,22 +2,20 @@
 // right-Jacobi BiCGStab (momentum, up to three systems sharing one matrix).  Paper Sec. "Numerical
 // schemes and linear solvers": CG for the symmetric pressure system, BiCGStab for momentum.
 //
-// Every dot product is reduced deterministically (fixed 256-cell tiles, the last tile to finish sums
-// the tile partials in a fixed order).  The scalars live in device memory and every kernel checks
-// the solver's "active" flag first, so iterations queued after convergence are no-ops and the
-// iterate is exactly the one at which the stopping test first held; the host reads the flag only
-// once per block of iterations.
+// Every dot product is reduced deterministically (per-tile partials re-summed in a fixed order by the
+// next kernel).  The scalars live in device memory and every kernel checks the solver's "done" flag
+// first, so iterations queued after convergence are no-ops and the iterate is exactly the one at
+// which the stopping test first held; the host reads the flag only once per block of iterations.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 
+#include "amg_dev.h"
 #include "device.h"
+#include "krylov_util.h"
 #include "ops.h"
 
 namespace difvm {
-
-
-struct PcgCtl;
 
 // BiCGStab state of one segment (up to three systems sharing its matrix)
 struct BiState {
@@ -76,38 +74,8 @@ void krylov_work_free(KrylovWork* w) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// matrix helpers
+// matrix helpers (SellView, sell_row: krylov_util.h)
 // ---------------------------------------------------------------------------------------------
-struct SellView {
-  int nc;
-  const uint8_t* __restrict__ nslot;
-  const int32_t* __restrict__ slice_start;
-  const int32_t* __restrict__ col;
-  const double* __restrict__ val;
-  const double* __restrict__ diag;
-};
-
-static SellView sview(const difvm_mesh* m, SellMatrix A) {
-  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag};
-}
-
-// (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
-template <int NC>
-__device__ __forceinline__ void sell_row(const SellView& A, int i, const double* __restrict__ x, double (&acc)[NC]) {
-  SlotRange R = slots_of(A.slice_start, i);
-  double di = A.diag[i];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    double a = A.val[at];
-    int j = A.col[at];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
-  }
-}
-
 __global__ __launch_bounds__(BLOCK) void k_sell_from_ldu(int nc, int nfi, const int32_t* __restrict__ slice_start,
                                                          const int32_t* __restrict__ slot_face, const double* __restrict__ up,
                                                          const double* __restrict__ lo, double* __restrict__ val) {
@@ -151,72 +119,6 @@ void sell_spmv(const difvm_mesh* m, int ncomp, SellMatrix A, const double* x, do
 }
 
 // ---------------------------------------------------------------------------------------------
-// Reduction tiles: TILE = 1024 cells per block (4 per thread), listed per segment.  A segment is one
-// independent mesh of a block-diagonal batch (a single mesh is one segment); its dot products are
-// the fixed-order sums of its own tiles' partials, so a batch member computes exactly what it would
-// alone.
-// ---------------------------------------------------------------------------------------------
-constexpr int CPT = TILE / BLOCK;  // cells per thread
-
-struct Tiles {
-  int ntile;
-  const int32_t* __restrict__ lo;
-  const int32_t* __restrict__ hi;
-  const int32_t* __restrict__ seg;
-  const int32_t* __restrict__ first;  // per segment
-  const int32_t* __restrict__ count;  // per segment
-};
-static Tiles tiles_of(const difvm_mesh* m) {
-  const DMesh& d = m->d;
-  return {d.ntile, d.tile_lo, d.tile_hi, d.tile_seg, d.seg_tile_first, d.seg_tile_n};
-}
-
-struct TileIdx {
-  int t, s, lo, hi;
-};
-__device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
-  int t = xcd_tile(blockIdx.x, gridDim.x);
-  return {t, T.seg[t], T.lo[t], T.hi[t]};
-}
-
-// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles) by a block of
-// NT threads; every thread ends with the totals
-template <int NV, int NT = BLOCK>
-__device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
-  __shared__ double lds[NV][NT / 64];
-  int f = T.first[s], n = T.count[s];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < n; q += NT) acc += part[(size_t)k * T.ntile + f + q];
-    out[k] = acc;
-  }
-  block_sum<NV, NT>(out, lds);
-}
-
-template <int NV, int NT = BLOCK>
-__device__ __forceinline__ void put_partial(double (&v)[NV], double* __restrict__ part, int ntile, int t) {
-  __shared__ double lds[NV][NT / 64];
-  block_sum<NV, NT>(v, lds);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[(size_t)k * ntile + t] = v[k];
-}
-
-// one read of a flag per block, shared through LDS, so every wave of the block takes the same branch
-// even while the segment's first tile of the same launch may be writing it
-__device__ __forceinline__ bool block_flag(const int* flag) {
-  __shared__ int f;
-  __syncthreads();  // a previous call's readers are done with f
-  if (threadIdx.x == 0) f = *flag;
-  __syncthreads();
-  return f != 0;
-}
-
-#define FOR_TILE_CELLS(I) \
-  _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) if (int I = ti.lo + c_ * BLOCK + threadIdx.x; I < ti.hi)
-
-// ---------------------------------------------------------------------------------------------
 // PCG: two kernels per iteration and no memory fences.
 //
 // Partials of each kernel are re-summed (per segment, fixed order) at the start of the NEXT kernel
@@ -234,11 +136,6 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
 // (measured best on gfx950 for these two memory patterns); the first four slots of a row are
 // unrolled so their loads are in flight together.
 // ---------------------------------------------------------------------------------------------
-struct PcgCtl {
-  double tol, bn, res;
-  double rho[2];  // rho_k at index k & 1
-  int maxit, done, iters, status;
-};
 static_assert(sizeof(PcgCtl) <= sizeof(BiState), "PCG states share the BiState-sized allocation");
 
 constexpr int PCG_SPMV_NT = 512;  // threads per block of the product kernel (TILE / NT cells each)
@@ -259,6 +156,9 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init1(SellView A, Tiles T, const 
   put_partial<2>(v, part, T.ntile, ti.t);
 }
 
+// JAC: Jacobi preconditioner (z = r/d here); otherwise z and the r.z partials come from the V-cycle
+// that follows, and this kernel stores only the r.r partials
+template <bool JAC>
 __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double* __restrict__ x, const double* __restrict__ r,
                                                      double* __restrict__ z, double* __restrict__ p0,
                                                      const double* __restrict__ part_in, double* __restrict__ partB,
@@ -281,15 +181,25 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double
     FOR_TILE_CELLS(i) x[i] = 0.0;
   }
   if (stop) return;
-  double v[2] = {0.0, 0.0};
-  FOR_TILE_CELLS(i) {
-    double ri = r[i], zi = ri / A.diag[i];
-    z[i] = zi;
-    p0[i] = 0.0;  // p_1 = z_0 + 0 * p_0
-    v[0] += ri * ri;
-    v[1] += ri * zi;
+  if constexpr (JAC) {
+    double v[2] = {0.0, 0.0};
+    FOR_TILE_CELLS(i) {
+      double ri = r[i], zi = ri / A.diag[i];
+      z[i] = zi;
+      p0[i] = 0.0;  // p_1 = z_0 + 0 * p_0
+      v[0] += ri * ri;
+      v[1] += ri * zi;
+    }
+    put_partial<2>(v, partB, T.ntile, ti.t);
+  } else {
+    double v[1] = {0.0};
+    FOR_TILE_CELLS(i) {
+      double ri = r[i];
+      p0[i] = 0.0;
+      v[0] += ri * ri;
+    }
+    put_partial<1>(v, partB, T.ntile, ti.t);
   }
-  put_partial<2>(v, partB, T.ntile, ti.t);
 }
 
 // (A (z + beta p))_i with the slot loads of a width-W row issued together
@@ -403,6 +313,7 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
 
 // iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (streaming loads issued
 // before the partial sum so they overlap its latency)
+template <bool JAC>
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
                                                       double* __restrict__ z, const double* __restrict__ p_cur,
                                                       const double* __restrict__ q, const double* __restrict__ partA,
@@ -430,14 +341,21 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, doubl
     if (i < ti.hi) {
       x[i] = xv[c] + alpha * pv[c];
       double ri = rv[c] - alpha * qv[c];
-      double zi = ri / dv[c];
       r[i] = ri;
-      z[i] = zi;
       v[0] += ri * ri;
-      v[1] += ri * zi;
+      if constexpr (JAC) {
+        double zi = ri / dv[c];
+        z[i] = zi;
+        v[1] += ri * zi;
+      }
     }
   }
-  put_partial<2>(v, partB, T.ntile, ti.t);
+  if constexpr (JAC) {
+    put_partial<2>(v, partB, T.ntile, ti.t);
+  } else {
+    double v1[1] = {v[0]};
+    put_partial<1>(v1, partB, T.ntile, ti.t);
+  }
 }
 
 // per-segment control state set on the device (no host buffer, so the launch can be captured)
@@ -503,7 +421,9 @@ static const void* wait_poll(KrylovWork* w, int slot) {
   return w->host_state[slot];
 }
 
-SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit, const QueueOnly* qo) {
+SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit, const QueueOnly* qo,
+                const AmgDev* amg) {
+  DIFVM_CHECK(!amg || m->d.nseg == 1, DIFVM_ERR_UNSUPPORTED, "the AMG preconditioner needs a one-segment mesh");
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
@@ -518,9 +438,26 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   double* partA = w->partials;
   double* partB = w->partials + 2 * (size_t)G;
   double* part0 = w->partials + 4 * (size_t)G;
+  // z = M^-1 r: Jacobi inside the init / update kernels, or one V-cycle after them (which also stores
+  // the r.z partials)
+  auto precondition = [&]() {
+    if (!amg) return;
+    ProfScope ps(m, "pcg_amg_vcycle");
+    amg_vcycle(amg, A, r, z, partB + G, w->pcg);
+  };
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
-  k_pcg_init2<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
+  if (amg) k_pcg_init2<false><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
+  else k_pcg_init2<true><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
   DIFVM_HIP(hipGetLastError());
+  precondition();
+  auto update = [&](int kk) {
+    {
+      ProfScope ps(m, "pcg_update_dot");
+      if (amg) k_pcg_update<false><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
+      else k_pcg_update<true><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
+    }
+    precondition();
+  };
   if (qo) {
     // queue-only: iterations 1..K and the stopping test of iterate K, no read-back
     int K = std::min(qo->budget, maxit);
@@ -529,10 +466,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
         ProfScope ps(m, "pcg_spmv_dot");
         k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
       }
-      if (kk <= K) {
-        ProfScope ps(m, "pcg_update_dot");
-        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
-      }
+      if (kk <= K) update(kk);
     }
     DIFVM_HIP(hipGetLastError());
     copy_state(qo->state_out, w->pcg, pcg_state_bytes(m), s);
@@ -548,10 +482,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
         ProfScope ps(m, "pcg_spmv_dot");
         k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
-      if (k <= maxit) {
-        ProfScope ps(m, "pcg_update_dot");
-        k_pcg_update<<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[k & 1], q, partA, partB, k, w->pcg);
-      }
+      if (k <= maxit) update(k);
     }
     DIFVM_HIP(hipGetLastError());
   };

@@ -1,0 +1,116 @@
+// Helpers shared by the Krylov solvers and the AMG V-cycle: the cell-slot matrix view, reduction
+// tiles with deterministic per-segment sums, and the PCG control state.
+#pragma once
+
+#include "device.h"
+#include "ops.h"
+
+namespace difvm {
+
+// ---------------------------------------------------------------------------------------------
+// matrix helpers
+// ---------------------------------------------------------------------------------------------
+struct SellView {
+  int nc;
+  const uint8_t* __restrict__ nslot;
+  const int32_t* __restrict__ slice_start;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ val;
+  const double* __restrict__ diag;
+};
+
+inline SellView sview(const difvm_mesh* m, SellMatrix A) {
+  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag};
+}
+
+// (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
+template <int NC>
+__device__ __forceinline__ void sell_row(const SellView& A, int i, const double* __restrict__ x, double (&acc)[NC]) {
+  SlotRange R = slots_of(A.slice_start, i);
+  double di = A.diag[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    double a = A.val[at];
+    int j = A.col[at];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reduction tiles: TILE = 1024 cells per block (4 per thread), listed per segment.  A segment is one
+// independent mesh of a block-diagonal batch (a single mesh is one segment); its dot products are
+// the fixed-order sums of its own tiles' partials, so a batch member computes exactly what it would
+// alone.
+// ---------------------------------------------------------------------------------------------
+constexpr int CPT = TILE / BLOCK;  // cells per thread
+
+struct Tiles {
+  int ntile;
+  const int32_t* __restrict__ lo;
+  const int32_t* __restrict__ hi;
+  const int32_t* __restrict__ seg;
+  const int32_t* __restrict__ first;  // per segment
+  const int32_t* __restrict__ count;  // per segment
+};
+inline Tiles tiles_of(const difvm_mesh* m) {
+  const DMesh& d = m->d;
+  return {d.ntile, d.tile_lo, d.tile_hi, d.tile_seg, d.seg_tile_first, d.seg_tile_n};
+}
+
+struct TileIdx {
+  int t, s, lo, hi;
+};
+__device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
+  int t = xcd_tile(blockIdx.x, gridDim.x);
+  return {t, T.seg[t], T.lo[t], T.hi[t]};
+}
+
+// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles) by a block of
+// NT threads; every thread ends with the totals
+template <int NV, int NT = BLOCK>
+__device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
+  __shared__ double lds[NV][NT / 64];
+  int f = T.first[s], n = T.count[s];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < n; q += NT) acc += part[(size_t)k * T.ntile + f + q];
+    out[k] = acc;
+  }
+  block_sum<NV, NT>(out, lds);
+}
+
+template <int NV, int NT = BLOCK>
+__device__ __forceinline__ void put_partial(double (&v)[NV], double* __restrict__ part, int ntile, int t) {
+  __shared__ double lds[NV][NT / 64];
+  block_sum<NV, NT>(v, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[(size_t)k * ntile + t] = v[k];
+}
+
+// one read of a flag per block, shared through LDS, so every wave of the block takes the same branch
+// even while the segment's first tile of the same launch may be writing it
+__device__ __forceinline__ bool block_flag(const int* flag) {
+  __shared__ int f;
+  __syncthreads();  // a previous call's readers are done with f
+  if (threadIdx.x == 0) f = *flag;
+  __syncthreads();
+  return f != 0;
+}
+
+#define FOR_TILE_CELLS(I) \
+  _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) if (int I = ti.lo + c_ * BLOCK + threadIdx.x; I < ti.hi)
+
+// per-segment PCG state (device)
+struct PcgCtl {
+  double tol, bn, res;
+  double rho[2];  // rho_k at index k & 1
+  int maxit, done, iters, status;
+};
+
+}  // namespace difvm

@@ -65,8 +65,10 @@ struct QueueOnly {
   int budget;
   void* state_out;
 };
+struct AmgDev;
+// amg: smoothed-aggregation V-cycle preconditioner (one-segment meshes) instead of Jacobi
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
-                const QueueOnly* qo = nullptr);
+                const QueueOnly* qo = nullptr, const AmgDev* amg = nullptr);
 SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
                      const QueueOnly* qo = nullptr);
 size_t pcg_state_bytes(const difvm_mesh* m);

@@ -480,6 +480,10 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
               "unknown convection scheme");
   DIFVM_CHECK(prm->time >= DIFVM_TIME_BACKWARD_EULER && prm->time <= DIFVM_TIME_CRANK_NICOLSON, DIFVM_ERR_INVALID_ARG,
               "unknown time scheme");
+  DIFVM_CHECK(prm->precond == DIFVM_PRECOND_JACOBI || prm->precond == DIFVM_PRECOND_AMG, DIFVM_ERR_INVALID_ARG,
+              "unknown pressure preconditioner");
+  DIFVM_CHECK(prm->precond != DIFVM_PRECOND_AMG || m->d.nseg == 1, DIFVM_ERR_UNSUPPORTED,
+              "the AMG pressure preconditioner needs a one-segment mesh");
   DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
   const DMesh& d = m->d;
   const HostLayout& L = m->host;
@@ -535,6 +539,7 @@ void piso_release(difvm_piso* P) {
   difvm_mesh* m = P->mesh;
   (void)hipStreamSynchronize(stream_of(m));
   piso_graph_free(P);
+  amg_free(P->amg);
   for (void* a : P->allocs) dfree(a);
   delete P;
   mesh_release(m);
@@ -725,7 +730,12 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
     k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->is_ref, prm.p_ref_value, P->dK, P->valK,
                                      P->rhsK);
     DIFVM_HIP(hipGetLastError());
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p, qu ? &qu->p[corr] : nullptr);
+    if (prm.precond == DIFVM_PRECOND_AMG && !P->amg) {
+      DIFVM_CHECK(!ctx_of(m).capturing, DIFVM_ERR_INVALID_ARG, "AMG hierarchy must exist before a step is captured");
+      P->amg = amg_create(m, SellMatrix{P->dK, P->valK}, AmgOptions{});
+    }
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p, qu ? &qu->p[corr] : nullptr,
+                         P->amg);
     st.it_p[corr] = rp.iters[0];
     st.res_p[corr] = rp.res[0];
     st.status = std::max(st.status, rp.status);
@@ -907,6 +917,15 @@ void piso_set_graph(difvm_piso* P, int enable, int extra) {
     G.backup = piso_alloc(P, state_words(d));
     DIFVM_HIP(hipHostMalloc(&G.state_host, bytes, hipHostMallocDefault));
   }
+}
+
+// drops the pressure preconditioner's hierarchy (and a captured step that uses it): the next AMG
+// solve builds one from its own matrix
+void piso_rebuild_preconditioner(difvm_piso* P) {
+  DIFVM_CHECK(P->prm.precond == DIFVM_PRECOND_AMG, DIFVM_ERR_INVALID_ARG, "the PISO object does not use AMG");
+  graph_drop(P->g);
+  amg_free(P->amg);
+  P->amg = nullptr;
 }
 
 void piso_graph_info(const difvm_piso* P, long long* replays, long long* redos, long long* captures) {

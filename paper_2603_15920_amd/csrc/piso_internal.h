@@ -1,6 +1,7 @@
 // PISO object shared by the forward step (piso.hip) and its discrete adjoint (adjoint.hip).
 #pragma once
 
+#include "amg_dev.h"
 #include "internal.h"
 
 // Captured step (graph mode): the whole step as one hipGraph with a fixed iteration budget per solve
@@ -34,6 +35,7 @@ struct difvm_piso {
   double *sc = nullptr, *scb = nullptr, *sg = nullptr, *sd = nullptr, *sval = nullptr, *sb = nullptr;  // scalar step
   std::vector<void*> allocs;
   std::vector<double> wk_host;  // Rp, C, Rd per id
+  difvm::AmgDev* amg = nullptr;  // pressure preconditioner hierarchy (built at the first AMG solve)
   int refs = 1;                 // the caller's handle plus one per tape
   PisoGraph g;
 };

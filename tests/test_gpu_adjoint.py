@@ -28,10 +28,11 @@ def channel_wk(nxyz=(6, 3, 3), seed=61):
 
 
 def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol=1e-13, conv="upwind",
-               time="backward_euler"):
+               time="backward_euler", precond="jacobi"):
     nwk = len(wk)
     M = B.Mesh(ctx(), m)
-    prm = B.piso_params(nu, dt, tol_p=tol, tol_u=tol, maxit_p=20000, maxit_u=5000, conv=conv, time=time)
+    prm = B.piso_params(nu, dt, tol_p=tol, tol_u=tol, maxit_p=20000, maxit_u=5000, conv=conv, time=time,
+                        precond=precond)
     P = B.Piso(M, prm)
     P.set_boundary(dev(Ub), dev(pb))
     for j, (Rp, Cc, Rd) in enumerate(wk):
@@ -51,12 +52,14 @@ def run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, tol
                 gpc0=gpc0, gwk=gwk)
 
 
-def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3, conv="upwind", time="backward_euler"):
+def check_dot(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, seed=3, conv="upwind", time="backward_euler",
+              precond="jacobi"):
     rng = np.random.default_rng(seed)
     nwk = len(wk)
     cot = dict(U=rng.standard_normal((m.n_cells, 3)), p=rng.standard_normal(m.n_cells),
                phi=rng.standard_normal(m.n_faces), pc=rng.standard_normal(nwk))
-    g = run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, conv=conv, time=time)
+    g = run_window(m, Ub, pb, wk, pc0, U0, p0, phi0, nu, dt, nsteps, every, cot, conv=conv, time=time,
+                   precond=precond)
     # tangent directions
     dirs = []
     for j in range(nwk):

@@ -22,9 +22,9 @@ def lid(m, u=1.0):
     return Ub
 
 
-def make(m, Ub, nu, dt, wk=(), pc0=(), seg=None, nus=None, conv="upwind", time="backward_euler"):
+def make(m, Ub, nu, dt, wk=(), pc0=(), seg=None, nus=None, conv="upwind", time="backward_euler", precond="jacobi"):
     M = B.Mesh(ctx(), m, seg_cell_start=seg)
-    P = B.Piso(M, B.piso_params(nu, dt, conv=conv, time=time))
+    P = B.Piso(M, B.piso_params(nu, dt, conv=conv, time=time, precond=precond))
     if nus is not None:
         P.set_viscosity(nus)
     P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
