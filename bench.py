@@ -25,8 +25,8 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE medians in KiB, scaled by what the counters read for a 256 MiB device
 # copy), valid only for the kernel source they were taken with.
 PCG_SPMV_COUNTERS = {"source": "paper_2603_15920_amd/csrc/krylov.hip",
-                     "sha256": "47b2cac6509a297dd94c08dd5bba63e316f4934785e059bcf5559e96f2059e0b",
-                     "fetch_kib": 38273.6875, "write_kib": 16472.625, "fetch_scale": 1.99974, "write_scale": 1.0}
+                     "sha256": "846f38541876dc172f3b5430edc7adc78ac61bbb4ecb2aec17bc8d136d9118b7",
+                     "fetch_kib": 40001.875, "write_kib": 16472.5625, "fetch_scale": 1.99974, "write_scale": 1.0}
 
 
 def counter_traffic(c):
@@ -226,6 +226,19 @@ def graph_rate(P, torch, steps, wk, extra=16):
             "pcg_iters_per_solve": round(float(itg[:, 3:].mean()), 1)}
 
 
+def precond_rate(B, M, torch, prm_kw, setup, precond, warmup, steps):
+    """The main workload with another pressure preconditioner: a fresh PISO object on the same mesh from
+    rest, `warmup` untimed steps, then `steps` timed steps."""
+    P = B.Piso(M, B.piso_params(**prm_kw, precond=precond))
+    setup(P)
+    P.step(warmup)
+    t, (st, it, _) = timed(torch, lambda: P.step(steps))
+    P.close()
+    return {"precond": precond, "steps": steps, "steps_per_s": round(steps / t, 4),
+            "ms_per_step": round(1e3 * t / steps, 3), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+            "status": int(st)}
+
+
 def poisson_run(B, mg, torch, ctx, sizes=(12, 18, 25, 56)):
     """The paper's 3D Poisson verification workload (manufactured solution on jittered Kuhn cubes of
     10,368 / 34,992 / 93,750 cells, plus the 1,053,696-cell cube): Dirichlet data from the exact field,
@@ -267,7 +280,7 @@ def poisson_run(B, mg, torch, ctx, sizes=(12, 18, 25, 56)):
                         "Jacobi-PCG tol 1e-12", "runs": out}
 
 
-def tube_run(B, mg, torch, ctx, steps):
+def tube_run(B, mg, torch, ctx, steps, precond="amg"):
     """The full PISO configuration on the straight tube (1,999,872 tets, L/D 10, parabolic inlet at
     Re 500, p = 0 outlet, nu 1e-3, dt 1e-3, 2 correctors, PCG tol 1e-8), from rest: the first step
     untimed, then `steps` timed steps (graph mode off, tuned launch shapes)."""
@@ -281,14 +294,14 @@ def tube_run(B, mg, torch, ctx, steps):
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
     M = B.Mesh(ctx, m)
     B.difvm_tune(M.h, None)
-    P = B.Piso(M, B.piso_params(1e-3, 1e-3, tol_p=1e-8, tol_u=1e-8, maxit_p=20000, maxit_u=2000))
+    P = B.Piso(M, B.piso_params(1e-3, 1e-3, tol_p=1e-8, tol_u=1e-8, maxit_p=20000, maxit_u=2000, precond=precond))
     P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
     P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
     log(f"tube: {m.n_cells} cells ready ({time.time() - t0:.1f}s)")
     P.step(1)
     t, (st, it, _) = timed(torch, lambda: P.step(steps))
     out = {"workload": f"tube {m.n_cells} tets, L/D 10, Re 500, p = 0 outlet, nu 1e-3, dt 1e-3, 2 correctors, "
-                       f"PCG tol 1e-8, steps 2-{steps + 1} from rest",
+                       f"PCG tol 1e-8 ({precond} preconditioner), steps 2-{steps + 1} from rest",
            "cells": m.n_cells, "steps": steps, "steps_per_s": round(steps / t, 4),
            "cell_steps_per_s": round(steps * m.n_cells / t, 0), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
            "status": int(st)}
@@ -297,7 +310,7 @@ def tube_run(B, mg, torch, ctx, steps):
     return out
 
 
-def small_case(B, mg, torch, ctx, steps=50):
+def small_case(B, mg, torch, ctx, steps=50, precond="amg"):
     """The small PISO case (lid-driven cavity, 2048 jittered triangle prisms, Re 100, nu 0.01,
     dt 1e-3): launch-bound, so eager stepping against graph mode."""
     import numpy as np
@@ -306,10 +319,11 @@ def small_case(B, mg, torch, ctx, steps=50):
     p = m.patch("lid")
     Ub[p.start - m.n_internal_faces:p.start - m.n_internal_faces + p.size, 0] = 1.0
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-    out = {"workload": f"cavity {m.n_cells} prisms, nu 0.01, dt 1e-3, 2 correctors, tol 1e-8", "cells": m.n_cells}
+    out = {"workload": f"cavity {m.n_cells} prisms, nu 0.01, dt 1e-3, 2 correctors, tol 1e-8 ({precond} preconditioner)",
+           "cells": m.n_cells}
     M = B.Mesh(ctx, m)
     for mode in ("eager", "graph"):
-        P = B.Piso(M, B.piso_params(0.01, 1e-3))
+        P = B.Piso(M, B.piso_params(0.01, 1e-3, precond=precond))
         P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
         P.set_state(dev(np.zeros((m.n_cells, 3))), dev(np.zeros(m.n_cells)), None)
         if mode == "graph":
@@ -326,7 +340,7 @@ def small_case(B, mg, torch, ctx, steps=50):
     return out
 
 
-def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10):
+def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10, precond="amg"):
     """Differentiated form on the Y-bifurcation (~400k tets, 3 Windkessel outlets, nu 1e-3, dt 1e-3):
     after a short spin-up from rest, the plain forward, the recorded forward (checkpoints every
     `every` steps) and the reverse sweep (recomputation of each checkpoint segment plus its adjoint
@@ -341,7 +355,8 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10):
     wk = mg.windkessel_nominal(m, mg.inlet_flow(m, Ub))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
     M = B.Mesh(ctx, m)
-    P = B.Piso(M, B.piso_params(1e-3, 1e-3, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000))
+    P = B.Piso(M, B.piso_params(1e-3, 1e-3, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000,
+                                precond=precond))
     P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
     for j, row in enumerate(wk):
         P.set_windkessel(j, *row, 0.0)
@@ -362,7 +377,7 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10):
     t_adj, (st_a, gpc, gwk) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
     B.difvm_tape_destroy(T)
     return {"workload": f"Y-bifurcation {m.n_cells} tets, 3 RCR outlets, nu 1e-3, dt 1e-3, {spinup}-step spin-up, "
-                        f"{steps}-step window, checkpoint every {every}, tol 1e-8",
+                        f"{steps}-step window, checkpoint every {every}, tol 1e-8 ({precond} preconditioner)",
             "cells": m.n_cells, "steps": steps, "ckpt_every": every,
             "forward_steps_per_s": round(steps / t_fwd, 3), "record_steps_per_s": round(steps / t_rec, 3),
             "adjoint_steps_per_s": round(steps / t_adj, 3), "adjoint_over_forward": round(t_adj / t_fwd, 3),
@@ -465,14 +480,15 @@ def main():
     ap.add_argument("--no-tube", action="store_true", help="skip the 2M-cell tube PISO run")
     ap.add_argument("--tube-steps", type=int, default=10)
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
-    ap.add_argument("--precond", choices=["jacobi", "amg"], default="jacobi",
+    ap.add_argument("--precond", choices=["jacobi", "amg"], default="amg",
                     help="pressure preconditioner of the timed PISO steps")
+    ap.add_argument("--no-other", action="store_true", help="skip the run with the other pressure preconditioner")
     ap.add_argument("--adj-steps", type=int, default=20)
     ap.add_argument("--adj-every", type=int, default=10)
     ap.add_argument("--batch-members", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-adj-steps", type=int, default=10)
-    ap.add_argument("--prof-every", type=int, default=256,
+    ap.add_argument("--prof-every", type=int, default=16,
                     help="time every n-th launch of each PCG kernel with HIP events in the timed region")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
@@ -506,13 +522,16 @@ def main():
     ctx = B.Context(0)
     M = B.Mesh(ctx, m)
     log("device mesh", M.info)
-    prm = B.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000, precond=args.precond)
-    P = B.Piso(M, prm)
+    prm_kw = dict(nu=nu, dt=dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
+    P = B.Piso(M, B.piso_params(**prm_kw, precond=args.precond))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-    P.set_boundary(dev(Ub), dev(np.zeros(nfb)))
-    P.set_windkessel(0, *wk, 0.0)
     U0, p0 = np.zeros((nc, 3)), np.zeros(nc)
-    P.set_state(dev(U0), dev(p0), None)
+
+    def setup(Pp):
+        Pp.set_boundary(dev(Ub), dev(np.zeros(nfb)))
+        Pp.set_windkessel(0, *wk, 0.0)
+        Pp.set_state(dev(U0), dev(p0), None)
+    setup(P)
     torch.cuda.synchronize()
     tuned = None
     if not args.no_tune:
@@ -572,17 +591,23 @@ def main():
                   "status": sts}
         log("scalar", scalar)
 
+    alt = None
+    if not args.no_other:
+        other = "jacobi" if args.precond == "amg" else "amg"
+        alt = precond_rate(B, M, torch, prm_kw, setup, other, args.warmup, min(args.steps, 5))
+        log("other preconditioner", alt)
+
     graph = None
     small = None
     if not args.no_graph:
         graph = graph_rate(P, torch, args.steps, [wk])
         log("graph mode", graph)
-        small = small_case(B, mg, torch, ctx)
+        small = small_case(B, mg, torch, ctx, precond=args.precond)
         log("small case", small)
 
     tube = None
     if not args.no_tube:
-        tube = tube_run(B, mg, torch, ctx, args.tube_steps)
+        tube = tube_run(B, mg, torch, ctx, args.tube_steps, precond=args.precond)
         log("tube", tube)
     poisson = None
     if not args.no_poisson:
@@ -590,7 +615,7 @@ def main():
         log("poisson", poisson)
     adjoint = None
     if not args.no_adjoint:
-        adjoint = adjoint_window(B, mg, torch, ctx, args.adj_steps, args.adj_every)
+        adjoint = adjoint_window(B, mg, torch, ctx, args.adj_steps, args.adj_every, precond=args.precond)
         log("adjoint window", adjoint)
     batched = None
     if not args.no_batch:
@@ -620,13 +645,16 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"PISO channel on the Kuhn cube {args.n}^3 hexes -> {nc} tets (jitter 0.15h), "
-                               "parabolic inlet, Windkessel outlet, Re 200, dt 1e-3, 2 correctors, PCG tol 1e-8",
+                               "parabolic inlet, Windkessel outlet, Re 200, dt 1e-3, 2 correctors, PCG tol 1e-8 "
+                               f"({args.precond} preconditioner)",
                    "cells": nc, "internal_faces": nfi, "boundary_faces": nfb, "nu": nu, "dt": dt, "n_corr": 2,
-                   "tol_p": 1e-8, "tol_u": 1e-8},
+                   "tol_p": 1e-8, "tol_u": 1e-8, "pressure_preconditioner": args.precond},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
-                   "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st)},
+                   "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st),
+                   "pressure_preconditioner": args.precond},
+        "other_preconditioner": alt,
         "kernel_avg_us_timed_region": kernel_us,
         "tuned_launch": tuned,
         "graph_mode": graph,
