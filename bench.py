@@ -385,7 +385,7 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10, precond="amg"):
             "status": [int(st), int(st_r), int(st_a)]}
 
 
-def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
+def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps, precond="amg"):
     """Batched form: n_members seeded meshes of uneven size packed block-diagonally into one mesh of
     segments, each with its own viscosity and Windkessel; steps/s of the batch against the same members
     advanced one after another as separate meshes, and a checkpointed window of adj_steps through the
@@ -400,7 +400,7 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
 
     def setup(mesh, Ub, wk, nus, seg=None):
         M = B.Mesh(ctx, mesh, seg_cell_start=seg)
-        P = B.Piso(M, B.piso_params(float(nus[0]), **prm))
+        P = B.Piso(M, B.piso_params(float(nus[0]), **prm, precond=precond))
         if seg is not None:
             P.set_viscosity(nus)
         P.set_boundary(dev(Ub), dev(np.zeros(mesh.n_boundary_faces)))
@@ -426,7 +426,8 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps):
         P.close()
         M.close()
     out = {"workload": f"{n_members} seeded members (even: tubes, odd: box channels), sizes log-uniform in "
-                       f"[2e4, 3e5] cells, Re in [100, 800], one RCR each, dt 1e-3, 2 correctors, tol 1e-8",
+                       f"[2e4, 3e5] cells, Re in [100, 800], one RCR each, dt 1e-3, 2 correctors, tol 1e-8 "
+                       f"({precond} preconditioner)",
            "members": n_members, "cells": Pm.n_cells, "steps": steps,
            "batch_steps_per_s": round(steps / t_b, 3),
            "batch_cell_steps_per_s": round(steps * Pm.n_cells / t_b, 0),
@@ -619,7 +620,8 @@ def main():
         log("adjoint window", adjoint)
     batched = None
     if not args.no_batch:
-        batched = batch_run(B, mg, torch, ctx, args.batch_members, args.batch_steps, args.batch_adj_steps)
+        batched = batch_run(B, mg, torch, ctx, args.batch_members, args.batch_steps, args.batch_adj_steps,
+                            precond=args.precond)
         log("batched", batched)
 
     ops = None

@@ -331,14 +331,15 @@ difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, in
  * after each coarse correction, and the dense inverse of the coarsest level (at most 96 rows if the
  * matrix coarsens that far, 1024 at most).  The hierarchy is built on the host from one matrix and
  * kept; the finest level of each V-cycle uses the matrix being solved, so M^-1 stays symmetric
- * positive definite while the matrix drifts.  One-segment meshes only (DIFVM_ERR_UNSUPPORTED
- * otherwise).  CG with it converges to the same solution as with Jacobi (the preconditioner changes
+ * positive definite while the matrix drifts.  On a batched mesh no aggregate crosses a segment, so
+ * the V-cycle is block-diagonal and each segment's CG still stops on its own test.  CG with it
+ * converges to the same solution as with Jacobi (the preconditioner changes
  * the iterates, not the stopping rule). */
 enum { DIFVM_PRECOND_JACOBI = 0, DIFVM_PRECOND_AMG = 1 };
 typedef struct difvm_amg difvm_amg;
 /* Builds the hierarchy of the symmetric F64 LDU matrix A (device arrays, lower ignored; synchronises).
  * The object holds a reference to the mesh and a copy of A for difvm_amg_apply.  Errors: INVALID_ARG
- * for a non-positive diagonal, UNSUPPORTED for a multi-segment mesh or a matrix that does not coarsen. */
+ * for a non-positive diagonal, UNSUPPORTED for a matrix that does not coarsen below 1,024 rows. */
 difvm_status difvm_amg_create(const difvm_mesh* mesh, const difvm_ldu* A, difvm_amg** out);
 difvm_status difvm_amg_destroy(difvm_amg* amg); /* NULL is a no-op */
 /* rows of each level, finest first, into rows[0..cap) (host); *n_levels receives the level count */
@@ -369,7 +370,10 @@ typedef struct {
   int32_t time;           /* time scheme (DIFVM_TIME_*) of the predictor and of scalar transport   */
   int32_t precond;        /* pressure preconditioner (DIFVM_PRECOND_*); AMG builds its hierarchy from
                              the pressure matrix of the first solve and keeps it (see
-                             difvm_piso_rebuild_preconditioner); one-segment meshes only       */
+                             difvm_piso_rebuild_preconditioner).  On a batched mesh the
+                             hierarchy is block-diagonal over the segments, but a member's
+                             iterates then differ from its standalone run's (its aggregates
+                             follow the packed numbering)                                       */
 } difvm_piso_params;
 
 typedef struct {

@@ -548,7 +548,6 @@ difvm_status difvm_amg_create(const difvm_mesh* cm, const difvm_ldu* A, difvm_am
   check_mesh(cm); check_ptr(out, "out");
   difvm_mesh* m = const_cast<difvm_mesh*>(cm);
   check_sym_ldu(m, A);
-  DIFVM_CHECK(m->d.nseg == 1, DIFVM_ERR_UNSUPPORTED, "the AMG preconditioner needs a one-segment mesh");
   difvm_amg* a = new difvm_amg();
   try {
     a->diag = dalloc<double>(m->d.nc);

@@ -230,7 +230,6 @@ __global__ __launch_bounds__(BLOCK) void k_amg_fine_post(SellView K, Tiles T, co
 
 AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
   const DMesh& d = m->d;
-  DIFVM_CHECK(d.nseg == 1, DIFVM_ERR_UNSUPPORTED, "the AMG preconditioner needs a one-segment mesh");
   const HostLayout& L = m->host;
   hipStream_t s = stream_of(m);
   std::vector<double> diag(d.nc), val(d.nslot);

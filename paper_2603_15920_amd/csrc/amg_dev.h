@@ -10,8 +10,9 @@ namespace difvm {
 struct PcgCtl;
 struct AmgDev;
 
-// Builds the hierarchy from the symmetric cell-slot matrix K of a one-segment mesh (copied to the
-// host; synchronises) and uploads it.  Throws Error.
+// Builds the hierarchy from the symmetric cell-slot matrix K (copied to the host; synchronises) and
+// uploads it.  No face joins two segments, so no aggregate does either and every level stays
+// block-diagonal over the segments.  Throws Error.
 AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt);
 void amg_free(AmgDev* a);
 // z = M^-1 r, one symmetric V-cycle (damped Jacobi, one sweep before and after each coarse

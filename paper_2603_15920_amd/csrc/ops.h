@@ -66,7 +66,7 @@ struct QueueOnly {
   void* state_out;
 };
 struct AmgDev;
-// amg: smoothed-aggregation V-cycle preconditioner (one-segment meshes) instead of Jacobi
+// amg: smoothed-aggregation V-cycle preconditioner instead of Jacobi
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
                 const QueueOnly* qo = nullptr, const AmgDev* amg = nullptr);
 SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,

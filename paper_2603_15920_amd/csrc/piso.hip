@@ -482,8 +482,6 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
               "unknown time scheme");
   DIFVM_CHECK(prm->precond == DIFVM_PRECOND_JACOBI || prm->precond == DIFVM_PRECOND_AMG, DIFVM_ERR_INVALID_ARG,
               "unknown pressure preconditioner");
-  DIFVM_CHECK(prm->precond != DIFVM_PRECOND_AMG || m->d.nseg == 1, DIFVM_ERR_UNSUPPORTED,
-              "the AMG pressure preconditioner needs a one-segment mesh");
   DIFVM_CHECK(prm->dt > 0 && prm->nu >= 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
   const DMesh& d = m->d;
   const HostLayout& L = m->host;
