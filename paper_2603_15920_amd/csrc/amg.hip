@@ -82,11 +82,28 @@ DevCsr upload_csr(AmgDev* a, const AmgCsr& M, bool with_diag, hipStream_t s) {
 }
 
 // ---- kernels ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool stopped(const PcgCtl* ctl) { return ctl && ctl->done; }
+// Every segment's CG stopped: the V-cycle of an iteration queued past the stop has nothing to do.
+// One thread reads the flags and the block shares the answer, so whole blocks return together.
+struct StopFlags {
+  const PcgCtl* ctl;  // nullptr: never stopped
+  int nseg;
+};
+__device__ __forceinline__ bool stopped(const StopFlags& st) {
+  if (!st.ctl) return false;
+  __shared__ int f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int all = 1;
+    for (int g = 0; g < st.nseg && all; ++g) all = st.ctl[g].done;
+    f = all;
+  }
+  __syncthreads();
+  return f != 0;
+}
 
 // level 0, down: res = r - K (w D^-1 r)
 __global__ __launch_bounds__(BLOCK) void k_amg_fine_pre(SellView K, const double* __restrict__ r,
-                                                        double* __restrict__ res, const PcgCtl* ctl) {
+                                                        double* __restrict__ res, StopFlags ctl) {
   if (stopped(ctl)) return;
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= K.nc) return;
@@ -115,7 +132,7 @@ template <int SW>
 __global__ __launch_bounds__(BLOCK) void k_amg_restrict(int n, const int32_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col, const double* __restrict__ val,
                                                         const double* __restrict__ xin, double* __restrict__ out,
-                                                        const PcgCtl* ctl) {
+                                                        StopFlags ctl) {
   if (stopped(ctl)) return;
   int g = blockIdx.x * BLOCK + threadIdx.x;
   int row = g / SW, lane = g % SW;
@@ -131,7 +148,7 @@ template <int SW>
 __global__ __launch_bounds__(BLOCK) void k_amg_pre(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, const double* __restrict__ diag,
                                                    const double* __restrict__ b, double* __restrict__ res,
-                                                   const PcgCtl* ctl) {
+                                                   StopFlags ctl) {
   if (stopped(ctl)) return;
   int g = blockIdx.x * BLOCK + threadIdx.x;
   int row = g / SW, lane = g % SW;
@@ -153,7 +170,7 @@ template <int SW>
 __global__ __launch_bounds__(BLOCK) void k_amg_post(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                     const double* __restrict__ val, const double* __restrict__ diag,
                                                     const double* __restrict__ b, const double* __restrict__ t,
-                                                    double* __restrict__ x, const PcgCtl* ctl) {
+                                                    double* __restrict__ x, StopFlags ctl) {
   if (stopped(ctl)) return;
   int g = blockIdx.x * BLOCK + threadIdx.x;
   int row = g / SW, lane = g % SW;
@@ -172,7 +189,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
                                                        const int32_t* __restrict__ col, const double* __restrict__ val,
                                                        const double* __restrict__ diag, const double* __restrict__ b,
                                                        const double* __restrict__ xc, double* __restrict__ t,
-                                                       const PcgCtl* ctl) {
+                                                       StopFlags ctl) {
   if (stopped(ctl)) return;
   int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
@@ -184,7 +201,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
 // coarsest: x = A_L^-1 b (dense, one thread per row, one block)
 __global__ __launch_bounds__(1024) void k_amg_coarsest(int n, const double* __restrict__ inv,
                                                        const double* __restrict__ b, double* __restrict__ x,
-                                                       const PcgCtl* ctl) {
+                                                       StopFlags ctl) {
   if (stopped(ctl)) return;
   int i = threadIdx.x;
   if (i >= n) return;
@@ -197,9 +214,9 @@ __global__ __launch_bounds__(1024) void k_amg_coarsest(int n, const double* __re
 // level 0, up: z = t + w D^-1 (r - K t), with per-tile partials of r.z
 __global__ __launch_bounds__(BLOCK) void k_amg_fine_post(SellView K, Tiles T, const double* __restrict__ r,
                                                          const double* __restrict__ t, double* __restrict__ z,
-                                                         double* __restrict__ part, const PcgCtl* ctl) {
+                                                         double* __restrict__ part, StopFlags ctl) {
   TileIdx ti = tile_idx(T);
-  if (ctl && block_flag(&ctl->done)) return;
+  if (stopped(ctl)) return;
   double v[1] = {0.0};
   FOR_TILE_CELLS(i) {
     double kt[1];
@@ -321,7 +338,7 @@ int amg_levels(const AmgDev* a, int* rows, int cap) {
 }
 
 static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const double* r, double* z, double* part,
-                          const PcgCtl* ctl) {
+                          StopFlags ctl) {
   difvm_mesh* m = a->mesh;
   SellView K = sview(m, Km);
   const int L = a->L, nc = m->d.nc;
@@ -354,14 +371,15 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
   DIFVM_HIP(hipGetLastError());
 }
 
-void amg_vcycle(const AmgDev* a, SellMatrix Km, const double* r, double* z, double* part, const PcgCtl* ctl) {
+void amg_vcycle(const AmgDev* a, SellMatrix Km, const double* r, double* z, double* part, const PcgCtl* ctls) {
   difvm_mesh* m = a->mesh;
   Ctx& c = ctx_of(m);
+  StopFlags ctl{ctls, m->d.nseg};
   if (c.capturing) {  // inside a captured step: the kernels join that graph
     launch_vcycle(a, c.stream, Km, r, z, part, ctl);
     return;
   }
-  const void* key[6] = {Km.diag, Km.val, r, z, part, ctl};
+  const void* key[6] = {Km.diag, Km.val, r, z, part, ctls};
   if (!a->vexec || !std::equal(key, key + 6, a->vkey)) {
     if (a->vexec) {
       DIFVM_HIP(hipStreamSynchronize(c.stream));  // a replay of the old graph may still be queued

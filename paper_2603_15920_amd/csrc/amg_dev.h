@@ -18,7 +18,8 @@ void amg_free(AmgDev* a);
 // z = M^-1 r, one symmetric V-cycle (damped Jacobi, one sweep before and after each coarse
 // correction; the finest level uses K, the coarser ones the stored Galerkin operators), queued on
 // the mesh's stream.  part != nullptr: the last kernel stores per-tile partials of r.z at part[t].
-// ctl != nullptr: every kernel returns at once when ctl->done (iterations queued after a stop).
+// ctl != nullptr (the per-segment CG states): every kernel returns at once when all segments have
+// stopped (iterations queued after the stop).
 void amg_vcycle(const AmgDev* a, SellMatrix K, const double* r, double* z, double* part, const PcgCtl* ctl);
 // rows per level (finest first) into rows[0..cap); returns the number of levels
 int amg_levels(const AmgDev* a, int* rows, int cap);

@@ -439,12 +439,12 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   double* part0 = w->partials + 4 * (size_t)G;
   // z = M^-1 r: Jacobi inside the init / update kernels, or one V-cycle after them (which also stores
   // the r.z partials)
-  // (the V-cycle's kernels skip their work once a one-segment solve has stopped; with several
-  // segments they run on, which changes nothing a stopped segment reads)
+  // (the V-cycle's kernels skip their work once every segment has stopped; while some segment runs
+  // on they compute for all, which changes nothing a stopped segment reads)
   auto precondition = [&]() {
     if (!amg) return;
     ProfScope ps(m, "pcg_amg_vcycle");
-    amg_vcycle(amg, A, r, z, partB + G, nseg == 1 ? w->pcg : nullptr);
+    amg_vcycle(amg, A, r, z, partB + G, w->pcg);
   };
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
   if (amg) k_pcg_init2<false><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
