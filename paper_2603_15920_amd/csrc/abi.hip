@@ -151,6 +151,23 @@ static void upload_mesh(difvm_mesh* m) {
   d.slice_start = up_vec(m, L.slice_start);
   d.slot_face = up_vec(m, L.slot_face);
   d.slot_col = up_vec(m, L.slot_col);
+  {
+    // the PCG product reads columns as 16-bit offsets from the row when RCM keeps them that close
+    std::vector<int16_t> off(L.slot_col.size(), 0);
+    bool fits = true;
+    for (int sl = 0; sl < L.nslice && fits; ++sl)
+      for (int at = L.slice_start[sl]; at < L.slice_start[sl + 1]; ++at) {
+        int row = sl * SLICE + (at - L.slice_start[sl]) % SLICE;
+        int o = L.slot_col[at] - row;
+        if (row >= L.nc) continue;  // padding rows of the last slice are never read
+        if (o < INT16_MIN || o > INT16_MAX) {
+          fits = false;
+          break;
+        }
+        off[at] = (int16_t)o;
+      }
+    d.slot_off16 = fits ? up_vec(m, off) : nullptr;
+  }
   d.cell_nslot = up_vec(m, L.cell_nslot);
   d.face_slot_own = up_vec(m, L.face_slot_own);
   d.face_slot_nbr = up_vec(m, L.face_slot_nbr);

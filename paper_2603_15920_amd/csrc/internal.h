@@ -102,6 +102,7 @@ struct DMesh {
   float* V32;
   // cell-slot layout (SELL, slices of 64 cells, slot-major inside a slice)
   int32_t *slice_start, *slot_face, *slot_col;
+  int16_t* slot_off16;  // slot_col - row as 16 bits, or NULL when some offset does not fit
   uint8_t* cell_nslot;
   int32_t *face_slot_own, *face_slot_nbr;
   // segments and reduction tiles

@@ -203,15 +203,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_init2(SellView A, Tiles T, double
 }
 
 // (A (z + beta p))_i with the slot loads of a width-W row issued together
-template <int W>
-__device__ __forceinline__ double dir_row(const SellView& A, int base, double acc, double beta,
+// OFF16: columns read as 16-bit offsets from the row (half the index bytes of the 32-bit columns)
+template <int W, bool OFF16>
+__device__ __forceinline__ double dir_row(const SellView& A, int i, int base, double acc, double beta,
                                           const double* __restrict__ z, const double* __restrict__ pp) {
   double a[W], zj[W], pj[W];
   int j[W];
 #pragma unroll
   for (int sl = 0; sl < W; ++sl) {
     a[sl] = A.val[base + sl * SLICE];
-    j[sl] = A.col[base + sl * SLICE];
+    if constexpr (OFF16) j[sl] = i + A.off16[base + sl * SLICE];
+    else j[sl] = A.col[base + sl * SLICE];
   }
 #pragma unroll
   for (int sl = 0; sl < W; ++sl) {
@@ -242,6 +244,7 @@ __device__ __forceinline__ TileWalk tile_walk(int ntile) {
 }
 
 // iteration k >= 1: stopping test of iterate k-1, then p_k and q = A p_k
+template <bool OFF16>
 __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, int k, const double* __restrict__ z,
                                                           const double* __restrict__ p_prev, double* __restrict__ p_cur,
                                                           double* __restrict__ q, const double* __restrict__ partB,
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
         const int nrow = row_len(A.nslot, i, R);
         double acc = A.diag[i] * pi;
         walk_row<4>(nrow, [&](auto Wc, int k0) {
-          acc = dir_row<decltype(Wc)::value>(A, R.base + k0 * SLICE, acc, beta, z, p_prev);
+          acc = dir_row<decltype(Wc)::value, OFF16>(A, i, R.base + k0 * SLICE, acc, beta, z, p_prev);
         });
         p_cur[i] = pi;
         q[i] = acc;
@@ -309,6 +312,13 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
     }
     put_partial<1, NT>(v, partA, T.ntile, t);
   }
+}
+
+static void launch_pcg_spmv(int G, hipStream_t s, const SellView& V, const Tiles& T, int k, const double* z,
+                            const double* p_prev, double* p_cur, double* q, const double* partB, double* partA,
+                            PcgCtl* ctls) {
+  if (V.off16) k_pcg_spmv<true><<<G, PCG_SPMV_NT, 0, s>>>(V, T, k, z, p_prev, p_cur, q, partB, partA, ctls);
+  else k_pcg_spmv<false><<<G, PCG_SPMV_NT, 0, s>>>(V, T, k, z, p_prev, p_cur, q, partB, partA, ctls);
 }
 
 // iteration k: alpha, x and r updates, z = r/d, partials of r.r and r.z (streaming loads issued
@@ -465,7 +475,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     for (int kk = 1; kk <= K + 1; ++kk) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
+        launch_pcg_spmv(GS, s, V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
       }
       if (kk <= K) update(kk);
     }
@@ -481,7 +491,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     for (int n = 0; n < nb && k <= maxit + 1; ++n, ++k) {
       {
         ProfScope ps(m, "pcg_spmv_dot");
-        k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
+        launch_pcg_spmv(GS, s, V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
       if (k <= maxit) update(k);
     }
@@ -905,10 +915,10 @@ double time_pcg_spmv(difvm_mesh* m, int grid, int reps, hipEvent_t e0, hipEvent_
     Tiles T = tiles_of(m);
     double* partA = w->partials;
     double* partB = w->partials + 2 * (size_t)T.ntile;
-    k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
+    launch_pcg_spmv(GS, s, V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
     DIFVM_HIP(hipEventRecord(e0, s));
     for (int r = 0; r < reps; ++r)
-      k_pcg_spmv<<<GS, PCG_SPMV_NT, 0, s>>>(V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
+      launch_pcg_spmv(GS, s, V, T, 2, w->z, w->p, w->v, w->q, partB, partA, ctl);
     DIFVM_HIP(hipEventRecord(e1, s));
     DIFVM_HIP(hipGetLastError());
     DIFVM_HIP(hipEventSynchronize(e1));

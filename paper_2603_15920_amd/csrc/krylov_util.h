@@ -17,10 +17,11 @@ struct SellView {
   const int32_t* __restrict__ col;
   const double* __restrict__ val;
   const double* __restrict__ diag;
+  const int16_t* __restrict__ off16;  // col - row in 16 bits (NULL when it does not fit)
 };
 
 inline SellView sview(const difvm_mesh* m, SellMatrix A) {
-  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag};
+  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag, m->d.slot_off16};
 }
 
 // (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
