@@ -101,7 +101,15 @@ __device__ __forceinline__ bool stopped(const StopFlags& st) {
   return f != 0;
 }
 
+// column of slot `at` in row i (16-bit offsets when the mesh has them)
+template <bool OFF16>
+__device__ __forceinline__ int slot_col_of(const SellView& K, int i, int at) {
+  if constexpr (OFF16) return i + K.off16[at];
+  else return K.col[at];
+}
+
 // level 0, down: res = r - K (w D^-1 r)
+template <bool OFF16>
 __global__ __launch_bounds__(BLOCK) void k_amg_fine_pre(SellView K, const double* __restrict__ r,
                                                         double* __restrict__ res, StopFlags ctl) {
   if (stopped(ctl)) return;
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_fine_pre(SellView K, const double
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
-    int j = K.col[at];
+    int j = slot_col_of<OFF16>(K, i, at);
     acc += K.val[at] * (r[j] / K.diag[j]);
   }
   double ri = r[i];
@@ -212,6 +220,7 @@ __global__ __launch_bounds__(1024) void k_amg_coarsest(int n, const double* __re
 }
 
 // level 0, up: z = t + w D^-1 (r - K t), with per-tile partials of r.z
+template <bool OFF16>
 __global__ __launch_bounds__(BLOCK) void k_amg_fine_post(SellView K, Tiles T, const double* __restrict__ r,
                                                          const double* __restrict__ t, double* __restrict__ z,
                                                          double* __restrict__ part, StopFlags ctl) {
@@ -219,10 +228,16 @@ __global__ __launch_bounds__(BLOCK) void k_amg_fine_post(SellView K, Tiles T, co
   if (stopped(ctl)) return;
   double v[1] = {0.0};
   FOR_TILE_CELLS(i) {
-    double kt[1];
-    sell_row<1>(K, i, t, kt);
+    SlotRange R = slots_of(K.slice_start, i);
+    double di = K.diag[i], ti = t[i];
+    double kt = di * ti;
+#pragma unroll 4
+    for (int k = 0; k < R.width; ++k) {
+      int at = R.base + k * SLICE;
+      kt += K.val[at] * t[slot_col_of<OFF16>(K, i, at)];
+    }
     double ri = r[i];
-    double zi = t[i] + OMEGA * (ri - kt[0]) / K.diag[i];
+    double zi = ti + OMEGA * (ri - kt) / di;
     z[i] = zi;
     v[0] += ri * zi;
   }
@@ -343,7 +358,8 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
   SellView K = sview(m, Km);
   const int L = a->L, nc = m->d.nc;
   // down
-  k_amg_fine_pre<<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->res[0], ctl);
+  if (K.off16) k_amg_fine_pre<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->res[0], ctl);
+  else k_amg_fine_pre<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->res[0], ctl);
   {
     const DevCsr& R = a->R[0];
     DIFVM_AMG_DISPATCH(k_amg_restrict, R.sw, R.n, s, R.n, R.ptr, R.col, R.val, a->res[0], a->b[1], ctl);
@@ -367,7 +383,8 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
     k_amg_prolong<<<grid_for(P.n), BLOCK, 0, s>>>(P.n, P.ptr, P.col, P.val, Km.diag, r, a->x[1], a->t[0], ctl);
   }
   Tiles T = tiles_of(m);
-  k_amg_fine_post<<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], z, part, ctl);
+  if (K.off16) k_amg_fine_post<true><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], z, part, ctl);
+  else k_amg_fine_post<false><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], z, part, ctl);
   DIFVM_HIP(hipGetLastError());
 }
 
