@@ -342,6 +342,13 @@ typedef struct difvm_amg difvm_amg;
  * for a non-positive diagonal, UNSUPPORTED for a matrix that does not coarsen below 1,024 rows. */
 difvm_status difvm_amg_create(const difvm_mesh* mesh, const difvm_ldu* A, difvm_amg** out);
 difvm_status difvm_amg_destroy(difvm_amg* amg); /* NULL is a no-op */
+/* Host-only setup of the same hierarchy (no device), for inspection: a symmetric matrix with n rows
+ * given as CSR of its off-diagonal entries (ptr[n+1], col, val; host arrays) and its diagonal diag[n].
+ * Outputs (host, may be NULL): agg[n], the finest level's aggregate of each row; rows[0..cap), the rows
+ * of each level, finest first; *n_levels.  Errors: INVALID_ARG for a malformed matrix or a
+ * non-positive diagonal, UNSUPPORTED when it does not coarsen below 1,024 rows. */
+difvm_status difvm_amg_setup_host(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, const double* diag,
+                                  int32_t* agg, int32_t* rows, int32_t cap, int32_t* n_levels);
 /* rows of each level, finest first, into rows[0..cap) (host); *n_levels receives the level count */
 difvm_status difvm_amg_levels(const difvm_amg* amg, int32_t* rows, int32_t cap, int32_t* n_levels);
 /* z = M^-1 r, one V-cycle with the stored copy of A as finest level (device arrays, internal order,

@@ -119,6 +119,7 @@ _SIGS = {
     "difvm_solve_pcg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
     "difvm_amg_create": (C.c_int32, [_vp, C.POINTER(Ldu), C.POINTER(_vp)]),
     "difvm_amg_destroy": (C.c_int32, [_vp]),
+    "difvm_amg_setup_host": (C.c_int32, [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, C.c_int32, _i32p]),
     "difvm_amg_levels": (C.c_int32, [_vp, _i32p, C.c_int32, _i32p]),
     "difvm_amg_apply": (C.c_int32, [_vp, _vp, _vp]),
     "difvm_solve_pcg_amg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
@@ -365,6 +366,22 @@ def difvm_amg_create(m, A):
     out = _vp()
     _check(lib().difvm_amg_create(m, C.byref(A), C.byref(out)), "difvm_amg_create")
     return out
+
+
+def difvm_amg_setup_host(ptr, col, val, diag):
+    """host-only hierarchy of a symmetric CSR matrix (off-diagonals) with diagonal diag: returns (agg, rows)"""
+    n = len(diag)
+    ptr = np.ascontiguousarray(ptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    diag = np.ascontiguousarray(diag, np.float64)
+    agg = np.empty(n, np.int32)
+    rows = np.zeros(64, np.int32)
+    nl = C.c_int32(0)
+    _check(lib().difvm_amg_setup_host(n, ptr.ctypes.data_as(_i32p), col.ctypes.data_as(_i32p), val.ctypes.data_as(_f64p),
+                                      diag.ctypes.data_as(_f64p), agg.ctypes.data_as(_i32p), rows.ctypes.data_as(_i32p),
+                                      64, C.byref(nl)), "difvm_amg_setup_host")
+    return agg, rows[:nl.value].tolist()
 
 
 def difvm_amg_destroy(a):

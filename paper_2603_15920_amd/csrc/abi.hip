@@ -586,6 +586,38 @@ difvm_status difvm_amg_create(const difvm_mesh* cm, const difvm_ldu* A, difvm_am
   return DIFVM_OK;
 }
 
+difvm_status difvm_amg_setup_host(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, const double* diag,
+                                  int32_t* agg, int32_t* rows, int32_t cap, int32_t* n_levels) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(n > 0 && ptr && diag && (ptr[n] == 0 || (col && val)), DIFVM_ERR_INVALID_ARG, "bad CSR matrix");
+  DIFVM_CHECK(cap >= 0 && (rows || cap == 0), DIFVM_ERR_INVALID_ARG, "rows is NULL");
+  AmgCsr A;
+  A.n = n;
+  A.ptr.assign(ptr, ptr + n + 1);
+  DIFVM_CHECK(A.ptr[0] == 0, DIFVM_ERR_INVALID_ARG, "ptr[0] must be 0");
+  for (int i = 0; i < n; ++i) DIFVM_CHECK(A.ptr[i + 1] >= A.ptr[i], DIFVM_ERR_INVALID_ARG, "ptr must not decrease");
+  A.col.assign(col, col + A.ptr[n]);
+  A.val.assign(val, val + A.ptr[n]);
+  A.diag.assign(diag, diag + n);
+  for (int i = 0; i < n; ++i) {
+    DIFVM_CHECK(A.diag[i] > 0.0, DIFVM_ERR_INVALID_ARG, "AMG needs a matrix with a positive diagonal");
+    for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q)
+      DIFVM_CHECK(A.col[q] >= 0 && A.col[q] < n && A.col[q] != i, DIFVM_ERR_INVALID_ARG, "column out of range or on the diagonal");
+  }
+  AmgHierarchy H;
+  try {
+    amg_build(A, AmgOptions{}, H);
+  } catch (const AmgError& e) {
+    throw Error{DIFVM_ERR_UNSUPPORTED, "AMG setup: " + e.msg};
+  }
+  if (agg) std::copy(H.agg0.begin(), H.agg0.end(), agg);
+  int nl = (int)H.levels.size() + 1;
+  for (int l = 0; l < nl && l < cap; ++l) rows[l] = l == 0 ? n : H.coarse[l - 1].n;
+  if (n_levels) *n_levels = nl;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
 difvm_status difvm_amg_destroy(difvm_amg* amg) {
   DIFVM_API_BEGIN
   amg_release(amg);

@@ -37,6 +37,7 @@ struct AmgOptions {
 // levels[l] maps level l to l+1; coarse[l] is the operator of level l+1; the coarsest operator's dense
 // inverse (row-major, n_coarsest^2) closes the V-cycle.
 struct AmgHierarchy {
+  std::vector<int32_t> agg0;  // aggregate of each finest-level row
   std::vector<AmgLevel> levels;
   std::vector<AmgCsr> coarse;
   int n_coarsest = 0;

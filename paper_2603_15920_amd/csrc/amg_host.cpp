@@ -188,9 +188,8 @@ struct SparseAcc {
 // rows), Galerkin operator P^T A P (off-diagonals in CSR, diagonal apart, symmetrised exactly) and the
 // coarse near-null-space vector.
 static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta, int radius, AmgLevel& L, AmgCsr& Ac,
-                    std::vector<double>& Bc) {
+                    std::vector<double>& Bc, std::vector<int32_t>& agg) {
   const int n = A.n;
-  std::vector<int32_t> agg;
   int na = aggregate(A, theta, agg, radius);
   if (na >= n || na == 0) return false;
   // tentative prolongator: the near-null-space vector restricted to each aggregate, normalised
@@ -328,7 +327,10 @@ void amg_build(const AmgCsr& A0, const AmgOptions& opt, AmgHierarchy& H) {
     AmgLevel L;
     AmgCsr Ac;
     std::vector<double> Bc;
-    if (!coarsen(A, B, l == 0 ? opt.theta_fine : opt.theta, l == 0 ? opt.radius_fine : opt.radius, L, Ac, Bc)) break;
+    std::vector<int32_t> agg;
+    if (!coarsen(A, B, l == 0 ? opt.theta_fine : opt.theta, l == 0 ? opt.radius_fine : opt.radius, L, Ac, Bc, agg))
+      break;
+    if (l == 0) H.agg0 = agg;
     if (Ac.n > (int)(0.85 * A.n)) break;  // no real coarsening: stop here
     H.levels.push_back(std::move(L));
     H.coarse.push_back(Ac);

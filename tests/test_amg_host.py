@@ -1,0 +1,154 @@
+"""Host logic of the AMG preconditioner's setup (difvm_amg_setup_host, no device): the finest level's
+aggregation against a plain Python implementation of the same rule (strong couplings
+|a_ij| >= 0.08 sqrt(a_ii a_jj), distance-2 neighbourhoods, three greedy phases in row order), the
+structure of the aggregates, the level sizes, and the argument errors."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15920_amd import binding as B
+from paper_2603_15920_amd import meshgen as mg
+
+
+def laplace_csr(m):
+    """off-diagonal CSR (ascending columns) and diagonal of the SPD Dirichlet Laplacian of a mesh"""
+    d, u, _ = O.assemble_laplace(m, phib=np.zeros(m.n_boundary_faces), table=O.TABLE_ALL_FIXED)
+    Fi = m.n_internal_faces
+    rows = np.concatenate([m.owner[:Fi], m.neighbour])
+    cols = np.concatenate([m.neighbour, m.owner[:Fi]])
+    vals = np.concatenate([u, u])
+    o = np.lexsort((cols, rows))
+    rows, cols, vals = rows[o], cols[o], vals[o]
+    ptr = np.zeros(m.n_cells + 1, np.int64)
+    np.add.at(ptr, rows + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), cols.astype(np.int32), vals, d
+
+
+def chain_csr(n):
+    """1D Laplacian on a path of n nodes (Dirichlet ends)"""
+    ptr, col, val = [0], [], []
+    for i in range(n):
+        for j in (i - 1, i + 1):
+            if 0 <= j < n:
+                col.append(j)
+                val.append(-1.0)
+        ptr.append(len(col))
+    return np.array(ptr, np.int32), np.array(col, np.int32), np.array(val), np.full(n, 2.0)
+
+
+def reference_aggregation(ptr, col, val, diag, theta=0.08):
+    n = len(diag)
+    strong = [[col[q] for q in range(ptr[i], ptr[i + 1])
+               if abs(val[q]) >= theta * np.sqrt(abs(diag[i] * diag[col[q]]))] for i in range(n)]
+    # distance-2 neighbourhoods, in the order: each strong neighbour, then its strong neighbours
+    G = []
+    for i in range(n):
+        seen, row = {i}, []
+        for j in strong[i]:
+            if j not in seen:
+                seen.add(j)
+                row.append(j)
+            for k in strong[j]:
+                if k not in seen:
+                    seen.add(k)
+                    row.append(k)
+        G.append(row)
+    agg = [-1] * n
+    na = 0
+    for i in range(n):                       # phase 1: roots whose neighbourhood is entirely free
+        if agg[i] >= 0 or any(agg[j] >= 0 for j in G[i]):
+            continue
+        agg[i] = na
+        for j in G[i]:
+            agg[j] = na
+        na += 1
+    phase1 = [a >= 0 for a in agg]
+    join = [-1] * n
+    for i in range(n):                       # phase 2: join the first phase-1 neighbour's aggregate
+        if phase1[i]:
+            continue
+        for j in G[i]:
+            if phase1[j]:
+                join[i] = agg[j]
+                break
+    for i in range(n):
+        if join[i] >= 0:
+            agg[i] = join[i]
+    for i in range(n):                       # phase 3: the rest with their free neighbours
+        if agg[i] >= 0:
+            continue
+        agg[i] = na
+        for j in G[i]:
+            if agg[j] < 0:
+                agg[j] = na
+        na += 1
+    return np.array(agg), na
+
+
+@pytest.mark.parametrize("case", ["chain", "kuhn6", "tube"])
+def test_aggregation_matches_reference(case):
+    if case == "chain":
+        ptr, col, val, diag = chain_csr(203)
+    elif case == "kuhn6":
+        ptr, col, val, diag = laplace_csr(mg.kuhn_cube(6, jitter=0.15, patches="walls", seed=3))
+    else:
+        ptr, col, val, diag = laplace_csr(mg.tube(n=6, m=3, layers=6))
+    agg, rows = B.difvm_amg_setup_host(ptr, col, val, diag)
+    ref, na = reference_aggregation(ptr, col, val, diag)
+    assert np.array_equal(agg, ref)
+    assert rows[0] == len(diag) and rows[1] == na
+
+
+def test_chain_aggregates_are_five_consecutive_nodes():
+    """on a path a phase-1 aggregate is a root with its distance-2 neighbourhood: node 0 takes {0, 1, 2},
+    every later root the five nodes around it, and the last aggregate absorbs the at most two nodes left
+    at the end (phase 2)"""
+    ptr, col, val, diag = chain_csr(500)
+    agg, rows = B.difvm_amg_setup_host(ptr, col, val, diag)
+    sizes = np.bincount(agg)
+    assert sizes[0] == 3 and np.all(sizes[1:-1] == 5) and 5 <= sizes[-1] <= 7, sizes
+    assert all(np.all(np.diff(np.flatnonzero(agg == a)) == 1) for a in range(agg.max() + 1))  # contiguous
+
+
+def test_kuhn_hierarchy_structure():
+    m = mg.kuhn_cube(12, jitter=0.15, patches="walls", seed=2603007)
+    ptr, col, val, diag = laplace_csr(m)
+    agg, rows = B.difvm_amg_setup_host(ptr, col, val, diag)
+    n = len(diag)
+    assert rows[0] == n and all(rows[i + 1] < rows[i] for i in range(len(rows) - 1))
+    assert rows[1] * 8 <= n            # distance-2 aggregates of tets: more than 8 rows each on average
+    assert rows[-1] <= 96
+    assert agg.min() == 0 and len(np.unique(agg)) == agg.max() + 1 == rows[1]   # a partition, no gaps
+    # every aggregate is connected through links of at most two matrix-graph edges (phase 1 takes a
+    # root's distance-2 neighbourhood; a phase-2 row joins an aggregate within distance 2 of it)
+    nbr1 = [set(col[ptr[i]:ptr[i + 1]].tolist()) for i in range(n)]
+    nbr = [nbr1[i] | set().union(*(nbr1[j] for j in nbr1[i])) for i in range(n)]
+    for a in np.unique(agg)[::7]:
+        members = set(np.flatnonzero(agg == a).tolist())
+        start = next(iter(members))
+        seen, stack = {start}, [start]
+        while stack:
+            i = stack.pop()
+            for j in nbr[i]:
+                if j in members and j not in seen:
+                    seen.add(j)
+                    stack.append(j)
+        assert seen == members, a
+
+
+def test_setup_errors():
+    ptr, col, val, diag = chain_csr(300)
+    bad = diag.copy()
+    bad[7] = 0.0
+    with pytest.raises(B.DifvmError) as e:
+        B.difvm_amg_setup_host(ptr, col, val, bad)
+    assert e.value.status == B.ERR_INVALID_ARG
+    col2 = col.copy()
+    col2[ptr[2]] = 2                       # row 2 pointing at its own diagonal
+    with pytest.raises(B.DifvmError) as e:
+        B.difvm_amg_setup_host(ptr, col2, val, diag)
+    assert e.value.status == B.ERR_INVALID_ARG
+    # no off-diagonal coupling at all: nothing to aggregate beyond singletons
+    with pytest.raises(B.DifvmError) as e:
+        B.difvm_amg_setup_host(np.zeros(301, np.int32), np.zeros(0, np.int32), np.zeros(0), np.ones(300))
+    assert e.value.status == B.ERR_UNSUPPORTED
