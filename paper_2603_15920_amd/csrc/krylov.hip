@@ -911,7 +911,7 @@ double time_pcg_spmv(difvm_mesh* m, int grid, int reps, hipEvent_t e0, hipEvent_
     m->tune[DIFVM_TUNE_PCG_GRID] = grid;
     int GS = pcg_spmv_grid(m);
     m->tune[DIFVM_TUNE_PCG_GRID] = old;
-    SellView V{d.nc, d.cell_nslot, d.slice_start, d.slot_col, val, diag};
+    SellView V = sview(m, SellMatrix{diag, val});  // the same column form the solves read
     Tiles T = tiles_of(m);
     double* partA = w->partials;
     double* partB = w->partials + 2 * (size_t)T.ntile;
