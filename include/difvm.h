@@ -125,7 +125,8 @@ difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
  * n = 0 disables it, n < 0 is DIFVM_ERR_INVALID_ARG.  Launches inside a captured step (graph mode,
  * difvm_piso_set_graph) are not timed.  difvm_ctx_profile_read
  * synchronises, returns per-kernel counts of timed launches and their summed event durations
- * (kernel names in out[k].name), and clears the record. */
+ * (kernel names in out[k].name), and clears the record.  Launches of CG iterations queued after the
+ * solve had stopped (they return at once) are reported under "<name> (idle)". */
 typedef struct {
   char name[32];
   int32_t launches;
@@ -327,11 +328,14 @@ difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, in
  * smoothed-aggregation algebraic multigrid per CG iteration: aggregates of distance-2 strong
  * neighbourhoods on the finest level and distance-1 below (strength threshold 0.08 on the finest,
  * 0 below), the constant vector as near-null space, prolongators smoothed by one damped-Jacobi step
- * with weight 4/(3 rho(D^-1 A)), Galerkin coarse operators, one damped-Jacobi sweep (2/3) before and
- * after each coarse correction, and the dense inverse of the coarsest level (at most 96 rows if the
- * matrix coarsens that far, 1024 at most).  The hierarchy is built on the host from one matrix and
- * kept; the finest level of each V-cycle uses the matrix being solved, so M^-1 stays symmetric
- * positive definite while the matrix drifts.  On a batched mesh no aggregate crosses a segment, so
+ * with weight 4/(3 rho(D^-1 A)), Galerkin coarse operators, and the dense inverse of the coarsest level
+ * (at most 96 rows if the matrix coarsens that far, 1024 at most).  The same smoothing sweep runs
+ * before and after each coarse correction: on the finest level a degree-2 Chebyshev polynomial in
+ * D^-1 A over [hi/10, hi], hi the largest of 2 and the Gershgorin bound of D^-1 A at setup (2 bounds
+ * every weakly diagonally dominant matrix, such as the pressure operators); on coarser levels one
+ * damped-Jacobi sweep (2/3).  The hierarchy is built on the host from one matrix and kept; the
+ * finest level of each V-cycle uses the matrix being solved, so M^-1 stays symmetric positive
+ * definite while the matrix drifts within that spectral bound.  On a batched mesh no aggregate crosses a segment, so
  * the V-cycle is block-diagonal and each segment's CG still stops on its own test.  CG with it
  * converges to the same solution as with Jacobi (the preconditioner changes
  * the iterates, not the stopping rule). */

@@ -34,21 +34,22 @@ static hipEvent_t pool_event(Profiler& P) {
   return e;
 }
 
-int prof_begin(Ctx& c, const char* name) {
+static int prof_id(Profiler& P, const std::string& name) {
+  for (size_t k = 0; k < P.names.size(); ++k)
+    if (P.names[k] == name) return (int)k;
+  P.names.push_back(name);
+  P.total_ms.push_back(0.0);
+  P.launches.push_back(0);
+  P.seen.push_back(0);
+  return (int)P.names.size() - 1;
+}
+
+int prof_begin(Ctx& c, const char* name, long iter) {
   Profiler& P = c.prof;
   if (!P.on || c.capturing) return -1;
-  int id = -1;
-  for (size_t k = 0; k < P.names.size(); ++k)
-    if (P.names[k] == name) id = (int)k;
-  if (id < 0) {
-    id = (int)P.names.size();
-    P.names.push_back(name);
-    P.total_ms.push_back(0.0);
-    P.launches.push_back(0);
-    P.seen.push_back(0);
-  }
+  int id = prof_id(P, name);
   if (P.seen[id]++ % P.stride != 0) return -1;
-  Profiler::Rec r{id, pool_event(P), pool_event(P)};
+  Profiler::Rec r{id, pool_event(P), pool_event(P), iter};
   DIFVM_HIP(hipEventRecord(r.a, c.stream));
   P.pending.push_back(r);
   return (int)P.pending.size() - 1;
@@ -57,6 +58,14 @@ int prof_begin(Ctx& c, const char* name) {
 void prof_end(Ctx& c, int handle) {
   if (handle < 0) return;
   (void)hipEventRecord(c.prof.pending[handle].b, c.stream);
+}
+
+void prof_idle_after(Ctx& c, size_t from, long last) {
+  Profiler& P = c.prof;
+  for (size_t k = from; k < P.pending.size(); ++k) {
+    Profiler::Rec& r = P.pending[k];
+    if (r.iter > last) r.id = prof_id(P, P.names[r.id] + " (idle)");
+  }
 }
 
 static void prof_collect(Ctx& c) {

@@ -2,15 +2,23 @@
 //
 // One V-cycle, z = M^-1 r, from level 0 (the cell-slot matrix K of the mesh, internal order) down to
 // a coarsest level solved with its dense inverse:
-//   down, level l:  x_l = w D_l^-1 b_l (one damped-Jacobi sweep from zero),  res_l = b_l - A_l x_l,
+//   down, level l:  x_l = S_l(b_l) (smoothing from zero),  res_l = b_l - A_l x_l,
 //                   b_{l+1} = R_l res_l                         (b_0 = r)
 //   coarsest:       x_L = A_L^-1 b_L
-//   up, level l:    t_l = x_l + P_l x_{l+1},  x_l = t_l + w D_l^-1 (b_l - A_l t_l)   (z = x_0)
-// with w = 2/3.  Pre- and post-smoothing are the same symmetric sweep and R_l = P_l^T, so M^-1 is
-// symmetric; it is positive definite since w rho(D^-1 A) < 2.  x_l = w D^-1 b_l is recomputed where
-// needed rather than stored.  Each stage is one kernel: row kernels on the cell-slot layout for
-// level 0, CSR kernels with SW lanes per row (rows summed by a fixed shuffle tree) on coarser levels,
-// so every result is deterministic.
+//   up, level l:    t_l = x_l + P_l x_{l+1},  x_l = t_l + S_l(b_l - A_l t_l)   (z = x_0)
+// Every smoother is one degree-2 Chebyshev sweep in D_l^-1 A_l over [hi_l / 10, hi_l] (a fixed
+// polynomial in D^-1 A times D^-1), the same before and after the coarse correction, and R_l = P_l^T,
+// so M^-1 is symmetric; it is positive definite while the spectrum of D^-1 A stays below
+// hi + lo = 1.1 hi, where the smoothing polynomial contracts.  hi_0 is a Gershgorin bound of D^-1 K
+// (at least 2, which bounds every weakly diagonally dominant K); hi_l = 1.1 times the setup's
+// power-iteration estimate of rho(D_l^-1 A_l) on the stored coarse operators.  A sweep takes two
+// passes over the level's operator: from zero, D^-1 b gives d0 without one; on the way up the first
+// pass uses b_l - A_l t_l = res_l - (A_l P_l) x_{l+1}, with A_l P_l stored, so prolongation and that
+// residual are one pass on levels l >= 1 (level 0 smooths with the operator of the current solve and
+// keeps the prolongation a pass of its own).  Degree-2 Chebyshev on every level takes about half the
+// CG iterations of one damped-Jacobi step per level, which more than pays for the extra passes.
+// Each stage is one kernel: row kernels on the cell-slot layout for level 0, CSR kernels with SW
+// lanes per row (rows summed by a fixed shuffle tree) elsewhere, so every result is deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -21,12 +29,12 @@
 namespace difvm {
 
 namespace {
-constexpr double OMEGA = 2.0 / 3.0;
 
 struct DevCsr {
   int n = 0, nnz = 0, sw = 1;  // sw: lanes per row in the CSR kernels
   int32_t *ptr = nullptr, *col = nullptr;
   double *val = nullptr, *diag = nullptr;
+  double* val2 = nullptr;  // A P: P's values on its pattern
 };
 }  // namespace
 
@@ -34,8 +42,12 @@ struct AmgDev {
   difvm_mesh* mesh = nullptr;
   int L = 0;                     // coarse levels 1..L (level L is the coarsest)
   std::vector<DevCsr> A;         // A[l], l = 1..L (A[0] unused: level 0 is K)
-  std::vector<DevCsr> P, R;      // P[l]: rows of level l, columns of l+1; R[l]: rows of level l+1
-  std::vector<double*> b, res, t, x;  // per level (index 0: res, t only)
+  DevCsr P0;                     // prolongation from level 1 to level 0
+  std::vector<DevCsr> R, AP;     // R[l]: rows of level l+1, columns of l; AP[l] (l >= 1): rows of l
+  std::vector<double*> b, bd, res, x;  // per level (index 0: res only; bd: D^-1 b, levels 1..L-1)
+  std::vector<double*> xs, t, d0;      // levels 0..L-1: pre-smoothed x, xs + P x_{l+1}, first
+                                       // post-smoothing step
+  std::vector<double> hi;        // levels 0..L-1: upper end of the Chebyshev interval
   double* cinv = nullptr;        // dense inverse of A_L, row-major
   std::vector<int> rows;
   std::vector<void*> allocs;
@@ -83,22 +95,72 @@ DevCsr upload_csr(AmgDev* a, const AmgCsr& M, bool with_diag, hipStream_t s) {
 
 // ---- kernels ------------------------------------------------------------------------------------
 // Every segment's CG stopped: the V-cycle of an iteration queued past the stop has nothing to do.
-// One thread reads the flags and the block shares the answer, so whole blocks return together.
+// The flags are written only by the CG kernels queued before the V-cycle on the same stream, so they
+// do not change while a V-cycle kernel runs: every wave reads them itself, one segment per lane, and
+// votes (no barrier), and whole blocks return together.  Called first thing, with every lane active.
 struct StopFlags {
   const PcgCtl* ctl;  // nullptr: never stopped
   int nseg;
 };
 __device__ __forceinline__ bool stopped(const StopFlags& st) {
   if (!st.ctl) return false;
-  __shared__ int f;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int all = 1;
-    for (int g = 0; g < st.nseg && all; ++g) all = st.ctl[g].done;
-    f = all;
+  int all = 1;
+  for (int g = threadIdx.x & 63; g < st.nseg; g += 64) all &= st.ctl[g].done;
+  return __all(all) != 0;
+}
+
+// Sum of val[q] x(col[q]) over q = lo, lo + SW, lo + 2 SW, ... < hi (one lane's share of a CSR row),
+// in that order, with the loads of UN entries in flight together (rows of a few entries per lane
+// would otherwise wait on one load chain per entry).  Entries past the row's end load its last entry
+// (no branch around a load, which would make each one wait) and are not added.
+template <int SW, int UN = 4, class X>
+__device__ __forceinline__ double csr_lane_dot(int lo, int hi, const int32_t* __restrict__ col,
+                                               const double* __restrict__ val, X&& x) {
+  double s = 0.0;
+  for (int q = lo; q < hi; q += UN * SW) {
+    int c[UN];
+    double v[UN], xv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      int k = min(q + u * SW, hi - 1);
+      c[u] = col[k];
+      v[u] = val[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) xv[u] = x(c[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (q + u * SW < hi) s += v[u] * xv[u];
   }
-  __syncthreads();
-  return f != 0;
+  return s;
+}
+
+// The same for two value arrays on one pattern: sa = sum va[q] x(col[q]), sb = sum vb[q] x(col[q]).
+template <int SW, int UN = 4, class X>
+__device__ __forceinline__ void csr_lane_dot2(int lo, int hi, const int32_t* __restrict__ col,
+                                              const double* __restrict__ va, const double* __restrict__ vb, X&& x,
+                                              double& sa, double& sb) {
+  sa = 0.0;
+  sb = 0.0;
+  for (int q = lo; q < hi; q += UN * SW) {
+    int c[UN];
+    double a[UN], b[UN], xv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      int k = min(q + u * SW, hi - 1);
+      c[u] = col[k];
+      a[u] = va[k];
+      b[u] = vb[k];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) xv[u] = x(c[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (q + u * SW < hi) {
+        sa += a[u] * xv[u];
+        sb += b[u] * xv[u];
+      }
+  }
 }
 
 // column of slot `at` in row i (16-bit offsets when the mesh has them)
@@ -108,23 +170,94 @@ __device__ __forceinline__ int slot_col_of(const SellView& K, int i, int at) {
   else return K.col[at];
 }
 
-// level 0, down: res = r - K (w D^-1 r)
-template <bool OFF16>
-__global__ __launch_bounds__(BLOCK) void k_amg_fine_pre(SellView K, const double* __restrict__ r,
-                                                        double* __restrict__ res, StopFlags ctl) {
-  if (stopped(ctl)) return;
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  if (i >= K.nc) return;
-  SlotRange R = slots_of(K.slice_start, i);
+// Off-diagonal part of row i of K applied to f: sum over the row's slots of K_ij f(j) (padding and
+// boundary slots hold 0 and the row's own index)
+template <bool OFF16, class F>
+__device__ __forceinline__ double sell_offdiag(const SellView& K, int i, SlotRange R, F&& f) {
   double acc = 0.0;
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
-    int j = slot_col_of<OFF16>(K, i, at);
-    acc += K.val[at] * (r[j] / K.diag[j]);
+    acc += K.val[at] * f(slot_col_of<OFF16>(K, i, at));
   }
-  double ri = r[i];
-  res[i] = ri - OMEGA * ri - OMEGA * acc;
+  return acc;
+}
+
+// The degree-2 Chebyshev sweep in D^-1 A over [lo, hi] (hi bounds the spectrum of D^-1 A), the same
+// before and after the coarse correction.  From x with residual rh0 = D^-1 (b - A x):  d0 = rh0 / theta,  rh1 = rh0 - D^-1 K d0,  d1 = c_d d0 + c_r rh1,
+// x <- x + d0 + d1,  with theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta,
+// rho0 = 1 / sigma, rho1 = 1 / (2 sigma - rho0), c_d = rho1 rho0, c_r = 2 rho1 / delta.
+struct Cheb {
+  double theta, inv_theta, c_d, c_r;
+};
+
+Cheb cheb_coefficients(double lo, double hi) {
+  double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  return {theta, 1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
+}
+
+// level 0, down, first pass (x = 0, b = r): xs = d0 + d1, with d0 = D^-1 r / theta
+template <bool OFF16>
+__global__ __launch_bounds__(BLOCK) void k_amg_cheb_pre1(SellView K, const double* __restrict__ r,
+                                                         double* __restrict__ xs, Cheb c, StopFlags ctl) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  // row range loaded at a clamped index, without a branch around the load, so that it is in flight
+  // together with the flag reads
+  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  if (stopped(ctl) || i >= K.nc) return;
+  double di = K.diag[i], rh0 = r[i] / di;
+  double d0 = rh0 * c.inv_theta;
+  double kd0 = di * d0 + sell_offdiag<OFF16>(K, i, R, [&](int j) { return r[j] / K.diag[j] * c.inv_theta; });
+  double rh1 = rh0 - kd0 / di;
+  xs[i] = d0 + (c.c_d * d0 + c.c_r * rh1);
+}
+
+// level 0, down, second pass: res = r - K xs
+template <bool OFF16>
+__global__ __launch_bounds__(BLOCK) void k_amg_cheb_pre2(SellView K, const double* __restrict__ r,
+                                                         const double* __restrict__ xs, double* __restrict__ res,
+                                                         StopFlags ctl) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  if (stopped(ctl) || i >= K.nc) return;
+  double kx = K.diag[i] * xs[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return xs[j]; });
+  res[i] = r[i] - kx;
+}
+
+// level 0, up, first pass (x = t): d0 = D^-1 (r - K t) / theta
+template <bool OFF16>
+__global__ __launch_bounds__(BLOCK) void k_amg_cheb_post1(SellView K, const double* __restrict__ r,
+                                                          const double* __restrict__ t, double* __restrict__ d0,
+                                                          Cheb c, StopFlags ctl) {
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  if (stopped(ctl) || i >= K.nc) return;
+  double di = K.diag[i];
+  double kt = di * t[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return t[j]; });
+  d0[i] = (r[i] - kt) / di * c.inv_theta;
+}
+
+// level 0, up, second pass: z = t + d0 + d1 with rh1 = theta d0 - D^-1 K d0, and per-tile partials
+// of r.z
+template <bool OFF16>
+__global__ __launch_bounds__(BLOCK) void k_amg_cheb_post2(SellView K, Tiles T, const double* __restrict__ r,
+                                                          const double* __restrict__ t, const double* __restrict__ d0,
+                                                          double* __restrict__ z, double* __restrict__ part, Cheb c,
+                                                          StopFlags ctl) {
+  TileIdx ti = tile_idx(T);
+  if (stopped(ctl)) return;
+  double v[1] = {0.0};
+  FOR_TILE_CELLS(i) {
+    SlotRange R = slots_of(K.slice_start, i);
+    double di = K.diag[i], d0i = d0[i];
+    double kd0 = di * d0i + sell_offdiag<OFF16>(K, i, R, [&](int j) { return d0[j]; });
+    double rh1 = c.theta * d0i - kd0 / di;
+    double zi = t[i] + d0i + (c.c_d * d0i + c.c_r * rh1);
+    z[i] = zi;
+    v[0] += r[i] * zi;
+  }
+  if (part) put_partial<1>(v, part, T.ntile, ti.t);
 }
 
 // SW lanes per row: partial sums of the row's entries, then a fixed xor-shuffle tree
@@ -135,113 +268,139 @@ __device__ __forceinline__ double lane_sum(double s) {
   return s;
 }
 
-// out = R x (rows of the coarser level)
+// Coarse levels smooth with the same degree-2 Chebyshev sweep as level 0 (interval [hi / 10, hi],
+// hi = 1.1 times the setup's power-iteration estimate of rho(D^-1 A)), two CSR passes per sweep.
+// Row bounds are loaded at a clamped index before the flag reads (no branch around the loads, so
+// both are in flight together); rows past the end get an empty range.
+#define DIFVM_AMG_ROW(ptr, n)                                  \
+  int g = blockIdx.x * BLOCK + threadIdx.x;                    \
+  int row = g / SW, lane = g % SW;                             \
+  int p0 = ptr[min(row, n - 1)], p1 = ptr[min(row, n - 1) + 1]; \
+  if (stopped(ctl)) return;                                    \
+  int lo = p0 + lane, hi = row < n ? p1 : 0
+
+// out = R x (rows of the coarser level); with diag, also outd = out / diag (what the coarser level's
+// pre-smoothing gathers)
 template <int SW>
 __global__ __launch_bounds__(BLOCK) void k_amg_restrict(int n, const int32_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                        const double* __restrict__ xin, double* __restrict__ out,
+                                                        const double* __restrict__ xin, const double* __restrict__ diag,
+                                                        double* __restrict__ out, double* __restrict__ outd,
                                                         StopFlags ctl) {
-  if (stopped(ctl)) return;
-  int g = blockIdx.x * BLOCK + threadIdx.x;
-  int row = g / SW, lane = g % SW;
-  double s = 0.0;
-  if (row < n)
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += SW) s += val[q] * xin[col[q]];
-  s = lane_sum<SW>(s);
-  if (row < n && lane == 0) out[row] = s;
-}
-
-// coarse level, down: res = b - A (w D^-1 b)
-template <int SW>
-__global__ __launch_bounds__(BLOCK) void k_amg_pre(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                                   const double* __restrict__ val, const double* __restrict__ diag,
-                                                   const double* __restrict__ b, double* __restrict__ res,
-                                                   StopFlags ctl) {
-  if (stopped(ctl)) return;
-  int g = blockIdx.x * BLOCK + threadIdx.x;
-  int row = g / SW, lane = g % SW;
-  double s = 0.0;
-  if (row < n)
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += SW) {
-      int j = col[q];
-      s += val[q] * (b[j] / diag[j]);
-    }
+  DIFVM_AMG_ROW(ptr, n);
+  double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return xin[j]; });
   s = lane_sum<SW>(s);
   if (row < n && lane == 0) {
-    double bi = b[row];
-    res[row] = bi - OMEGA * bi - OMEGA * s;
+    out[row] = s;
+    if (diag) outd[row] = s / diag[row];
   }
 }
 
-// coarse level, up: x = t + w D^-1 (b - A t)
+// coarse level, down, first pass (x = 0): xs = d0 + d1 with d0 = bd / theta (bd = D^-1 b)
 template <int SW>
-__global__ __launch_bounds__(BLOCK) void k_amg_post(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                                    const double* __restrict__ val, const double* __restrict__ diag,
-                                                    const double* __restrict__ b, const double* __restrict__ t,
-                                                    double* __restrict__ x, StopFlags ctl) {
-  if (stopped(ctl)) return;
-  int g = blockIdx.x * BLOCK + threadIdx.x;
-  int row = g / SW, lane = g % SW;
-  double s = 0.0;
-  if (row < n)
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += SW) s += val[q] * t[col[q]];
+__global__ __launch_bounds__(BLOCK) void k_amg_cpre1(int n, const int32_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                     const double* __restrict__ diag, const double* __restrict__ bd,
+                                                     double* __restrict__ xs, Cheb c, StopFlags ctl) {
+  DIFVM_AMG_ROW(ptr, n);
+  double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return bd[j]; });
   s = lane_sum<SW>(s);
   if (row < n && lane == 0) {
-    double d = diag[row], ti = t[row];
-    x[row] = ti + OMEGA * (b[row] - d * ti - s) / d;
+    double di = diag[row], rh0 = bd[row], d0 = rh0 * c.inv_theta;
+    double kd0 = di * d0 + s * c.inv_theta;
+    double rh1 = rh0 - kd0 / di;
+    xs[row] = d0 + (c.c_d * d0 + c.c_r * rh1);
   }
 }
 
-// up: t = w D^-1 b + P xc (one thread per row of the finer level)
+// coarse level, down, second pass: res = b - A xs
+template <int SW>
+__global__ __launch_bounds__(BLOCK) void k_amg_cpre2(int n, const int32_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                     const double* __restrict__ diag, const double* __restrict__ b,
+                                                     const double* __restrict__ xs, double* __restrict__ res,
+                                                     StopFlags ctl) {
+  DIFVM_AMG_ROW(ptr, n);
+  double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return xs[j]; });
+  s = lane_sum<SW>(s);
+  if (row < n && lane == 0) res[row] = b[row] - diag[row] * xs[row] - s;
+}
+
+// coarse level, up, first pass: t = xs + P xc and, since b - A t = res - (A P) xc,
+// d0 = D^-1 (res - (A P) xc) / theta; one pass over the pattern of A P
+template <int SW>
+__global__ __launch_bounds__(BLOCK) void k_amg_cup1(int n, const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const double* __restrict__ ap,
+                                                    const double* __restrict__ pv, const double* __restrict__ diag,
+                                                    const double* __restrict__ xs, const double* __restrict__ res,
+                                                    const double* __restrict__ xc, double* __restrict__ t,
+                                                    double* __restrict__ d0, Cheb c, StopFlags ctl) {
+  DIFVM_AMG_ROW(ptr, n);
+  double sp, sq;
+  csr_lane_dot2<SW>(lo, hi, col, pv, ap, [&](int j) { return xc[j]; }, sp, sq);
+  sp = lane_sum<SW>(sp);
+  sq = lane_sum<SW>(sq);
+  if (row < n && lane == 0) {
+    t[row] = xs[row] + sp;
+    d0[row] = (res[row] - sq) / diag[row] * c.inv_theta;
+  }
+}
+
+// coarse level, up, second pass: x = t + d0 + d1 with rh1 = theta d0 - D^-1 A d0
+template <int SW>
+__global__ __launch_bounds__(BLOCK) void k_amg_cup2(int n, const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                    const double* __restrict__ diag, const double* __restrict__ t,
+                                                    const double* __restrict__ d0, double* __restrict__ x, Cheb c,
+                                                    StopFlags ctl) {
+  DIFVM_AMG_ROW(ptr, n);
+  double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return d0[j]; });
+  s = lane_sum<SW>(s);
+  if (row < n && lane == 0) {
+    double di = diag[row], d0i = d0[row];
+    double rh1 = c.theta * d0i - (di * d0i + s) / di;
+    x[row] = t[row] + d0i + (c.c_d * d0i + c.c_r * rh1);
+  }
+}
+
+// level 0, up: t = xs + P xc (one thread per row)
 __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                       const double* __restrict__ diag, const double* __restrict__ b,
-                                                       const double* __restrict__ xc, double* __restrict__ t,
-                                                       StopFlags ctl) {
-  if (stopped(ctl)) return;
+                                                       const double* __restrict__ xs, const double* __restrict__ xc,
+                                                       double* __restrict__ t, StopFlags ctl) {
   int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int q = ptr[i]; q < ptr[i + 1]; ++q) s += val[q] * xc[col[q]];
-  t[i] = OMEGA * b[i] / diag[i] + s;
+  int lo = ptr[min(i, n - 1)], hi = ptr[min(i, n - 1) + 1];
+  if (stopped(ctl) || i >= n) return;
+  double s = csr_lane_dot<1>(lo, hi, col, val, [&](int j) { return xc[j]; });
+  t[i] = xs[i] + s;
 }
 
-// coarsest: x = A_L^-1 b (dense, one thread per row, one block)
+// coarsest: x = A_L^-1 b (dense, n <= 1024, one block of 16 waves): b staged in LDS, one wave per
+// row with the lanes over the columns and a fixed shuffle tree, four rows per wave in flight
 __global__ __launch_bounds__(1024) void k_amg_coarsest(int n, const double* __restrict__ inv,
                                                        const double* __restrict__ b, double* __restrict__ x,
                                                        StopFlags ctl) {
   if (stopped(ctl)) return;
-  int i = threadIdx.x;
-  if (i >= n) return;
-  const double* row = inv + (size_t)i * n;
-  double s = 0.0;
-  for (int j = 0; j < n; ++j) s += row[j] * b[j];
-  x[i] = s;
-}
-
-// level 0, up: z = t + w D^-1 (r - K t), with per-tile partials of r.z
-template <bool OFF16>
-__global__ __launch_bounds__(BLOCK) void k_amg_fine_post(SellView K, Tiles T, const double* __restrict__ r,
-                                                         const double* __restrict__ t, double* __restrict__ z,
-                                                         double* __restrict__ part, StopFlags ctl) {
-  TileIdx ti = tile_idx(T);
-  if (stopped(ctl)) return;
-  double v[1] = {0.0};
-  FOR_TILE_CELLS(i) {
-    SlotRange R = slots_of(K.slice_start, i);
-    double di = K.diag[i], ti = t[i];
-    double kt = di * ti;
-#pragma unroll 4
-    for (int k = 0; k < R.width; ++k) {
-      int at = R.base + k * SLICE;
-      kt += K.val[at] * t[slot_col_of<OFF16>(K, i, at)];
+  __shared__ double bl[1024];
+  for (int j = threadIdx.x; j < n; j += 1024) bl[j] = b[j];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r0 = wave; r0 < n; r0 += 64) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < n; j += 64) {
+      double bj = bl[j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int r = min(r0 + 16 * u, n - 1);  // rows past the end load row n-1 and are not stored
+        s[u] += inv[(size_t)r * n + j] * bj;
+      }
     }
-    double ri = r[i];
-    double zi = ti + OMEGA * (ri - kt) / di;
-    z[i] = zi;
-    v[0] += ri * zi;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double t = lane_sum<64>(s[u]);
+      if (lane == 0 && r0 + 16 * u < n) x[r0 + 16 * u] = t;
+    }
   }
-  if (part) put_partial<1>(v, part, T.ntile, ti.t);
 }
 
 #define DIFVM_AMG_LAUNCH(KERNEL, SW, N, S, ...)                                                           \
@@ -305,26 +464,46 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
     a->L = (int)H.levels.size();
     int L_ = a->L;
     a->A.resize(L_ + 1);
-    a->P.resize(L_);
     a->R.resize(L_);
+    a->AP.resize(L_);
     a->b.assign(L_ + 1, nullptr);
+    a->bd.assign(L_ + 1, nullptr);
     a->res.assign(L_ + 1, nullptr);
-    a->t.assign(L_ + 1, nullptr);
     a->x.assign(L_ + 1, nullptr);
     a->rows.push_back(d.nc);
+    a->P0 = upload_csr(a, H.levels[0].P, false, s);
     for (int l = 0; l < L_; ++l) {
-      a->P[l] = upload_csr(a, H.levels[l].P, false, s);
+      if (l > 0) {
+        a->AP[l] = upload_csr(a, H.levels[l].AP, false, s);
+        a->AP[l].val2 = up(a, H.levels[l].P_on_AP, s);
+      }
       a->R[l] = upload_csr(a, H.levels[l].R, false, s);
       a->A[l + 1] = upload_csr(a, H.coarse[l], true, s);
       a->rows.push_back(H.coarse[l].n);
     }
+    // Gershgorin: the eigenvalues of D^-1 K lie in the discs around 1 of radius sum_j |k_ij| / k_ii.
+    // At least 2, the bound of every weakly diagonally dominant K (the pressure operators), so that it
+    // holds for the later operators of the same kind the preconditioner is applied with.
+    double g = 2.0;
+    for (int i = 0; i < d.nc; ++i) {
+      double off = 0.0;
+      for (int q = A0.ptr[i]; q < A0.ptr[i + 1]; ++q) off += std::fabs(A0.val[q]);
+      g = std::max(g, 1.0 + off / diag[i]);
+    }
+    a->hi.push_back(g);
+    for (int l = 1; l < L_; ++l) a->hi.push_back(1.1 * H.levels[l].rho);
     for (int l = 0; l <= L_; ++l) {
       size_t n = a->rows[l];
       a->res[l] = work(a, n);
-      a->t[l] = work(a, n);
+      if (l < L_) {
+        a->xs.push_back(work(a, n));
+        a->t.push_back(work(a, n));
+        a->d0.push_back(work(a, n));
+      }
       if (l > 0) {
         a->b[l] = work(a, n);
         a->x[l] = work(a, n);
+        if (l < L_) a->bd[l] = work(a, n);
       }
     }
     DIFVM_CHECK(H.n_coarsest <= 1024, DIFVM_ERR_UNSUPPORTED, "coarsest AMG level too large");
@@ -357,34 +536,50 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
   difvm_mesh* m = a->mesh;
   SellView K = sview(m, Km);
   const int L = a->L, nc = m->d.nc;
+  std::vector<Cheb> c(L);
+  for (int l = 0; l < L; ++l) c[l] = cheb_coefficients(0.1 * a->hi[l], a->hi[l]);
   // down
-  if (K.off16) k_amg_fine_pre<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->res[0], ctl);
-  else k_amg_fine_pre<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->res[0], ctl);
-  {
-    const DevCsr& R = a->R[0];
-    DIFVM_AMG_DISPATCH(k_amg_restrict, R.sw, R.n, s, R.n, R.ptr, R.col, R.val, a->res[0], a->b[1], ctl);
+  if (K.off16) {
+    k_amg_cheb_pre1<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->xs[0], c[0], ctl);
+    k_amg_cheb_pre2<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->xs[0], a->res[0], ctl);
+  } else {
+    k_amg_cheb_pre1<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->xs[0], c[0], ctl);
+    k_amg_cheb_pre2<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->xs[0], a->res[0], ctl);
   }
-  for (int l = 1; l < L; ++l) {
-    const DevCsr& A = a->A[l];
-    DIFVM_AMG_DISPATCH(k_amg_pre, A.sw, A.n, s, A.n, A.ptr, A.col, A.val, A.diag, a->b[l], a->res[l], ctl);
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) {
+      const DevCsr& A = a->A[l];
+      DIFVM_AMG_DISPATCH(k_amg_cpre1, A.sw, A.n, s, A.n, A.ptr, A.col, A.val, A.diag, a->bd[l], a->xs[l], c[l], ctl);
+      DIFVM_AMG_DISPATCH(k_amg_cpre2, A.sw, A.n, s, A.n, A.ptr, A.col, A.val, A.diag, a->b[l], a->xs[l], a->res[l],
+                         ctl);
+    }
     const DevCsr& R = a->R[l];
-    DIFVM_AMG_DISPATCH(k_amg_restrict, R.sw, R.n, s, R.n, R.ptr, R.col, R.val, a->res[l], a->b[l + 1], ctl);
+    const double* dc = l + 1 < L ? a->A[l + 1].diag : nullptr;  // the coarsest level needs no D^-1 b
+    DIFVM_AMG_DISPATCH(k_amg_restrict, R.sw, R.n, s, R.n, R.ptr, R.col, R.val, a->res[l], dc, a->b[l + 1],
+                       a->bd[l + 1], ctl);
   }
   k_amg_coarsest<<<1, 1024, 0, s>>>(a->rows[L], a->cinv, a->b[L], a->x[L], ctl);
   // up
   for (int l = L - 1; l >= 1; --l) {
-    const DevCsr& P = a->P[l];
+    const DevCsr& Q = a->AP[l];
     const DevCsr& A = a->A[l];
-    k_amg_prolong<<<grid_for(P.n), BLOCK, 0, s>>>(P.n, P.ptr, P.col, P.val, A.diag, a->b[l], a->x[l + 1], a->t[l], ctl);
-    DIFVM_AMG_DISPATCH(k_amg_post, A.sw, A.n, s, A.n, A.ptr, A.col, A.val, A.diag, a->b[l], a->t[l], a->x[l], ctl);
+    DIFVM_AMG_DISPATCH(k_amg_cup1, Q.sw, Q.n, s, Q.n, Q.ptr, Q.col, Q.val, Q.val2, A.diag, a->xs[l], a->res[l],
+                       a->x[l + 1], a->t[l], a->d0[l], c[l], ctl);
+    DIFVM_AMG_DISPATCH(k_amg_cup2, A.sw, A.n, s, A.n, A.ptr, A.col, A.val, A.diag, a->t[l], a->d0[l], a->x[l], c[l],
+                       ctl);
   }
   {
-    const DevCsr& P = a->P[0];
-    k_amg_prolong<<<grid_for(P.n), BLOCK, 0, s>>>(P.n, P.ptr, P.col, P.val, Km.diag, r, a->x[1], a->t[0], ctl);
+    const DevCsr& P = a->P0;
+    k_amg_prolong<<<grid_for(P.n), BLOCK, 0, s>>>(P.n, P.ptr, P.col, P.val, a->xs[0], a->x[1], a->t[0], ctl);
   }
   Tiles T = tiles_of(m);
-  if (K.off16) k_amg_fine_post<true><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], z, part, ctl);
-  else k_amg_fine_post<false><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], z, part, ctl);
+  if (K.off16) {
+    k_amg_cheb_post1<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->t[0], a->d0[0], c[0], ctl);
+    k_amg_cheb_post2<true><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
+  } else {
+    k_amg_cheb_post1<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->t[0], a->d0[0], c[0], ctl);
+    k_amg_cheb_post2<false><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
+  }
   DIFVM_HIP(hipGetLastError());
 }
 

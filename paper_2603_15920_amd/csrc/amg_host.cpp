@@ -185,10 +185,10 @@ struct SparseAcc {
 }  // namespace
 
 // One coarsening step: aggregates, smoothed prolongator P (fine rows), restriction R = P^T (coarse
-// rows), Galerkin operator P^T A P (off-diagonals in CSR, diagonal apart, symmetrised exactly) and the
-// coarse near-null-space vector.
-static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta, int radius, AmgLevel& L, AmgCsr& Ac,
-                    std::vector<double>& Bc, std::vector<int32_t>& agg) {
+// rows), Galerkin operator P^T A P (off-diagonals in CSR, diagonal apart, symmetrised exactly), the
+// coarse near-null-space vector and, with_ap, A P with P's values on its pattern.
+static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta, int radius, bool with_ap,
+                    AmgLevel& L, AmgCsr& Ac, std::vector<double>& Bc, std::vector<int32_t>& agg) {
   const int n = A.n;
   int na = aggregate(A, theta, agg, radius);
   if (na >= n || na == 0) return false;
@@ -199,7 +199,8 @@ static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta,
   std::vector<double> tent(n);
   for (int i = 0; i < n; ++i) tent[i] = Bc[agg[i]] > 0.0 ? B[i] / Bc[agg[i]] : 0.0;
   // smoothed prolongator P = (I - w D^-1 A) P_tent, w = 4 / (3 rho(D^-1 A))
-  double w = 4.0 / (3.0 * spectral_radius_dinv_a(A, 20));
+  L.rho = spectral_radius_dinv_a(A, 20);
+  double w = 4.0 / (3.0 * L.rho);
   AmgCsr& P = L.P;
   P.n = n;
   P.ptr.assign(n + 1, 0);
@@ -234,6 +235,19 @@ static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta,
       ap_val.push_back(v);
     });
     ap_ptr[i + 1] = (int32_t)ap_col.size();
+  }
+  if (with_ap) {
+    L.AP.n = n;
+    L.AP.ptr = ap_ptr;
+    L.AP.col = ap_col;
+    L.AP.val = ap_val;
+    L.P_on_AP.assign(ap_val.size(), 0.0);
+    for (int i = 0; i < n; ++i) {
+      int q = P.ptr[i];
+      for (int k = ap_ptr[i]; k < ap_ptr[i + 1] && q < P.ptr[i + 1]; ++k)
+        if (P.col[q] == ap_col[k]) L.P_on_AP[k] = P.val[q++];
+      if (q != P.ptr[i + 1]) throw AmgError{"prolongator pattern not inside that of A P"};
+    }
   }
   // A_c = R (A P) by coarse rows
   Ac.n = na;
@@ -328,7 +342,8 @@ void amg_build(const AmgCsr& A0, const AmgOptions& opt, AmgHierarchy& H) {
     AmgCsr Ac;
     std::vector<double> Bc;
     std::vector<int32_t> agg;
-    if (!coarsen(A, B, l == 0 ? opt.theta_fine : opt.theta, l == 0 ? opt.radius_fine : opt.radius, L, Ac, Bc, agg))
+    if (!coarsen(A, B, l == 0 ? opt.theta_fine : opt.theta, l == 0 ? opt.radius_fine : opt.radius, l > 0, L, Ac, Bc,
+                 agg))
       break;
     if (l == 0) H.agg0 = agg;
     if (Ac.n > (int)(0.85 * A.n)) break;  // no real coarsening: stop here

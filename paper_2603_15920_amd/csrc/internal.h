@@ -50,6 +50,7 @@ struct Profiler {
   struct Rec {
     int id;
     hipEvent_t a, b;
+    long iter;  // CG iteration of the launch (-1: none)
   };
   std::vector<std::string> names;
   std::vector<Rec> pending;
@@ -66,8 +67,11 @@ struct Ctx {
 };
 
 // Brackets the next launch on `s` with events when profiling is on; returns a handle for prof_end.
-int prof_begin(Ctx& c, const char* name);
+int prof_begin(Ctx& c, const char* name, long iter = -1);
 void prof_end(Ctx& c, int handle);
+// Timed launches recorded since pending index `from` with an iteration past `last` (queued after the
+// CG stopped, they returned at once) are moved to "<name> (idle)".
+void prof_idle_after(Ctx& c, size_t from, long last);
 
 void* dmalloc(size_t bytes);
 void dfree(void* p);
@@ -145,7 +149,8 @@ inline Ctx& ctx_of(const difvm_mesh* m) { return m->ctx->c; }
 struct ProfScope {
   Ctx& c;
   int h;
-  ProfScope(const difvm_mesh* m, const char* name) : c(ctx_of(m)), h(prof_begin(ctx_of(m), name)) {}
+  ProfScope(const difvm_mesh* m, const char* name, long iter = -1)
+      : c(ctx_of(m)), h(prof_begin(ctx_of(m), name, iter)) {}
   ~ProfScope() { prof_end(c, h); }
 };
 inline int grid_for(int n, int per_block = BLOCK) { return (n + per_block - 1) / per_block; }

@@ -438,6 +438,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   SellView V = sview(m, A);
   Tiles T = tiles_of(m);
   int G = T.ntile, nseg = m->d.nseg;
+  const size_t prof_mark = ctx_of(m).prof.pending.size();  // timed launches of this solve start here
   k_pcg_ctl_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->pcg, nseg, tol, maxit);
   const int GS = pcg_spmv_grid(m);
   double* r = w->r;
@@ -451,30 +452,30 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   // the r.z partials)
   // (the V-cycle's kernels skip their work once every segment has stopped; while some segment runs
   // on they compute for all, which changes nothing a stopped segment reads)
-  auto precondition = [&]() {
+  auto precondition = [&](int kk) {
     if (!amg) return;
-    ProfScope ps(m, "pcg_amg_vcycle");
+    ProfScope ps(m, "pcg_amg_vcycle", kk);
     amg_vcycle(amg, A, r, z, partB + G, w->pcg);
   };
   k_pcg_init1<<<G, BLOCK, 0, s>>>(V, T, b, x, r, part0);
   if (amg) k_pcg_init2<false><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
   else k_pcg_init2<true><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[0], part0, partB, w->pcg);
   DIFVM_HIP(hipGetLastError());
-  precondition();
+  precondition(0);
   auto update = [&](int kk) {
     {
-      ProfScope ps(m, "pcg_update_dot");
+      ProfScope ps(m, "pcg_update_dot", kk);
       if (amg) k_pcg_update<false><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
       else k_pcg_update<true><<<G, BLOCK, 0, s>>>(V, T, x, r, z, Pk[kk & 1], q, partA, partB, kk, w->pcg);
     }
-    precondition();
+    precondition(kk);
   };
   if (qo) {
     // queue-only: iterations 1..K and the stopping test of iterate K, no read-back
     int K = std::min(qo->budget, maxit);
     for (int kk = 1; kk <= K + 1; ++kk) {
       {
-        ProfScope ps(m, "pcg_spmv_dot");
+        ProfScope ps(m, "pcg_spmv_dot", kk);
         launch_pcg_spmv(GS, s, V, T, kk, z, Pk[(kk - 1) & 1], Pk[kk & 1], q, partB, partA, w->pcg);
       }
       if (kk <= K) update(kk);
@@ -483,14 +484,16 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     copy_state(qo->state_out, w->pcg, pcg_state_bytes(m), s);
     return SolveResult{};
   }
-  // First block sized from the previous solve, then short blocks, each queued before the host waits
-  // for the state copied after the block before it; iteration k's stopping test runs at the start of
-  // iteration k+1, so the host queues up to iteration maxit+1.
+  // First block sized from the previous solve, then blocks of two iterations, each queued before the
+  // host waits for the state copied after the block before it (an iteration's GPU time covers the
+  // host's queueing of the next block); iterations queued past the stop are idle launches, about one
+  // block on average.  Iteration k's stopping test runs at the start of iteration k+1, so the host
+  // queues up to iteration maxit+1.
   int k = 1;  // next iteration to queue
   auto queue_block = [&](int nb) {
     for (int n = 0; n < nb && k <= maxit + 1; ++n, ++k) {
       {
-        ProfScope ps(m, "pcg_spmv_dot");
+        ProfScope ps(m, "pcg_spmv_dot", k);
         launch_pcg_spmv(GS, s, V, T, k, z, Pk[(k - 1) & 1], Pk[k & 1], q, partB, partA, w->pcg);
       }
       if (k <= maxit) update(k);
@@ -505,7 +508,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   while (true) {
     bool more = k <= maxit + 1;
     if (more) {
-      queue_block(4);
+      queue_block(2);
       post_poll(m, w, w->pcg, bytes, slot ^ 1);
     }
     hs = static_cast<const PcgCtl*>(wait_poll(w, slot));
@@ -515,6 +518,8 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     slot ^= 1;
   }
   SolveResult R = pcg_result(m, hs, nullptr);
+  // iteration k's kernels ran while some segment had not stopped, i.e. for k <= the largest count
+  prof_idle_after(ctx_of(m), prof_mark, R.iters[0]);  // iters[0]: the largest over the segments
   w->pcg_hint = R.iters[0];
   return R;
 }

@@ -71,16 +71,29 @@ __device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
 }
 
 // fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles) by a block of
-// NT threads; every thread ends with the totals
+// NT threads; every thread ends with the totals.  Each thread adds the partials q = tid, tid + NT,
+// ... in that order; the loads of four such steps (all NV arrays) are issued together, past the end
+// at the clamped index n - 1 and not added, so the chain is one load latency per 4 NT tiles.
 template <int NV, int NT = BLOCK>
 __device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
   __shared__ double lds[NV][NT / 64];
+  constexpr int UN = 4;
   int f = T.first[s], n = T.count[s];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < n; q += NT) acc += part[(size_t)k * T.ntile + f + q];
-    out[k] = acc;
+  for (int k = 0; k < NV; ++k) out[k] = 0.0;
+  for (int q = threadIdx.x; q < n; q += UN * NT) {
+    double v[UN][NV];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      int at = f + min(q + u * NT, n - 1);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = part[(size_t)k * T.ntile + at];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (q + u * NT < n)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] += v[u][k];
   }
   block_sum<NV, NT>(out, lds);
 }
