@@ -25,8 +25,8 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE medians in KiB, scaled by what the counters read for a 256 MiB device
 # copy), valid only for the kernel source they were taken with.
 PCG_SPMV_COUNTERS = {"source": "paper_2603_15920_amd/csrc/krylov.hip",
-                     "sha256": "13163a6c75ec44a96f2c8696e4b159de99a0d834b49116b904e8322c1bd127b0",
-                     "fetch_kib": 34185.75, "write_kib": 16472.65625, "fetch_scale": 1.99974, "write_scale": 1.0}
+                     "sha256": "2b6eeb1c3defaf2a30cc74d8698dc9af53b8b1c595cbfc61cdfbda42fecfe8e0",
+                     "fetch_kib": 34990.5, "write_kib": 16472.78125, "fetch_scale": 1.99974, "write_scale": 1.0}
 
 
 def counter_traffic(c):
@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--no-tube", action="store_true", help="skip the 2M-cell tube PISO run")
     ap.add_argument("--tube-steps", type=int, default=10)
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
+    ap.add_argument("--graph-extra", type=str, default="16",
+                    help="graph mode's iteration margin per solve; several, comma-separated, time one window each")
     ap.add_argument("--precond", choices=["jacobi", "amg"], default="amg",
                     help="pressure preconditioner of the timed PISO steps")
     ap.add_argument("--no-other", action="store_true", help="skip the run with the other pressure preconditioner")
@@ -617,8 +619,10 @@ def main():
     graph = None
     small = None
     if not args.no_graph:
-        graph = graph_rate(P, torch, args.steps, [wk])
-        log("graph mode", graph)
+        extras = [int(e) for e in args.graph_extra.split(",")]
+        for e in extras:
+            graph = graph_rate(P, torch, args.steps, [wk], extra=e)
+            log("graph mode", graph)
         small = small_case(B, mg, torch, ctx, precond=args.precond)
         log("small case", small)
 

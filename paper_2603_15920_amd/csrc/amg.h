@@ -22,13 +22,13 @@ struct AmgCsr {
 // Transfer between level l (fine) and l+1: P (rows of level l, columns of level l+1) and R = P^T.
 // For levels l >= 1 also A P (rows of level l) with P's values on its pattern (P_on_AP; the columns
 // of row i of A P include those of row i of P, A having a positive diagonal), so that one pass gives
-// both P x and A P x; and rho, the power-iteration estimate of rho(D^-1 A) of level l.  The finest
-// level smooths with the operator of the current solve, which may have changed since the setup, so it
-// keeps P alone.
+// both P x and A P x; and hi, the upper end of level l's Chebyshev smoothing interval (a bound on the
+// spectrum of D^-1 A).  The finest level smooths with the operator of the current solve, which may
+// have changed since the setup, so it keeps P alone and its bound is taken on the device side.
 struct AmgLevel {
   AmgCsr P, R, AP;
   std::vector<double> P_on_AP;
-  double rho = 0.0;
+  double hi = 0.0;
 };
 
 struct AmgOptions {

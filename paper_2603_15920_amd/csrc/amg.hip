@@ -11,11 +11,11 @@
 // so M^-1 is symmetric; it is positive definite while the spectrum of D^-1 A stays below
 // hi + lo = 1.1 hi, where the smoothing polynomial contracts.  hi_0 is a Gershgorin bound of D^-1 K
 // (at least 2, which bounds every weakly diagonally dominant K); hi_l = 1.1 times the setup's
-// power-iteration estimate of rho(D_l^-1 A_l) on the stored coarse operators.  A sweep takes two
-// passes over the level's operator: from zero, D^-1 b gives d0 without one; on the way up the first
-// pass uses b_l - A_l t_l = res_l - (A_l P_l) x_{l+1}, with A_l P_l stored, so prolongation and that
-// residual are one pass on levels l >= 1 (level 0 smooths with the operator of the current solve and
-// keeps the prolongation a pass of its own).  Degree-2 Chebyshev on every level takes about half the
+// power-iteration estimate of rho(D_l^-1 A_l) on the stored coarse operators, capped by their
+// Gershgorin bound.  A sweep takes two passes over the level's operator: from zero, D^-1 b gives d0
+// without one; on the way up the first pass uses b_l - A_l t_l = res_l - (A_l P_l) x_{l+1}, with
+// A_l P_l stored, so prolongation and that residual are one pass on levels l >= 1 (level 0 smooths
+// with the operator of the current solve and keeps the prolongation a pass of its own).  Degree-2 Chebyshev on every level takes about half the
 // CG iterations of one damped-Jacobi step per level, which more than pays for the extra passes.
 // Each stage is one kernel: row kernels on the cell-slot layout for level 0, CSR kernels with SW
 // lanes per row (rows summed by a fixed shuffle tree) elsewhere, so every result is deterministic.
@@ -74,10 +74,13 @@ double* work(AmgDev* a, size_t n) {
   return p;
 }
 
+// Lanes per CSR row: 4 to 8 entries per lane on average, so that a lane's loads (four in flight at
+// once) hide the gather latency without many short-lived waves; these kernels wait on memory
+// latency more than on bandwidth.
 int lanes_for(int n, size_t nnz) {
   double avg = n ? (double)nnz / n : 0.0;
   int sw = 1;
-  while (sw < 64 && sw * 2 <= avg) sw *= 2;
+  while (sw < 64 && sw * 8 <= avg) sw *= 2;
   return sw;
 }
 
@@ -269,11 +272,13 @@ __device__ __forceinline__ double lane_sum(double s) {
 }
 
 // Coarse levels smooth with the same degree-2 Chebyshev sweep as level 0 (interval [hi / 10, hi],
-// hi = 1.1 times the setup's power-iteration estimate of rho(D^-1 A)), two CSR passes per sweep.
+// hi from the setup), two CSR passes per sweep.
 // Row bounds are loaded at a clamped index before the flag reads (no branch around the loads, so
-// both are in flight together); rows past the end get an empty range.
+// both are in flight together); rows past the end get an empty range.  Blocks map to rows XCD by XCD
+// (each XCD a contiguous run of rows), so the finer-level entries that neighbouring rows gather meet
+// in one L2.
 #define DIFVM_AMG_ROW(ptr, n)                                  \
-  int g = blockIdx.x * BLOCK + threadIdx.x;                    \
+  int g = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x; \
   int row = g / SW, lane = g % SW;                             \
   int p0 = ptr[min(row, n - 1)], p1 = ptr[min(row, n - 1) + 1]; \
   if (stopped(ctl)) return;                                    \
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
                                                        const int32_t* __restrict__ col, const double* __restrict__ val,
                                                        const double* __restrict__ xs, const double* __restrict__ xc,
                                                        double* __restrict__ t, StopFlags ctl) {
-  int i = blockIdx.x * BLOCK + threadIdx.x;
+  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   int lo = ptr[min(i, n - 1)], hi = ptr[min(i, n - 1) + 1];
   if (stopped(ctl) || i >= n) return;
   double s = csr_lane_dot<1>(lo, hi, col, val, [&](int j) { return xc[j]; });
@@ -491,7 +496,7 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
       g = std::max(g, 1.0 + off / diag[i]);
     }
     a->hi.push_back(g);
-    for (int l = 1; l < L_; ++l) a->hi.push_back(1.1 * H.levels[l].rho);
+    for (int l = 1; l < L_; ++l) a->hi.push_back(H.levels[l].hi);
     for (int l = 0; l <= L_; ++l) {
       size_t n = a->rows[l];
       a->res[l] = work(a, n);
