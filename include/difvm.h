@@ -329,7 +329,7 @@ difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, in
  * neighbourhoods on the finest level and distance-1 below (strength threshold 0.08 on the finest,
  * 0 below), the constant vector as near-null space, prolongators smoothed by one damped-Jacobi step
  * with weight 4/(3 rho(D^-1 A)), Galerkin coarse operators, and the dense inverse of the coarsest level
- * (at most 96 rows if the matrix coarsens that far, 1024 at most).  The same smoothing sweep runs
+ * (coarsening stops at or below 2,048 rows; the inverse is taken on the device at setup).  The same smoothing sweep runs
  * before and after each coarse correction: on the finest level a degree-2 Chebyshev polynomial in
  * D^-1 A over [hi/10, hi], hi the largest of 2 and the Gershgorin bound of D^-1 A at setup (2 bounds
  * every weakly diagonally dominant matrix, such as the pressure operators); on coarser levels one
@@ -343,14 +343,16 @@ enum { DIFVM_PRECOND_JACOBI = 0, DIFVM_PRECOND_AMG = 1 };
 typedef struct difvm_amg difvm_amg;
 /* Builds the hierarchy of the symmetric F64 LDU matrix A (device arrays, lower ignored; synchronises).
  * The object holds a reference to the mesh and a copy of A for difvm_amg_apply.  Errors: INVALID_ARG
- * for a non-positive diagonal, UNSUPPORTED for a matrix that does not coarsen below 1,024 rows. */
+ * for a non-positive diagonal, UNSUPPORTED for a matrix that does not coarsen below 2,048 rows or whose
+ * coarsest operator is not positive definite. */
 difvm_status difvm_amg_create(const difvm_mesh* mesh, const difvm_ldu* A, difvm_amg** out);
 difvm_status difvm_amg_destroy(difvm_amg* amg); /* NULL is a no-op */
 /* Host-only setup of the same hierarchy (no device), for inspection: a symmetric matrix with n rows
  * given as CSR of its off-diagonal entries (ptr[n+1], col, val; host arrays) and its diagonal diag[n].
  * Outputs (host, may be NULL): agg[n], the finest level's aggregate of each row; rows[0..cap), the rows
  * of each level, finest first; *n_levels.  Errors: INVALID_ARG for a malformed matrix or a
- * non-positive diagonal, UNSUPPORTED when it does not coarsen below 1,024 rows. */
+ * non-positive diagonal, UNSUPPORTED when it does not coarsen below 2,048 rows (the coarsest operator's
+ * definiteness is checked by difvm_amg_create only). */
 difvm_status difvm_amg_setup_host(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, const double* diag,
                                   int32_t* agg, int32_t* rows, int32_t cap, int32_t* n_levels);
 /* rows of each level, finest first, into rows[0..cap) (host); *n_levels receives the level count */

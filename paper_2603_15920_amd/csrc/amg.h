@@ -37,18 +37,19 @@ struct AmgOptions {
   int radius_fine = 2;       // aggregation over distance-1 or distance-2 strong neighbourhoods
   int radius = 1;
   int max_levels = 12;
-  int coarsest = 96;         // stop coarsening at or below this many rows
-  int max_dense = 1024;      // largest coarsest level solved by its dense inverse
+  int coarsest = 2048;       // stop coarsening at or below this many rows (below the finest level)
+  int tiny = 96;             // the finest level is coarsened when it has more rows than this
+  int max_dense = 2048;      // largest coarsest level solved by its dense inverse
 };
 
-// levels[l] maps level l to l+1; coarse[l] is the operator of level l+1; the coarsest operator's dense
-// inverse (row-major, n_coarsest^2) closes the V-cycle.
+// levels[l] maps level l to l+1; coarse[l] is the operator of level l+1; the coarsest operator as a
+// dense row-major n_coarsest^2 matrix, whose inverse (taken on the device) closes the V-cycle.
 struct AmgHierarchy {
   std::vector<int32_t> agg0;  // aggregate of each finest-level row
   std::vector<AmgLevel> levels;
   std::vector<AmgCsr> coarse;
   int n_coarsest = 0;
-  std::vector<double> coarsest_inv;
+  std::vector<double> coarsest_dense;
 };
 
 // Builds the hierarchy of a symmetric positive definite matrix A0 (diagonal apart).  Throws AmgError.

@@ -380,32 +380,103 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
   t[i] = xs[i] + s;
 }
 
-// coarsest: x = A_L^-1 b (dense, n <= 1024, one block of 16 waves): b staged in LDS, one wave per
-// row with the lanes over the columns and a fixed shuffle tree, four rows per wave in flight
-__global__ __launch_bounds__(1024) void k_amg_coarsest(int n, const double* __restrict__ inv,
-                                                       const double* __restrict__ b, double* __restrict__ x,
-                                                       StopFlags ctl) {
+// coarsest: x = A_L^-1 b with the dense inverse (row-major, n <= 2048): one block per row, threads
+// over the columns (every load of a thread in flight at once: n / BLOCK <= 8), per-wave shuffle trees
+// and the four wave sums added in order; b is read through L2
+constexpr int MAX_DENSE = 2048;
+__global__ __launch_bounds__(BLOCK) void k_amg_coarsest(int n, const double* __restrict__ inv,
+                                                        const double* __restrict__ b, double* __restrict__ x,
+                                                        StopFlags ctl) {
   if (stopped(ctl)) return;
-  __shared__ double bl[1024];
-  for (int j = threadIdx.x; j < n; j += 1024) bl[j] = b[j];
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r0 = wave; r0 < n; r0 += 64) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = lane; j < n; j += 64) {
-      double bj = bl[j];
+  __shared__ double ws[BLOCK / 64];
+  const double* row = inv + (size_t)blockIdx.x * n;
+  constexpr int U = MAX_DENSE / BLOCK;
+  double v[U], w[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int r = min(r0 + 16 * u, n - 1);  // rows past the end load row n-1 and are not stored
-        s[u] += inv[(size_t)r * n + j] * bj;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double t = lane_sum<64>(s[u]);
-      if (lane == 0 && r0 + 16 * u < n) x[r0 + 16 * u] = t;
-    }
+  for (int u = 0; u < U; ++u) {  // columns past the end load column n-1 (no branch around a load)
+    int j = min((int)threadIdx.x + u * BLOCK, n - 1);
+    v[u] = row[j];
+    w[u] = b[j];
   }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if ((int)threadIdx.x + u * BLOCK < n) s += v[u] * w[u];
+  s = lane_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) t += ws[w];
+    x[blockIdx.x] = t;
+  }
+}
+
+// Setup: in-place Gauss-Jordan inversion of the dense SPD coarsest matrix M (row-major), one pivot k
+// per pair of launches.  Without pivoting: the pivots of an SPD matrix are Schur-complement diagonals,
+// all positive; a pivot that is not sets *bad.
+//   for i, j != k:  m_ij <- m_ij - m_ik m_kj / p;   m_kj <- m_kj / p;   m_ik <- -m_ik / p;   m_kk <- 1 / p
+// with p = m_kk; after the last pivot M holds M^-1.  Row and column k are copied first, so the update
+// reads no entry it writes.
+__global__ __launch_bounds__(BLOCK) void k_gj_save(int n, int k, const double* __restrict__ M, double* __restrict__ rowk,
+                                                   double* __restrict__ colk, int* __restrict__ bad) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  rowk[i] = M[(size_t)k * n + i];
+  colk[i] = M[(size_t)i * n + k];
+  if (i == k && !(M[(size_t)k * n + k] > 0.0)) *bad = 1;
+}
+__global__ __launch_bounds__(BLOCK) void k_gj_step(int n, int k, double* __restrict__ M, const double* __restrict__ rowk,
+                                                   const double* __restrict__ colk) {
+  size_t e = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  int i = (int)(e / n), j = (int)(e % n);
+  double p = rowk[k];
+  double v;
+  if (i == k) v = j == k ? 1.0 / p : rowk[j] / p;
+  else if (j == k) v = -colk[i] / p;
+  else v = M[e] - colk[i] * rowk[j] / p;
+  M[e] = v;
+}
+// exact symmetry: m_ij and m_ji replaced by their mean
+__global__ __launch_bounds__(BLOCK) void k_symmetrise(int n, double* __restrict__ M) {
+  size_t e = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  int i = (int)(e / n), j = (int)(e % n);
+  if (j <= i) return;
+  double m = 0.5 * (M[e] + M[(size_t)j * n + i]);
+  M[e] = m;
+  M[(size_t)j * n + i] = m;
+}
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+// M <- M^-1 for the dense SPD coarsest matrix (device, n x n); throws when a pivot is not positive
+void dense_inverse_spd(int n, double* M, hipStream_t s) {
+  double* rc = dalloc<double>(2 * (size_t)n);
+  int* bad = dalloc<int>(1);
+  int hbad = 0;
+  try {
+    k_zero_int<<<1, 64, 0, s>>>(bad);
+    const int ge = (int)(((size_t)n * n + BLOCK - 1) / BLOCK);
+    for (int k = 0; k < n; ++k) {
+      k_gj_save<<<grid_for(n), BLOCK, 0, s>>>(n, k, M, rc, rc + n, bad);
+      k_gj_step<<<ge, BLOCK, 0, s>>>(n, k, M, rc, rc + n);
+    }
+    k_symmetrise<<<ge, BLOCK, 0, s>>>(n, M);
+    DIFVM_HIP(hipGetLastError());
+    DIFVM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    dfree(rc);
+    dfree(bad);
+    throw;
+  }
+  dfree(rc);
+  dfree(bad);
+  DIFVM_CHECK(!hbad, DIFVM_ERR_UNSUPPORTED, "AMG setup: coarsest matrix is not positive definite");
 }
 
 #define DIFVM_AMG_LAUNCH(KERNEL, SW, N, S, ...)                                                           \
@@ -511,8 +582,9 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
         if (l < L_) a->bd[l] = work(a, n);
       }
     }
-    DIFVM_CHECK(H.n_coarsest <= 1024, DIFVM_ERR_UNSUPPORTED, "coarsest AMG level too large");
-    a->cinv = up(a, H.coarsest_inv, s);
+    DIFVM_CHECK(H.n_coarsest <= MAX_DENSE, DIFVM_ERR_UNSUPPORTED, "coarsest AMG level too large");
+    a->cinv = up(a, H.coarsest_dense, s);
+    dense_inverse_spd(H.n_coarsest, a->cinv, s);
     DIFVM_HIP(hipStreamSynchronize(s));
   } catch (...) {
     amg_free(a);
@@ -563,7 +635,7 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
     DIFVM_AMG_DISPATCH(k_amg_restrict, R.sw, R.n, s, R.n, R.ptr, R.col, R.val, a->res[l], dc, a->b[l + 1],
                        a->bd[l + 1], ctl);
   }
-  k_amg_coarsest<<<1, 1024, 0, s>>>(a->rows[L], a->cinv, a->b[L], a->x[L], ctl);
+  k_amg_coarsest<<<a->rows[L], BLOCK, 0, s>>>(a->rows[L], a->cinv, a->b[L], a->x[L], ctl);
   // up
   for (int l = L - 1; l >= 1; --l) {
     const DevCsr& Q = a->AP[l];

@@ -299,56 +299,14 @@ static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta,
   return true;
 }
 
-static void dense_inverse_spd(int n, const AmgCsr& A, std::vector<double>& inv) {
-  // Cholesky of the dense coarsest matrix, then the inverse column by column
-  std::vector<double> M((size_t)n * n, 0.0), Lc((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    M[(size_t)i * n + i] = A.diag[i];
-    for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) M[(size_t)i * n + A.col[q]] = A.val[q];
-  }
-  for (int j = 0; j < n; ++j) {
-    double s = M[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= Lc[(size_t)j * n + k] * Lc[(size_t)j * n + k];
-    if (!(s > 0.0)) throw AmgError{"coarsest AMG matrix is not positive definite"};
-    double d = std::sqrt(s);
-    Lc[(size_t)j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double t = M[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= Lc[(size_t)i * n + k] * Lc[(size_t)j * n + k];
-      Lc[(size_t)i * n + j] = t / d;
-    }
-  }
-  inv.assign((size_t)n * n, 0.0);
-  std::vector<double> y(n), x(n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double t = i == c ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) t -= Lc[(size_t)i * n + k] * y[k];
-      y[i] = t / Lc[(size_t)i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int k = i + 1; k < n; ++k) t -= Lc[(size_t)k * n + i] * x[k];
-      x[i] = t / Lc[(size_t)i * n + i];
-    }
-    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
-  }
-  // symmetrise
-  for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) {
-      double m = 0.5 * (inv[(size_t)i * n + j] + inv[(size_t)j * n + i]);
-      inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = m;
-    }
-}
-
 void amg_build(const AmgCsr& A0, const AmgOptions& opt, AmgHierarchy& H) {
   H.levels.clear();
   H.coarse.clear();
-  H.coarsest_inv.clear();
+  H.coarsest_dense.clear();
   std::vector<double> B(A0.n, 1.0);
   AmgCsr A = A0;
   for (int l = 0; l < opt.max_levels; ++l) {
-    if (A.n <= opt.coarsest) break;
+    if (A.n <= (l == 0 ? opt.tiny : opt.coarsest)) break;
     AmgLevel L;
     AmgCsr Ac;
     std::vector<double> Bc;
@@ -366,7 +324,12 @@ void amg_build(const AmgCsr& A0, const AmgOptions& opt, AmgHierarchy& H) {
   if (H.levels.empty()) throw AmgError{"the matrix does not coarsen"};
   if (A.n > opt.max_dense) throw AmgError{"coarsest AMG level too large for the dense solve"};
   H.n_coarsest = A.n;
-  dense_inverse_spd(A.n, A, H.coarsest_inv);
+  const size_t n = A.n;
+  H.coarsest_dense.assign(n * n, 0.0);
+  for (size_t i = 0; i < n; ++i) {
+    H.coarsest_dense[i * n + i] = A.diag[i];
+    for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) H.coarsest_dense[i * n + A.col[q]] = A.val[q];
+  }
 }
 
 }  // namespace difvm

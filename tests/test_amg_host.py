@@ -117,7 +117,7 @@ def test_kuhn_hierarchy_structure():
     n = len(diag)
     assert rows[0] == n and all(rows[i + 1] < rows[i] for i in range(len(rows) - 1))
     assert rows[1] * 8 <= n            # distance-2 aggregates of tets: more than 8 rows each on average
-    assert rows[-1] <= 96
+    assert rows[-1] <= 2048
     assert agg.min() == 0 and len(np.unique(agg)) == agg.max() + 1 == rows[1]   # a partition, no gaps
     # every aggregate is connected through links of at most two matrix-graph edges (phase 1 takes a
     # root's distance-2 neighbourhood; a phase-2 row joins an aggregate within distance 2 of it)
