@@ -27,8 +27,8 @@ struct BiState {
 
 struct KrylovWork {
   int nc = 0, ntile = 0;
-  double *r = nullptr, *p = nullptr, *q = nullptr, *rh = nullptr, *v = nullptr, *y = nullptr, *s = nullptr,
-         *z = nullptr, *t = nullptr;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *rh = nullptr, *v = nullptr, *s = nullptr, *z = nullptr,
+         *t = nullptr;
   double* partials = nullptr;
   struct PcgCtl* pcg = nullptr;  // [nseg]
   BiState* bi = nullptr;         // [nseg]
@@ -48,9 +48,9 @@ static KrylovWork* make_work(difvm_mesh* m) {
   w->ntile = m->d.ntile;  // reduction tiles over all segments (at least ceil(nc / 1024))
   size_t n3 = (size_t)nc * 3;
   w->r = dalloc<double>(n3); w->p = dalloc<double>(n3); w->q = dalloc<double>(n3); w->rh = dalloc<double>(n3);
-  w->v = dalloc<double>(n3); w->y = dalloc<double>(n3); w->s = dalloc<double>(n3); w->z = dalloc<double>(n3);
+  w->v = dalloc<double>(n3); w->s = dalloc<double>(n3); w->z = dalloc<double>(n3);
   w->t = dalloc<double>(n3);
-  w->partials = dalloc<double>((size_t)8 * w->ntile);  // up to 8 values per tile (PCG uses 6, BiCGStab 6)
+  w->partials = dalloc<double>((size_t)9 * w->ntile);  // up to 9 values per tile (PCG uses 6, BiCGStab 9)
   int nseg = m->d.nseg;
   w->pcg = static_cast<PcgCtl*>(dmalloc(sizeof(BiState) * nseg));  // PcgCtl is smaller (asserted below)
   w->bi = dalloc<BiState>(nseg);
@@ -63,7 +63,7 @@ static KrylovWork* make_work(difvm_mesh* m) {
 
 void krylov_work_free(KrylovWork* w) {
   if (!w) return;
-  for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->y, w->s, w->z, w->t, w->partials}) dfree(a);
+  for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->s, w->z, w->t, w->partials}) dfree(a);
   dfree(w->pcg);
   dfree(w->bi);
   for (int q = 0; q < 2; ++q) {
@@ -529,13 +529,13 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
 // kernel writes per-tile partials; a finalize kernel (one block per segment) sums them in a fixed
 // order and advances the segment's scalar recurrences in device memory.
 // ---------------------------------------------------------------------------------------------
-enum BiStage { BI_INIT = 0, BI_ALPHA = 1, BI_S = 2, BI_OMEGA = 3, BI_X = 4 };
+enum BiStage { BI_INIT = 0, BI_ALPHA = 1, BI_SO = 2, BI_X = 3 };
 
-template <int NC>
+// NV partial arrays: NC for BI_ALPHA, 3 NC for BI_SO (t.s, t.t, s.s), 2 NC otherwise
+template <int NC, int NV>
 __global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __restrict__ part, Tiles T, BiState* sts) {
   BiState* st = sts + blockIdx.x;
   if (stage != BI_INIT && !st->any) return;
-  constexpr int NV = 2 * NC;
   double tot[NV];
   sum_seg<NV>(part, T, blockIdx.x, tot);
   if (threadIdx.x != 0) return;
@@ -564,20 +564,17 @@ __global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __res
       continue;
     } else if (stage == BI_ALPHA) {
       st->alpha[c] = st->rho1[c] / tot[c];
-    } else if (stage == BI_S) {
-      double sn = sqrt(tot[c]);
+    } else if (stage == BI_SO) {
+      // the test on |s| first (the iteration ends with x += alpha y if it passes), then omega
+      double sn = sqrt(tot[(2 * NC + c) % NV]);  // NV = 3 NC in this stage
       if (sn <= st->tol * st->bn[c]) {
         st->phase[c] = 1;
         st->res[c] = sn / st->bn[c];
-      }
-    } else if (stage == BI_OMEGA) {
-      if (!st->phase[c]) {
-        if (tot[NC + c] == 0.0) {
-          st->active[c] = 0;
-          st->status[c] = DIFVM_WARN_BREAKDOWN;
-        } else {
-          st->omega[c] = tot[c] / tot[NC + c];
-        }
+      } else if (tot[NC + c] == 0.0) {
+        st->active[c] = 0;
+        st->status[c] = DIFVM_WARN_BREAKDOWN;
+      } else {
+        st->omega[c] = tot[c] / tot[NC + c];
       }
     } else {  // BI_X
       int it = st->iters[c] + 1;
@@ -647,29 +644,45 @@ __global__ __launch_bounds__(BLOCK) void k_bi_zero(Tiles T, double* __restrict__
   }
 }
 
-// p = r + beta (p - omega v); y = p / d
+// (A f)_i for NC interleaved components, f(j, c) giving the operand of cell j; padding and boundary
+// slots carry val = 0 and col = i
+template <int NC, class F>
+__device__ __forceinline__ void sell_row_f(const SellView& A, int i, F&& f, double (&acc)[NC]) {
+  SlotRange R = slots_of(A.slice_start, i);
+  double di = A.diag[i];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = di * f(i, c);
+#pragma unroll 4
+  for (int k = 0; k < R.width; ++k) {
+    int at = R.base + k * SLICE;
+    double a = A.val[at];
+    int j = A.col[at];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += a * f(j, c);
+  }
+}
+
+// The right-preconditioned vectors y = p / d and z = s / d are formed where they are used, not stored.
+// p = r + beta (p - omega v)
 template <int NC>
 __global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, Tiles T, const double* __restrict__ r, double* __restrict__ p,
-                                                  const double* __restrict__ v, double* __restrict__ y, const BiState* sts) {
+                                                  const double* __restrict__ v, const BiState* sts) {
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
   if (!st->any) return;
   FOR_TILE_CELLS(i) {
-    double di = A.diag[i];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
       size_t at = (size_t)i * NC + c;
-      double pi = r[at] + st->beta[c] * (p[at] - st->omega[c] * v[at]);
-      p[at] = pi;
-      y[at] = pi / di;
+      p[at] = r[at] + st->beta[c] * (p[at] - st->omega[c] * v[at]);
     }
   }
 }
 
-// v = A y; partial rhat . v
+// v = A y, y = p / d; partial rhat . v
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const double* __restrict__ y, double* __restrict__ v,
+__global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const double* __restrict__ p, double* __restrict__ v,
                                                 const double* __restrict__ rh, double* __restrict__ part, const BiState* sts) {
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
@@ -679,7 +692,7 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   FOR_TILE_CELLS(i) {
     double ay[NC];
-    sell_row<NC>(A, i, y, ay);
+    sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
@@ -691,79 +704,65 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   put_partial<NC>(acc, part, T.ntile, ti.t);
 }
 
-// s = r - alpha v; z = s / d; partial s.s
+// s = r - alpha v (stored for k_bi_x), t = A z with z = s / d (the neighbours' s formed from r and v);
+// partials t.s, t.t, s.s
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_s(SellView A, Tiles T, const double* __restrict__ r, const double* __restrict__ v,
-                                                double* __restrict__ s, double* __restrict__ z, double* __restrict__ part,
-                                                const BiState* sts) {
+__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const double* __restrict__ r,
+                                                const double* __restrict__ v, double* __restrict__ s,
+                                                double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
   if (!st->any) return;
-  double acc[NC];
+  double acc[3 * NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int k = 0; k < 3 * NC; ++k) acc[k] = 0.0;
+  FOR_TILE_CELLS(i) {
+    auto s_of = [&](int j, int c) {
+      size_t at = (size_t)j * NC + c;
+      return r[at] - st->alpha[c] * v[at];
+    };
+    double az[NC];
+    sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (!st->active[c]) continue;
+      size_t at = (size_t)i * NC + c;
+      double si = s_of(i, c);
+      s[at] = si;
+      t[at] = az[c];
+      acc[c] += az[c] * si;
+      acc[NC + c] += az[c] * az[c];
+      acc[2 * NC + c] += si * si;
+    }
+  }
+  put_partial<3 * NC>(acc, part, T.ntile, ti.t);
+}
+
+// x += alpha y (+ omega z); r = s - omega t; partials r.r, rhat.r
+template <int NC>
+__global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ rh, const double* __restrict__ p,
+                                                const double* __restrict__ s, const double* __restrict__ t,
+                                                double* __restrict__ part, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
+  if (!st->any) return;
+  double acc[2 * NC];
+#pragma unroll
+  for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
   FOR_TILE_CELLS(i) {
     double di = A.diag[i];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
       size_t at = (size_t)i * NC + c;
-      double si = r[at] - st->alpha[c] * v[at];
-      s[at] = si;
-      z[at] = si / di;
-      acc[c] += si * si;
-    }
-  }
-  put_partial<NC>(acc, part, T.ntile, ti.t);
-}
-
-// t = A z; partials t.s, t.t
-template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const double* __restrict__ z, const double* __restrict__ s,
-                                                double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
-  TileIdx ti = tile_idx(T);
-  const BiState* st = sts + ti.s;
-  if (!st->any) return;
-  double acc[2 * NC];
-#pragma unroll
-  for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  FOR_TILE_CELLS(i) {
-    double az[NC];
-    sell_row<NC>(A, i, z, az);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c] || st->phase[c]) continue;
-      size_t at = (size_t)i * NC + c;
-      t[at] = az[c];
-      acc[c] += az[c] * s[at];
-      acc[NC + c] += az[c] * az[c];
-    }
-  }
-  put_partial<2 * NC>(acc, part, T.ntile, ti.t);
-}
-
-// x += alpha y (+ omega z); r = s - omega t; partials r.r, rhat.r
-template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, Tiles T, double* __restrict__ x, double* __restrict__ r,
-                                                const double* __restrict__ rh, const double* __restrict__ y,
-                                                const double* __restrict__ z, const double* __restrict__ s,
-                                                const double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
-  TileIdx ti = tile_idx(T);
-  const BiState* st = sts + ti.s;
-  if (!st->any) return;
-  double acc[2 * NC];
-#pragma unroll
-  for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  FOR_TILE_CELLS(i) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c]) continue;
-      size_t at = (size_t)i * NC + c;
+      double yi = p[at] / di;
       if (st->phase[c]) {
-        x[at] += st->alpha[c] * y[at];
+        x[at] += st->alpha[c] * yi;
       } else {
-        x[at] += st->alpha[c] * y[at] + st->omega[c] * z[at];
-        double ri = s[at] - st->omega[c] * t[at];
+        double si = s[at];
+        x[at] += st->alpha[c] * yi + st->omega[c] * (si / di);
+        double ri = si - st->omega[c] * t[at];
         r[at] = ri;
         acc[c] += ri * ri;
         acc[NC + c] += rh[at] * ri;
@@ -819,21 +818,19 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
   k_bi_state_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->bi, nseg, tol, maxit);
   double* part = w->partials;
   k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, T, b, x, w->r, w->rh, w->p, w->v, part);
-  k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
+  k_bi_fin<NC, 2 * NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
   k_bi_zero<NC><<<G, BLOCK, 0, s>>>(T, x, w->bi);
   DIFVM_HIP(hipGetLastError());
   int done = 0;  // iterations queued
   auto queue_iters = [&](int nb) {
     for (int it = 0; it < nb; ++it) {
-      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->y, w->bi);
-      k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->y, w->v, w->rh, part, w->bi);
-      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
-      k_bi_s<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->v, w->s, w->z, part, w->bi);
-      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_S, part, T, w->bi);
-      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, T, w->z, w->s, w->t, part, w->bi);
-      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_OMEGA, part, T, w->bi);
-      k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, T, x, w->r, w->rh, w->y, w->z, w->s, w->t, part, w->bi);
-      k_bi_fin<NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
+      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->bi);
+      k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->p, w->v, w->rh, part, w->bi);
+      k_bi_fin<NC, NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
+      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->v, w->s, w->t, part, w->bi);
+      k_bi_fin<NC, 3 * NC><<<nseg, BLOCK, 0, s>>>(BI_SO, part, T, w->bi);
+      k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, T, x, w->r, w->rh, w->p, w->s, w->t, part, w->bi);
+      k_bi_fin<NC, 2 * NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
     }
     done += nb;
     DIFVM_HIP(hipGetLastError());
