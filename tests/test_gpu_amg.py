@@ -92,6 +92,29 @@ def test_vcycle_is_symmetric_positive_definite():
     B.difvm_amg_destroy(amg)
 
 
+def test_profile_separates_idle_launches():
+    """the benchmark's kernel events with every launch timed: the PCG kernels of iterations 1..k and the
+    V-cycles after iterations 0..k count as active, launches queued after the stop as idle"""
+    m = MESHES["kuhn12"]()
+    cx = ctx()
+    M = B.Mesh(cx, m)
+    d, u, b = laplace_system(m, 9)
+    A = device_ldu(M, m, d, u)
+    amg = B.difvm_amg_create(M.h, A)
+    x = dev(np.zeros(m.n_cells))
+    B.difvm_ctx_profile(cx.h, 1)
+    B.difvm_ctx_profile_read(cx.h)
+    st, it, res = B.difvm_solve_pcg_amg(amg, A, to_int(M, b, B.KIND_CELL), x, 1e-10, 500)
+    prof = B.difvm_ctx_profile_read(cx.h)
+    B.difvm_ctx_profile(cx.h, 0)
+    note("profile", it, prof)
+    assert st == 0
+    assert prof["pcg_spmv_dot"][0] == it and prof["pcg_update_dot"][0] == it
+    assert prof["pcg_amg_vcycle"][0] == it + 1
+    assert prof["pcg_spmv_dot (idle)"][0] >= 1   # at least the launch that finds the stop
+    B.difvm_amg_destroy(amg)
+
+
 def test_poisson_mms_with_amg():
     """the paper's Poisson case at 34,992 cells: the AMG-preconditioned solve reaches the same discrete
     solution (and so the same error against the manufactured solution) as Jacobi"""
