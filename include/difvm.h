@@ -329,13 +329,14 @@ difvm_status difvm_solve_bicgstab(const difvm_mesh* mesh, const difvm_ldu* A, in
  * neighbourhoods on the finest level and distance-1 below (strength threshold 0.08 on the finest,
  * 0 below), the constant vector as near-null space, prolongators smoothed by one damped-Jacobi step
  * with weight 4/(3 rho(D^-1 A)), Galerkin coarse operators, and the dense inverse of the coarsest level
- * (coarsening stops at or below 2,048 rows; the inverse is taken on the device at setup).  The same smoothing sweep runs
- * before and after each coarse correction: on the finest level a degree-2 Chebyshev polynomial in
- * D^-1 A over [hi/10, hi], hi the largest of 2 and the Gershgorin bound of D^-1 A at setup (2 bounds
- * every weakly diagonally dominant matrix, such as the pressure operators); on coarser levels one
- * damped-Jacobi sweep (2/3).  The hierarchy is built on the host from one matrix and kept; the
- * finest level of each V-cycle uses the matrix being solved, so M^-1 stays symmetric positive
- * definite while the matrix drifts within that spectral bound.  On a batched mesh no aggregate crosses a segment, so
+ * (coarsening stops at or below 2,048 rows; the inverse is taken on the device at setup).  Every
+ * level smooths with one degree-2 Chebyshev sweep in D^-1 A over [hi/10, hi], the same before and
+ * after each coarse correction: on the finest level hi is the largest of 2 and the Gershgorin bound
+ * of D^-1 A at setup (2 bounds every weakly diagonally dominant matrix, such as the pressure
+ * operators); on coarser levels 1.1 times a power-iteration estimate of rho(D^-1 A), capped by the
+ * Gershgorin bound.  The hierarchy is built on the host from one matrix and kept; the finest level
+ * of each V-cycle uses the matrix being solved, so M^-1 stays symmetric positive definite while the
+ * matrix drifts within that spectral bound.  On a batched mesh no aggregate crosses a segment, so
  * the V-cycle is block-diagonal and each segment's CG still stops on its own test.  CG with it
  * converges to the same solution as with Jacobi (the preconditioner changes
  * the iterates, not the stopping rule). */

@@ -15,10 +15,9 @@ struct AmgDev;
 // block-diagonal over the segments.  Throws Error.
 AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt);
 void amg_free(AmgDev* a);
-// z = M^-1 r, one symmetric V-cycle (degree-2 Chebyshev smoothing on the finest level, one
-// damped-Jacobi sweep on the coarser ones, before and after each coarse correction; the finest level
-// uses K, the coarser ones the stored Galerkin operators), queued on
-// the mesh's stream.  part != nullptr: the last kernel stores per-tile partials of r.z at part[t].
+// z = M^-1 r, one symmetric V-cycle (one degree-2 Chebyshev sweep on every level before and after
+// each coarse correction, a dense solve on the coarsest; the finest level uses K, the coarser ones
+// the stored Galerkin operators), queued on the mesh's stream.  part != nullptr: the last kernel stores per-tile partials of r.z at part[t].
 // ctl != nullptr (the per-segment CG states): every kernel returns at once when all segments have
 // stopped (iterations queued after the stop).
 void amg_vcycle(const AmgDev* a, SellMatrix K, const double* r, double* z, double* part, const PcgCtl* ctl);
