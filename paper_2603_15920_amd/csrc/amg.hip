@@ -74,21 +74,21 @@ double* work(AmgDev* a, size_t n) {
   return p;
 }
 
-// Lanes per CSR row: 4 to 8 entries per lane on average, so that a lane's loads (four in flight at
-// once) hide the gather latency without many short-lived waves; these kernels wait on memory
-// latency more than on bandwidth.
-int lanes_for(int n, size_t nnz) {
+// Lanes per CSR row: per_lane to 2 per_lane entries per lane on average.  The single-product kernels
+// take 4 to 8 (their eight loads in flight hide the gather latency without many short-lived waves;
+// they wait on memory latency more than on bandwidth); the two-product pass over A P takes 2 to 4.
+int lanes_for(int n, size_t nnz, int per_lane) {
   double avg = n ? (double)nnz / n : 0.0;
   int sw = 1;
-  while (sw < 64 && sw * 8 <= avg) sw *= 2;
+  while (sw < 64 && sw * 2 * per_lane <= avg) sw *= 2;
   return sw;
 }
 
-DevCsr upload_csr(AmgDev* a, const AmgCsr& M, bool with_diag, hipStream_t s) {
+DevCsr upload_csr(AmgDev* a, const AmgCsr& M, bool with_diag, hipStream_t s, int per_lane = 4) {
   DevCsr d;
   d.n = M.n;
   d.nnz = (int)M.col.size();
-  d.sw = lanes_for(M.n, M.col.size());
+  d.sw = lanes_for(M.n, M.col.size(), per_lane);
   d.ptr = up(a, M.ptr, s);
   d.col = up(a, M.col, s);
   d.val = up(a, M.val, s);
@@ -114,9 +114,9 @@ __device__ __forceinline__ bool stopped(const StopFlags& st) {
 
 // Sum of val[q] x(col[q]) over q = lo, lo + SW, lo + 2 SW, ... < hi (one lane's share of a CSR row),
 // in that order, with the loads of UN entries in flight together (rows of a few entries per lane
-// would otherwise wait on one load chain per entry).  Entries past the row's end load its last entry
+// would otherwise wait on one load chain per entry; with 4 to 8 entries per lane, one round).  Entries past the row's end load its last entry
 // (no branch around a load, which would make each one wait) and are not added.
-template <int SW, int UN = 4, class X>
+template <int SW, int UN = 8, class X>
 __device__ __forceinline__ double csr_lane_dot(int lo, int hi, const int32_t* __restrict__ col,
                                                const double* __restrict__ val, X&& x) {
   double s = 0.0;
@@ -368,7 +368,8 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cup2(int n, const int32_t* __rest
   }
 }
 
-// level 0, up: t = xs + P xc (one thread per row)
+// level 0, up: t = xs + P xc (one thread per row; almost every row of the finest prolongator has at
+// most four entries, so four in flight)
 __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col, const double* __restrict__ val,
                                                        const double* __restrict__ xs, const double* __restrict__ xc,
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   int lo = ptr[min(i, n - 1)], hi = ptr[min(i, n - 1) + 1];
   if (stopped(ctl) || i >= n) return;
-  double s = csr_lane_dot<1>(lo, hi, col, val, [&](int j) { return xc[j]; });
+  double s = csr_lane_dot<1, 4>(lo, hi, col, val, [&](int j) { return xc[j]; });
   t[i] = xs[i] + s;
 }
 
@@ -550,7 +551,7 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
     a->P0 = upload_csr(a, H.levels[0].P, false, s);
     for (int l = 0; l < L_; ++l) {
       if (l > 0) {
-        a->AP[l] = upload_csr(a, H.levels[l].AP, false, s);
+        a->AP[l] = upload_csr(a, H.levels[l].AP, false, s, 1);
         a->AP[l].val2 = up(a, H.levels[l].P_on_AP, s);
       }
       a->R[l] = upload_csr(a, H.levels[l].R, false, s);
