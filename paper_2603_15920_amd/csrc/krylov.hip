@@ -484,10 +484,10 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     copy_state(qo->state_out, w->pcg, pcg_state_bytes(m), s);
     return SolveResult{};
   }
-  // First block sized from the previous solve, then blocks of two iterations, each queued before the
+  // First block sized from the previous solve, then blocks of one iteration, each queued before the
   // host waits for the state copied after the block before it (an iteration's GPU time covers the
-  // host's queueing of the next block); iterations queued past the stop are idle launches, about one
-  // block on average.  Iteration k's stopping test runs at the start of iteration k+1, so the host
+  // host's queueing of the next block); iterations queued past the stop are idle launches, one or two
+  // per solve.  Iteration k's stopping test runs at the start of iteration k+1, so the host
   // queues up to iteration maxit+1.
   int k = 1;  // next iteration to queue
   auto queue_block = [&](int nb) {
@@ -508,7 +508,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   while (true) {
     bool more = k <= maxit + 1;
     if (more) {
-      queue_block(2);
+      queue_block(1);
       post_poll(m, w, w->pcg, bytes, slot ^ 1);
     }
     hs = static_cast<const PcgCtl*>(wait_poll(w, slot));
