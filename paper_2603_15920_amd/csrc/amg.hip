@@ -51,12 +51,6 @@ struct AmgDev {
   double* cinv = nullptr;        // dense inverse of A_L, row-major
   std::vector<int> rows;
   std::vector<void*> allocs;
-  // Eager solves replay the V-cycle as one captured graph (one host submission instead of one per
-  // kernel; the cycle is launch-bound below the finest levels).  It is captured on a private stream
-  // for one set of arguments and recaptured when they change.
-  mutable hipStream_t cap = nullptr;
-  mutable hipGraphExec_t vexec = nullptr;
-  mutable const void* vkey[6] = {};
 };
 
 namespace {
@@ -597,8 +591,6 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
 void amg_free(AmgDev* a) {
   if (!a) return;
   if (a->mesh) (void)hipStreamSynchronize(stream_of(a->mesh));
-  if (a->vexec) (void)hipGraphExecDestroy(a->vexec);
-  if (a->cap) (void)hipStreamDestroy(a->cap);
   for (void* p : a->allocs) dfree(p);
   delete a;
 }
@@ -663,36 +655,10 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
 
 void amg_vcycle(const AmgDev* a, SellMatrix Km, const double* r, double* z, double* part, const PcgCtl* ctls) {
   difvm_mesh* m = a->mesh;
-  Ctx& c = ctx_of(m);
-  StopFlags ctl{ctls, m->d.nseg};
-  if (c.capturing) {  // inside a captured step: the kernels join that graph
-    launch_vcycle(a, c.stream, Km, r, z, part, ctl);
-    return;
-  }
-  const void* key[6] = {Km.diag, Km.val, r, z, part, ctls};
-  if (!a->vexec || !std::equal(key, key + 6, a->vkey)) {
-    if (a->vexec) {
-      DIFVM_HIP(hipStreamSynchronize(c.stream));  // a replay of the old graph may still be queued
-      DIFVM_HIP(hipGraphExecDestroy(a->vexec));
-      a->vexec = nullptr;
-    }
-    if (!a->cap) DIFVM_HIP(hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking));
-    DIFVM_HIP(hipStreamBeginCapture(a->cap, hipStreamCaptureModeThreadLocal));
-    hipGraph_t g = nullptr;
-    try {
-      launch_vcycle(a, a->cap, Km, r, z, part, ctl);
-    } catch (...) {
-      (void)hipStreamEndCapture(a->cap, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    DIFVM_HIP(hipStreamEndCapture(a->cap, &g));
-    hipError_t e = hipGraphInstantiate(&a->vexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    DIFVM_HIP(e);
-    std::copy(key, key + 6, a->vkey);
-  }
-  DIFVM_HIP(hipGraphLaunch(a->vexec, c.stream));
+  // queued kernel by kernel on the solve's stream (inside a captured step they join that graph): the
+  // host queues a cycle in well under one iteration's GPU time, and a replayed graph of the cycle
+  // cost about 9 us of idle GPU between its end and the next kernel on the stream
+  launch_vcycle(a, ctx_of(m).stream, Km, r, z, part, StopFlags{ctls, m->d.nseg});
 }
 
 }  // namespace difvm
