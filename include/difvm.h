@@ -344,8 +344,8 @@ enum { DIFVM_PRECOND_JACOBI = 0, DIFVM_PRECOND_AMG = 1 };
 typedef struct difvm_amg difvm_amg;
 /* Builds the hierarchy of the symmetric F64 LDU matrix A (device arrays, lower ignored; synchronises).
  * The object holds a reference to the mesh and a copy of A for difvm_amg_apply.  Errors: INVALID_ARG
- * for a non-positive diagonal, UNSUPPORTED for a matrix that does not coarsen below 2,048 rows or whose
- * coarsest operator is not positive definite. */
+ * for a non-positive diagonal, UNSUPPORTED for a matrix of at most 96 rows, one that does not coarsen
+ * below 2,048 rows, or one whose coarsest operator is not positive definite. */
 difvm_status difvm_amg_create(const difvm_mesh* mesh, const difvm_ldu* A, difvm_amg** out);
 difvm_status difvm_amg_destroy(difvm_amg* amg); /* NULL is a no-op */
 /* Host-only setup of the same hierarchy (no device), for inspection: a symmetric matrix with n rows

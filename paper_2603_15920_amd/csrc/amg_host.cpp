@@ -202,15 +202,15 @@ static bool coarsen(const AmgCsr& A, const std::vector<double>& B, double theta,
   double w = 4.0 / (3.0 * spectral_radius_dinv_a(A, 20));
   if (with_ap) {
     // upper end of the level's Chebyshev smoothing interval: 1.1 times a longer power iteration's
-    // estimate of rho(D^-1 A), capped by the Gershgorin bound (discs around 1 of radius
-    // sum_j |a_ij| / a_ii), which always holds
+    // estimate of rho(D^-1 A), at least 1.1 (the eigenvalues of D^-1 A average 1, so rho >= 1), capped
+    // by the Gershgorin bound (discs around 1 of radius sum_j |a_ij| / a_ii), which always holds
     double g = 0.0;
     for (int i = 0; i < n; ++i) {
       double off = 0.0;
       for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) off += std::fabs(A.val[q]);
       g = std::max(g, 1.0 + off / A.diag[i]);
     }
-    L.hi = std::min(g, 1.1 * spectral_radius_dinv_a(A, 50));
+    L.hi = std::min(g, 1.1 * std::max(1.0, spectral_radius_dinv_a(A, 50)));
   }
   AmgCsr& P = L.P;
   P.n = n;

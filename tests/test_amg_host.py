@@ -148,6 +148,12 @@ def test_setup_errors():
     with pytest.raises(B.DifvmError) as e:
         B.difvm_amg_setup_host(ptr, col2, val, diag)
     assert e.value.status == B.ERR_INVALID_ARG
+    # at most 96 rows: too small to coarsen
+    with pytest.raises(B.DifvmError) as e:
+        B.difvm_amg_setup_host(*chain_csr(96))
+    assert e.value.status == B.ERR_UNSUPPORTED
+    agg, rows = B.difvm_amg_setup_host(*chain_csr(97))
+    assert rows[0] == 97 and len(rows) == 2 and rows[1] < 97
     # no off-diagonal coupling at all: nothing to aggregate beyond singletons
     with pytest.raises(B.DifvmError) as e:
         B.difvm_amg_setup_host(np.zeros(301, np.int32), np.zeros(0, np.int32), np.zeros(0), np.ones(300))
