@@ -218,6 +218,33 @@ def test_amg_errors():
         B.Piso(M, prm)
 
 
+def test_vcycle_is_block_diagonal_on_a_packed_mesh():
+    """no aggregate crosses a member, the coarsest dense inverse keeps the blocks' exact zeros: a residual
+    on one member of a packed mesh leaves the V-cycle's output exactly zero on the other"""
+    a = mg.kuhn_cube(10, jitter=0.15, patches="walls", seed=61)
+    b = mg.kuhn_cube(8, jitter=0.15, patches="walls", seed=62)
+    packed, starts = mg.pack([a, b])
+    M = B.Mesh(ctx(), packed, seg_cell_start=starts)
+    d, u, _ = laplace_system(packed, 3)
+    A = device_ldu(M, packed, d, u)
+    amg = B.difvm_amg_create(M.h, A)
+    note("packed levels", B.difvm_amg_levels(amg))
+    rng = np.random.default_rng(11)
+    for k in range(2):
+        mb = packed.meta["members"][k]
+        cs = slice(mb["cell_start"], mb["cell_start"] + mb["n_cells"])
+        r = np.zeros(packed.n_cells)
+        r[cs] = rng.standard_normal(mb["n_cells"])
+        z = empty(packed.n_cells)
+        B.difvm_amg_apply(amg, to_int(M, r, B.KIND_CELL), z)
+        zu = to_user(M, z, B.KIND_CELL)
+        other = np.ones(packed.n_cells, bool)
+        other[cs] = False
+        assert np.all(zu[other] == 0.0), k
+        assert (zu[cs] * r[cs]).sum() > 0
+    B.difvm_amg_destroy(amg)
+
+
 def test_packed_members_with_amg():
     """a batch of three uneven members under one AMG hierarchy: each member's state after 4 steps equals
     the oracle's run of that member alone within 1e-9 (tolerances 1e-12), every member converging"""
