@@ -20,6 +20,9 @@ pytestmark = pytest.mark.gpu
 
 MESHES = {
     "kuhn12": lambda: mg.kuhn_cube(12, jitter=0.15, patches="walls", seed=2603007),   # 10368 cells
+    # 82,944 cells: three levels, so the coarse Chebyshev passes, the A P pass and the restriction that
+    # also writes D^-1 b run (two-level hierarchies use none of them)
+    "kuhn24": lambda: mg.kuhn_cube(24, jitter=0.15, patches="walls", seed=2603008),
     "tube": lambda: mg.tube(n=8, m=4, layers=12, L=3.0),
     "hex": lambda: mg.hex_box(13, 11, 7, A=np.array([[1, 0.3, 0.1], [0, 1, 0.2], [0, 0, 1.0]]), patches="walls"),
     "cavity": lambda: mg.cavity(32),
@@ -51,6 +54,8 @@ def test_pcg_amg_matches_oracle_solution(name):
     levels = B.difvm_amg_levels(amg)
     note("amg", name, m.n_cells, levels)
     assert levels[0] == m.n_cells and all(levels[i + 1] < levels[i] for i in range(len(levels) - 1))
+    if name == "kuhn24":
+        assert len(levels) >= 3, levels
     x = dev(np.zeros(m.n_cells))
     st, it, res = B.difvm_solve_pcg_amg(amg, A, to_int(M, b, B.KIND_CELL), x, 1e-12, 500)
     assert st == 0 and res <= 1e-12
@@ -64,8 +69,9 @@ def test_pcg_amg_matches_oracle_solution(name):
     B.difvm_amg_destroy(amg)
 
 
-def test_vcycle_is_symmetric_positive_definite():
-    m = MESHES["kuhn12"]()
+@pytest.mark.parametrize("name", ["kuhn12", "kuhn24"])
+def test_vcycle_is_symmetric_positive_definite(name):
+    m = MESHES[name]()
     M = B.Mesh(ctx(), m)
     d, u, _ = laplace_system(m, 6)
     A = device_ldu(M, m, d, u)
