@@ -71,10 +71,13 @@ double* work(AmgDev* a, size_t n) {
 // Lanes per CSR row: per_lane to 2 per_lane entries per lane on average.  The single-product kernels
 // take 4 to 8 (their eight loads in flight hide the gather latency without many short-lived waves;
 // they wait on memory latency more than on bandwidth); the two-product pass over A P takes 2 to 4.
+// A matrix of few rows gets more lanes (down to 2 entries each) until the launch has 64k threads:
+// there the chip is far from full and each lane's chain of loads is the whole kernel's time.
 int lanes_for(int n, size_t nnz, int per_lane) {
   double avg = n ? (double)nnz / n : 0.0;
   int sw = 1;
   while (sw < 64 && sw * 2 * per_lane <= avg) sw *= 2;
+  while (sw < 64 && (size_t)n * sw < 65536 && sw * 4 <= avg) sw *= 2;
   return sw;
 }
 

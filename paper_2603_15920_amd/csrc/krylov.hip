@@ -848,7 +848,7 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
   while (true) {
     bool more = done < maxit;
     if (more) {
-      queue_iters(std::min(2, maxit - done));
+      queue_iters(std::min(1, maxit - done));
       post_poll(m, w, w->bi, bytes, slot ^ 1);
     }
     hs = static_cast<const BiState*>(wait_poll(w, slot));
