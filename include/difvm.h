@@ -118,6 +118,25 @@ difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out);
 difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream);
 difvm_status difvm_ctx_destroy(difvm_ctx* ctx); /* NULL is a no-op */
 
+/* Device-memory allocator of the context.  The paper keeps the whole simulation on the device and
+ * leaves memory to its framework (Sec. "Computational Efficiency": the run's GPU footprint); here the
+ * caller supplies it, so that under Python every block the library holds is memory of torch's
+ * caching allocator.  Every device allocation the library makes for objects of this context (mesh
+ * arrays, solver workspaces and scratch, PISO state, AMG hierarchies, tapes, autotuner scratch)
+ * calls alloc(bytes, stream, user), with stream the context's hipStream_t, and returns the block
+ * with free(ptr, stream, user); alloc returns NULL on failure (the call that needed the memory then
+ * fails with DIFVM_ERR_OOM).  Blocks must be device memory of the context's device, aligned to at
+ * least 256 bytes; the library frees a block only after the work that used it has finished on the
+ * context's stream (or that stream has been synchronised).  Both NULL restores the default
+ * (hipMalloc / hipFree).  Pinned host mirrors of solver flags are not device memory and are not
+ * routed here.  Allocations happen when objects are created and at the first use of a workspace
+ * (first solve on a mesh, first AMG solve of a PISO object, first step with a tape or in graph mode);
+ * repeated solves, steps and operator calls allocate nothing.  Errors: DIFVM_ERR_INVALID_ARG when
+ * exactly one of alloc and free is NULL, or when an object (mesh, PISO, ...) still holds the
+ * context, since every block must be returned to the allocator that made it. */
+difvm_status difvm_ctx_set_allocator(difvm_ctx* ctx, void* (*alloc)(size_t bytes, void* stream, void* user),
+                                     void (*free)(void* ptr, void* stream, void* user), void* user);
+
 /* Kernel timing for benchmarks.  difvm_ctx_profile(ctx, n) with n >= 1 enables it: every n-th launch
  * of each of the library's PCG kernels inside difvm_solve_pcg and difvm_piso_step (counted per
  * kernel name from the call that enabled it) is bracketed by a pair of HIP events on the context's
@@ -462,9 +481,28 @@ difvm_status difvm_piso_graph_info(const difvm_piso* piso, int64_t* replays, int
  * DIFVM_ERR_INVALID_ARG when the PISO object uses Jacobi. */
 difvm_status difvm_piso_rebuild_preconditioner(difvm_piso* piso);
 
+/* The pressure preconditioner's hierarchy (AMG only; DIFVM_ERR_INVALID_ARG for Jacobi): *n_levels
+ * (0 before the first pressure solve built it), the rows of each level, finest first, into
+ * rows[0..cap) (host), and *vcycle_bytes (may be NULL) the algorithmic bytes of one V-cycle: every
+ * kernel's distinct inputs read once and outputs written once, the finest matrix counted in its LDU
+ * form (diagonal; owner, neighbour and coefficient per internal face), coarse matrices in CSR (row
+ * pointers, 4-byte columns, 8-byte values, diagonal) and the coarsest level's dense inverse.  For
+ * rooflines of the preconditioner phase. */
+difvm_status difvm_piso_precond_info(const difvm_piso* piso, int32_t* n_levels, int32_t* rows, int32_t cap,
+                                     double* vcycle_bytes);
+
 /* Advances nsteps time steps.  stats_host[nsteps] (may be NULL) receives solver iterations and
  * residuals per step.  Synchronises.  Returns the worst solver status over the steps. */
 difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats* stats_host);
+
+/* One step as difvm_piso_step(piso, 1, stats_host) (run eagerly, also in graph mode) that also writes
+ * the solution of each linear system of the step, in USER order, to device arrays: U_star[Nc*3], the
+ * momentum predictor's solution (eq. momentum_predictor, before the correctors), and p_corr[n_corr*Nc],
+ * the pressure solved by each corrector in turn (eq. pressure_poisson).  With the state before the
+ * step, these let a caller assemble every system of the step independently and check each solution's
+ * true residual against the solver tolerance.  The first call allocates the internal-order copies
+ * (kept by the PISO object).  Synchronises; returns the step's worst solver status. */
+difvm_status difvm_piso_step_trace(difvm_piso* piso, void* U_star, void* p_corr, difvm_step_stats* stats_host);
 
 /* ---- differentiation (paper Sec. "End-to-End Automatic Differentiation") -------------------
  * Reverse mode through an N-step window of the PISO: a discrete adjoint of every step (transposed

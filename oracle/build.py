@@ -1,5 +1,7 @@
 """Compile oracle.cpp into liboracle.so next to this file (plain g++, strict IEEE: no fast-math and no
-FMA contraction, so every operation rounds as written)."""
+FMA contraction, so every operation rounds as written), and the same source with OpenMP into
+liboracle_omp.so (the all-threads timing variant of the Krylov kernels; the parity tests use the
+serial library)."""
 import os
 import subprocess
 import sys
@@ -7,16 +9,24 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.cpp")
 OUT = os.path.join(HERE, "liboracle.so")
+OUT_OMP = os.path.join(HERE, "liboracle_omp.so")
+FLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra",
+         "-Wno-unused-parameter", "-Wno-unknown-pragmas"]
 
 
 def build(verbose=False):
-    cmd = ["g++", "-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", SRC, "-o", OUT + ".tmp"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
+    for out, extra in ((OUT, []), (OUT_OMP, ["-fopenmp"])):
+        cmd = ["g++", *FLAGS, *extra, SRC, "-o", out + ".tmp"]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return OUT
+
+
+def compiler_version():
+    r = subprocess.run(["g++", "--version"], capture_output=True, text=True)
+    return r.stdout.splitlines()[0] if r.returncode == 0 and r.stdout else "g++"
 
 
 if __name__ == "__main__":

@@ -15,6 +15,14 @@
 // nonortho_flux); delta_f follows the chosen correction scheme (over-relaxed by default, see
 // face_split), delta_b likewise with d_b and k_b = 0.  Empty faces are skipped everywhere.
 //
+// Timing variant: built with -fopenmp (liboracle_omp.so) the double-precision LDU product, dot
+// products and vector updates of the Krylov solvers, where a PISO step spends its time, run on all
+// host threads: faces are split into one contiguous range per thread, each thread sums its faces
+// into its own accumulator (covering the cells its range touches), and the accumulators are added
+// in thread order; dot products add per-thread partial sums in thread order.  Results are
+// deterministic for a given thread count and differ from the serial build only by rounding order.
+// The parity tests use the serial build (liboracle.so).
+//
 // Parity pins live in tests/test_oracle_*.py.  Readings of points the paper leaves open are listed in
 // the repository's design notes; the ones used here are restated at each function.
 #include <algorithm>
@@ -23,6 +31,9 @@
 #include <cstring>
 #include <deque>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -354,19 +365,80 @@ void spmv(const om_mesh& m, int ncomp, bool transpose, const T* diag, const T* u
 // solvers": CG for the symmetric pressure system, BiCGStab for momentum; Jacobi preconditioning).
 // ------------------------------------------------------------------------------------------------
 double dotv(const double* a, const double* b, int n) {
+#ifdef _OPENMP
+  std::vector<double> part(omp_get_max_threads(), 0.0);
+#pragma omp parallel
+  {
+    int t = omp_get_thread_num(), T = omp_get_num_threads();
+    int lo = (int)((long long)n * t / T), hi = (int)((long long)n * (t + 1) / T);
+    double s = 0.0;
+    for (int i = lo; i < hi; ++i) s += a[i] * b[i];
+    part[t] = s;
+  }
+  double s = 0.0;
+  for (double v : part) s += v;
+  return s;
+#else
   double s = 0.0;
   for (int i = 0; i < n; ++i) s += a[i] * b[i];
   return s;
+#endif
 }
 
+#ifdef _OPENMP
+// all-threads LDU product of the timing variant (see the file header), one component
+void spmv_threads(const om_mesh& m, const double* diag, const double* u, const double* l, const double* x, double* y) {
+  int T = omp_get_max_threads();
+  std::vector<std::vector<double>> acc(T);
+  std::vector<int> lo(T, 0), hi(T, -1);
+#pragma omp parallel num_threads(T)
+  {
+    int t = omp_get_thread_num();
+    int f0 = (int)((long long)m.nfi * t / T), f1 = (int)((long long)m.nfi * (t + 1) / T);
+    int a = m.nc, b = -1;
+    for (int f = f0; f < f1; ++f) {
+      a = std::min(a, std::min(m.owner[f], m.nbr[f]));
+      b = std::max(b, std::max(m.owner[f], m.nbr[f]));
+    }
+    lo[t] = a;
+    hi[t] = b;
+    std::vector<double>& c = acc[t];
+    c.assign(b >= a ? b - a + 1 : 0, 0.0);
+    for (int f = f0; f < f1; ++f) {
+      int O = m.owner[f], N = m.nbr[f];
+      c[O - a] += u[f] * x[N];
+      c[N - a] += l[f] * x[O];
+    }
+#pragma omp barrier
+#pragma omp for schedule(static)
+    for (int i = 0; i < m.nc; ++i) {
+      double v = diag[i] * x[i];
+      for (int q = 0; q < T; ++q)
+        if (i >= lo[q] && i <= hi[q]) v += acc[q][i - lo[q]];
+      y[i] = v;
+    }
+  }
+}
+#endif
+
 struct SolveInfo { int iters; double res; int status; };  // status 0 ok, 1 not converged, 2 breakdown
+
+// y = A x for one component (all threads in the timing variant)
+void ldu_apply(const om_mesh& m, const double* d, const double* u, const double* l, const double* x, double* y) {
+#ifdef _OPENMP
+  spmv_threads(m, d, u, l, x, y);
+#else
+  spmv<double>(m, 1, false, d, u, l, x, y);
+#endif
+}
 
 // Jacobi-preconditioned CG for a symmetric LDU matrix (upper == lower).
 SolveInfo pcg(const om_mesh& m, const double* diag, const double* upper, const double* b, double* x, double tol,
               int maxit) {
   int n = m.nc;
   std::vector<double> r(n), z(n), p(n), q(n);
-  spmv<double>(m, 1, false, diag, upper, upper, x, q.data());
+  ldu_apply(m, diag, upper, upper, x, q.data());
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
   double bn = std::sqrt(dotv(b, b, n));
   SolveInfo info{0, 0.0, 0};
@@ -374,20 +446,24 @@ SolveInfo pcg(const om_mesh& m, const double* diag, const double* upper, const d
   double rn = std::sqrt(dotv(r.data(), r.data(), n));
   info.res = rn / bn;
   if (rn <= tol * bn) return info;
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) { z[i] = r[i] / diag[i]; p[i] = z[i]; }
   double rho = dotv(r.data(), z.data(), n);
   while (true) {
     if (info.iters >= maxit) { info.status = 1; return info; }
-    spmv<double>(m, 1, false, diag, upper, upper, p.data(), q.data());
+    ldu_apply(m, diag, upper, upper, p.data(), q.data());
     double alpha = rho / dotv(p.data(), q.data(), n);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
     info.iters++;
     rn = std::sqrt(dotv(r.data(), r.data(), n));
     info.res = rn / bn;
     if (rn <= tol * bn) return info;
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
     double rho1 = dotv(r.data(), z.data(), n);
     double beta = rho1 / rho;
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     rho = rho1;
   }
@@ -398,7 +474,8 @@ SolveInfo bicgstab(const om_mesh& m, const double* diag, const double* upper, co
                    double* x, double tol, int maxit) {
   int n = m.nc;
   std::vector<double> r(n), rh(n), p(n, 0.0), v(n, 0.0), y(n), s(n), z(n), t(n);
-  spmv<double>(m, 1, false, diag, upper, lower, x, t.data());
+  ldu_apply(m, diag, upper, lower, x, t.data());
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) { r[i] = b[i] - t[i]; rh[i] = r[i]; }
   double bn = std::sqrt(dotv(b, b, n));
   SolveInfo info{0, 0.0, 0};
@@ -412,22 +489,27 @@ SolveInfo bicgstab(const om_mesh& m, const double* diag, const double* upper, co
     double rho1 = dotv(rh.data(), r.data(), n);
     if (rho1 == 0.0) { info.status = 2; return info; }
     double beta = (rho1 / rho) * (alpha / omega);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) { p[i] = r[i] + beta * (p[i] - omega * v[i]); y[i] = p[i] / diag[i]; }
-    spmv<double>(m, 1, false, diag, upper, lower, y.data(), v.data());
+    ldu_apply(m, diag, upper, lower, y.data(), v.data());
     alpha = rho1 / dotv(rh.data(), v.data(), n);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
     double sn = std::sqrt(dotv(s.data(), s.data(), n));
     if (sn <= tol * bn) {
+      #pragma omp parallel for schedule(static)
       for (int i = 0; i < n; ++i) x[i] += alpha * y[i];
       info.iters++;
       info.res = sn / bn;
       return info;
     }
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) z[i] = s[i] / diag[i];
-    spmv<double>(m, 1, false, diag, upper, lower, z.data(), t.data());
+    ldu_apply(m, diag, upper, lower, z.data(), t.data());
     double tt = dotv(t.data(), t.data(), n);
     if (tt == 0.0) { info.status = 2; return info; }
     omega = dotv(t.data(), s.data(), n) / tt;
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) { x[i] += alpha * y[i] + omega * z[i]; r[i] = s[i] - omega * t[i]; }
     rho = rho1;
     info.iters++;
@@ -492,6 +574,26 @@ SolveInfo solve_nonsym(const om_mesh& m, const Dual* d, const Dual* u, const Dua
   return solve_dual<false>(m, d, u, l, b, x, tol, maxit, tol_tan);
 }
 
+// Verification of a solution computed elsewhere: x is taken as given (no solve) and the true relative
+// residual ||b - A x||_2 / ||b||_2 of the system is returned (0 when b = 0), with A x the plain LDU
+// product above.  The stopping rule of both Krylov solvers bounds this quantity by tol, up to the
+// rounding by which a recursively updated residual drifts from the true one.
+double true_residual(const om_mesh& m, const double* d, const double* u, const double* l, const double* b,
+                     const double* x) {
+  std::vector<double> ax(m.nc);
+  spmv<double>(m, 1, false, d, u, l, x, ax.data());
+  double rr = 0.0, bb = 0.0;
+  for (int i = 0; i < m.nc; ++i) {
+    double r = b[i] - ax[i];
+    rr += r * r;
+    bb += b[i] * b[i];
+  }
+  return bb == 0.0 ? 0.0 : std::sqrt(rr) / std::sqrt(bb);
+}
+double true_residual(const om_mesh&, const Dual*, const Dual*, const Dual*, const Dual*, const Dual*) {
+  return -1.0;  // verification runs on plain doubles only
+}
+
 // ------------------------------------------------------------------------------------------------
 // PISO (paper Sec. "PISO as divergence-free constrained message passing", eqs. momentum_predictor,
 // Ap_H, pressure_poisson, velocity_correction; Windkessel eqs. windkessel_Q, windkessel_discrete).
@@ -519,6 +621,16 @@ struct Piso {
   std::vector<int> wk_of_face;           // per boundary face: Windkessel id or -1
   int nwk = 0;
   bool has_fixed_p = false;
+  // Verification mode (plain doubles): the solutions of the step's linear systems are supplied by
+  // the caller instead of solved here, the predictor's U*[nc*3] and the pressure after each corrector
+  // [n_corr*nc]; the true relative residual of each system is recorded.  Every other operation of
+  // the step is unchanged, so the step's outputs are those implied by the supplied solutions.
+  const double* given_U = nullptr;
+  const double* given_p = nullptr;
+  double given_res_u[3] = {0, 0, 0}, given_res_p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // when set, the values of those solutions are copied out (same layouts) after every solve
+  double* trace_U = nullptr;
+  double* trace_p = nullptr;
   Piso(const om_mesh& mesh, const om_piso_params& p) : m(mesh), prm(p) {
     codeU = bc_codes(m, TABLE_U);
     codeP = bc_codes(m, TABLE_P);
@@ -610,8 +722,15 @@ struct Piso {
       std::vector<T> rhs(nc), x(nc);
       for (int c = 0; c < 3; ++c) {
         for (int i = 0; i < nc; ++i) { rhs[i] = bM[i * 3 + c] - m.V[i] * gp[i * 3 + c]; x[i] = U[i * 3 + c]; }
-        SolveInfo si = solve_nonsym(m, dM.data(), uM.data(), lM.data(), rhs.data(), x.data(), prm.tol_u, prm.maxit_u,
-                                    prm.tol_tangent);
+        SolveInfo si{0, 0.0, 0};
+        if (given_U) {
+          for (int i = 0; i < nc; ++i) x[i] = T(given_U[i * 3 + c]);
+          given_res_u[c] = true_residual(m, dM.data(), uM.data(), lM.data(), rhs.data(), x.data());
+        } else {
+          si = solve_nonsym(m, dM.data(), uM.data(), lM.data(), rhs.data(), x.data(), prm.tol_u, prm.maxit_u,
+                            prm.tol_tangent);
+        }
+        if (trace_U) for (int i = 0; i < nc; ++i) trace_U[i * 3 + c] = val(x[i]);
         st.it_u[c] = si.iters;
         st.res_u[c] = si.res;
         if (si.status) st.status = std::max(st.status, si.status);
@@ -690,8 +809,14 @@ struct Piso {
         rhs[ref] += d0 * prm.p_ref_value;
         dK[ref] = d0 + d0;
       }
-      SolveInfo si = solve_sym(m, dK.data(), uK.data(), rhs.data(), p.data(), prm.tol_p, prm.maxit_p,
-                               prm.tol_tangent);
+      SolveInfo si{0, 0.0, 0};
+      if (given_p) {
+        for (int i = 0; i < nc; ++i) p[i] = T(given_p[(size_t)corr * nc + i]);
+        if (corr < 8) given_res_p[corr] = true_residual(m, dK.data(), uK.data(), uK.data(), rhs.data(), p.data());
+      } else {
+        si = solve_sym(m, dK.data(), uK.data(), rhs.data(), p.data(), prm.tol_p, prm.maxit_p, prm.tol_tangent);
+      }
+      if (trace_p) for (int i = 0; i < nc; ++i) trace_p[(size_t)corr * nc + i] = val(p[i]);
       if (corr < 8) { st.it_p[corr] = si.iters; st.res_p[corr] = si.res; }
       if (si.status) st.status = std::max(st.status, si.status);
       // flux correction with the same explicit correction as the right-hand side
@@ -804,7 +929,15 @@ std::vector<int> rcm_order(const om_mesh& m) {
 // ================================================================================================
 extern "C" {
 
-int oracle_version(void) { return 5; }  // 5: boundary-value tangents
+int oracle_version(void) { return 6; }  // 6: verification step with supplied solutions
+// host threads the Krylov kernels use: 1 in the serial build, the OpenMP thread count in the timing build
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Renumbering.  rcm = 0 keeps the cell order.  Outputs (new -> old where a permutation):
 //  cell_perm[nc], face_perm[nfi], face_flip[nfi], owner[nfi], nbr[nfi], own_start[nc+1],
@@ -1099,12 +1232,24 @@ int oracle_initial_flux(const om_mesh* m, const double* U, const double* Ub, dou
   return 0;
 }
 
+int oracle_piso_run_trace(const om_mesh* m, const om_piso_params* prm, const double* Ub, const double* pb,
+                          const double* wk, int nwk, double* pc, double* U, double* p, double* phi, int nsteps,
+                          int32_t* iters, double* res, double* Ustar, double* pcorr);
+
 // PISO run: nsteps steps from (U, p, phi, pc); all updated in place.  Ub[nfb*3] / pb[nfb] hold the
 // fixed values (ignored on other faces); wk[nwk*3] = (Rp, C, Rd) per Windkessel.
 // stats: per step [3 it_u, n_corr it_p] as int32 and [3 res_u, n_corr res_p] as double.
 int oracle_piso_run(const om_mesh* m, const om_piso_params* prm, const double* Ub, const double* pb, const double* wk,
                     int nwk, double* pc, double* U, double* p, double* phi, int nsteps, int32_t* iters,
                     double* res) {
+  return oracle_piso_run_trace(m, prm, Ub, pb, wk, nwk, pc, U, p, phi, nsteps, iters, res, nullptr, nullptr);
+}
+
+// As oracle_piso_run, also copying out the solution of every linear solve (may be NULL):
+// Ustar[nsteps*nc*3] (predictor) and pcorr[nsteps*n_corr*nc] (pressure after each corrector).
+int oracle_piso_run_trace(const om_mesh* m, const om_piso_params* prm, const double* Ub, const double* pb,
+                          const double* wk, int nwk, double* pc, double* U, double* p, double* phi, int nsteps,
+                          int32_t* iters, double* res, double* Ustar, double* pcorr) {
   Piso<double> S(*m, *prm);
   S.Ub.assign(Ub, Ub + (size_t)m->nfb * 3);
   S.pb.assign(pb, pb + m->nfb);
@@ -1115,6 +1260,8 @@ int oracle_piso_run(const om_mesh* m, const om_piso_params* prm, const double* U
   int per = 3 + prm->n_corr;
   for (int s = 0; s < nsteps; ++s) {
     StepStats st{};
+    S.trace_U = Ustar ? Ustar + (size_t)s * m->nc * 3 : nullptr;
+    S.trace_p = pcorr ? pcorr + (size_t)s * prm->n_corr * m->nc : nullptr;
     S.step(vU, vp, vphi, vpc, st);
     status = std::max(status, st.status);
     if (iters) {
@@ -1127,6 +1274,33 @@ int oracle_piso_run(const om_mesh* m, const om_piso_params* prm, const double* U
   std::copy(vphi.begin(), vphi.end(), phi);
   std::copy(vpc.begin(), vpc.end(), pc);
   return status;
+}
+
+// One PISO step from (U, p, phi, pc) with the solutions of its linear systems supplied (verification
+// mode of Piso): Ustar[nc*3] for the predictor, pcorr[n_corr*nc] for the pressure after each
+// corrector.  The state is updated in place to what the step computes from those solutions, and
+// res_u[3] / res_p[n_corr] receive the true relative residual of each system.
+int oracle_piso_check_step(const om_mesh* m, const om_piso_params* prm, const double* Ub, const double* pb,
+                           const double* wk, int nwk, double* pc, double* U, double* p, double* phi,
+                           const double* Ustar, const double* pcorr, double* res_u, double* res_p) {
+  if (prm->n_corr < 1 || prm->n_corr > 8) return -1;
+  Piso<double> S(*m, *prm);
+  S.Ub.assign(Ub, Ub + (size_t)m->nfb * 3);
+  S.pb.assign(pb, pb + m->nfb);
+  S.wk.assign(wk, wk + 3 * std::max(nwk, S.nwk));
+  S.given_U = Ustar;
+  S.given_p = pcorr;
+  std::vector<double> vU(U, U + (size_t)m->nc * 3), vp(p, p + m->nc), vphi(phi, phi + m->nfi + m->nfb),
+      vpc(pc, pc + std::max(nwk, S.nwk));
+  StepStats st{};
+  S.step(vU, vp, vphi, vpc, st);
+  std::copy(vU.begin(), vU.end(), U);
+  std::copy(vp.begin(), vp.end(), p);
+  std::copy(vphi.begin(), vphi.end(), phi);
+  std::copy(vpc.begin(), vpc.end(), pc);
+  for (int c = 0; c < 3; ++c) res_u[c] = S.given_res_u[c];
+  for (int c = 0; c < prm->n_corr; ++c) res_p[c] = S.given_res_p[c];
+  return 0;
 }
 
 // Tangent (forward-mode) PISO run with nd <= 10 directions.  Seeds per direction k:

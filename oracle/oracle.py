@@ -9,7 +9,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = None
+
 
 TABLE_U, TABLE_P, TABLE_ALL_FIXED, TABLE_ALL_ZEROGRAD = 0, 1, 2, 3
 SCHEME_ONE, SCHEME_UPWIND, SCHEME_LINEAR = 0, 1, 2
@@ -44,18 +44,36 @@ CONV = {"upwind": 0, "linear": 1, "sou": 2, "quick": 3}
 TIME = {"backward_euler": 0, "forward_euler": 1, "crank_nicolson": 2}
 
 
+_LIBS = {}
+_VARIANT = "serial"
+
+
+def use_threads(on=True):
+    """Switch every later call to the all-threads timing build (liboracle_omp.so, OpenMP threads from
+    OMP_NUM_THREADS) or back to the serial build the parity tests use."""
+    global _VARIANT
+    _VARIANT = "omp" if on else "serial"
+
+
+def threads():
+    """Host threads of the current build's Krylov kernels."""
+    L = lib()
+    L.oracle_threads.restype = C.c_int
+    return L.oracle_threads()
+
+
 def lib():
-    global _LIB
-    if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+    if _VARIANT not in _LIBS:
+        path = os.path.join(HERE, "liboracle_omp.so" if _VARIANT == "omp" else "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        _LIB = C.CDLL(path)
-        _LIB.oracle_version.restype = C.c_int
-        if _LIB.oracle_version() != 5:
-            raise RuntimeError(f"{path} is stale (version {_LIB.oracle_version()}); rebuild the oracle")
-    return _LIB
+        L = C.CDLL(path)
+        L.oracle_version.restype = C.c_int
+        if L.oracle_version() != 6:
+            raise RuntimeError(f"{path} is stale (version {L.oracle_version()}); rebuild the oracle")
+        _LIBS[_VARIANT] = L
+    return _LIBS[_VARIANT]
 
 
 def _p(a, t=_f64p):
@@ -242,8 +260,9 @@ def piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=2000, maxit_u=
                         CONV[conv], TIME[time])
 
 
-def piso_run(mesh, prm, U, p, phi, Ub, pb, wk=None, pc=None, nsteps=1):
-    """Returns (U, p, phi, pc, iters[nsteps, 3+n_corr], res[nsteps, 3+n_corr], status)."""
+def piso_run(mesh, prm, U, p, phi, Ub, pb, wk=None, pc=None, nsteps=1, trace=False):
+    """Returns (U, p, phi, pc, iters[nsteps, 3+n_corr], res[nsteps, 3+n_corr], status); with trace=True
+    also (Ustar[nsteps, nc, 3], pcorr[nsteps, n_corr, nc]): the solution of every linear solve."""
     U, p, phi = _f(U).copy(), _f(p).copy(), _f(phi).copy()
     wk = np.zeros((0, 3)) if wk is None else _f(wk)
     nwk = wk.shape[0]
@@ -251,9 +270,35 @@ def piso_run(mesh, prm, U, p, phi, Ub, pb, wk=None, pc=None, nsteps=1):
     per = 3 + prm.n_corr
     iters = np.zeros((nsteps, per), np.int32)
     res = np.zeros((nsteps, per))
-    st = lib().oracle_piso_run(om(mesh), C.byref(prm), _p(_f(Ub)), _p(_f(pb)), _p(np.ascontiguousarray(wk.ravel())),
-                               nwk, _p(pc), _p(U), _p(p), _p(phi), int(nsteps), _p(iters, _i32p), _p(res))
+    Us = np.zeros((nsteps, mesh.n_cells, 3)) if trace else None
+    pcs = np.zeros((nsteps, prm.n_corr, mesh.n_cells)) if trace else None
+    st = lib().oracle_piso_run_trace(om(mesh), C.byref(prm), _p(_f(Ub)), _p(_f(pb)),
+                                     _p(np.ascontiguousarray(wk.ravel())), nwk, _p(pc), _p(U), _p(p), _p(phi),
+                                     int(nsteps), _p(iters, _i32p), _p(res), _p(Us), _p(pcs))
+    if trace:
+        return U, p, phi, pc[:nwk], iters, res, st, Us, pcs
     return U, p, phi, pc[:nwk], iters, res, st
+
+
+def piso_check_step(mesh, prm, U, p, phi, Ub, pb, Ustar, pcorr, wk=None, pc=None):
+    """One step from (U, p, phi, pc) in verification mode: the predictor solution Ustar[nc, 3] and the
+    pressure after each corrector pcorr[n_corr, nc] are supplied instead of solved.  Returns
+    (U, p, phi, pc, res_u[3], res_p[n_corr]): the state the step computes from those solutions and the
+    true relative residual ||b - A x||_2 / ||b||_2 of each of its linear systems."""
+    U, p, phi = _f(U).copy(), _f(p).copy(), _f(phi).copy()
+    wk = np.zeros((0, 3)) if wk is None else _f(wk)
+    nwk = wk.shape[0]
+    pc = np.zeros(max(nwk, 1)) if pc is None else _f(pc).copy()
+    Ustar = _f(Ustar)
+    pcorr = _f(pcorr)
+    assert Ustar.size == 3 * mesh.n_cells and pcorr.size == prm.n_corr * mesh.n_cells
+    res_u, res_p = np.zeros(3), np.zeros(prm.n_corr)
+    st = lib().oracle_piso_check_step(om(mesh), C.byref(prm), _p(_f(Ub)), _p(_f(pb)),
+                                      _p(np.ascontiguousarray(wk.ravel())), nwk, _p(pc), _p(U), _p(p), _p(phi),
+                                      _p(Ustar), _p(pcorr), _p(res_u), _p(res_p))
+    if st != 0:
+        raise ValueError("oracle_piso_check_step: n_corr out of range")
+    return U, p, phi, pc[:nwk], res_u, res_p
 
 
 def piso_tangent(mesh, prm, U, p, phi, Ub, pb, wk, pc, nsteps, dwk=None, dU0=None, dp0=None, dphi0=None, dpc0=None,

@@ -96,6 +96,7 @@ _SIGS = {
     "difvm_ctx_create": (C.c_int32, [C.c_int, _vp, C.POINTER(_vp)]),
     "difvm_ctx_set_stream": (C.c_int32, [_vp, _vp]),
     "difvm_ctx_destroy": (C.c_int32, [_vp]),
+    "difvm_ctx_set_allocator": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_ctx_profile": (C.c_int32, [_vp, C.c_int]),
     "difvm_ctx_profile_read": (C.c_int32, [_vp, C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]),
     "difvm_mesh_renumber_host": (C.c_int32, [C.POINTER(MeshDesc), C.c_uint32] + [_vp] * 14),
@@ -138,6 +139,8 @@ _SIGS = {
     "difvm_piso_set_state": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_piso_get_state": (C.c_int32, [_vp, _vp, _vp, _vp, _f64p]),
     "difvm_piso_step": (C.c_int32, [_vp, C.c_int32, C.POINTER(StepStats)]),
+    "difvm_piso_step_trace": (C.c_int32, [_vp, _vp, _vp, C.POINTER(StepStats)]),
+    "difvm_piso_precond_info": (C.c_int32, [_vp, _i32p, _i32p, C.c_int32, _f64p]),
     "difvm_tape_create": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(_vp)]),
     "difvm_tape_destroy": (C.c_int32, [_vp]),
     "difvm_piso_forward_record": (C.c_int32, [_vp, _vp, C.POINTER(StepStats)]),
@@ -200,6 +203,71 @@ def difvm_ctx_create(device=0, hip_stream=None):
 
 def difvm_ctx_set_stream(ctx, hip_stream):
     _check(lib().difvm_ctx_set_stream(ctx, hip_stream), "difvm_ctx_set_stream")
+
+
+# allocator callbacks of difvm_ctx_set_allocator: void* alloc(size_t, void* stream, void* user) and
+# void free(void*, void* stream, void* user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def difvm_ctx_set_allocator(ctx, alloc_fn, free_fn):
+    """alloc_fn / free_fn: ALLOC_FN / FREE_FN objects (the caller keeps them alive), or both None."""
+    _check(lib().difvm_ctx_set_allocator(ctx, C.cast(alloc_fn, _vp) if alloc_fn else None,
+                                         C.cast(free_fn, _vp) if free_fn else None, None),
+           "difvm_ctx_set_allocator")
+
+
+class TorchAllocator:
+    """Routes the library's device memory through torch's caching allocator (the blocks show up in
+    torch.cuda.memory_allocated and are reused by torch after the library returns them).  Counts the
+    calls.  After interpreter shutdown has begun, frees are dropped (the process is ending)."""
+
+    def __init__(self, device):
+        import torch
+        self.device = int(device)
+        self.n_alloc = 0
+        self.n_free = 0
+        self.live = {}
+        self._torch = torch
+
+        def alloc(nbytes, stream, user):
+            try:
+                p = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:  # an exception must not cross the C boundary: NULL means out of memory
+                return None
+            self.n_alloc += 1
+            self.live[p] = int(nbytes)
+            return p
+
+        def free(ptr, stream, user):
+            if _SHUTDOWN or not ptr:
+                return
+            try:
+                self._torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                return
+            self.n_free += 1
+            self.live.pop(int(ptr), None)
+
+        self.alloc_fn = ALLOC_FN(alloc)
+        self.free_fn = FREE_FN(free)
+
+    def counts(self):
+        return self.n_alloc, self.n_free
+
+
+_SHUTDOWN = False
+
+
+def _mark_shutdown():
+    global _SHUTDOWN
+    _SHUTDOWN = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_mark_shutdown)
 
 
 def difvm_ctx_destroy(ctx):
@@ -497,6 +565,24 @@ def difvm_piso_step(p, nsteps, n_corr=2):
     return status, it, res
 
 
+def difvm_piso_precond_info(p):
+    """(rows per level, finest first; algorithmic bytes of one V-cycle) of the AMG preconditioner."""
+    n = C.c_int32()
+    rows = (C.c_int32 * 64)()
+    vb = C.c_double()
+    _check(lib().difvm_piso_precond_info(p, C.byref(n), rows, 64, C.byref(vb)), "difvm_piso_precond_info")
+    return [rows[k] for k in range(min(n.value, 64))], vb.value
+
+
+def difvm_piso_step_trace(p, U_star, p_corr, n_corr=2):
+    """One step that also writes the predictor's solution U_star[Nc, 3] and each corrector's pressure
+    p_corr[n_corr, Nc] (device tensors, user order).  Returns (status, iters[3+n_corr], res)."""
+    st = StepStats()
+    status = _check(lib().difvm_piso_step_trace(p, _ptr(U_star), _ptr(p_corr), C.byref(st)), "difvm_piso_step_trace")
+    it, res = _stats_arrays([st], n_corr)
+    return status, it[0], res[0]
+
+
 def difvm_tape_create(p, nsteps, ckpt_every):
     out = _vp()
     _check(lib().difvm_tape_create(p, int(nsteps), int(ckpt_every), C.byref(out)), "difvm_tape_create")
@@ -534,13 +620,20 @@ def difvm_piso_adjoint(p, t, gU_N, gp_N, gphi_N, gpc_N, adj_tol, gU_0, gp_0, gph
 # owning handles
 # ------------------------------------------------------------------------------------------------
 class Context:
-    def __init__(self, device=0, stream=None):
+    """A library context on one device and stream.  torch_allocator=True (default) routes every device
+    allocation of the library through torch's caching allocator (difvm_ctx_set_allocator)."""
+
+    def __init__(self, device=0, stream=None, torch_allocator=True):
         import torch
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self.h = difvm_ctx_create(device, C.c_void_p(stream.cuda_stream))
+        self.allocator = None
+        if torch_allocator:
+            self.allocator = TorchAllocator(device)
+            difvm_ctx_set_allocator(self.h, self.allocator.alloc_fn, self.allocator.free_fn)
 
     def close(self):
         if self.h:
@@ -649,3 +742,14 @@ class Piso:
 
     def step(self, nsteps=1):
         return difvm_piso_step(self.h, nsteps, self.params.n_corr)
+
+    def step_trace(self):
+        """One step; returns (status, iters, res, U_star[Nc, 3], p_corr[n_corr, Nc]) with the solution of
+        each linear solve of the step (device tensors, user order)."""
+        import torch
+        src = self.mesh.src
+        dev = self.mesh.ctx.device
+        Us = torch.empty((src.n_cells, 3), dtype=torch.float64, device=dev)
+        pc = torch.empty((self.params.n_corr, src.n_cells), dtype=torch.float64, device=dev)
+        status, it, res = difvm_piso_step_trace(self.h, Us, pc, self.params.n_corr)
+        return status, it, res, Us, pc

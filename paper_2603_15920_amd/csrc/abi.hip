@@ -12,14 +12,22 @@ namespace difvm {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-void* dmalloc(size_t bytes) {
+void* dmalloc(const Ctx& c, size_t bytes) {
+  bytes = bytes ? bytes : 1;
+  if (c.alloc.alloc) {
+    void* p = c.alloc.alloc(bytes, c.stream, c.alloc.user);
+    if (!p) throw Error{DIFVM_ERR_OOM, "the context's allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+    return p;
+  }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+  hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) throw Error{DIFVM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
   return p;
 }
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
+void dfree(const Ctx& c, void* p) {
+  if (!p) return;
+  if (c.alloc.free) c.alloc.free(p, c.stream, c.alloc.user);
+  else (void)hipFree(p);
 }
 
 static hipEvent_t pool_event(Profiler& P) {
@@ -96,6 +104,8 @@ void piso_segment_stats(const difvm_piso* P, int nseg, difvm_step_stats* out);
 void piso_set_state(difvm_piso* P, const double* U, const double* p, const double* phi);
 void piso_get_state(difvm_piso* P, double* U, double* p, double* phi, double* pc_host);
 int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats);
+int piso_step_trace(difvm_piso* P, double* Ustar_user, double* p_user, difvm_step_stats* stats);
+void piso_precond_info(const difvm_piso* P, int32_t* n_levels, int32_t* rows, int32_t cap, double* vcycle_bytes);
 void piso_rebuild_preconditioner(difvm_piso* P);
 
 static void check_mesh(const difvm_mesh* m) { DIFVM_CHECK(m != nullptr, DIFVM_ERR_INVALID_ARG, "mesh is NULL"); }
@@ -110,7 +120,7 @@ static void check_ptr(const void* p, const char* what) {
 
 template <class T>
 static T* up_vec(difvm_mesh* m, const std::vector<T>& v) {
-  T* p = dalloc<T>(v.size());
+  T* p = dalloc<T>(ctx_of(m), v.size());
   m->allocs.push_back(p);
   upload(p, v, stream_of(m));
   return p;
@@ -220,10 +230,18 @@ static void free_mesh(difvm_mesh* m) {
   if (!m) return;
   if (m->ctx) (void)hipStreamSynchronize(stream_of(m));
   krylov_work_free(m->krylov);
-  for (void* a : m->allocs) dfree(a);
+  for (void* a : m->allocs) dfree(ctx_of(m), a);
   difvm_ctx* ctx = m->ctx;
   delete m;
   ctx_release(ctx);
+}
+
+double* mesh_scratch(difvm_mesh* m, int slot, size_t n) {
+  if (!m->scratch[slot]) {
+    m->scratch[slot] = dalloc<double>(ctx_of(m), n);
+    m->allocs.push_back(m->scratch[slot]);
+  }
+  return m->scratch[slot];
 }
 
 void mesh_release(difvm_mesh* m) {
@@ -258,6 +276,19 @@ difvm_status difvm_ctx_set_stream(difvm_ctx* ctx, void* hip_stream) {
   DIFVM_API_BEGIN
   check_ptr(ctx, "ctx");
   ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_set_allocator(difvm_ctx* ctx, void* (*alloc)(size_t, void*, void*),
+                                     void (*free_fn)(void*, void*, void*), void* user) {
+  DIFVM_API_BEGIN
+  check_ptr(ctx, "ctx");
+  DIFVM_CHECK((alloc == nullptr) == (free_fn == nullptr), DIFVM_ERR_INVALID_ARG,
+              "alloc and free must both be set or both be NULL");
+  // every block must go back to the allocator that made it: no object may hold memory yet
+  DIFVM_CHECK(ctx->refs == 1, DIFVM_ERR_INVALID_ARG, "the allocator can only change while no object uses the context");
+  ctx->c.alloc = Allocator{alloc, free_fn, alloc ? user : nullptr};
   DIFVM_API_END
   return DIFVM_OK;
 }
@@ -483,17 +514,13 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
   DIFVM_CHECK((A->upper && A->lower) || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper or A->lower is NULL");
   DIFVM_CHECK(dt > 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0");
   DIFVM_CHECK(U_b || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "U_b is NULL");
-  double* gU = dalloc<double>((size_t)9 * m->d.nc);
-  try {
-    op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
-    op_assemble_momentum(m, DIFVM_CONV_UPWIND, DIFVM_TIME_BACKWARD_EULER, nu, nullptr, dt, (const double*)flux, (const double*)U, gU, (const double*)U_b, (double*)A->diag,
-                         (double*)A->upper, (double*)A->lower, nullptr, (double*)b);
-    DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
-  } catch (...) {
-    dfree(gU);
-    throw;
-  }
-  dfree(gU);
+  // the gradient of U lives in mesh scratch: no allocation after the first call
+  double* gU = mesh_scratch(const_cast<difvm_mesh*>(m), 1, (size_t)9 * m->d.nc);
+  op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
+  op_assemble_momentum(m, DIFVM_CONV_UPWIND, DIFVM_TIME_BACKWARD_EULER, nu, nullptr, dt, (const double*)flux,
+                       (const double*)U, gU, (const double*)U_b, (double*)A->diag, (double*)A->upper,
+                       (double*)A->lower, nullptr, (double*)b);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
   DIFVM_API_END
   return DIFVM_OK;
 }
@@ -506,18 +533,14 @@ static difvm_status solve_common(const difvm_mesh* cm, const difvm_ldu* A, int n
   check_ptr(A->diag, "A->diag");
   DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
   DIFVM_CHECK(tol >= 0 && maxit >= 0, DIFVM_ERR_INVALID_ARG, "tol and maxit must be >= 0");
-  double* val = dalloc<double>(m->d.nslot);
+  // the cell-slot copy of the matrix lives in mesh scratch: no allocation after the first call
+  double* val = mesh_scratch(m, 0, m->d.nslot);
   SolveResult R;
-  try {
-    sell_from_ldu(m, (const double*)A->upper, sym ? nullptr : (const double*)A->lower, val);
-    SellMatrix S{(const double*)A->diag, val};
-    if (sym) R = pcg(m, S, (const double*)b, (double*)x, tol, maxit, nullptr, amg);
-    else R = bicgstab(m, ncomp, S, (const double*)b, (double*)x, tol, maxit);
-  } catch (...) {
-    dfree(val);
-    throw;
-  }
-  dfree(val);
+  sell_from_ldu(m, (const double*)A->upper, sym ? nullptr : (const double*)A->lower, val);
+  SellMatrix S{(const double*)A->diag, val};
+  int* hint = &m->abi_hint[sym ? (amg ? 1 : 0) : 2];
+  if (sym) R = pcg(m, S, (const double*)b, (double*)x, tol, maxit, nullptr, amg, hint);
+  else R = bicgstab(m, ncomp, S, (const double*)b, (double*)x, tol, maxit, nullptr, hint);
   if (stats) {
     for (int c = 0; c < 3; ++c) { stats->iters[c] = R.iters[c]; stats->residual[c] = R.res[c]; }
     stats->status = R.status;
@@ -553,8 +576,8 @@ struct difvm_amg {
 static void amg_release(difvm_amg* a) {
   if (!a) return;
   amg_free(a->dev);
-  dfree(a->diag);
-  dfree(a->val);
+  dfree(ctx_of(a->mesh), a->diag);
+  dfree(ctx_of(a->mesh), a->val);
   difvm_mesh* m = a->mesh;
   delete a;
   mesh_release(m);
@@ -576,15 +599,15 @@ difvm_status difvm_amg_create(const difvm_mesh* cm, const difvm_ldu* A, difvm_am
   check_sym_ldu(m, A);
   difvm_amg* a = new difvm_amg();
   try {
-    a->diag = dalloc<double>(m->d.nc);
-    a->val = dalloc<double>(m->d.nslot);
+    a->diag = dalloc<double>(ctx_of(m), m->d.nc);
+    a->val = dalloc<double>(ctx_of(m), m->d.nslot);
     DIFVM_HIP(hipMemcpyAsync(a->diag, A->diag, sizeof(double) * m->d.nc, hipMemcpyDeviceToDevice, stream_of(m)));
     sell_from_ldu(m, (const double*)A->upper, nullptr, a->val);
     a->dev = amg_create(m, SellMatrix{a->diag, a->val}, AmgOptions{});
   } catch (...) {
     amg_free(a->dev);
-    dfree(a->diag);
-    dfree(a->val);
+    dfree(ctx_of(m), a->diag);
+    dfree(ctx_of(m), a->val);
     delete a;
     throw;
   }
@@ -781,6 +804,27 @@ difvm_status difvm_piso_step(difvm_piso* piso, int32_t nsteps, difvm_step_stats*
   check_ptr(piso, "piso");
   DIFVM_CHECK(nsteps >= 0, DIFVM_ERR_INVALID_ARG, "nsteps must be >= 0");
   return piso_step(piso, nsteps, stats_host);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_precond_info(const difvm_piso* piso, int32_t* n_levels, int32_t* rows, int32_t cap,
+                                     double* vcycle_bytes) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  check_ptr(n_levels, "n_levels");
+  DIFVM_CHECK(cap >= 0 && (rows || cap == 0), DIFVM_ERR_INVALID_ARG, "rows is NULL");
+  piso_precond_info(piso, n_levels, rows, cap, vcycle_bytes);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_piso_step_trace(difvm_piso* piso, void* U_star, void* p_corr, difvm_step_stats* stats_host) {
+  DIFVM_API_BEGIN
+  check_ptr(piso, "piso");
+  check_ptr(U_star, "U_star");
+  check_ptr(p_corr, "p_corr");
+  return piso_step_trace(piso, (double*)U_star, (double*)p_corr, stats_host);
   DIFVM_API_END
   return DIFVM_OK;
 }

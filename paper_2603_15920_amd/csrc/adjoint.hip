@@ -539,7 +539,7 @@ struct difvm_tape {
 namespace difvm {
 
 static double* tape_alloc(difvm_tape* T, size_t n) {
-  double* a = dalloc<double>(n);
+  double* a = dalloc<double>(ctx_of(T->piso->mesh), n);
   T->allocs.push_back(a);
   DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * (n ? n : 1), stream_of(T->piso->mesh)));
   return a;
@@ -614,7 +614,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     if (P->prm.conv != DIFVM_CONV_UPWIND) T->gUn = tape_alloc(T, 9 * nc);
     T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
   } catch (...) {
-    for (void* a : T->allocs) dfree(a);
+    for (void* a : T->allocs) dfree(ctx_of(P->mesh), a);
     delete T;
     throw;
   }
@@ -625,7 +625,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
 void tape_destroy(difvm_tape* T) {
   if (!T) return;
   (void)hipStreamSynchronize(stream_of(T->piso->mesh));
-  for (void* a : T->allocs) dfree(a);
+  for (void* a : T->allocs) dfree(ctx_of(T->piso->mesh), a);
   difvm_piso* P = T->piso;
   delete T;
   piso_release(P);
@@ -699,7 +699,8 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     k_axpy<<<Gc, BLOCK, 0, s>>>(nc, 1.0, T->tmp, T->pbar);
     // pressure solve: lambda = K^-1 pbar (K symmetric)
     zero(T->lam, nc, s);
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, nullptr, P->amg);
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, nullptr, P->amg,
+                         &P->hint_adj_p[c]);
     worst = std::max(worst, rp.status);
     k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);
@@ -715,7 +716,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   }
   // predictor: U* = M^-1 (b - V grad p^n);  mu = M^-T Ubar
   zero(T->mu, 3 * nc, s);
-  SolveResult ru = bicgstab(m, 3, SellMatrix{R.dM, T->valT}, T->Ubar, T->mu, adj_tol, maxit_u);
+  SolveResult ru = bicgstab(m, 3, SellMatrix{R.dM, T->valT}, T->Ubar, T->mu, adj_tol, maxit_u, nullptr, &P->hint_adj_u);
   worst = std::max(worst, ru.status);
   k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->mu, R.Ustar, T->valbar, nullptr);
   k_adj_pred<<<Gc, BLOCK, 0, s>>>(d.nc, T->mu, R.Ustar, d.V, T->dbar, T->bbar, T->gbar);

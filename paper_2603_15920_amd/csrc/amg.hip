@@ -57,13 +57,13 @@ namespace {
 
 template <class T>
 T* up(AmgDev* a, const std::vector<T>& v, hipStream_t s) {
-  T* p = dalloc<T>(v.size());
+  T* p = dalloc<T>(ctx_of(a->mesh), v.size());
   a->allocs.push_back(p);
   upload(p, v, s);
   return p;
 }
 double* work(AmgDev* a, size_t n) {
-  double* p = dalloc<double>(n);
+  double* p = dalloc<double>(ctx_of(a->mesh), n);
   a->allocs.push_back(p);
   return p;
 }
@@ -452,9 +452,9 @@ __global__ void k_zero_int(int* p) {
 }
 
 // M <- M^-1 for the dense SPD coarsest matrix (device, n x n); throws when a pivot is not positive
-void dense_inverse_spd(int n, double* M, hipStream_t s) {
-  double* rc = dalloc<double>(2 * (size_t)n);
-  int* bad = dalloc<int>(1);
+void dense_inverse_spd(const Ctx& c, int n, double* M, hipStream_t s) {
+  double* rc = dalloc<double>(c, 2 * (size_t)n);
+  int* bad = dalloc<int>(c, 1);
   int hbad = 0;
   try {
     k_zero_int<<<1, 64, 0, s>>>(bad);
@@ -468,12 +468,12 @@ void dense_inverse_spd(int n, double* M, hipStream_t s) {
     DIFVM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     DIFVM_HIP(hipStreamSynchronize(s));
   } catch (...) {
-    dfree(rc);
-    dfree(bad);
+    dfree(c, rc);
+    dfree(c, bad);
     throw;
   }
-  dfree(rc);
-  dfree(bad);
+  dfree(c, rc);
+  dfree(c, bad);
   DIFVM_CHECK(!hbad, DIFVM_ERR_UNSUPPORTED, "AMG setup: coarsest matrix is not positive definite");
 }
 
@@ -582,7 +582,7 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
     }
     DIFVM_CHECK(H.n_coarsest <= MAX_DENSE, DIFVM_ERR_UNSUPPORTED, "coarsest AMG level too large");
     a->cinv = up(a, H.coarsest_dense, s);
-    dense_inverse_spd(H.n_coarsest, a->cinv, s);
+    dense_inverse_spd(ctx_of(m), H.n_coarsest, a->cinv, s);
     DIFVM_HIP(hipStreamSynchronize(s));
   } catch (...) {
     amg_free(a);
@@ -594,7 +594,7 @@ AmgDev* amg_create(difvm_mesh* m, SellMatrix K, const AmgOptions& opt) {
 void amg_free(AmgDev* a) {
   if (!a) return;
   if (a->mesh) (void)hipStreamSynchronize(stream_of(a->mesh));
-  for (void* p : a->allocs) dfree(p);
+  for (void* p : a->allocs) dfree(ctx_of(a->mesh), p);
   delete a;
 }
 
@@ -602,6 +602,37 @@ int amg_levels(const AmgDev* a, int* rows, int cap) {
   int n = (int)a->rows.size();
   for (int l = 0; l < n && l < cap; ++l) rows[l] = a->rows[l];
   return n;
+}
+
+double amg_vcycle_bytes(const AmgDev* a) {
+  const difvm_mesh* m = a->mesh;
+  const int L = a->L;
+  auto rows = [&](int l) { return (double)a->rows[l]; };
+  auto csr = [](const DevCsr& M, bool diag, int val_words) {
+    return 4.0 * (M.n + 1) + (4.0 + 8.0 * val_words) * M.nnz + (diag ? 8.0 * M.n : 0.0);
+  };
+  const double n0 = m->d.nc;
+  const double K = 8.0 * n0 + 16.0 * m->d.nfi;  // LDU: diagonal; owner, neighbour, coefficient per face
+  double b = 0.0;
+  b += K + 16.0 * n0;  // first pre-smoothing pass: r -> xs
+  b += K + 24.0 * n0;  // second: r, xs -> res
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) {
+      b += csr(a->A[l], true, 1) + 16.0 * rows(l);  // bd -> xs
+      b += csr(a->A[l], true, 1) + 24.0 * rows(l);  // b, xs -> res
+    }
+    bool coarsest = l + 1 == L;
+    b += csr(a->R[l], false, 1) + 8.0 * rows(l) + (coarsest ? 8.0 : 24.0) * rows(l + 1);  // res -> b (, D^-1 b)
+  }
+  b += 8.0 * rows(L) * rows(L) + 16.0 * rows(L);  // dense solve
+  for (int l = L - 1; l >= 1; --l) {
+    b += csr(a->AP[l], true, 2) + 32.0 * rows(l) + 8.0 * rows(l + 1);  // xs, res, x_c -> t, d0
+    b += csr(a->A[l], true, 1) + 24.0 * rows(l);                       // t, d0 -> x
+  }
+  b += csr(a->P0, false, 1) + 16.0 * n0 + 8.0 * rows(1);  // xs, x_1 -> t
+  b += K + 24.0 * n0;                                     // r, t -> d0
+  b += K + 32.0 * n0;                                     // r, t, d0 -> z
+  return b;
 }
 
 static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const double* r, double* z, double* part,

@@ -23,5 +23,10 @@ void amg_free(AmgDev* a);
 void amg_vcycle(const AmgDev* a, SellMatrix K, const double* r, double* z, double* part, const PcgCtl* ctl);
 // rows per level (finest first) into rows[0..cap); returns the number of levels
 int amg_levels(const AmgDev* a, int* rows, int cap);
+// Algorithmic bytes of one V-cycle: every kernel's distinct inputs read once and outputs written
+// once, the finest level's matrix in its LDU form (diagonal, one coefficient and the owner /
+// neighbour indices per internal face), coarse matrices in CSR (row pointers, 4-byte columns, 8-byte
+// values, diagonal), the coarsest inverse dense.
+double amg_vcycle_bytes(const AmgDev* a);
 
 }  // namespace difvm

@@ -59,11 +59,19 @@ struct Profiler {
   std::vector<long> launches;
 };
 
+// device memory of the library: the caller's allocator (difvm_ctx_set_allocator) or hipMalloc/hipFree
+struct Allocator {
+  void* (*alloc)(size_t bytes, void* stream, void* user) = nullptr;
+  void (*free)(void* p, void* stream, void* user) = nullptr;
+  void* user = nullptr;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   Profiler prof;
   bool capturing = false;  // a step is being captured: launches are not timed
+  Allocator alloc;
 };
 
 // Brackets the next launch on `s` with events when profiling is on; returns a handle for prof_end.
@@ -73,11 +81,12 @@ void prof_end(Ctx& c, int handle);
 // CG stopped, they returned at once) are moved to "<name> (idle)".
 void prof_idle_after(Ctx& c, size_t from, long last);
 
-void* dmalloc(size_t bytes);
-void dfree(void* p);
+// every device allocation of the library goes through its context's allocator
+void* dmalloc(const Ctx& c, size_t bytes);
+void dfree(const Ctx& c, void* p);
 template <class T>
-T* dalloc(size_t n) {
-  return static_cast<T*>(dmalloc(sizeof(T) * (n ? n : 1)));
+T* dalloc(const Ctx& c, size_t n) {
+  return static_cast<T*>(dmalloc(c, sizeof(T) * (n ? n : 1)));
 }
 template <class T>
 void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
@@ -137,6 +146,8 @@ struct difvm_mesh {
   difvm::DMesh d;
   std::vector<void*> allocs;                 // device allocations owned by the mesh
   difvm::KrylovWork* krylov = nullptr;       // solver workspace, created on first solve
+  double* scratch[2] = {nullptr, nullptr};   // entry-point scratch (slot matrix; 3-component gradient)
+  int abi_hint[3] = {0, 0, 0};               // iterations of the last difvm_solve_pcg / _pcg_amg / _bicgstab
   int refs = 1;
   int tune[DIFVM_TUNE_COUNT] = {256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 0};  // launch knobs
 };
@@ -145,6 +156,8 @@ namespace difvm {
 inline hipStream_t stream_of(const difvm_mesh* m) { return m->ctx->c.stream; }
 void mesh_release(difvm_mesh* m);  // drops one reference (frees at zero)
 inline Ctx& ctx_of(const difvm_mesh* m) { return m->ctx->c; }
+// scratch buffer `slot` of the mesh (n doubles), allocated at its first use and kept with the mesh
+double* mesh_scratch(difvm_mesh* m, int slot, size_t n);
 // RAII event bracket around one launch
 struct ProfScope {
   Ctx& c;

@@ -34,38 +34,50 @@ struct KrylovWork {
   BiState* bi = nullptr;         // [nseg]
   void* host_state[2] = {nullptr, nullptr};  // pinned mirrors of the solver states (two polls in flight)
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
-  int pcg_hint = 0, bi_hint = 0;  // iterations of the previous solve: sizes the first unpolled block
+  const Ctx* ctx = nullptr;  // allocator of the buffers above
 };
 
 KrylovWork* krylov_work(difvm_mesh* m) { return m->krylov; }
 
+void krylov_work_free(KrylovWork* w);
+
 static KrylovWork* make_work(difvm_mesh* m) {
   if (m->krylov) return m->krylov;
   KrylovWork* w = new KrylovWork();
-  m->krylov = w;
-  int nc = m->d.nc;
-  w->nc = nc;
-  w->ntile = m->d.ntile;  // reduction tiles over all segments (at least ceil(nc / 1024))
-  size_t n3 = (size_t)nc * 3;
-  w->r = dalloc<double>(n3); w->p = dalloc<double>(n3); w->q = dalloc<double>(n3); w->rh = dalloc<double>(n3);
-  w->v = dalloc<double>(n3); w->s = dalloc<double>(n3); w->z = dalloc<double>(n3);
-  w->t = dalloc<double>(n3);
-  w->partials = dalloc<double>((size_t)9 * w->ntile);  // up to 9 values per tile (PCG uses 6, BiCGStab 9)
-  int nseg = m->d.nseg;
-  w->pcg = static_cast<PcgCtl*>(dmalloc(sizeof(BiState) * nseg));  // PcgCtl is smaller (asserted below)
-  w->bi = dalloc<BiState>(nseg);
-  for (int q = 0; q < 2; ++q) {
-    DIFVM_HIP(hipHostMalloc((void**)&w->host_state[q], sizeof(BiState) * nseg, hipHostMallocDefault));
-    DIFVM_HIP(hipEventCreateWithFlags(&w->poll_ev[q], hipEventDisableTiming));
+  try {
+    int nc = m->d.nc;
+    w->nc = nc;
+    w->ntile = m->d.ntile;  // reduction tiles over all segments (at least ceil(nc / 1024))
+    size_t n3 = (size_t)nc * 3;
+    const Ctx& c = ctx_of(m);
+    w->ctx = &c;
+    w->r = dalloc<double>(c, n3); w->p = dalloc<double>(c, n3); w->q = dalloc<double>(c, n3);
+    w->rh = dalloc<double>(c, n3); w->v = dalloc<double>(c, n3); w->s = dalloc<double>(c, n3);
+    w->z = dalloc<double>(c, n3); w->t = dalloc<double>(c, n3);
+    w->partials = dalloc<double>(c, (size_t)9 * w->ntile);  // up to 9 values per tile (PCG uses 6, BiCGStab 9)
+    int nseg = m->d.nseg;
+    w->pcg = static_cast<PcgCtl*>(dmalloc(c, sizeof(BiState) * nseg));  // PcgCtl is smaller (asserted below)
+    w->bi = dalloc<BiState>(c, nseg);
+    for (int q = 0; q < 2; ++q) {
+      DIFVM_HIP(hipHostMalloc((void**)&w->host_state[q], sizeof(BiState) * nseg, hipHostMallocDefault));
+      DIFVM_HIP(hipEventCreateWithFlags(&w->poll_ev[q], hipEventDisableTiming));
+    }
+  } catch (...) {
+    krylov_work_free(w);
+    throw;
   }
+  m->krylov = w;
   return w;
 }
 
 void krylov_work_free(KrylovWork* w) {
   if (!w) return;
-  for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->s, w->z, w->t, w->partials}) dfree(a);
-  dfree(w->pcg);
-  dfree(w->bi);
+  if (w->ctx) {
+    const Ctx& c = *w->ctx;
+    for (double* a : {w->r, w->p, w->q, w->rh, w->v, w->s, w->z, w->t, w->partials}) dfree(c, a);
+    dfree(c, w->pcg);
+    dfree(c, w->bi);
+  }
   for (int q = 0; q < 2; ++q) {
     if (w->host_state[q]) (void)hipHostFree(w->host_state[q]);
     if (w->poll_ev[q]) (void)hipEventDestroy(w->poll_ev[q]);
@@ -432,7 +444,7 @@ static const void* wait_poll(KrylovWork* w, int slot) {
 }
 
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit, const QueueOnly* qo,
-                const AmgDev* amg) {
+                const AmgDev* amg, int* hint) {
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
@@ -501,7 +513,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
     DIFVM_HIP(hipGetLastError());
   };
   const size_t bytes = pcg_state_bytes(m);
-  queue_block(std::max(4, w->pcg_hint - 2));
+  queue_block(std::max(4, (hint ? *hint : 0) - 2));
   int slot = 0;
   post_poll(m, w, w->pcg, bytes, slot);
   const PcgCtl* hs = nullptr;
@@ -520,7 +532,7 @@ SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double 
   SolveResult R = pcg_result(m, hs, nullptr);
   // iteration k's kernels ran while some segment had not stopped, i.e. for k <= the largest count
   prof_idle_after(ctx_of(m), prof_mark, R.iters[0]);  // iters[0]: the largest over the segments
-  w->pcg_hint = R.iters[0];
+  if (hint) *hint = R.iters[0];
   return R;
 }
 
@@ -809,7 +821,7 @@ SolveResult bicgstab_result(const difvm_mesh* m, int ncomp, const void* host_sta
 
 template <int NC>
 static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
-                               const QueueOnly* qo) {
+                               const QueueOnly* qo, int* hint) {
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   SellView V = sview(m, A);
@@ -841,7 +853,7 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
     return SolveResult{};
   }
   const size_t bytes = bicgstab_state_bytes(m);
-  queue_iters(std::min(maxit, std::max(2, w->bi_hint - 1)));
+  queue_iters(std::min(maxit, std::max(2, (hint ? *hint : 0) - 1)));
   int slot = 0;
   post_poll(m, w, w->bi, bytes, slot);
   const BiState* hs = nullptr;
@@ -858,14 +870,14 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
     slot ^= 1;
   }
   SolveResult R = bicgstab_result(m, NC, hs, nullptr);
-  w->bi_hint = std::max(R.iters[0], std::max(R.iters[1], R.iters[2]));
+  if (hint) *hint = std::max(R.iters[0], std::max(R.iters[1], R.iters[2]));
   return R;
 }
 
 SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
-                     const QueueOnly* qo) {
-  if (ncomp == 1) return bicgstab_nc<1>(m, A, b, x, tol, maxit, qo);
-  return bicgstab_nc<3>(m, A, b, x, tol, maxit, qo);
+                     const QueueOnly* qo, int* hint) {
+  if (ncomp == 1) return bicgstab_nc<1>(m, A, b, x, tol, maxit, qo, hint);
+  return bicgstab_nc<3>(m, A, b, x, tol, maxit, qo, hint);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -892,13 +904,14 @@ double time_pcg_spmv(difvm_mesh* m, int grid, int reps, hipEvent_t e0, hipEvent_
   KrylovWork* w = make_work(m);
   hipStream_t s = stream_of(m);
   const DMesh& d = m->d;
-  double* val = dalloc<double>(d.nslot);
+  const Ctx& cx = ctx_of(m);
+  double* val = dalloc<double>(cx, d.nslot);
   double* diag = nullptr;
   PcgCtl* ctl = nullptr;
   double t = 0.0;
   try {
-    diag = dalloc<double>(d.nc);
-    ctl = static_cast<PcgCtl*>(dmalloc(sizeof(PcgCtl) * d.nseg));
+    diag = dalloc<double>(cx, d.nc);
+    ctl = static_cast<PcgCtl*>(dmalloc(cx, sizeof(PcgCtl) * d.nseg));
     auto fill = [&](double* a, size_t n, double v) {
       k_fill_const<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, n, v);
     };
@@ -929,14 +942,14 @@ double time_pcg_spmv(difvm_mesh* m, int grid, int reps, hipEvent_t e0, hipEvent_
     t = ms * 1e-3 / reps;
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    dfree(val);
-    dfree(diag);
-    dfree(ctl);
+    dfree(cx, val);
+    dfree(cx, diag);
+    dfree(cx, ctl);
     throw;
   }
-  dfree(val);
-  dfree(diag);
-  dfree(ctl);
+  dfree(cx, val);
+  dfree(cx, diag);
+  dfree(cx, ctl);
   return t;
 }
 

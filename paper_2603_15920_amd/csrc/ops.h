@@ -67,10 +67,14 @@ struct QueueOnly {
 };
 struct AmgDev;
 // amg: smoothed-aggregation V-cycle preconditioner instead of Jacobi
+// hint (may be NULL): the iteration count of the previous solve made from the same call site; it sizes
+// the first block of iterations queued before the host polls, and receives this solve's count.  Each
+// call site (a PISO object's predictor, each corrector, scalar transport, adjoint solves, each solve
+// entry point of the C-ABI) keeps its own, so a solve never inherits another system's count.
 SolveResult pcg(difvm_mesh* m, SellMatrix A, const double* b, double* x, double tol, int maxit,
-                const QueueOnly* qo = nullptr, const AmgDev* amg = nullptr);
+                const QueueOnly* qo = nullptr, const AmgDev* amg = nullptr, int* hint = nullptr);
 SolveResult bicgstab(difvm_mesh* m, int ncomp, SellMatrix A, const double* b, double* x, double tol, int maxit,
-                     const QueueOnly* qo = nullptr);
+                     const QueueOnly* qo = nullptr, int* hint = nullptr);
 size_t pcg_state_bytes(const difvm_mesh* m);
 int pcg_spmv_grid(const difvm_mesh* m);
 size_t bicgstab_state_bytes(const difvm_mesh* m);

@@ -467,7 +467,7 @@ __global__ __launch_bounds__(BLOCK) void k_initial_flux(MeshView<double> m, cons
 namespace difvm {
 
 static double* piso_alloc(difvm_piso* P, size_t n) {
-  double* a = dalloc<double>(n);
+  double* a = dalloc<double>(ctx_of(P->mesh), n);
   P->allocs.push_back(a);
   DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * (n ? n : 1), stream_of(P->mesh)));
   return a;
@@ -501,7 +501,7 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
       int s = L.cell_seg[i];
       if (!L.seg_has_fixed_p[s] && cp[i] == L.seg_user_start[s] + prm->p_ref_cell) ref[i] = 1;
     }
-    P->is_ref = dalloc<int8_t>(nc);
+    P->is_ref = dalloc<int8_t>(ctx_of(m), nc);
     P->allocs.push_back(P->is_ref);
     upload(P->is_ref, ref, stream_of(m));
     P->seg_nu.assign(d.nseg, prm->nu);
@@ -522,7 +522,7 @@ void piso_create(difvm_mesh* m, const difvm_piso_params* prm, difvm_piso** out) 
     upload(P->wk, P->wk_host, stream_of(m));
     DIFVM_HIP(hipStreamSynchronize(stream_of(m)));  // the host vectors above are temporaries
   } catch (...) {
-    for (void* a : P->allocs) dfree(a);
+    for (void* a : P->allocs) dfree(ctx_of(m), a);
     delete P;
     throw;
   }
@@ -538,7 +538,7 @@ void piso_release(difvm_piso* P) {
   (void)hipStreamSynchronize(stream_of(m));
   piso_graph_free(P);
   amg_free(P->amg);
-  for (void* a : P->allocs) dfree(a);
+  for (void* a : P->allocs) dfree(ctx_of(m), a);
   delete P;
   mesh_release(m);
 }
@@ -580,7 +580,8 @@ SolveResult piso_transport_scalar(difvm_piso* P, double D, int table, const doub
   op_grad(m, DIFVM_F64, 1, table, P->sc, P->scb, P->sg);
   launch_momentum<1>(m, P->prm.conv, time_theta(P->prm.time), table, D, nullptr, P->prm.dt, P->phi, P->sc, P->sg, P->scb, P->sd, nullptr,
                      nullptr, P->sval, P->sb);
-  SolveResult r = bicgstab(m, 1, SellMatrix{P->sd, P->sval}, P->sb, P->sc, P->prm.tol_u, P->prm.maxit_u);
+  SolveResult r = bicgstab(m, 1, SellMatrix{P->sd, P->sval}, P->sb, P->sc, P->prm.tol_u, P->prm.maxit_u, nullptr,
+                           &P->hint_sc);
   permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->sc, c_user);
   DIFVM_HIP(hipStreamSynchronize(s));
   return r;
@@ -702,10 +703,12 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
   k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
   DIFVM_HIP(hipGetLastError());
-  SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u, qu ? &qu->u : nullptr);
+  SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u, qu ? &qu->u : nullptr,
+                            &P->hint_u);
   for (int c = 0; c < 3; ++c) { st.it_u[c] = ru.iters[c]; st.res_u[c] = ru.res[c]; }
   st.status = ru.status;
   if (!qu) set_seg_stats_u(P, ru);
+  if (P->trace_U) dcopy(P->trace_U, P->U, 3 * nc, s);
   if (rec) {
     dcopy(rec->dM, P->dM, nc, s);
     dcopy(rec->valM, P->valM, d.nslot, s);
@@ -718,7 +721,9 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
       dcopy(rec->pold[corr], P->p, nc, s);
     }
     k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
-    op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
+    // grad of the entering pressure: at the first corrector p and its boundary values are those of the
+    // predictor, whose gradient P->gp still holds
+    if (corr > 0) op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
     if (rec) {
       dcopy(rec->HbyA[corr], P->HbyA, 3 * nc, s);
       dcopy(rec->gpo[corr], P->gp, 3 * nc, s);
@@ -733,11 +738,12 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
       P->amg = amg_create(m, SellMatrix{P->dK, P->valK}, AmgOptions{});
     }
     SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p, qu ? &qu->p[corr] : nullptr,
-                         P->amg);
+                         P->amg, &P->hint_p[corr]);
     st.it_p[corr] = rp.iters[0];
     st.res_p[corr] = rp.res[0];
     st.status = std::max(st.status, rp.status);
     if (!qu) set_seg_stats_p(P, corr, rp);
+    if (P->trace_p) dcopy(P->trace_p + (size_t)corr * nc, P->p, nc, s);
     k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
     k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
     DIFVM_HIP(hipGetLastError());
@@ -926,10 +932,49 @@ void piso_rebuild_preconditioner(difvm_piso* P) {
   P->amg = nullptr;
 }
 
+void piso_precond_info(const difvm_piso* P, int32_t* n_levels, int32_t* rows, int32_t cap, double* vcycle_bytes) {
+  DIFVM_CHECK(P->prm.precond == DIFVM_PRECOND_AMG, DIFVM_ERR_INVALID_ARG, "the PISO object does not use AMG");
+  *n_levels = 0;
+  if (vcycle_bytes) *vcycle_bytes = 0.0;
+  if (!P->amg) return;
+  int r[64];
+  int n = amg_levels(P->amg, r, 64);
+  *n_levels = n;
+  for (int l = 0; l < n && l < cap; ++l) rows[l] = r[l];
+  if (vcycle_bytes) *vcycle_bytes = amg_vcycle_bytes(P->amg);
+}
+
 void piso_graph_info(const difvm_piso* P, long long* replays, long long* redos, long long* captures) {
   if (replays) *replays = P->g.replays;
   if (redos) *redos = P->g.redos;
   if (captures) *captures = P->g.captures;
+}
+
+// One eager step that also hands out the solution of each linear solve (user order, device arrays):
+// the predictor's U* and the pressure solved by each corrector.  The internal-order copies live in
+// buffers of the PISO object made at the first call.
+int piso_step_trace(difvm_piso* P, double* Ustar_user, double* p_user, difvm_step_stats* stats) {
+  difvm_mesh* m = P->mesh;
+  const DMesh& d = m->d;
+  size_t nc = d.nc;
+  if (!P->trace_buf) P->trace_buf = piso_alloc(P, 3 * nc + (size_t)StepRecord::MAXC * nc);
+  P->trace_U = P->trace_buf;
+  P->trace_p = P->trace_buf + 3 * nc;
+  difvm_step_stats st{};
+  try {
+    piso_advance(P, &st, nullptr);
+  } catch (...) {
+    P->trace_U = P->trace_p = nullptr;
+    throw;
+  }
+  P->trace_U = P->trace_p = nullptr;
+  permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->trace_buf, Ustar_user);
+  for (int c = 0; c < P->prm.n_corr; ++c)
+    permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, P->trace_buf + 3 * nc + (size_t)c * nc,
+            p_user + (size_t)c * nc);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+  if (stats) *stats = st;
+  return st.status;
 }
 
 int piso_step(difvm_piso* P, int nsteps, difvm_step_stats* stats) {

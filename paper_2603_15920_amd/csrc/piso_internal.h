@@ -38,6 +38,13 @@ struct difvm_piso {
   difvm::AmgDev* amg = nullptr;  // pressure preconditioner hierarchy (built at the first AMG solve)
   int refs = 1;                 // the caller's handle plus one per tape
   PisoGraph g;
+  // when set, the step copies the solution of each linear solve here (internal order): the
+  // predictor's U* [nc*3] and the pressure after each corrector [n_corr][nc]
+  double* trace_U = nullptr;
+  double* trace_p = nullptr;
+  double* trace_buf = nullptr;  // backing buffer of difvm_piso_step_trace (made at its first call)
+  // iterations of the last solve per call site (sizes the first unpolled block of the next one)
+  int hint_u = 0, hint_p[8] = {}, hint_sc = 0, hint_adj_u = 0, hint_adj_p[8] = {};
 };
 
 

@@ -44,12 +44,14 @@ __global__ void k_fill(T* __restrict__ a, size_t n, T v) {
 struct Scratch {
   void *phi = nullptr, *phib = nullptr, *flux = nullptr, *g = nullptr, *out = nullptr, *diag = nullptr, *up = nullptr;
   std::vector<void*> all;
+  const Ctx* ctx;
+  explicit Scratch(const Ctx& c) : ctx(&c) {}
   ~Scratch() {
-    for (void* a : all) dfree(a);
+    for (void* a : all) dfree(*ctx, a);
   }
   template <class T>
   void* make(size_t n, hipStream_t s) {
-    T* a = dalloc<T>(n);
+    T* a = dalloc<T>(*ctx, n);
     all.push_back(a);
     size_t m = n ? n : 1;
     k_fill<T><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(a, m, T(1));
@@ -146,7 +148,7 @@ int tune(difvm_mesh* m, const char* cache_path) {
   DIFVM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   int timed = 0;
   try {
-    Scratch S64, S32;
+    Scratch S64(ctx_of(m)), S32(ctx_of(m));
     bool made64 = false, made32 = false;
     for (int k = 0; k < DIFVM_TUNE_COUNT; ++k) {
       std::string key = prefix + KNOB_NAME[k] + suffix;
