@@ -75,6 +75,10 @@ def op_bytes(op, nfi, nfb, nc, fp):
         return nfi * (2 * i4 + fp) + nc * 3 * fp
     if op == "interp":
         return nfi * (2 * i4 + fp + fp) + nfb * (i4 + fp + fp) + nc * fp
+    if op == "pcg_spmv":
+        # the PCG product with its fused direction update p_k = z + beta p_(k-1): per face O, N and the
+        # symmetric coefficient; per cell diag, z and p_(k-1) read, p_k and q = K p_k written
+        return nfi * (2 * i4 + fp) + nc * 5 * fp
     raise KeyError(op)
 
 
@@ -326,6 +330,53 @@ def tube_run(B, mg, torch, ctx, steps, precond="amg"):
     return out
 
 
+def halo_run(B, mg, torch, ctx, n_parts=8, part=3, reps=50):
+    """The part of a single-mesh multi-GPU run that one GPU can show: the 1,999,872-tet tube split into
+    n_parts RCM slabs; on one interior slab (one GPU's share) the pack and unpack kernels of one halo
+    exchange (scalar and 3-vector rows) and the operators on the slab's cells plus ghosts, all timed
+    with HIP events (average over reps back-to-back launches, warm).  The transfer between GPUs is not
+    run (one GPU); its volume is reported."""
+    import numpy as np
+    t0 = time.time()
+    m = mg.tube()
+    Pt = B.Partition(m, n_parts)
+    pm = B.PartMesh(ctx, Pt, part)
+    info = pm.part
+    log(f"halo: {n_parts} slabs of the {m.n_cells}-cell tube ready ({time.time() - t0:.1f}s)", info)
+    nl = pm.info["n_cells"]
+    tm = HipTimer(torch.cuda.current_stream())
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+
+    def avg_us(fn):
+        fn()
+        tm.start()
+        for _ in range(reps):
+            fn()
+        return round(tm.stop_s() / reps * 1e6, 2)
+
+    out = {"workload": f"tube {m.n_cells} tets in {n_parts} RCM slabs; slab {part} (interior)",
+           "owned_cells": info["n_owned"], "ghost_cells": info["n_ghost"], "sent_rows": info["n_send"],
+           "neighbour_slabs": info["n_neighbours"], "local_internal_faces": info["n_internal_faces"],
+           "exchange_bytes_scalar_f64": 8 * info["n_ghost"], "exchange_bytes_vector_f64": 24 * info["n_ghost"]}
+    for ncomp, tag in ((1, "scalar"), (3, "vector")):
+        x = torch.rand((nl, ncomp) if ncomp > 1 else nl, **f64)
+        sb = torch.empty((info["n_send"], ncomp) if ncomp > 1 else info["n_send"], **f64)
+        rb = torch.rand((info["n_ghost"], ncomp) if ncomp > 1 else info["n_ghost"], **f64)
+        out[f"pack_{tag}_us"] = avg_us(lambda: pm.pack(x, sb))
+        out[f"unpack_{tag}_us"] = avg_us(lambda: pm.unpack(rb, x))
+    phi = torch.rand(nl, **f64)
+    phib = torch.rand(info["n_boundary_faces"], **f64)
+    g = torch.empty((nl, 3), **f64)
+    o1 = torch.empty(nl, **f64)
+    out["grad_us"] = avg_us(lambda: B.difvm_op_grad(pm.h, 1, B.BC_ALL_FIXED, phi, phib, g))
+    out["laplacian_us"] = avg_us(lambda: B.difvm_op_laplacian(pm.h, B.BC_ALL_FIXED, None, phi, g, phib, o1))
+    A = B.ldu(torch.full((nl,), 6.0, **f64), -torch.rand(info["n_internal_faces"], **f64))
+    out["spmv_sym_us"] = avg_us(lambda: B.difvm_ldu_spmv(pm.h, 1, 0, A, phi, o1))
+    pm.close()
+    Pt.close()
+    return out
+
+
 def small_case(B, mg, torch, ctx, steps=50, precond="amg"):
     """The small PISO case (lid-driven cavity, 2048 jittered triangle prisms, Re 100, nu 0.01,
     dt 1e-3): launch-bound, so eager stepping against graph mode."""
@@ -356,7 +407,7 @@ def small_case(B, mg, torch, ctx, steps=50, precond="amg"):
     return out
 
 
-def adjoint_window(B, mg, torch, ctx, steps, every, spinup=10, precond="amg"):
+def adjoint_window(B, mg, torch, ctx, steps, every, spinup=50, precond="amg"):
     """Differentiated form on the Y-bifurcation (~400k tets, 3 Windkessel outlets, nu 1e-3, dt 1e-3):
     after a short spin-up from rest, the plain forward, the recorded forward (checkpoints every
     `every` steps) and the reverse sweep (recomputation of each checkpoint segment plus its adjoint
@@ -471,7 +522,18 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps, precond="amg"):
 
 
 def cpu_info():
+    """CPU model from lscpu (else /proc/cpuinfo) and the host threads available to this process."""
     model = ""
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model:
+        return f"{model} ({len(os.sched_getaffinity(0))} threads available)"
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -495,18 +557,19 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson verification workload")
     ap.add_argument("--no-tube", action="store_true", help="skip the 2M-cell tube PISO run")
-    ap.add_argument("--tube-steps", type=int, default=10)
+    ap.add_argument("--tube-steps", type=int, default=50)
+    ap.add_argument("--no-halo", action="store_true", help="skip the slab-partition halo measurement")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode measurements")
     ap.add_argument("--graph-extra", type=str, default="16",
                     help="graph mode's iteration margin per solve; several, comma-separated, time one window each")
     ap.add_argument("--precond", choices=["jacobi", "amg"], default="amg",
                     help="pressure preconditioner of the timed PISO steps")
     ap.add_argument("--no-other", action="store_true", help="skip the run with the other pressure preconditioner")
-    ap.add_argument("--adj-steps", type=int, default=20)
+    ap.add_argument("--adj-steps", type=int, default=100)
     ap.add_argument("--adj-every", type=int, default=10)
     ap.add_argument("--batch-members", type=int, default=64)
-    ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--batch-adj-steps", type=int, default=10)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-adj-steps", type=int, default=20)
     ap.add_argument("--prof-every", type=int, default=16,
                     help="time every n-th launch of each PCG kernel with HIP events in the timed region")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -569,6 +632,12 @@ def main():
             first_iters = it[0].tolist()
         log(f"warmup step {k}: {time.time() - ts:.3f}s iters {it[0].tolist()} status {st}")
 
+    # the state the timed region starts from (the CPU oracle is timed on the step from it)
+    state0 = None
+    if not args.no_cpu:
+        U_s, p_s, phi_s, pc_s = P.get_state()
+        state0 = (U_s.cpu().numpy(), p_s.cpu().numpy(), phi_s.cpu().numpy(), np.array(pc_s, dtype=np.float64))
+        del U_s, p_s, phi_s
     # timed region: eager steps, HIP events around every prof_every-th launch of each PCG kernel
     B.difvm_ctx_profile(ctx.h, args.prof_every)
     B.difvm_ctx_profile_read(ctx.h)
@@ -589,7 +658,7 @@ def main():
     name = "pcg_spmv_dot"
     launches, total_ms = prof.get(name, (0, 0.0))  # every prof_every-th launch, HIP events
     avg_s = total_ms * 1e-3 / max(launches, 1)
-    alg = op_bytes("spmv_sym", nfi, nfb, nc, 8)
+    alg = op_bytes("pcg_spmv", nfi, nfb, nc, 8)
     achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
     traffic = counter_traffic(PCG_SPMV_COUNTERS)
     roofline = {"bound": "hbm", "kernel": "k_pcg_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -597,6 +666,18 @@ def main():
                 "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
                 "timed_every": args.prof_every, "active_iterations": int(pcg_iters)}
     kernel_us = {k: round(1e3 * v[1] / max(v[0], 1), 2) for k, v in prof.items()}
+    vcycle = None
+    if args.precond == "amg" and "pcg_amg_vcycle" in prof:
+        # the preconditioner phase as a whole: one V-cycle's algorithmic bytes (library accounting,
+        # difvm_piso_precond_info) over the HIP-event time of one V-cycle (all its kernels)
+        levels, vbytes = B.difvm_piso_precond_info(P.h)
+        vl, vms = prof["pcg_amg_vcycle"]
+        v_s = vms * 1e-3 / max(vl, 1)
+        vcycle = {"bound": "hbm", "phase": "AMG V-cycle (all kernels of one application)", "levels": levels,
+                  "alg_bytes_per_vcycle": int(vbytes), "avg_vcycle_us": round(v_s * 1e6, 2),
+                  "achieved": round(vbytes / v_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(vbytes / v_s / 1e9 / HBM_PEAK_GBS, 4), "timed_vcycles": vl}
+        log("v-cycle roofline", vcycle)
 
     # passive scalar carried by the flow of the last step (D = 1e-4, zeroGradient walls and outlet)
     scalar = None
@@ -630,6 +711,10 @@ def main():
     if not args.no_tube:
         tube = tube_run(B, mg, torch, ctx, args.tube_steps, precond=args.precond)
         log("tube", tube)
+    halo = None
+    if not args.no_halo:
+        halo = halo_run(B, mg, torch, ctx)
+        log("halo", halo)
     poisson = None
     if not args.no_poisson:
         poisson = poisson_run(B, mg, torch, ctx)
@@ -650,16 +735,33 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        from oracle import build as OB
         from oracle import oracle as O
         oprm = O.piso_params(nu, dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
-        phi0 = O.initial_flux(m, U0, Ub)
-        tc = time.time()
-        r = O.piso_run(m, oprm, U0, p0, phi0, Ub, np.zeros(nfb), wk=np.array([wk]), pc=np.zeros(1), nsteps=1)
-        tcpu = time.time() - tc
-        cpu = {"value": round(1.0 / tcpu, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"first PISO step from rest on the same mesh and setup (oracle iterations {r[4][0].tolist()}); "
-                         f"the GPU's first warm-up step took {first_step_s:.4f}s with iterations {first_iters}",
-               "seconds": round(tcpu, 2), "cpu_model": cpu_info(), "gpu_first_step_s": round(first_step_s, 4)}
+        legs = {}
+        for variant in ("omp", "serial"):
+            O.use_threads(variant == "omp")
+            nthr = O.threads()
+            tc = time.time()
+            r = O.piso_run(m, oprm, state0[0], state0[1], state0[2], Ub, np.zeros(nfb), wk=np.array([wk]),
+                           pc=state0[3], nsteps=1)
+            legs[variant] = {"seconds": round(time.time() - tc, 3), "threads": nthr, "iters": r[4][0].tolist(),
+                             "status": int(r[6])}
+            log(f"cpu oracle ({variant})", legs[variant])
+        O.use_threads(False)
+        om = legs["omp"]
+        cpu = {"value": round(1.0 / om["seconds"], 5), "unit": "steps/s", "cores": om["threads"], "kind": "oracle",
+               "sample": f"one PISO step of the oracle from the GPU's state at the start of the timed region (step "
+                         f"{args.warmup + 1} of the run: same mesh, physics and tolerances); the oracle's pressure "
+                         f"CG is Jacobi-preconditioned (it has no AMG), so it iterates more: oracle iterations "
+                         f"{om['iters']} against the GPU's {it[0].tolist()} on that step",
+               "seconds": om["seconds"],
+               "single_core": {"value": round(1.0 / legs["serial"]["seconds"], 5), "cores": 1,
+                               "seconds": legs["serial"]["seconds"]},
+               "threading": "OpenMP over the Krylov kernels (LDU product and dot products: contiguous face and "
+                            "cell ranges per thread, partial sums added in thread order)",
+               "cpu_model": cpu_info(), "compiler": OB.compiler_version(),
+               "flags": "-O2 -fno-fast-math -ffp-contract=off (-fopenmp)"}
         log("cpu oracle", cpu)
 
     line = {
@@ -683,6 +785,7 @@ def main():
         "small_case": small,
         "scalar_transport": scalar,
         "tube": tube,
+        "halo": halo,
         "poisson": poisson,
         "adjoint": adjoint,
         "batched": batched,

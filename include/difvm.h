@@ -224,6 +224,61 @@ difvm_status difvm_mesh_create_segments(difvm_ctx* ctx, const difvm_mesh_desc* d
 difvm_status difvm_mesh_get_info(const difvm_mesh* mesh, difvm_mesh_info* info);
 difvm_status difvm_mesh_destroy(difvm_mesh* mesh); /* NULL is a no-op; waits for the stream */
 
+/* ---- slab partition and halo exchange ------------------------------------------------------
+ * The paper runs one mesh per GPU and leaves multi-GPU partitioning to future work (Sec.
+ * "Limitations and Future Work").  These calls hold the part of that design that one GPU can run: a
+ * partition of one mesh into n_parts slabs, each slab's mesh with ghost copies of the cells across
+ * its cut faces, and the pack / unpack of one exchange.  The transfer between GPUs (RCCL send/recv
+ * or a peer copy of each send segment into the matching receive segment) is the caller's.
+ *
+ * Part p owns the internal (renumbered) cells [cell_lo, cell_hi) of the whole mesh, with cell_lo =
+ * floor(p Nc / n_parts): RCM ranges are slabs across the mesh.  Its local cell order is the owned
+ * cells in whole-mesh order, then the ghosts in ascending whole-mesh index.  Its internal faces are
+ * those of the whole mesh with an owned side (whole-mesh orientation and order), its boundary faces
+ * those of its owned cells (patch order kept).  Every owned cell keeps its whole-mesh row (the same
+ * faces in the same order), so once the ghost rows hold the current values, the owned rows of
+ * every operator (difvm_op_*, difvm_ldu_spmv, difvm_ldu_assemble_laplace) equal the whole mesh's
+ * rows bit for bit; ghost rows of the outputs are not meaningful.  Part meshes take fields in their
+ * local order (difvm_permute is the identity on them).  Solvers, AMG and PISO objects need
+ * reductions over the whole mesh and refuse part meshes (DIFVM_ERR_UNSUPPORTED). */
+typedef struct difvm_partition difvm_partition;
+typedef struct {
+  int32_t n_parts;
+  int32_t cell_lo, cell_hi;                    /* owned cells, whole-mesh internal numbering          */
+  int32_t n_owned, n_ghost;                    /* local cells: n_owned + n_ghost                      */
+  int32_t n_internal_faces, n_boundary_faces;  /* local faces                                         */
+  int32_t n_send;                              /* rows this part sends per exchange, all destinations */
+  int32_t n_neighbours;                        /* parts it sends to or receives from                  */
+} difvm_part_info;
+
+/* Renumbers the mesh as difvm_mesh_create does (same flags) and splits it into n_parts slabs (host
+ * only, no device needed).  Errors as difvm_mesh_create; DIFVM_ERR_INVALID_ARG unless 1 <= n_parts
+ * <= Nc. */
+difvm_status difvm_partition_create(const difvm_mesh_desc* desc, uint32_t flags, int32_t n_parts,
+                                    difvm_partition** out);
+difvm_status difvm_partition_destroy(difvm_partition* part); /* NULL is a no-op */
+difvm_status difvm_partition_info(const difvm_partition* part, int32_t p, difvm_part_info* info);
+/* Host maps of part p (each output may be NULL): cell_global[n_owned+n_ghost] (local cell -> whole-
+ * mesh internal cell), face_global[n_internal_faces] and bface_global[n_boundary_faces] (local ->
+ * whole-mesh internal face, boundary index within the boundary block), recv_start[n_parts+1] (the
+ * ghosts owned by part q are local ghost rows [recv_start[q], recv_start[q+1]) after the owned
+ * rows), send_start[n_parts+1] and send_cells[n_send] (local owned rows sent to part q:
+ * send_cells[send_start[q] .. send_start[q+1]), in the receiving part's ghost order).  So the
+ * receive buffer of one exchange, in ghost order, takes from part q's send buffer the rows
+ * [send_start_q[p], send_start_q[p+1]) at rows [recv_start_p[q], recv_start_p[q+1]).  Errors:
+ * DIFVM_ERR_INVALID_ARG for p out of range. */
+difvm_status difvm_partition_maps(const difvm_partition* part, int32_t p, int32_t* cell_global,
+                                  int32_t* face_global, int32_t* bface_global, int32_t* recv_start,
+                                  int32_t* send_start, int32_t* send_cells);
+/* Uploads part p as a mesh of ctx (synchronises).  The partition may be destroyed afterwards. */
+difvm_status difvm_mesh_create_part(difvm_ctx* ctx, const difvm_partition* part, int32_t p, difvm_mesh** out);
+/* One exchange on the mesh's stream (device arrays, rows of ncomp values, dtype DIFVM_F64/F32):
+ * pack writes send_buf[n_send*ncomp] = the sent rows of x[(n_owned+n_ghost)*ncomp]; unpack copies
+ * recv_buf[n_ghost*ncomp] (ghost order) into the ghost rows of x.  Errors: DIFVM_ERR_INVALID_ARG on a
+ * mesh that is not a part, ncomp outside 1..9 or NULL buffers where rows are moved. */
+difvm_status difvm_halo_pack(const difvm_mesh* mesh, int dtype, int ncomp, const void* x, void* send_buf);
+difvm_status difvm_halo_unpack(const difvm_mesh* mesh, int dtype, int ncomp, const void* recv_buf, void* x);
+
 /* ---- launch tuning (autotuner) ------------------------------------------------------------
  * Knobs that change how work is spread over the GPU but not what any output computes: threads per
  * block of the operator kernels (one cell or face per thread, no reductions), and the grid of the

@@ -64,6 +64,11 @@ class MeshInfo(C.Structure):
                                           "n_segments")]
 
 
+class PartInfo(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_parts", "cell_lo", "cell_hi", "n_owned", "n_ghost", "n_internal_faces",
+                                          "n_boundary_faces", "n_send", "n_neighbours")]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("total_ms", C.c_double)]
 
@@ -104,6 +109,13 @@ _SIGS = {
     "difvm_mesh_create_segments": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.c_int32, _i32p,
                                                C.POINTER(_vp)]),
     "difvm_mesh_get_info": (C.c_int32, [_vp, C.POINTER(MeshInfo)]),
+    "difvm_partition_create": (C.c_int32, [C.POINTER(MeshDesc), C.c_uint32, C.c_int32, C.POINTER(_vp)]),
+    "difvm_partition_destroy": (C.c_int32, [_vp]),
+    "difvm_partition_info": (C.c_int32, [_vp, C.c_int32, C.POINTER(PartInfo)]),
+    "difvm_partition_maps": (C.c_int32, [_vp, C.c_int32] + [_i32p] * 6),
+    "difvm_mesh_create_part": (C.c_int32, [_vp, _vp, C.c_int32, C.POINTER(_vp)]),
+    "difvm_halo_pack": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp]),
+    "difvm_halo_unpack": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp]),
     "difvm_mesh_set_launch": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
     "difvm_mesh_get_launch": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_int32)]),
     "difvm_tune": (C.c_int32, [_vp, C.c_char_p, C.POINTER(C.c_int32)]),
@@ -341,6 +353,53 @@ def difvm_mesh_create_segments(ctx, mesh, seg_cell_start, flags=RENUMBER_RCM):
     _check(lib().difvm_mesh_create_segments(ctx, C.byref(h.desc), int(flags), int(starts.size - 1),
                                             starts.ctypes.data_as(_i32p), C.byref(out)), "difvm_mesh_create_segments")
     return out
+
+
+def difvm_partition_create(mesh, n_parts, flags=RENUMBER_RCM):
+    h = mesh_desc(mesh)
+    out = _vp()
+    _check(lib().difvm_partition_create(C.byref(h.desc), int(flags), int(n_parts), C.byref(out)),
+           "difvm_partition_create")
+    return out
+
+
+def difvm_partition_destroy(part):
+    _check(lib().difvm_partition_destroy(part), "difvm_partition_destroy")
+
+
+def difvm_partition_info(part, p):
+    info = PartInfo()
+    _check(lib().difvm_partition_info(part, int(p), C.byref(info)), "difvm_partition_info")
+    return {n: getattr(info, n) for n, _ in PartInfo._fields_}
+
+
+def difvm_partition_maps(part, p):
+    """Host maps of part p as numpy int32 arrays (see include/difvm.h)."""
+    info = difvm_partition_info(part, p)
+    n = info["n_parts"]
+    out = dict(cell_global=np.empty(info["n_owned"] + info["n_ghost"], np.int32),
+               face_global=np.empty(info["n_internal_faces"], np.int32),
+               bface_global=np.empty(info["n_boundary_faces"], np.int32),
+               recv_start=np.empty(n + 1, np.int32), send_start=np.empty(n + 1, np.int32),
+               send_cells=np.empty(info["n_send"], np.int32))
+    _check(lib().difvm_partition_maps(part, int(p), *[a.ctypes.data_as(_i32p) for a in out.values()]),
+           "difvm_partition_maps")
+    return out
+
+
+def difvm_mesh_create_part(ctx, part, p):
+    out = _vp()
+    _check(lib().difvm_mesh_create_part(ctx, part, int(p), C.byref(out)), "difvm_mesh_create_part")
+    return out
+
+
+def difvm_halo_pack(m, ncomp, x, send_buf):
+    return _check(lib().difvm_halo_pack(m, _dtype_code(x), int(ncomp), _ptr(x), _ptr(send_buf)), "difvm_halo_pack")
+
+
+def difvm_halo_unpack(m, ncomp, recv_buf, x):
+    return _check(lib().difvm_halo_unpack(m, _dtype_code(x), int(ncomp), _ptr(recv_buf), _ptr(x)),
+                  "difvm_halo_unpack")
 
 
 def difvm_mesh_set_launch(m, knob, value):
@@ -687,6 +746,62 @@ class Mesh:
         out = torch.empty_like(t)
         difvm_permute(self.h, ncomp, kind, FROM_INTERNAL, t.contiguous(), out)
         return out
+
+
+class Partition:
+    """Slab partition of a meshgen.Mesh for a halo exchange (host only): per part its info dict and
+    host maps (difvm_partition_info / difvm_partition_maps)."""
+
+    def __init__(self, mesh, n_parts, flags=None):
+        if flags is None:
+            flags = RENUMBER_RCM | NONORTH[mesh.meta.get("nonorth", "overrelaxed")]
+        self.src = mesh
+        self.n_parts = int(n_parts)
+        self.h = difvm_partition_create(mesh, n_parts, flags)
+        self.info = [difvm_partition_info(self.h, p) for p in range(self.n_parts)]
+        self.maps = [difvm_partition_maps(self.h, p) for p in range(self.n_parts)]
+
+    def close(self):
+        if self.h:
+            difvm_partition_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PartMesh:
+    """Part p of a Partition uploaded to the device (local order: owned cells, then ghosts)."""
+
+    def __init__(self, ctx, partition, p):
+        self.ctx = ctx
+        self.p = int(p)
+        self.part = partition.info[p]
+        self.maps = partition.maps[p]
+        self.h = difvm_mesh_create_part(ctx.h, partition.h, p)
+        self.info = difvm_mesh_get_info(self.h)
+
+    def pack(self, x, send_buf):
+        ncomp = 1 if x.dim() == 1 else int(np.prod(x.shape[1:]))
+        difvm_halo_pack(self.h, ncomp, x, send_buf)
+
+    def unpack(self, recv_buf, x):
+        ncomp = 1 if x.dim() == 1 else int(np.prod(x.shape[1:]))
+        difvm_halo_unpack(self.h, ncomp, recv_buf, x)
+
+    def close(self):
+        if self.h:
+            difvm_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Piso:

@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libdifvm.so")
 ARCH = os.environ.get("DIFVM_OFFLOAD_ARCH", "gfx950")
 HIP_SOURCES = ["abi.hip", "ops.hip", "krylov.hip", "amg.hip", "piso.hip", "adjoint.hip", "tune.hip"]
-HOST_SOURCES = ["mesh_host.cpp", "amg_host.cpp"]
+HOST_SOURCES = ["mesh_host.cpp", "amg_host.cpp", "partition.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

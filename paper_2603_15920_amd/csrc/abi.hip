@@ -109,6 +109,12 @@ void piso_precond_info(const difvm_piso* P, int32_t* n_levels, int32_t* rows, in
 void piso_rebuild_preconditioner(difvm_piso* P);
 
 static void check_mesh(const difvm_mesh* m) { DIFVM_CHECK(m != nullptr, DIFVM_ERR_INVALID_ARG, "mesh is NULL"); }
+// solvers reduce over every cell of the mesh: a partition part (ghost rows included, no exchange
+// inside the iteration) is refused
+static void check_whole(const difvm_mesh* m) {
+  DIFVM_CHECK(m->part_n_owned < 0, DIFVM_ERR_UNSUPPORTED,
+              "solves and PISO steps run on a whole mesh, not on a partition part");
+}
 static void check_dtype(int dtype) {
   DIFVM_CHECK(dtype == DIFVM_F64 || dtype == DIFVM_F32, DIFVM_ERR_INVALID_ARG, "dtype must be DIFVM_F64 or DIFVM_F32");
 }
@@ -252,6 +258,11 @@ void mesh_release(difvm_mesh* m) {
 
 using namespace difvm;
 
+struct difvm_partition {
+  HostLayout G;                 // the whole mesh, renumbered, with its cell-slot layout
+  std::vector<PartMaps> parts;
+};
+
 extern "C" {
 
 int difvm_abi_version(void) { return DIFVM_ABI_VERSION; }
@@ -374,6 +385,118 @@ difvm_status difvm_mesh_create_segments(difvm_ctx* ctx, const difvm_mesh_desc* d
     throw;
   }
   *out = m;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_partition_create(const difvm_mesh_desc* desc, uint32_t flags, int32_t n_parts,
+                                    difvm_partition** out) {
+  DIFVM_API_BEGIN
+  check_ptr(out, "out");
+  difvm_partition* P = new difvm_partition();
+  try {
+    build_layout(desc, flags, P->G, true);
+    build_partition(P->G, n_parts, P->parts);
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  *out = P;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_partition_destroy(difvm_partition* P) {
+  delete P;
+  return DIFVM_OK;
+}
+
+static const PartMaps& part_maps(const difvm_partition* P, int32_t part) {
+  DIFVM_CHECK(P != nullptr, DIFVM_ERR_INVALID_ARG, "partition is NULL");
+  DIFVM_CHECK(part >= 0 && part < (int32_t)P->parts.size(), DIFVM_ERR_INVALID_ARG, "part out of range");
+  return P->parts[part];
+}
+
+difvm_status difvm_partition_info(const difvm_partition* P, int32_t part, difvm_part_info* info) {
+  DIFVM_API_BEGIN
+  const PartMaps& M = part_maps(P, part);
+  check_ptr(info, "info");
+  info->n_parts = (int32_t)P->parts.size();
+  info->cell_lo = M.lo;
+  info->cell_hi = M.hi;
+  info->n_owned = M.n_owned;
+  info->n_ghost = M.n_ghost;
+  info->n_internal_faces = (int32_t)M.face_global.size();
+  info->n_boundary_faces = (int32_t)M.bface_global.size();
+  info->n_send = (int32_t)M.send_cells.size();
+  int nb = 0;
+  for (size_t q = 0; q + 1 < M.recv_start.size(); ++q)
+    nb += (M.recv_start[q + 1] > M.recv_start[q] || M.send_start[q + 1] > M.send_start[q]) ? 1 : 0;
+  info->n_neighbours = nb;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_partition_maps(const difvm_partition* P, int32_t part, int32_t* cell_global, int32_t* face_global,
+                                  int32_t* bface_global, int32_t* recv_start, int32_t* send_start, int32_t* send_cells) {
+  DIFVM_API_BEGIN
+  const PartMaps& M = part_maps(P, part);
+  auto put = [](int32_t* dst, const std::vector<int32_t>& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), sizeof(int32_t) * v.size());
+  };
+  put(cell_global, M.cell_global); put(face_global, M.face_global); put(bface_global, M.bface_global);
+  put(recv_start, M.recv_start); put(send_start, M.send_start); put(send_cells, M.send_cells);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_mesh_create_part(difvm_ctx* ctx, const difvm_partition* P, int32_t part, difvm_mesh** out) {
+  DIFVM_API_BEGIN
+  const PartMaps& M = part_maps(P, part);
+  check_ptr(ctx, "ctx");
+  check_ptr(out, "out");
+  DIFVM_HIP(hipSetDevice(ctx->c.device));
+  difvm_mesh* m = new difvm_mesh();
+  m->ctx = ctx;
+  ctx->refs++;  // released by free_mesh, also on the failure path below
+  try {
+    build_part_layout(P->G, M, m->host);
+    upload_mesh(m);
+    m->part_n_owned = M.n_owned;
+    m->part_n_ghost = M.n_ghost;
+    m->part_n_send = (int)M.send_cells.size();
+    m->part_send = up_vec(m, M.send_cells);
+    DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+  } catch (...) {
+    free_mesh(m);
+    throw;
+  }
+  *out = m;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+static void check_part(const difvm_mesh* m) {
+  check_mesh(m);
+  DIFVM_CHECK(m->part_n_owned >= 0, DIFVM_ERR_INVALID_ARG, "the mesh is not a partition part");
+}
+
+difvm_status difvm_halo_pack(const difvm_mesh* m, int dtype, int ncomp, const void* x, void* send_buf) {
+  DIFVM_API_BEGIN
+  check_part(m); check_dtype(dtype);
+  DIFVM_CHECK(ncomp >= 1 && ncomp <= 9, DIFVM_ERR_INVALID_ARG, "ncomp must be in 1..9");
+  if (m->part_n_send) { check_ptr(x, "x"); check_ptr(send_buf, "send_buf"); }
+  op_halo_pack(m, dtype, ncomp, x, send_buf);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_halo_unpack(const difvm_mesh* m, int dtype, int ncomp, const void* recv_buf, void* x) {
+  DIFVM_API_BEGIN
+  check_part(m); check_dtype(dtype);
+  DIFVM_CHECK(ncomp >= 1 && ncomp <= 9, DIFVM_ERR_INVALID_ARG, "ncomp must be in 1..9");
+  if (m->part_n_ghost) { check_ptr(x, "x"); check_ptr(recv_buf, "recv_buf"); }
+  op_halo_unpack(m, dtype, ncomp, recv_buf, x);
   DIFVM_API_END
   return DIFVM_OK;
 }
@@ -529,6 +652,7 @@ static difvm_status solve_common(const difvm_mesh* cm, const difvm_ldu* A, int n
                                  int32_t maxit, difvm_solve_stats* stats, bool sym, const AmgDev* amg = nullptr) {
   difvm_mesh* m = const_cast<difvm_mesh*>(cm);
   check_mesh(m); check_ptr(A, "A"); check_ptr(b, "b"); check_ptr(x, "x"); check_ncomp(ncomp);
+  check_whole(m);
   DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "solvers are F64 only");
   check_ptr(A->diag, "A->diag");
   DIFVM_CHECK(A->upper || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper is NULL");
@@ -595,6 +719,7 @@ extern "C" {
 difvm_status difvm_amg_create(const difvm_mesh* cm, const difvm_ldu* A, difvm_amg** out) {
   DIFVM_API_BEGIN
   check_mesh(cm); check_ptr(out, "out");
+  check_whole(cm);
   difvm_mesh* m = const_cast<difvm_mesh*>(cm);
   check_sym_ldu(m, A);
   difvm_amg* a = new difvm_amg();
@@ -699,6 +824,7 @@ difvm_status difvm_piso_rebuild_preconditioner(difvm_piso* piso) {
 difvm_status difvm_piso_create(const difvm_mesh* m, const difvm_piso_params* params, difvm_piso** out) {
   DIFVM_API_BEGIN
   check_mesh(m); check_ptr(params, "params"); check_ptr(out, "out");
+  check_whole(m);
   piso_create(const_cast<difvm_mesh*>(m), params, out);
   DIFVM_API_END
   return DIFVM_OK;

@@ -150,6 +150,10 @@ struct difvm_mesh {
   int abi_hint[3] = {0, 0, 0};               // iterations of the last difvm_solve_pcg / _pcg_amg / _bicgstab
   int refs = 1;
   int tune[DIFVM_TUNE_COUNT] = {256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 0};  // launch knobs
+  // part of a slab partition (difvm_mesh_create_part): owned cells first, then ghosts; n_owned < 0
+  // for a whole mesh
+  int part_n_owned = -1, part_n_ghost = 0, part_n_send = 0;
+  int32_t* part_send = nullptr;              // device: local indices of the owned cells sent
 };
 
 namespace difvm {

@@ -65,5 +65,28 @@ constexpr int TILE = 1024;  // cells per reduction tile of the Krylov kernels
 void build_layout(const difvm_mesh_desc* d, uint32_t flags, HostLayout& L, bool with_slots, int nseg = 1,
                   const int32_t* seg_start = nullptr);
 
+// ---------------------------------------------------------------------------------------------
+// slab partition for a halo exchange: part p owns the contiguous internal cell range [lo, hi) of
+// the whole mesh (RCM order, so a slab touches few others) and keeps ghost copies of the cells
+// across its cut faces.  Local cell order: owned cells (whole-mesh order), then ghosts (ascending
+// whole-mesh index, so the ghosts each other part owns are one contiguous run).
+// ---------------------------------------------------------------------------------------------
+struct PartMaps {
+  int lo = 0, hi = 0, n_owned = 0, n_ghost = 0;
+  std::vector<int32_t> cell_global;   // local cell -> whole-mesh internal cell
+  std::vector<int32_t> face_global;   // local internal face -> whole-mesh internal face (ascending)
+  std::vector<int32_t> bface_global;  // local boundary face -> whole-mesh boundary face (ascending)
+  std::vector<int32_t> recv_start;    // [n_parts+1]: ghosts owned by part q are [recv_start[q], recv_start[q+1])
+  std::vector<int32_t> send_start;    // [n_parts+1]: cells sent to part q are send_cells[send_start[q] ..]
+  std::vector<int32_t> send_cells;    // local indices of owned cells, by destination, ascending in each
+};
+
+// Maps of every part of the whole layout G (single segment, with slots); n_parts in [1, G.nc].
+void build_partition(const HostLayout& G, int n_parts, std::vector<PartMaps>& parts);
+// Layout of one part: its owned cells keep their whole-mesh slots in the same order (so every owned
+// row is computed exactly as in the whole mesh), faces keep their whole-mesh orientation, ghost
+// cells have no slots.  Permutations are the identity: a part's fields are in its local order.
+void build_part_layout(const HostLayout& G, const PartMaps& P, HostLayout& L);
+
 
 }  // namespace difvm

@@ -14,6 +14,10 @@ void op_laplacian(const difvm_mesh* m, int dtype, int bc, const void* gamma, con
                   const void* phib, void* out);
 void op_ldu_spmv(const difvm_mesh* m, int dtype, int ncomp, int transpose, const void* diag, const void* up,
                  const void* lo, const void* x, void* y);
+// halo exchange of a partition part: buf[k] = x[send[k]] (n_send rows of ncomp), and
+// x[n_owned + k] = buf[k] for the n_ghost ghost rows
+void op_halo_pack(const difvm_mesh* m, int dtype, int ncomp, const void* x, void* buf);
+void op_halo_unpack(const difvm_mesh* m, int dtype, int ncomp, const void* buf, void* x);
 void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const double* phib, double* diag,
                          double* upper, double* rhs);
 

@@ -492,4 +492,45 @@ void op_assemble_laplace(const difvm_mesh* m, int bc, const double* gamma, const
   DIFVM_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------------------------
+// halo exchange of a partition part.  One thread per value (row-major rows of ncomp), so a wave's
+// stores to the send buffer and its loads from the receive buffer are contiguous; the pack's loads
+// gather owned rows next to the cut, which RCM keeps within a few cache lines of each other.
+// ---------------------------------------------------------------------------------------------
+template <class T>
+__global__ void k_halo_pack(int n_val, int ncomp, const int32_t* __restrict__ send, const T* __restrict__ x,
+                            T* __restrict__ buf) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_val) return;
+  int k = e / ncomp, c = e - k * ncomp;
+  buf[e] = x[(size_t)send[k] * ncomp + c];
+}
+
+template <class T>
+__global__ void k_halo_unpack(int n_val, const T* __restrict__ buf, T* __restrict__ xg) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_val) xg[e] = buf[e];
+}
+
+void op_halo_pack(const difvm_mesh* m, int dtype, int ncomp, const void* x, void* buf) {
+  int n = m->part_n_send * ncomp;
+  if (!n) return;
+  if (dtype == DIFVM_F64)
+    k_halo_pack<double><<<grid_for(n), BLOCK, 0, stream_of(m)>>>(n, ncomp, m->part_send, (const double*)x, (double*)buf);
+  else
+    k_halo_pack<float><<<grid_for(n), BLOCK, 0, stream_of(m)>>>(n, ncomp, m->part_send, (const float*)x, (float*)buf);
+  DIFVM_HIP(hipGetLastError());
+}
+
+void op_halo_unpack(const difvm_mesh* m, int dtype, int ncomp, const void* buf, void* x) {
+  int n = m->part_n_ghost * ncomp;
+  if (!n) return;
+  size_t off = (size_t)m->part_n_owned * ncomp;
+  if (dtype == DIFVM_F64)
+    k_halo_unpack<double><<<grid_for(n), BLOCK, 0, stream_of(m)>>>(n, (const double*)buf, (double*)x + off);
+  else
+    k_halo_unpack<float><<<grid_for(n), BLOCK, 0, stream_of(m)>>>(n, (const float*)buf, (float*)x + off);
+  DIFVM_HIP(hipGetLastError());
+}
+
 }  // namespace difvm
