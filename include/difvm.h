@@ -517,13 +517,15 @@ difvm_status difvm_piso_transport_scalar(difvm_piso* piso, double D, int32_t bc,
 /* Graph mode (the paper runs its time loop as one compiled scan, Sec. 2.4; here the step is a
  * replayed hipGraph).  With enable != 0, the first difvm_piso_step step after this call runs eagerly
  * and records its Krylov iteration counts; the whole step (Windkessel, assembly, BiCGStab, every
- * corrector) is then captured once on a private stream with a budget per solve of the largest count
- * of its kind (BiCGStab components, or pressure correctors) plus extra_iters (>= 0) plus 1/16 of that
- * count, and each later step is one hipGraphLaunch on the context's stream followed by
- * one read of the solvers' states.  Iterations past a solve's stop are predicated no-ops, so results
- * are bitwise those of eager stepping.  A step in which some solve had not stopped within its budget
- * is discarded (its starting state, saved by the graph, is restored on the device) and run eagerly;
- * the graph is then recaptured with the larger counts.  enable = 0 returns to eager stepping.
+ * corrector) is then captured once on a private stream with a budget per solve: the largest count of
+ * its kind (BiCGStab components, or pressure correctors) over the last 8 steps, plus a margin, plus
+ * 1/64 of that count.  Each later step is one hipGraphLaunch on the context's stream followed by one
+ * read of the solvers' states.  Iterations past a solve's stop are predicated no-ops, so results are
+ * bitwise those of eager stepping.  A step in which some solve had not stopped within its budget is
+ * discarded (its starting state, saved by the graph, is restored on the device) and run eagerly; the
+ * margin grows by one and the graph is recaptured with the larger counts.  The margin starts at
+ * min(2, extra_iters) and never exceeds extra_iters (>= 0); when the recent counts fall two or more
+ * below the budgets the step is recaptured with tighter ones.  enable = 0 returns to eager stepping.
  * Changing boundary values, Windkessel parameters, viscosity or the state between steps is allowed
  * (the graph reads the device buffers).  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */
 difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extra_iters);
@@ -584,6 +586,26 @@ difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm
 difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* gU_N, const void* gp_N,
                                 const void* gphi_N, const double* gpc_N_host, double adj_tol, void* gU_0, void* gp_0,
                                 void* gphi_0, double* gpc_0_host, double* gwk_host);
+
+/* Graph mode of the reverse sweep (the paper differentiates its time loop as one compiled scan, Sec.
+ * "Computational Efficiency"; here the checkpoint segments are replayed hipGraphs).  With enable != 0,
+ * difvm_piso_adjoint runs each segment of ckpt_every steps as two graphs: the recomputation of the
+ * segment from its checkpoint (forward steps with their records) and its reverse sweep (the adjoint
+ * steps, last first).  The first full segment runs eagerly and records the Krylov counts; both
+ * graphs are then captured with a budget per solve kind (momentum, pressure) of the segment's largest
+ * count plus a margin plus 1/64 of that count, and each later full segment is two hipGraphLaunches
+ * and one read of the solvers' states per graph.  Iterations past a solve's stop are predicated
+ * no-ops, so results are bitwise those of the eager sweep.  A replay in which some solve had not
+ * stopped within its budget is discarded (the recomputation restarts from the checkpoint; the reverse
+ * sweep restores the cotangents saved by the graph's first nodes), run eagerly, and the graph is
+ * recaptured with the margin widened by one; when the counts fall two or more below the budgets the
+ * graph is recaptured with tighter ones.  The margin starts at min(2, extra_iters) and never exceeds
+ * extra_iters (>= 0).  A shorter last segment (nsteps not a multiple of ckpt_every) runs eagerly, and a
+ * new adj_tol recaptures the reverse graph.  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */
+difvm_status difvm_tape_set_graph(difvm_tape* tape, int32_t enable, int32_t extra_iters);
+/* Graph-mode counters of the tape since creation: replayed graphs (two per full segment after the
+ * first), discarded-and-redone segments, captures. */
+difvm_status difvm_tape_graph_info(const difvm_tape* tape, int64_t* replays, int64_t* redos, int64_t* captures);
 
 /* Cotangent of the fixed velocity boundary values U_b of the window from the last difvm_piso_adjoint
  * on this tape (the boundary values are inputs of every step; their cotangent is summed over the

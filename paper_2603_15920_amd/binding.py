@@ -158,6 +158,8 @@ _SIGS = {
     "difvm_piso_forward_record": (C.c_int32, [_vp, _vp, C.POINTER(StepStats)]),
     "difvm_piso_adjoint": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _f64p, C.c_double, _vp, _vp, _vp, _f64p, _f64p]),
     "difvm_tape_boundary_cotangent": (C.c_int32, [_vp, _vp]),
+    "difvm_tape_set_graph": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "difvm_tape_graph_info": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
 }
 
 
@@ -661,6 +663,17 @@ def difvm_piso_forward_record(p, t, nsteps, n_corr=2):
 
 def difvm_tape_boundary_cotangent(t, gU_b):
     return _check(lib().difvm_tape_boundary_cotangent(t, _ptr(gU_b)), "difvm_tape_boundary_cotangent")
+
+
+def difvm_tape_set_graph(t, enable=True, extra_iters=16):
+    _check(lib().difvm_tape_set_graph(t, int(bool(enable)), int(extra_iters)), "difvm_tape_set_graph")
+
+
+def difvm_tape_graph_info(t):
+    """(replays, redos, captures) of the tape's graph mode."""
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().difvm_tape_graph_info(t, C.byref(a), C.byref(b), C.byref(c)), "difvm_tape_graph_info")
+    return a.value, b.value, c.value
 
 
 def difvm_piso_adjoint(p, t, gU_N, gp_N, gphi_N, gpc_N, adj_tol, gU_0, gp_0, gphi_0, n_wk):

@@ -508,6 +508,35 @@ __global__ __launch_bounds__(BLOCK) void k_adj_wk_spread(int nfi, const int32_t*
   for (int q = wk_start[j] + threadIdx.x; q < wk_start[j + 1]; q += BLOCK) phibar[nfi + wk_faces[q]] += Qbar[j];
 }
 
+// Windkessel reverse of one step, one thread per outlet.  Forward: E = exp(-dt/(Rd C)),
+// p_c' = p_c E + Rd Q (1 - E), p_o = p_c' + Rp Q.  In: pobar_Qbar[j] = cotangent of p_o (summed over
+// the outlet's faces), pcbar[j] = cotangent of p_c'.  Out: pcbar[j] = cotangent of p_c, wkbar[3j..]
+// += cotangents of (Rp, C, Rd), pobar_Qbar[j] = cotangent of Q.
+__global__ void k_adj_wk_step(int nwk, double dt, const double* __restrict__ wk, const double* __restrict__ wk_out,
+                              const double* __restrict__ pc_in, double* __restrict__ pobar_Qbar,
+                              double* __restrict__ pcbar, double* __restrict__ wkbar) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nwk) return;
+  double Rp = wk[3 * j], Cc = wk[3 * j + 1], Rd = wk[3 * j + 2];
+  double Q = wk_out[2 * j], pc0 = pc_in[j];
+  double E = exp(-dt / (Rd * Cc));
+  double pob = pobar_Qbar[j];
+  double pc1bar = pcbar[j] + pob;  // p_o = p_c' + Rp Q
+  double Qb = pob * Rp + pc1bar * Rd * (1.0 - E);
+  double Eb = pc1bar * (pc0 - Rd * Q);
+  wkbar[3 * j] += pob * Q;
+  wkbar[3 * j + 1] += Eb * E * dt / (Rd * Cc * Cc);
+  wkbar[3 * j + 2] += pc1bar * Q * (1.0 - E) + Eb * E * dt / (Rd * Rd * Cc);
+  pcbar[j] = pc1bar * E;
+  pobar_Qbar[j] = Qb;
+}
+
+// clears n doubles (a kernel, not a memset, so the reverse sweep can be captured)
+__global__ void k_zero(size_t n, double* __restrict__ a) {
+  size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
 __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) y[i] += a * x[i];
@@ -533,7 +562,25 @@ struct difvm_tape {
   double* Ubbar = nullptr;  // cotangent of the fixed velocity boundary values, summed over the window [nfb*3]
   double *endU = nullptr, *endp = nullptr, *endphi = nullptr;
   std::vector<double> endpc;
+  double *pcbar = nullptr, *wkacc = nullptr;  // device: capacitor and parameter cotangents [n_wk], [3 n_wk]
   std::vector<void*> allocs;
+  // Graph mode of the reverse sweep: each full checkpoint segment is recomputed by one replayed graph
+  // (graph 0: `every` forward steps with their records) and reversed by another (graph 1: `every`
+  // reverse steps), with a budget per solve kind as in the forward graph mode.
+  struct Graph {
+    bool on = false;
+    int extra = 16, margin = 2;
+    hipStream_t cap = nullptr;
+    hipGraph_t g[2] = {nullptr, nullptr};
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+    int bud_u[2] = {0, 0}, bud_p[2] = {0, 0};
+    double tol = -1.0;                 // adjoint tolerance the reverse graph was captured with
+    void* state_dev = nullptr;         // solver states of one segment: [graph][step][momentum, correctors]
+    void* state_host = nullptr;
+    size_t bytes_u = 0, bytes_p = 0, per_step = 0;
+    double* backup = nullptr;          // cotangents entering a reverse segment
+    long long replays = 0, redos = 0, captures = 0;
+  } gr;
 };
 
 namespace difvm {
@@ -546,7 +593,9 @@ static double* tape_alloc(difvm_tape* T, size_t n) {
 }
 
 static void zero(double* a, size_t n, hipStream_t s) {
-  if (n) DIFVM_HIP(hipMemsetAsync(a, 0, sizeof(double) * n, s));
+  if (!n) return;
+  k_zero<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(n, a);
+  DIFVM_HIP(hipGetLastError());
 }
 
 static void host_pc(difvm_piso* P, std::vector<double>& out) {
@@ -613,6 +662,7 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk); T->Ubbar = tape_alloc(T, 3 * (size_t)d.nfb);
     if (P->prm.conv != DIFVM_CONV_UPWIND) T->gUn = tape_alloc(T, 9 * nc);
     T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
+    T->pcbar = tape_alloc(T, nwk); T->wkacc = tape_alloc(T, 3 * (size_t)nwk);
   } catch (...) {
     for (void* a : T->allocs) dfree(ctx_of(P->mesh), a);
     delete T;
@@ -622,9 +672,21 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
   *out = T;
 }
 
+static void tape_graph_drop(difvm_tape* T) {
+  for (int k = 0; k < 2; ++k) {
+    if (T->gr.x[k]) (void)hipGraphExecDestroy(T->gr.x[k]);
+    if (T->gr.g[k]) (void)hipGraphDestroy(T->gr.g[k]);
+    T->gr.x[k] = nullptr;
+    T->gr.g[k] = nullptr;
+  }
+}
+
 void tape_destroy(difvm_tape* T) {
   if (!T) return;
   (void)hipStreamSynchronize(stream_of(T->piso->mesh));
+  tape_graph_drop(T);
+  if (T->gr.cap) (void)hipStreamDestroy(T->gr.cap);
+  if (T->gr.state_host) (void)hipHostFree(T->gr.state_host);
   for (void* a : T->allocs) dfree(ctx_of(T->piso->mesh), a);
   difvm_piso* P = T->piso;
   delete T;
@@ -667,9 +729,13 @@ int forward_record(difvm_piso* P, difvm_tape* T, difvm_step_stats* stats) {
 }
 
 // Reverse of one recorded step.  On entry T->Ubar, T->pbar, T->phibar_in (flux cotangent) and
-// pcbar (host) hold the cotangents of the step's outputs; on exit they hold those of its inputs.
-static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const double* phi_n, std::vector<double>& pcbar,
-                        std::vector<double>& wkbar, double adj_tol) {
+// T->pcbar hold the cotangents of the step's outputs; on exit they hold those of its inputs, and the
+// Windkessel parameter cotangents are added to T->wkacc.  With q (capture), every solve queues its
+// budget and leaves its state at q's state_out (nothing is read back, counts untouched); otherwise
+// counts (may be NULL) receive the iterations of the momentum solve (largest component) and of each
+// corrector's pressure solve.
+static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const double* phi_n, double adj_tol,
+                        const StepQueue* q, int* counts) {
   difvm_mesh* m = P->mesh;
   const DMesh& d = m->d;
   hipStream_t s = stream_of(m);
@@ -699,9 +765,10 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     k_axpy<<<Gc, BLOCK, 0, s>>>(nc, 1.0, T->tmp, T->pbar);
     // pressure solve: lambda = K^-1 pbar (K symmetric)
     zero(T->lam, nc, s);
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, nullptr, P->amg,
-                         &P->hint_adj_p[c]);
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, q ? &q->p[c] : nullptr,
+                         P->amg, &P->hint_adj_p[c]);
     worst = std::max(worst, rp.status);
+    if (counts && !q) counts[1 + c] = rp.iters[0];
     k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);
     k_adj_corr_cells<<<Gc, BLOCK, 0, s>>>(mv, T->fHb, T->faF, T->fnc, R.rAU, R.gpo[c], T->rAUbar, T->HbyAbar, T->gbar);
@@ -716,8 +783,10 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   }
   // predictor: U* = M^-1 (b - V grad p^n);  mu = M^-T Ubar
   zero(T->mu, 3 * nc, s);
-  SolveResult ru = bicgstab(m, 3, SellMatrix{R.dM, T->valT}, T->Ubar, T->mu, adj_tol, maxit_u, nullptr, &P->hint_adj_u);
+  SolveResult ru = bicgstab(m, 3, SellMatrix{R.dM, T->valT}, T->Ubar, T->mu, adj_tol, maxit_u, q ? &q->u : nullptr,
+                            &P->hint_adj_u);
   worst = std::max(worst, ru.status);
+  if (counts && !q) counts[0] = std::max(ru.iters[0], std::max(ru.iters[1], ru.iters[2]));
   k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->mu, R.Ustar, T->valbar, nullptr);
   k_adj_pred<<<Gc, BLOCK, 0, s>>>(d.nc, T->mu, R.Ustar, d.V, T->dbar, T->bbar, T->gbar);
   k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
@@ -742,36 +811,182 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
   }
   if (d.nfb) k_adj_ub_src<<<grid_for(d.nfb), BLOCK, 0, s>>>(mv, P->nu_cell, phi_n, T->bbar, T->Ubbar);
   DIFVM_HIP(hipGetLastError());
-  // Windkessel (tiny, on the host): pbv = p_o on each outlet
+  // Windkessel (pbv = p_o on each outlet): one thread per outlet, on the device
   int nwk = d.n_wk;
   if (nwk) {
     k_adj_wk_sum<<<nwk, BLOCK, 0, s>>>(d.wk_start, d.wk_faces, T->pbvbar, T->wkbar);
-    std::vector<double> pobar(nwk), wko(2 * nwk), pcin(nwk);
-    DIFVM_HIP(hipMemcpyAsync(pobar.data(), T->wkbar, sizeof(double) * nwk, hipMemcpyDeviceToHost, s));
-    DIFVM_HIP(hipMemcpyAsync(wko.data(), R.wk_out, sizeof(double) * 2 * nwk, hipMemcpyDeviceToHost, s));
-    DIFVM_HIP(hipMemcpyAsync(pcin.data(), R.pc_in, sizeof(double) * nwk, hipMemcpyDeviceToHost, s));
-    DIFVM_HIP(hipStreamSynchronize(s));
-    std::vector<double> Qbar(nwk);
-    for (int j = 0; j < nwk; ++j) {
-      double Rp = P->wk_host[3 * j], Cc = P->wk_host[3 * j + 1], Rd = P->wk_host[3 * j + 2];
-      double Q = wko[2 * j], pc0 = pcin[j];
-      double E = std::exp(-prm.dt / (Rd * Cc));
-      double pc1bar = pcbar[j] + pobar[j];  // p_o = p_c1 + Rp Q
-      double Qb = pobar[j] * Rp + pc1bar * Rd * (1.0 - E);
-      double Eb = pc1bar * (pc0 - Rd * Q);
-      wkbar[3 * j] += pobar[j] * Q;
-      wkbar[3 * j + 1] += Eb * E * prm.dt / (Rd * Cc * Cc);
-      wkbar[3 * j + 2] += pc1bar * Q * (1.0 - E) + Eb * E * prm.dt / (Rd * Rd * Cc);
-      pcbar[j] = pc1bar * E;
-      Qbar[j] = Qb;
-    }
-    DIFVM_HIP(hipMemcpyAsync(T->wkbar, Qbar.data(), sizeof(double) * nwk, hipMemcpyHostToDevice, s));
+    k_adj_wk_step<<<1, 64, 0, s>>>(nwk, prm.dt, P->wk, R.wk_out, R.pc_in, T->wkbar, T->pcbar, T->wkacc);
     k_adj_wk_spread<<<nwk, BLOCK, 0, s>>>(d.nfi, d.wk_start, d.wk_faces, T->wkbar, T->phibar);
-    DIFVM_HIP(hipStreamSynchronize(s));  // Qbar lives on the stack
+    DIFVM_HIP(hipGetLastError());
   }
   // outputs become the next (earlier) step's incoming cotangents
   dcopy(T->Ubar, T->Ubar0, 3 * nc, s);
   dcopy(T->phibar_in, T->phibar, nf, s);
+  return worst;
+}
+
+// ---- graph mode of the reverse sweep ----------------------------------------------------------
+static size_t seg_words(const DMesh& d) { return 4 * (size_t)d.nc + d.nfi + d.nfb + 3 * (size_t)d.nfb; }
+
+// save (to backup) or restore the cotangents entering a reverse segment: Ubar, pbar, phibar_in,
+// Ubbar (summed over the window), and the Windkessel cotangents
+static void backup_cot(difvm_tape* T, bool save, hipStream_t s) {
+  const DMesh& d = T->piso->mesh->d;
+  size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
+  int nwk = d.n_wk;
+  double* b = T->gr.backup;
+  double* a[6] = {T->Ubar, T->pbar, T->phibar_in, T->Ubbar, T->pcbar, T->wkacc};
+  size_t len[6] = {3 * nc, nc, nf, 3 * (size_t)d.nfb, (size_t)nwk, 3 * (size_t)nwk};
+  for (int k = 0; k < 6; ++k) {
+    if (save) dcopy(b, a[k], len[k], s);
+    else dcopy(a[k], b, len[k], s);
+    b += len[k];
+  }
+}
+
+static char* seg_state(difvm_tape* T, int graph, int step) {
+  return static_cast<char*>(T->gr.state_dev) + ((size_t)graph * T->every + step) * T->gr.per_step;
+}
+
+// recompute (graph 0) or reverse (graph 1) one full segment, queue-only, captured on the private stream
+static void tape_capture(difvm_tape* T, int graph, double adj_tol) {
+  difvm_piso* P = T->piso;
+  difvm_mesh* m = P->mesh;
+  Ctx& c = ctx_of(m);
+  auto& G = T->gr;
+  hipStream_t orig = c.stream;
+  c.stream = G.cap;
+  c.capturing = true;
+  DIFVM_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+  try {
+    auto queue_of = [&](int step) {
+      StepQueue qu;
+      char* st = seg_state(T, graph, step);
+      qu.u = QueueOnly{G.bud_u[graph], st};
+      for (int k = 0; k < P->prm.n_corr; ++k) qu.p[k] = QueueOnly{G.bud_p[graph], st + G.bytes_u + k * G.bytes_p};
+      return qu;
+    };
+    if (graph == 0) {
+      for (int n = 0; n < T->every; ++n) {
+        StepQueue qu = queue_of(n);
+        piso_advance_q(P, nullptr, &T->rec[n], &qu);
+      }
+    } else {
+      backup_cot(T, true, G.cap);
+      for (int n = T->every - 1; n >= 0; --n) {
+        StepQueue qu = queue_of(n);
+        reverse_step(P, T, T->rec[n], T->rec[n].phi_in, adj_tol, &qu, nullptr);
+      }
+    }
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(G.cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c.stream = orig;
+    c.capturing = false;
+    throw;
+  }
+  hipError_t e = hipStreamEndCapture(G.cap, &G.g[graph]);
+  c.stream = orig;
+  c.capturing = false;
+  DIFVM_HIP(e);
+  DIFVM_HIP(hipGraphInstantiate(&G.x[graph], G.g[graph], nullptr, nullptr, 0));
+  if (graph == 1) G.tol = adj_tol;
+  G.captures++;
+}
+
+static void tape_drop_one(difvm_tape* T, int graph) {
+  if (T->gr.x[graph]) (void)hipGraphExecDestroy(T->gr.x[graph]);
+  if (T->gr.g[graph]) (void)hipGraphDestroy(T->gr.g[graph]);
+  T->gr.x[graph] = nullptr;
+  T->gr.g[graph] = nullptr;
+}
+
+// replays graph `graph` and reads its solver states: true when every solve stopped within its budget;
+// the largest counts per kind go to cu / cp
+static bool tape_replay(difvm_tape* T, int graph, int* cu, int* cp, int* worst) {
+  difvm_piso* P = T->piso;
+  difvm_mesh* m = P->mesh;
+  hipStream_t s = stream_of(m);
+  auto& G = T->gr;
+  DIFVM_HIP(hipGraphLaunch(G.x[graph], s));
+  size_t bytes = (size_t)T->every * G.per_step;
+  DIFVM_HIP(hipMemcpyAsync(G.state_host, seg_state(T, graph, 0), bytes, hipMemcpyDeviceToHost, s));
+  DIFVM_HIP(hipStreamSynchronize(s));
+  G.replays++;
+  bool ok = true;
+  *cu = *cp = 0;
+  for (int n = 0; n < T->every; ++n) {
+    const char* hs = static_cast<const char*>(G.state_host) + (size_t)n * G.per_step;
+    bool c1 = true;
+    SolveResult ru = bicgstab_result(m, 3, hs, &c1);
+    ok = ok && c1;
+    *cu = std::max(*cu, std::max(ru.iters[0], std::max(ru.iters[1], ru.iters[2])));
+    *worst = std::max(*worst, ru.status);
+    for (int k = 0; k < P->prm.n_corr; ++k) {
+      SolveResult rp = pcg_result(m, hs + G.bytes_u + k * G.bytes_p, &c1);
+      ok = ok && c1;
+      *cp = std::max(*cp, rp.iters[0]);
+      *worst = std::max(*worst, rp.status);
+    }
+  }
+  return ok;
+}
+
+static void set_tape_budgets(difvm_tape* T, int graph, int cu, int cp, bool grow_only) {
+  auto& G = T->gr;
+  int bu = cu + G.margin + cu / 64, bp = cp + G.margin + cp / 64;
+  G.bud_u[graph] = grow_only ? std::max(G.bud_u[graph], bu) : bu;
+  G.bud_p[graph] = grow_only ? std::max(G.bud_p[graph], bp) : bp;
+}
+
+void tape_set_graph(difvm_tape* T, int enable, int extra) {
+  DIFVM_CHECK(extra >= 0, DIFVM_ERR_INVALID_ARG, "extra_iters must be >= 0");
+  difvm_piso* P = T->piso;
+  auto& G = T->gr;
+  tape_graph_drop(T);
+  G.on = enable != 0;
+  G.extra = extra;
+  G.margin = std::min(2, extra);
+  if (!G.on) return;
+  difvm_mesh* m = P->mesh;
+  if (!G.cap) DIFVM_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  G.bytes_u = bicgstab_state_bytes(m);
+  G.bytes_p = pcg_state_bytes(m);
+  G.per_step = G.bytes_u + (size_t)P->prm.n_corr * G.bytes_p;
+  if (!G.state_dev) {
+    size_t bytes = 2 * (size_t)T->every * G.per_step;
+    G.state_dev = tape_alloc(T, (bytes + 7) / 8);
+    G.backup = tape_alloc(T, seg_words(m->d));
+    DIFVM_HIP(hipHostMalloc(&G.state_host, (size_t)T->every * G.per_step, hipHostMallocDefault));
+  }
+}
+
+// eager recompute of steps [s0, s1) from the loaded checkpoint; largest counts per kind
+static int recompute_eager(difvm_tape* T, int s0, int s1, int* cu, int* cp) {
+  difvm_piso* P = T->piso;
+  int worst = 0;
+  *cu = *cp = 0;
+  for (int n = s0; n < s1; ++n) {
+    difvm_step_stats st{};
+    piso_advance(P, &st, &T->rec[n - s0]);
+    worst = std::max(worst, st.status);
+    *cu = std::max(*cu, std::max(st.it_u[0], std::max(st.it_u[1], st.it_u[2])));
+    for (int k = 0; k < P->prm.n_corr; ++k) *cp = std::max(*cp, st.it_p[k]);
+  }
+  return worst;
+}
+
+static int reverse_eager(difvm_tape* T, int s0, int s1, double adj_tol, int* cu, int* cp) {
+  difvm_piso* P = T->piso;
+  int worst = 0;
+  *cu = *cp = 0;
+  for (int n = s1 - 1; n >= s0; --n) {
+    int cnt[1 + StepRecord::MAXC] = {};
+    worst = std::max(worst, reverse_step(P, T, T->rec[n - s0], T->rec[n - s0].phi_in, adj_tol, nullptr, cnt));
+    *cu = std::max(*cu, cnt[0]);
+    for (int k = 0; k < P->prm.n_corr; ++k) *cp = std::max(*cp, cnt[1 + k]);
+  }
   return worst;
 }
 
@@ -788,26 +1003,77 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
   zero(T->pbar, nc, s);
   zero(T->phibar_in, nf, s);
   zero(T->Ubbar, 3 * (size_t)d.nfb, s);
+  zero(T->wkacc, 3 * (size_t)nwk, s);
+  zero(T->pcbar, nwk, s);
   if (gU) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gU, T->Ubar);
   if (gp) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gp, T->pbar);
   if (gphi) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_TO_INTERNAL, gphi, T->phibar_in);
-  std::vector<double> pcbar(nwk, 0.0), wkbar(3 * nwk, 0.0);
-  if (gpc_host) for (int j = 0; j < nwk; ++j) pcbar[j] = gpc_host[j];
+  if (gpc_host && nwk) {
+    DIFVM_HIP(hipMemcpyAsync(T->pcbar, gpc_host, sizeof(double) * nwk, hipMemcpyHostToDevice, s));
+    DIFVM_HIP(hipStreamSynchronize(s));
+  }
+  auto& G = T->gr;
+  if (G.on && G.x[1] && G.tol != adj_tol) tape_drop_one(T, 1);  // the tolerance is baked into the graph
   int worst = 0;
   for (int seg = T->nseg - 1; seg >= 0; --seg) {
     int s0 = seg * T->every, s1 = std::min(T->nsteps, s0 + T->every);
+    bool graphed = G.on && s1 - s0 == T->every;
+    int cu = 0, cp = 0;
     // recompute the segment from its checkpoint, keeping every step's intermediates
     load_state(P, T->ckU[seg], T->ckp[seg], T->ckphi[seg], T->ckpc[seg]);
-    for (int n = s0; n < s1; ++n) piso_advance(P, nullptr, &T->rec[n - s0]);
-    for (int n = s1 - 1; n >= s0; --n)
-      worst = std::max(worst, reverse_step(P, T, T->rec[n - s0], T->rec[n - s0].phi_in, pcbar, wkbar, adj_tol));
+    if (!graphed) {
+      worst = std::max(worst, recompute_eager(T, s0, s1, &cu, &cp));
+    } else if (!G.x[0]) {
+      worst = std::max(worst, recompute_eager(T, s0, s1, &cu, &cp));
+      set_tape_budgets(T, 0, cu, cp, false);
+      tape_capture(T, 0, adj_tol);
+    } else if (!tape_replay(T, 0, &cu, &cp, &worst)) {
+      // some solve outran its budget: redo the segment eagerly, widen the margin, recapture
+      load_state(P, T->ckU[seg], T->ckp[seg], T->ckphi[seg], T->ckpc[seg]);
+      worst = std::max(worst, recompute_eager(T, s0, s1, &cu, &cp));
+      G.margin = std::min(G.margin + 1, G.extra);
+      set_tape_budgets(T, 0, cu, cp, true);
+      tape_drop_one(T, 0);
+      tape_capture(T, 0, adj_tol);
+      G.redos++;
+    } else if (G.bud_u[0] - (cu + G.margin + cu / 64) >= 2 || G.bud_p[0] - (cp + G.margin + cp / 64) >= 2) {
+      set_tape_budgets(T, 0, cu, cp, false);  // counts fell: tighter budgets
+      tape_drop_one(T, 0);
+      tape_capture(T, 0, adj_tol);
+    }
+    // reverse sweep of the segment
+    if (!graphed) {
+      worst = std::max(worst, reverse_eager(T, s0, s1, adj_tol, &cu, &cp));
+    } else if (!G.x[1]) {
+      worst = std::max(worst, reverse_eager(T, s0, s1, adj_tol, &cu, &cp));
+      set_tape_budgets(T, 1, cu, cp, false);
+      tape_capture(T, 1, adj_tol);
+    } else if (!tape_replay(T, 1, &cu, &cp, &worst)) {
+      backup_cot(T, false, s);  // the graph's first nodes saved the segment's incoming cotangents
+      worst = std::max(worst, reverse_eager(T, s0, s1, adj_tol, &cu, &cp));
+      G.margin = std::min(G.margin + 1, G.extra);
+      set_tape_budgets(T, 1, cu, cp, true);
+      tape_drop_one(T, 1);
+      tape_capture(T, 1, adj_tol);
+      G.redos++;
+    } else if (G.bud_u[1] - (cu + G.margin + cu / 64) >= 2 || G.bud_p[1] - (cp + G.margin + cp / 64) >= 2) {
+      set_tape_budgets(T, 1, cu, cp, false);
+      tape_drop_one(T, 1);
+      tape_capture(T, 1, adj_tol);
+    }
   }
   // outgoing cotangents (internal -> user order)
   if (gU0) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, T->Ubar, gU0);
   if (gp0) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_FROM_INTERNAL, T->pbar, gp0);
   if (gphi0) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_FROM_INTERNAL, T->phibar_in, gphi0);
-  if (gpc0_host) for (int j = 0; j < nwk; ++j) gpc0_host[j] = pcbar[j];
-  if (gwk_host) for (int j = 0; j < 3 * nwk; ++j) gwk_host[j] = wkbar[j];
+  if (nwk && (gpc0_host || gwk_host)) {
+    std::vector<double> pcb(nwk), wkb(3 * nwk);
+    DIFVM_HIP(hipMemcpyAsync(pcb.data(), T->pcbar, sizeof(double) * nwk, hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipMemcpyAsync(wkb.data(), T->wkacc, sizeof(double) * 3 * nwk, hipMemcpyDeviceToHost, s));
+    DIFVM_HIP(hipStreamSynchronize(s));
+    if (gpc0_host) for (int j = 0; j < nwk; ++j) gpc0_host[j] = pcb[j];
+    if (gwk_host) for (int j = 0; j < 3 * nwk; ++j) gwk_host[j] = wkb[j];
+  }
   T->reversed = 1;
   // leave the PISO at the end of the forward window
   load_state(P, T->endU, T->endp, T->endphi, T->endpc);
@@ -842,6 +1108,24 @@ difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm
   int st = forward_record(piso, tape, stats_host);
   DIFVM_HIP(hipStreamSynchronize(stream_of(piso->mesh)));
   return st;
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_tape_set_graph(difvm_tape* tape, int32_t enable, int32_t extra_iters) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(tape, DIFVM_ERR_INVALID_ARG, "tape is NULL");
+  tape_set_graph(tape, enable, extra_iters);
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_tape_graph_info(const difvm_tape* tape, int64_t* replays, int64_t* redos, int64_t* captures) {
+  DIFVM_API_BEGIN
+  DIFVM_CHECK(tape, DIFVM_ERR_INVALID_ARG, "tape is NULL");
+  if (replays) *replays = tape->gr.replays;
+  if (redos) *redos = tape->gr.redos;
+  if (captures) *captures = tape->gr.captures;
   DIFVM_API_END
   return DIFVM_OK;
 }

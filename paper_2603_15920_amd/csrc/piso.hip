@@ -639,9 +639,17 @@ void piso_pressure_matrix(difvm_piso* P, const double* HbyA, const double* rAU, 
   DIFVM_HIP(hipGetLastError());
 }
 
-void dcopy(double* dst, const double* src, size_t n, hipStream_t s) {
-  DIFVM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+// device-to-device copies are kernels, so a captured step or adjoint segment holds kernel nodes only
+__global__ void k_dcopy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[q];
 }
+static void dcopy_k(double* dst, const double* src, size_t n, hipStream_t s) {
+  if (!n) return;
+  k_dcopy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n);
+  DIFVM_HIP(hipGetLastError());
+}
+void dcopy(double* dst, const double* src, size_t n, hipStream_t s) { dcopy_k(dst, src, n, s); }
 
 static void set_seg_stats_u(difvm_piso* P, const SolveResult& ru) {
   for (size_t g = 0; g < P->seg_stats.size(); ++g) {
@@ -663,16 +671,6 @@ static void set_seg_stats_p(difvm_piso* P, int corr, const SolveResult& rp) {
     sg.status = std::max(sg.status, rp.seg[g].status);
   }
 }
-
-struct StepQueue;
-void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const StepQueue* qu);
-
-// Queue-only variant of a step for capture: solves queue fixed budgets and leave their states in
-// P->g.state_dev; nothing is read back.
-struct StepQueue {
-  QueueOnly u;
-  QueueOnly p[StepRecord::MAXC];
-};
 
 void piso_advance(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec) { piso_advance_q(P, stp, rec, nullptr); }
 
@@ -763,15 +761,6 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
 // within its budget is discarded: the state saved by the graph's first node is restored and the
 // step is run eagerly, then the graph is recaptured with budgets from the new counts.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_dcopy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) dst[q] = src[q];
-}
-static void dcopy_k(double* dst, const double* src, size_t n, hipStream_t s) {
-  if (!n) return;
-  k_dcopy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n);
-  DIFVM_HIP(hipGetLastError());
-}
 
 static size_t state_words(const DMesh& d) { return 4 * (size_t)d.nc + d.nfi + d.nfb + std::max(1, d.n_wk); }
 
@@ -837,16 +826,38 @@ static void graph_capture(difvm_piso* P) {
   G.captures++;
 }
 
-// budgets: the largest count of the step (over components or correctors) plus the margin and 1/16 of
-// that count, since later steps' counts drift a little around the first one's
-static void set_budgets(difvm_piso* P, const difvm_step_stats& st, bool grow_only) {
-  PisoGraph& G = P->g;
+// Budgets track the counts: a solve's budget is the largest count of its kind (BiCGStab components,
+// or pressure correctors) over the last few steps, plus the margin and 1/64 of that count (long
+// Jacobi solves drift by a few per cent from step to step).  A replay in which some solve ran out of
+// budget is redone eagerly and widens the margin by one (up to extra); once the recent counts have
+// fallen two or more below the budgets, the step is recaptured with tighter ones.  Idle iterations
+// of a replay (past every solve's stop) are predicated no-ops but still launches, about 30 us each
+// with the AMG V-cycle at 1M cells, so budgets close to the counts keep replays cheap.
+static void push_counts(PisoGraph& G, const difvm_step_stats& st, int n_corr) {
   int mu = std::max(st.it_u[0], std::max(st.it_u[1], st.it_u[2]));
-  int bu = mu + G.extra + mu / 16;
-  G.budget_u = grow_only ? std::max(G.budget_u, bu) : bu;
   int mp = 0;
-  for (int k = 0; k < P->prm.n_corr; ++k) mp = std::max(mp, st.it_p[k]);
-  int bp = mp + G.extra + mp / 16;
+  for (int k = 0; k < n_corr; ++k) mp = std::max(mp, st.it_p[k]);
+  G.hist_u[G.hist_at] = mu;
+  G.hist_p[G.hist_at] = mp;
+  G.hist_at = (G.hist_at + 1) % PisoGraph::HIST;
+  G.nhist = std::min(G.nhist + 1, PisoGraph::HIST);
+}
+
+static void wanted_budgets(const PisoGraph& G, int* bu, int* bp) {
+  int mu = 0, mp = 0;
+  for (int k = 0; k < G.nhist; ++k) {
+    mu = std::max(mu, G.hist_u[k]);
+    mp = std::max(mp, G.hist_p[k]);
+  }
+  *bu = mu + G.margin + mu / 64;
+  *bp = mp + G.margin + mp / 64;
+}
+
+static void set_budgets(difvm_piso* P, bool grow_only) {
+  PisoGraph& G = P->g;
+  int bu, bp;
+  wanted_budgets(G, &bu, &bp);
+  G.budget_u = grow_only ? std::max(G.budget_u, bu) : bu;
   for (int k = 0; k < P->prm.n_corr; ++k) G.budget_p[k] = grow_only ? std::max(G.budget_p[k], bp) : bp;
 }
 
@@ -858,7 +869,8 @@ static void graph_step(difvm_piso* P, difvm_step_stats* out) {
   if (!G.exec) {
     // learn the iteration counts eagerly, then capture with budgets from them
     piso_advance(P, &st, nullptr);
-    set_budgets(P, st, false);
+    push_counts(G, st, P->prm.n_corr);
+    set_budgets(P, false);
     graph_capture(P);
     *out = st;
     return;
@@ -878,10 +890,13 @@ static void graph_step(difvm_piso* P, difvm_step_stats* out) {
     ok = ok && c1;
   }
   if (!ok) {
-    // some solve needed more than its budget: discard the replay, redo the step eagerly
+    // some solve needed more than its budget: discard the replay, redo the step eagerly, widen the
+    // margin and recapture
     backup_state(P, false, s);
     piso_advance(P, &st, nullptr);
-    set_budgets(P, st, true);
+    push_counts(G, st, P->prm.n_corr);
+    G.margin = std::min(G.margin + 1, G.extra);
+    set_budgets(P, true);
     graph_drop(G);
     graph_capture(P);
     G.redos++;
@@ -901,6 +916,17 @@ static void graph_step(difvm_piso* P, difvm_step_stats* out) {
     set_seg_stats_p(P, k, rp[k]);
   }
   *out = st;
+  // tighten the budgets once the recent counts sit two or more below them
+  push_counts(G, st, P->prm.n_corr);
+  int bu, bp;
+  wanted_budgets(G, &bu, &bp);
+  bool slack = G.budget_u - bu >= 2;
+  for (int k = 0; k < P->prm.n_corr; ++k) slack = slack || G.budget_p[k] - bp >= 2;
+  if (slack && G.nhist >= 4) {
+    set_budgets(P, false);
+    graph_drop(G);
+    graph_capture(P);
+  }
 }
 
 void piso_set_graph(difvm_piso* P, int enable, int extra) {
@@ -909,6 +935,8 @@ void piso_set_graph(difvm_piso* P, int enable, int extra) {
   graph_drop(G);
   G.on = enable != 0;
   G.extra = extra;
+  G.margin = std::min(2, extra);
+  G.nhist = G.hist_at = 0;
   if (!G.on) return;
   difvm_mesh* m = P->mesh;
   const DMesh& d = m->d;

@@ -3,12 +3,17 @@
 
 #include "amg_dev.h"
 #include "internal.h"
+#include "ops.h"
 
 // Captured step (graph mode): the whole step as one hipGraph with a fixed iteration budget per solve
 struct PisoGraph {
   bool on = false;
-  int extra = 16;                       // iterations added to the last counts to form the budgets
+  int extra = 16;                       // largest margin the budgets may carry
+  int margin = 2;                       // iterations added to the recent counts (adapts in [0, extra])
   int budget_u = 0, budget_p[8] = {};
+  static constexpr int HIST = 8;
+  int hist_u[HIST] = {}, hist_p[HIST] = {};  // largest counts of the last steps (ring)
+  int nhist = 0, hist_at = 0;
   hipStream_t cap = nullptr;            // private stream the step is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -73,6 +78,13 @@ struct StepRecord {
 
 // one PISO step of P's state; when rec != nullptr the intermediates are copied into it
 void piso_advance(difvm_piso* P, difvm_step_stats* st, StepRecord* rec);
+// Queue-only variant for capture: every solve queues its fixed budget and leaves its state at its
+// QueueOnly::state_out; nothing is read back (st is left untouched).
+struct StepQueue {
+  QueueOnly u;
+  QueueOnly p[StepRecord::MAXC];
+};
+void piso_advance_q(difvm_piso* P, difvm_step_stats* st, StepRecord* rec, const StepQueue* qu);
 // pressure matrix (P->dK, P->valK) from the corrector quantities (also refreshes P->phiH, aF, ncorr, rhsK)
 void piso_pressure_matrix(difvm_piso* P, const double* HbyA, const double* rAU, const double* gp, const double* pbv);
 void dcopy(double* dst, const double* src, size_t n, hipStream_t s);

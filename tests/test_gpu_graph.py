@@ -88,7 +88,8 @@ def test_graph_redo_when_budget_exceeded():
     note("graph redo", m.n_cells)
     run_pair(Pe, Pg, 8, between)
     replays, redos, captures = Pg.graph_info()
-    assert redos >= 1 and captures == 1 + redos, (replays, redos, captures)
+    # every redo recaptures; tighter budgets may recapture once the counts fall back
+    assert redos >= 1 and captures >= 1 + redos, (replays, redos, captures)
 
 
 def test_windkessel_channel_graph_with_parameter_change():
@@ -185,8 +186,29 @@ def test_graph_replays_are_not_timed():
     run_pair(Pe, Pg, 1)          # eager step (timed) + capture
     first = B.difvm_ctx_profile_read(cx.h)
     assert first["pcg_spmv_dot"][0] > 0
-    run_pair(Pe, Pg, 3)          # replays
+    r0 = Pg.graph_info()
+    run_pair(Pe, Pg, 3)          # replays (a redo, if a solve outran its budget, runs eagerly)
     prof = B.difvm_ctx_profile_read(cx.h)
     B.difvm_ctx_profile(cx.h, 0)
-    assert all(v[0] == 0 for v in prof.values()), prof
-    assert Pg.graph_info()[0] == 3
+    r1 = Pg.graph_info()
+    assert (r1[0] - r0[0]) + (r1[1] - r0[1]) == 3
+    if r1[1] == r0[1]:
+        assert all(v[0] == 0 for v in prof.values()), prof
+    else:
+        assert prof["pcg_spmv_dot"][0] > 0
+
+
+def test_adaptive_budgets_track_the_counts():
+    """A long window with the AMG preconditioner from rest: the counts fall as the flow develops, the
+    budgets follow them (recaptures stay few), and every step is bitwise that of eager stepping."""
+    m = mg.cavity(16)
+    Ub = lid(m)
+    _, Pe = make(m, Ub, 0.01, 1e-3, precond="amg")
+    _, Pg = make(m, Ub, 0.01, 1e-3, precond="amg")
+    Pg.set_graph(True, 16)
+    note("graph adaptive", m.n_cells)
+    run_pair(Pe, Pg, 40)
+    replays, redos, captures = Pg.graph_info()
+    note("graph adaptive: replays", replays, "redos", redos, "captures", captures)
+    assert replays + redos == 39
+    assert replays >= 30 and captures <= 1 + redos + 8, (replays, redos, captures)
