@@ -106,7 +106,7 @@ class HipTimer:
         return ms.value * 1e-3
 
 
-def operator_sweep(B, M, m, torch, reps=30):
+def operator_sweep(B, M, m, torch, reps=30, warm_runs=True):
     """Per-operator kernel time with HIP events on the launch stream; the 256 MB Infinity Cache is
     flushed by reading a 1 GiB buffer before every timed launch (cold numbers; a read leaves no dirty
     lines to write back), warm numbers back to back."""
@@ -180,17 +180,19 @@ def operator_sweep(B, M, m, torch, reps=30):
                 tm.start()
                 fn()
                 cold.append(tm.stop_s())
-            tm.start()
-            for _ in range(reps):
-                fn()
-            warm = tm.stop_s() / reps
+            warm = float("nan")
+            if warm_runs:
+                tm.start()
+                for _ in range(reps):
+                    fn()
+                warm = tm.stop_s() / reps
             tc = sorted(cold)[len(cold) // 2]
             nbytes = op_bytes(name, nfi, nfb, nc, fp)
             out[f"{name}_{tag}"] = {
-                "us_cold": round(tc * 1e6, 2), "us_warm": round(warm * 1e6, 2),
+                "us_cold": round(tc * 1e6, 2), "us_warm": round(warm * 1e6, 2) if warm_runs else None,
                 "faces_per_s": round(nfi / tc, 0), "alg_MB": round(nbytes / 1e6, 2),
                 "GBps_cold": round(nbytes / tc / 1e9, 1), "frac_hbm_cold": round(nbytes / tc / 1e9 / HBM_PEAK_GBS, 3),
-                "GBps_warm": round(nbytes / warm / 1e9, 1)}
+                "GBps_warm": round(nbytes / warm / 1e9, 1) if warm_runs else None}
             log(name, tag, out[f"{name}_{tag}"])
     del flush
     return out
@@ -551,6 +553,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=56, help="hexes per side of the Kuhn cube")
     ap.add_argument("--no-ops", action="store_true", help="skip the per-operator sweep")
+    ap.add_argument("--ops-only", action="store_true",
+                    help="only the per-operator sweep (prints its own JSON line, not the benchmark line)")
+    ap.add_argument("--ops-reps", type=int, default=30, help="cold (and warm) launches per operator")
+    ap.add_argument("--ops-warm", type=int, default=1, help="with --ops-only: 0 times cold launches only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated-window measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-mesh batch measurement")
@@ -604,6 +610,16 @@ def main():
     ctx = B.Context(0)
     M = B.Mesh(ctx, m)
     log("device mesh", M.info)
+    if args.ops_only:
+        # operator timings alone (for a kernel trace: cold launches only unless --ops-warm)
+        if not args.no_tune:
+            B.difvm_tune(M.h, None)
+        ops = operator_sweep(B, M, m, torch, reps=args.ops_reps, warm_runs=args.ops_warm)
+        print(json.dumps({"operators": ops, "cells": nc, "internal_faces": nfi, "boundary_faces": nfb,
+                          "reps": args.ops_reps, "tuned_launch": {name: B.difvm_mesh_get_launch(M.h, k)
+                                                                  for k, name in enumerate(B.TUNE_KNOBS)}}),
+              flush=True)
+        return
     prm_kw = dict(nu=nu, dt=dt, n_corr=2, tol_p=1e-8, tol_u=1e-8, maxit_p=5000, maxit_u=1000)
     P = B.Piso(M, B.piso_params(**prm_kw, precond=args.precond))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")

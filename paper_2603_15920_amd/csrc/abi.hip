@@ -194,6 +194,15 @@ static void upload_mesh(difvm_mesh* m) {
     d.slot_off16 = fits ? up_vec(m, off) : nullptr;
   }
   d.cell_nslot = up_vec(m, L.cell_nslot);
+  // uniform rows: every cell has the same slot count (then slice s starts at slot s * 64 * uw)
+  d.uw = 0;
+  if (L.nc > 0 && L.cell_nslot[0] > 0 && L.cell_nslot[0] < 255) {
+    int c = L.cell_nslot[0];
+    bool same = true;
+    for (int i = 1; i < L.nc && same; ++i) same = L.cell_nslot[i] == c;
+    for (int sl = 0; sl <= L.nslice && same; ++sl) same = L.slice_start[sl] == sl * SLICE * c;
+    if (same) d.uw = c;
+  }
   d.face_slot_own = up_vec(m, L.face_slot_own);
   d.face_slot_nbr = up_vec(m, L.face_slot_nbr);
   d.nseg = L.nseg;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradT(MeshView<double> m, int table, 
                                                  double* __restrict__ phibar, double* __restrict__ phib_bar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double rvi = 1.0 / m.V[i];
   double gi[NC][3];
 #pragma unroll
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_corr_cells(MeshView<double> m, co
                                                           double* __restrict__ gpobar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double ra = 0.0, hb[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
   const double* gi = gpo + 3 * (size_t)i;
   const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
@@ -265,13 +265,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_hbya(int nc, const double* __rest
 
 // H = b - offdiag(M) Uin:  valbar(i,j) -= Hbar_i.Uin_j ;  Ubar = -offdiag(M)^T Hbar  (written)
 // also used for the predictor with xbar = mu: valbar -= mu_i.U*_j (then Ubar unused)
-__global__ __launch_bounds__(BLOCK) void k_adj_offdiag(int nc, const int32_t* __restrict__ slice_start,
+__global__ __launch_bounds__(BLOCK) void k_adj_offdiag(int nc, const int32_t* __restrict__ slice_start, int uw,
                                                        const int32_t* __restrict__ col, const double* __restrict__ valT,
                                                        const double* __restrict__ ybar, const double* __restrict__ x,
                                                        double* __restrict__ valbar, double* __restrict__ Ubar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= nc) return;
-  SlotRange R = slots_of(slice_start, i);
+  SlotRange R = slots_of(slice_start, uw, i);
   double yi[3] = {ybar[3 * (size_t)i], ybar[3 * (size_t)i + 1], ybar[3 * (size_t)i + 2]};
   double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_bsrc(MeshView<double> m, const do
                                                     double* __restrict__ gUbar) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double nu = nu_cell[i];
   const double* bi = bbar + 3 * (size_t)i;
   double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -778,7 +778,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
     k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
     // HbyA = (b - offdiag U_in) / d
     k_adj_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, T->HbyAbar, R.HbyA[c], R.dM, T->Hbar, T->dbar, T->bbar);
-    k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->Hbar, R.Uin[c], T->valbar, T->Ubar);
+    k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.uw, d.slot_col, T->valT, T->Hbar, R.Uin[c], T->valbar, T->Ubar);
     DIFVM_HIP(hipGetLastError());
   }
   // predictor: U* = M^-1 (b - V grad p^n);  mu = M^-T Ubar
@@ -787,7 +787,7 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
                             &P->hint_adj_u);
   worst = std::max(worst, ru.status);
   if (counts && !q) counts[0] = std::max(ru.iters[0], std::max(ru.iters[1], ru.iters[2]));
-  k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, T->valT, T->mu, R.Ustar, T->valbar, nullptr);
+  k_adj_offdiag<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.uw, d.slot_col, T->valT, T->mu, R.Ustar, T->valbar, nullptr);
   k_adj_pred<<<Gc, BLOCK, 0, s>>>(d.nc, T->mu, R.Ustar, d.V, T->dbar, T->bbar, T->gbar);
   k_gradT<1><<<Gc, BLOCK, 0, s>>>(mv, DIFVM_BC_P, T->gbar, T->pbar, T->pbvbar);
   k_adj_rau<<<Gc, BLOCK, 0, s>>>(d.nc, T->rAUbar, R.rAU, R.dM, T->dbar);
@@ -915,6 +915,7 @@ static bool tape_replay(difvm_tape* T, int graph, int* cu, int* cp, int* worst) 
   DIFVM_HIP(hipStreamSynchronize(s));
   G.replays++;
   bool ok = true;
+  int w = 0;
   *cu = *cp = 0;
   for (int n = 0; n < T->every; ++n) {
     const char* hs = static_cast<const char*>(G.state_host) + (size_t)n * G.per_step;
@@ -922,14 +923,16 @@ static bool tape_replay(difvm_tape* T, int graph, int* cu, int* cp, int* worst) 
     SolveResult ru = bicgstab_result(m, 3, hs, &c1);
     ok = ok && c1;
     *cu = std::max(*cu, std::max(ru.iters[0], std::max(ru.iters[1], ru.iters[2])));
-    *worst = std::max(*worst, ru.status);
+    w = std::max(w, ru.status);
     for (int k = 0; k < P->prm.n_corr; ++k) {
       SolveResult rp = pcg_result(m, hs + G.bytes_u + k * G.bytes_p, &c1);
       ok = ok && c1;
       *cp = std::max(*cp, rp.iters[0]);
-      *worst = std::max(*worst, rp.status);
+      w = std::max(w, rp.status);
     }
   }
+  // a replay that ran out of budget is discarded: its (incomplete) solves' statuses do not count
+  if (ok) *worst = std::max(*worst, w);
   return ok;
 }
 

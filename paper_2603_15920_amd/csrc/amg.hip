@@ -204,7 +204,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_pre1(SellView K, const doubl
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   // row range loaded at a clamped index, without a branch around the load, so that it is in flight
   // together with the flag reads
-  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  SlotRange R = slots_of(K, min(i, K.nc - 1));
   if (stopped(ctl) || i >= K.nc) return;
   double di = K.diag[i], rh0 = r[i] / di;
   double d0 = rh0 * c.inv_theta;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_pre2(SellView K, const doubl
                                                          const double* __restrict__ xs, double* __restrict__ res,
                                                          StopFlags ctl) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  SlotRange R = slots_of(K, min(i, K.nc - 1));
   if (stopped(ctl) || i >= K.nc) return;
   double kx = K.diag[i] * xs[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return xs[j]; });
   res[i] = r[i] - kx;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_post1(SellView K, const doub
                                                           const double* __restrict__ t, double* __restrict__ d0,
                                                           Cheb c, StopFlags ctl) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  SlotRange R = slots_of(K.slice_start, min(i, K.nc - 1));
+  SlotRange R = slots_of(K, min(i, K.nc - 1));
   if (stopped(ctl) || i >= K.nc) return;
   double di = K.diag[i];
   double kt = di * t[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return t[j]; });
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_post2(SellView K, Tiles T, c
   if (stopped(ctl)) return;
   double v[1] = {0.0};
   FOR_TILE_CELLS(i) {
-    SlotRange R = slots_of(K.slice_start, i);
+    SlotRange R = slots_of(K, i);
     double di = K.diag[i], d0i = d0[i];
     double kd0 = di * d0i + sell_offdiag<OFF16>(K, i, R, [&](int j) { return d0[j]; });
     double rh1 = c.theta * d0i - kd0 / di;

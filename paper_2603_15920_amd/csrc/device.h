@@ -46,6 +46,7 @@ struct MeshView {
   const int32_t* __restrict__ slot_face;
   const int32_t* __restrict__ slot_col;
   const uint8_t* __restrict__ nslot;  // slots of each cell (255: use the slice width)
+  int uw;                             // > 0: every cell has exactly uw slots (uniform rows)
 };
 
 template <class T>
@@ -53,31 +54,43 @@ MeshView<T> view(const DMesh& d);
 template <>
 inline MeshView<double> view<double>(const DMesh& d) {
   return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS, d.geomK, d.w, d.bown, d.bgeom, d.bcode, d.V,
-          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot};
+          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot, d.uw};
 }
 template <>
 inline MeshView<float> view<float>(const DMesh& d) {
   return {d.nc, d.nfi, d.nfb, d.own, d.nbr, d.geomS32, d.geomK32, d.w32, d.bown, d.bgeom32, d.bcode, d.V32,
-          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot};
+          d.slice_start, d.slot_face, d.slot_col, d.cell_nslot, d.uw};
 }
 
 // slot range of cell i: slots base + k*SLICE for k < width (the slice's width: trailing pads
-// possible)
+// possible).  With uniform rows (uw > 0: every cell has exactly uw slots, as in a tet mesh whose
+// boundary faces all carry slots) every slice has width uw and the range follows from i alone, so the
+// slot loads need not wait for a load of the slice table.
 struct SlotRange {
   int base, width;
 };
-__device__ __forceinline__ SlotRange slots_of(const int32_t* slice_start, int i) {
+__device__ __forceinline__ SlotRange slots_of(const int32_t* slice_start, int uw, int i) {
+  if (uw > 0) return {(i >> 6) * (SLICE * uw) + (i & (SLICE - 1)), uw};
   int s = i >> 6;
   int b = slice_start[s];
   return {b + (i & (SLICE - 1)), (slice_start[s + 1] - b) >> 6};
+}
+template <class V>
+__device__ __forceinline__ SlotRange slots_of(const V& v, int i) {
+  return slots_of(v.slice_start, v.uw, i);
 }
 
 // number of slots a row walker visits for cell i: the cell's own count, so that a cell's arithmetic
 // never depends on the other cells of its slice (cells of one mesh packed beside another compute the
 // same bits as alone); 255 marks a count too large for the byte, then the slice width is used
-__device__ __forceinline__ int row_len(const uint8_t* __restrict__ nslot, int i, const SlotRange& R) {
+__device__ __forceinline__ int row_len(const uint8_t* __restrict__ nslot, int uw, int i, const SlotRange& R) {
+  if (uw > 0) return uw;
   int n = nslot[i];
   return n == 255 ? R.width : n;
+}
+template <class V>
+__device__ __forceinline__ int row_len(const V& v, int i, const SlotRange& R) {
+  return row_len(v.nslot, v.uw, i, R);
 }
 
 // Walks a row of n slots in order: body(W, k0) handles slots k0 .. k0+W-1 with W a compile-time
@@ -96,6 +109,56 @@ __device__ __forceinline__ void walk_row(int n, F&& body) {
     }
   }
   for (; k0 < n; ++k0) body(std::integral_constant<int, 1>{}, k0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stores of cell-major rows ([n][NC]: vectors, gradients).  One thread per row storing its NC values
+// writes at a stride of NC values, so each store instruction covers only part of every cache line it
+// touches, and such partial-line writes reach HBM amplified (2.7x measured for 3-vectors).  A block
+// whose threads own the consecutive rows [base, base + blockDim.x) stages its rows in LDS and writes
+// them back as consecutive values: every store instruction covers whole lines.  Every thread of the
+// block must call these (they synchronise twice); rows >= n are not written.  lds holds NC values
+// per thread of the block.
+// ---------------------------------------------------------------------------------------------
+extern __shared__ unsigned char difvm_dyn_lds[];  // dynamic LDS of kernels launched with tuned block sizes
+template <class T>
+__device__ __forceinline__ T* dyn_lds() {
+  return reinterpret_cast<T*>(difvm_dyn_lds);
+}
+
+template <int NC, class T>
+__device__ __forceinline__ void store_rows(T* __restrict__ out, int base, int n, const T (&v)[NC], T* lds) {
+  const int nb = blockDim.x;
+  if (base + (int)threadIdx.x < n)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lds[NC * threadIdx.x + c] = v[c];
+  __syncthreads();
+  const int cnt = NC * min(nb, n - base);
+  T* o = out + (size_t)NC * base;
+  for (int q = threadIdx.x; q < cnt; q += nb) o[q] = lds[q];
+  __syncthreads();  // the block may stage again
+}
+
+// the same, writing only the values of the components c with keep[c] != 0 (the others keep what they
+// hold)
+template <int NC, class T>
+__device__ __forceinline__ void store_rows_if(T* __restrict__ out, int base, int n, const T (&v)[NC],
+                                              const bool (&keep)[NC], T* lds) {
+  const int nb = blockDim.x;
+  if (base + (int)threadIdx.x < n)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lds[NC * threadIdx.x + c] = v[c];
+  __syncthreads();
+  const int cnt = NC * min(nb, n - base);
+  T* o = out + (size_t)NC * base;
+  for (int q = threadIdx.x; q < cnt; q += nb) {
+    int c = q % NC;
+    bool k = keep[0];
+#pragma unroll
+    for (int u = 1; u < NC; ++u) k = c == u ? keep[u] : k;
+    if (k) o[q] = lds[q];
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------------

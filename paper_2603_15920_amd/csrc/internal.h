@@ -117,6 +117,7 @@ struct DMesh {
   int32_t *slice_start, *slot_face, *slot_col;
   int16_t* slot_off16;  // slot_col - row as 16 bits, or NULL when some offset does not fit
   uint8_t* cell_nslot;
+  int uw;               // > 0: every cell has exactly uw slots (uniform rows), else 0
   int32_t *face_slot_own, *face_slot_nbr;
   // segments and reduction tiles
   int nseg, ntile;

@@ -88,12 +88,12 @@ void krylov_work_free(KrylovWork* w) {
 // ---------------------------------------------------------------------------------------------
 // matrix helpers (SellView, sell_row: krylov_util.h)
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_sell_from_ldu(int nc, int nfi, const int32_t* __restrict__ slice_start,
+__global__ __launch_bounds__(BLOCK) void k_sell_from_ldu(int nc, int nfi, const int32_t* __restrict__ slice_start, int uw,
                                                          const int32_t* __restrict__ slot_face, const double* __restrict__ up,
                                                          const double* __restrict__ lo, double* __restrict__ val) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= nc) return;
-  SlotRange R = slots_of(slice_start, i);
+  SlotRange R = slots_of(slice_start, uw, i);
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     int sf = slot_face[at];
@@ -118,7 +118,7 @@ void sell_from_ldu(const difvm_mesh* m, const double* upper, const double* lower
   // padding rows of the last slice are never read by row kernels; clear the whole array once so no
   // slot holds stale values
   DIFVM_HIP(hipMemsetAsync(val, 0, sizeof(double) * (size_t)d.nslot, stream_of(m)));
-  k_sell_from_ldu<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(d.nc, d.nfi, d.slice_start, d.slot_face, upper,
+  k_sell_from_ldu<<<grid_for(d.nc), BLOCK, 0, stream_of(m)>>>(d.nc, d.nfi, d.slice_start, d.uw, d.slot_face, upper,
                                                               lower ? lower : upper, val);
   DIFVM_HIP(hipGetLastError());
 }
@@ -311,8 +311,8 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
       int i = lo + c * NT + threadIdx.x;
       if (i < hi) {
         double pi = z[i] + beta * p_prev[i];
-        SlotRange R = slots_of(A.slice_start, i);
-        const int nrow = row_len(A.nslot, i, R);
+        SlotRange R = slots_of(A, i);
+        const int nrow = row_len(A, i, R);
         double acc = A.diag[i] * pi;
         walk_row<4>(nrow, [&](auto Wc, int k0) {
           acc = dir_row<decltype(Wc)::value, OFF16>(A, i, R.base + k0 * SLICE, acc, beta, z, p_prev);
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void k_bi_zero(Tiles T, double* __restrict__
 // slots carry val = 0 and col = i
 template <int NC, class F>
 __device__ __forceinline__ void sell_row_f(const SellView& A, int i, F&& f, double (&acc)[NC]) {
-  SlotRange R = slots_of(A.slice_start, i);
+  SlotRange R = slots_of(A, i);
   double di = A.diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * f(i, c);
@@ -682,13 +682,15 @@ __global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, Tiles T, const dou
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
   if (!st->any) return;
-  FOR_TILE_CELLS(i) {
+  // one thread per value of the tile's rows (consecutive lanes, consecutive doubles)
+  const int e1 = NC * ti.hi;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c]) continue;
-      size_t at = (size_t)i * NC + c;
-      p[at] = r[at] + st->beta[c] * (p[at] - st->omega[c] * v[at]);
-    }
+  for (int q = 0; q < NC * CPT; ++q) {
+    int e = NC * ti.lo + q * BLOCK + (int)threadIdx.x;
+    if (e >= e1) break;
+    int c = e % NC;
+    if (!st->active[c]) continue;
+    p[e] = r[e] + st->beta[c] * (p[e] - st->omega[c] * v[e]);
   }
 }
 
@@ -700,17 +702,27 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   const BiState* st = sts + ti.s;
   if (!st->any) return;
   double acc[NC];
+  bool keep[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  FOR_TILE_CELLS(i) {
-    double ay[NC];
-    sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
+  for (int c = 0; c < NC; ++c) {
+    acc[c] = 0.0;
+    keep[c] = st->active[c] != 0;
+  }
+  __shared__ double lds[NC * BLOCK];
+  FOR_TILE_ROUNDS(base, i) {
+    double ay[NC] = {};
+    if (i < ti.hi) {
+      sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c]) continue;
-      size_t at = (size_t)i * NC + c;
-      v[at] = ay[c];
-      acc[c] += rh[at] * ay[c];
+      for (int c = 0; c < NC; ++c) {
+        if (!keep[c]) continue;
+        acc[c] += rh[(size_t)i * NC + c] * ay[c];
+      }
+    }
+    if constexpr (NC == 1) {
+      if (i < ti.hi && keep[0]) v[i] = ay[0];
+    } else {
+      store_rows_if<NC>(v, base, ti.hi, ay, keep, lds);
     }
   }
   put_partial<NC>(acc, part, T.ntile, ti.t);
@@ -728,23 +740,36 @@ __global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const doubl
   double acc[3 * NC];
 #pragma unroll
   for (int k = 0; k < 3 * NC; ++k) acc[k] = 0.0;
-  FOR_TILE_CELLS(i) {
-    auto s_of = [&](int j, int c) {
-      size_t at = (size_t)j * NC + c;
-      return r[at] - st->alpha[c] * v[at];
-    };
-    double az[NC];
-    sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
+  bool keep[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c]) continue;
-      size_t at = (size_t)i * NC + c;
-      double si = s_of(i, c);
-      s[at] = si;
-      t[at] = az[c];
-      acc[c] += az[c] * si;
-      acc[NC + c] += az[c] * az[c];
-      acc[2 * NC + c] += si * si;
+  for (int c = 0; c < NC; ++c) keep[c] = st->active[c] != 0;
+  __shared__ double lds[NC * BLOCK];
+  auto s_of = [&](int j, int c) {
+    size_t at = (size_t)j * NC + c;
+    return r[at] - st->alpha[c] * v[at];
+  };
+  FOR_TILE_ROUNDS(base, i) {
+    double az[NC] = {}, sv[NC] = {};
+    if (i < ti.hi) {
+      sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (!keep[c]) continue;
+        double si = s_of(i, c);
+        sv[c] = si;
+        acc[c] += az[c] * si;
+        acc[NC + c] += az[c] * az[c];
+        acc[2 * NC + c] += si * si;
+      }
+    }
+    if constexpr (NC == 1) {
+      if (i < ti.hi && keep[0]) {
+        s[i] = sv[0];
+        t[i] = az[0];
+      }
+    } else {
+      store_rows_if<NC>(s, base, ti.hi, sv, keep, lds);
+      store_rows_if<NC>(t, base, ti.hi, az, keep, lds);
     }
   }
   put_partial<3 * NC>(acc, part, T.ntile, ti.t);
@@ -762,23 +787,40 @@ __global__ __launch_bounds__(BLOCK) void k_bi_x(SellView A, Tiles T, double* __r
   double acc[2 * NC];
 #pragma unroll
   for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  FOR_TILE_CELLS(i) {
-    double di = A.diag[i];
+  bool keep_x[NC], keep_r[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!st->active[c]) continue;
-      size_t at = (size_t)i * NC + c;
-      double yi = p[at] / di;
-      if (st->phase[c]) {
-        x[at] += st->alpha[c] * yi;
-      } else {
-        double si = s[at];
-        x[at] += st->alpha[c] * yi + st->omega[c] * (si / di);
-        double ri = si - st->omega[c] * t[at];
-        r[at] = ri;
-        acc[c] += ri * ri;
-        acc[NC + c] += rh[at] * ri;
+  for (int c = 0; c < NC; ++c) {
+    keep_x[c] = st->active[c] != 0;
+    keep_r[c] = keep_x[c] && !st->phase[c];
+  }
+  __shared__ double lds[NC * BLOCK];
+  FOR_TILE_ROUNDS(base, i) {
+    double xv[NC] = {}, rv[NC] = {};
+    if (i < ti.hi) {
+      double di = A.diag[i];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (!keep_x[c]) continue;
+        size_t at = (size_t)i * NC + c;
+        double yi = p[at] / di;
+        if (!keep_r[c]) {
+          xv[c] = x[at] + st->alpha[c] * yi;
+        } else {
+          double si = s[at];
+          xv[c] = x[at] + (st->alpha[c] * yi + st->omega[c] * (si / di));
+          double ri = si - st->omega[c] * t[at];
+          rv[c] = ri;
+          acc[c] += ri * ri;
+          acc[NC + c] += rh[at] * ri;
+        }
       }
+    }
+    if constexpr (NC == 1) {
+      if (i < ti.hi && keep_x[0]) x[i] = xv[0];
+      if (i < ti.hi && keep_r[0]) r[i] = rv[0];
+    } else {
+      store_rows_if<NC>(x, base, ti.hi, xv, keep_x, lds);
+      store_rows_if<NC>(r, base, ti.hi, rv, keep_r, lds);
     }
   }
   put_partial<2 * NC>(acc, part, T.ntile, ti.t);

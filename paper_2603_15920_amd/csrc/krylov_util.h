@@ -18,16 +18,17 @@ struct SellView {
   const double* __restrict__ val;
   const double* __restrict__ diag;
   const int16_t* __restrict__ off16;  // col - row in 16 bits (NULL when it does not fit)
+  int uw;                             // uniform row width (0: rows of varying width)
 };
 
 inline SellView sview(const difvm_mesh* m, SellMatrix A) {
-  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag, m->d.slot_off16};
+  return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag, m->d.slot_off16, m->d.uw};
 }
 
 // (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
 template <int NC>
 __device__ __forceinline__ void sell_row(const SellView& A, int i, const double* __restrict__ x, double (&acc)[NC]) {
-  SlotRange R = slots_of(A.slice_start, i);
+  SlotRange R = slots_of(A, i);
   double di = A.diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
@@ -119,6 +120,14 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
 
 #define FOR_TILE_CELLS(I) \
   _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) if (int I = ti.lo + c_ * BLOCK + threadIdx.x; I < ti.hi)
+
+// The same cells in rounds of BLOCK consecutive cells [BASE, BASE + BLOCK), every thread of the block
+// in every round whether or not its cell I < ti.hi exists: for kernels that stage their stores
+// through LDS (store_rows synchronises the block).  Each thread still visits its cells in the same
+// order as FOR_TILE_CELLS.
+#define FOR_TILE_ROUNDS(BASE, I) \
+  _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) \
+    if (const int BASE = ti.lo + c_ * BLOCK, I = BASE + (int)threadIdx.x; BASE < ti.hi)
 
 // per-segment PCG state (device)
 struct PcgCtl {

@@ -71,12 +71,14 @@ static int op_block(const difvm_mesh* m, int knob_f64, int dtype_is_f32) { retur
 template <class T, int NC>
 __global__ __launch_bounds__(OP_MAX_BLOCK) void k_interp(MeshView<T> m, int table, const T* __restrict__ phi,
                                                   const T* __restrict__ phib, T* __restrict__ out) {
-  int f = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x;
+  const int f = base + threadIdx.x;
+  T res[NC];
   if (f < m.nfi) {
     T w = m.w[f];
     int O = m.own[f], N = m.nbr[f];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) out[(size_t)f * NC + c] = w * phi[(size_t)O * NC + c] + (T(1) - w) * phi[(size_t)N * NC + c];
+    for (int c = 0; c < NC; ++c) res[c] = w * phi[(size_t)O * NC + c] + (T(1) - w) * phi[(size_t)N * NC + c];
   } else if (f < m.nfi + m.nfb) {
     int b = f - m.nfi;
     int8_t code = m.bcode[table * m.nfb + b];
@@ -86,8 +88,13 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_interp(MeshView<T> m, int tabl
       T v = T(0);
       if (code == BC_FIXED) v = phib[(size_t)b * NC + c];
       else if (code == BC_ZEROGRAD) v = phi[(size_t)O * NC + c];
-      out[(size_t)f * NC + c] = v;
+      res[c] = v;
     }
+  }
+  if constexpr (NC == 1) {
+    if (f < m.nfi + m.nfb) out[f] = res[0];
+  } else {
+    store_rows<NC>(out, base, m.nfi + m.nfb, res, dyn_lds<T>());
   }
 }
 
@@ -108,9 +115,11 @@ __device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_in
 template <class T, int NC>
 __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table, const T* __restrict__ phi,
                                                 const T* __restrict__ phib, T* __restrict__ out) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
-  if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x;
+  const int i = base + threadIdx.x;
+  T res[3 * NC];
+  if (i < m.nc) {
+  SlotRange R = slots_of(m, i);
   T pi[NC], acc[NC][3];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -118,7 +127,7 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
     acc[c][0] = acc[c][1] = acc[c][2] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-  walk_row<(NC == 3 ? 2 : 4)>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+  walk_row<(NC == 3 ? 2 : 4)>(row_len(m, i, R), [&](auto Wc, int k0) {
     constexpr int N = decltype(Wc)::value;
     {
       int sf[N], j[N];
@@ -169,7 +178,9 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) out[((size_t)i * NC + c) * 3 + e] = acc[c][e] * rv;
+    for (int e = 0; e < 3; ++e) res[3 * c + e] = acc[c][e] * rv;
+  }
+  store_rows<3 * NC>(out, base, m.nc, res, dyn_lds<T>());
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -178,17 +189,19 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
 template <class T, int NC, int SCHEME>
 __global__ __launch_bounds__(OP_MAX_BLOCK) void k_div(MeshView<T> m, int table, const T* __restrict__ flux,
                                                const T* __restrict__ psi, const T* __restrict__ psib, T* __restrict__ out) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
-  if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
-  T pi[NC], acc[NC];
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x;
+  const int i = base + threadIdx.x;
+  T acc[NC];
+  if (i < m.nc) {
+  SlotRange R = slots_of(m, i);
+  T pi[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     pi[c] = SCHEME == DIFVM_SCHEME_ONE ? T(0) : psi[(size_t)i * NC + c];
     acc[c] = T(0);
   }
   const int8_t* code = m.bcode + table * m.nfb;
-  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+  walk_row<4>(row_len(m, i, R), [&](auto Wc, int k0) {
     constexpr int N = decltype(Wc)::value;
     {
       int sf[N], j[N];
@@ -241,8 +254,12 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_div(MeshView<T> m, int table, 
       }
     }
   });
-#pragma unroll
-  for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
+  }
+  if constexpr (NC == 1) {
+    if (i < m.nc) out[i] = acc[0];
+  } else {
+    store_rows<NC>(out, base, m.nc, acc, dyn_lds<T>());
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -254,12 +271,12 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_laplacian(MeshView<T> m, int t
                                                      const T* __restrict__ phib, T* __restrict__ out) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   T pi = phi[i];
   T gi0 = g[3 * (size_t)i], gi1 = g[3 * (size_t)i + 1], gi2 = g[3 * (size_t)i + 2];
   T acc = T(0);
   const int8_t* code = m.bcode + table * m.nfb;
-  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+  walk_row<4>(row_len(m, i, R), [&](auto Wc, int k0) {
     constexpr int N = decltype(Wc)::value;
     int sf[N], j[N];
     typename Geo<T>::v4 kd[N];
@@ -314,14 +331,15 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_laplacian(MeshView<T> m, int t
 template <class T, int NC>
 __global__ __launch_bounds__(OP_MAX_BLOCK) void k_ldu_spmv(MeshView<T> m, const T* __restrict__ diag, const T* __restrict__ up,
                                                     const T* __restrict__ lo, const T* __restrict__ x, T* __restrict__ y) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
-  if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x;
+  const int i = base + threadIdx.x;
   T acc[NC];
+  if (i < m.nc) {
+  SlotRange R = slots_of(m, i);
   T di = diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
-  walk_row<4>(row_len(m.nslot, i, R), [&](auto Wc, int k0) {
+  walk_row<4>(row_len(m, i, R), [&](auto Wc, int k0) {
     constexpr int N = decltype(Wc)::value;
     {
       int sf[N], j[N];
@@ -349,8 +367,12 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_ldu_spmv(MeshView<T> m, const 
       }
     }
   });
-#pragma unroll
-  for (int c = 0; c < NC; ++c) y[(size_t)i * NC + c] = acc[c];
+  }
+  if constexpr (NC == 1) {
+    if (i < m.nc) y[i] = acc[0];
+  } else {
+    store_rows<NC>(y, base, m.nc, acc, dyn_lds<T>());
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -361,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_laplace(MeshView<double> m, 
                                                             double* __restrict__ upper, double* __restrict__ rhs) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double d = 0.0, r = 0.0;
   const int8_t* code = m.bcode + table * m.nfb;
 #pragma unroll 4
@@ -399,7 +421,7 @@ void interp_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T*
   MeshView<T> v = view<T>(d);
   int nb = op_block(mm, DIFVM_TUNE_INTERP_F64, sizeof(T) == 4);
   if (ncomp == 1) k_interp<T, 1><<<grid_for(n, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
-  else k_interp<T, 3><<<grid_for(n, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_interp<T, 3><<<grid_for(n, nb), nb, 3 * nb * sizeof(T), stream_of(mm)>>>(v, table, phi, phib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -408,8 +430,8 @@ void grad_t(const difvm_mesh* mm, int ncomp, int table, const T* phi, const T* p
   const DMesh& d = mm->d;
   MeshView<T> v = view<T>(d);
   int nb = op_block(mm, DIFVM_TUNE_GRAD_F64, sizeof(T) == 4);
-  if (ncomp == 1) k_grad<T, 1><<<grid_for(d.nc, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
-  else k_grad<T, 3><<<grid_for(d.nc, nb), nb, 0, stream_of(mm)>>>(v, table, phi, phib, out);
+  if (ncomp == 1) k_grad<T, 1><<<grid_for(d.nc, nb), nb, 3 * nb * sizeof(T), stream_of(mm)>>>(v, table, phi, phib, out);
+  else k_grad<T, 3><<<grid_for(d.nc, nb), nb, 9 * nb * sizeof(T), stream_of(mm)>>>(v, table, phi, phib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -420,9 +442,10 @@ void div_nc(const difvm_mesh* mm, int scheme, int table, const T* flux, const T*
   int nb = op_block(mm, DIFVM_TUNE_DIV_F64, sizeof(T) == 4);
   int G = grid_for(d.nc, nb);
   hipStream_t s = stream_of(mm);
-  if (scheme == DIFVM_SCHEME_ONE) k_div<T, NC, DIFVM_SCHEME_ONE><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
-  else if (scheme == DIFVM_SCHEME_UPWIND) k_div<T, NC, DIFVM_SCHEME_UPWIND><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
-  else k_div<T, NC, DIFVM_SCHEME_LINEAR><<<G, nb, 0, s>>>(v, table, flux, psi, psib, out);
+  size_t lds = NC > 1 ? NC * nb * sizeof(T) : 0;
+  if (scheme == DIFVM_SCHEME_ONE) k_div<T, NC, DIFVM_SCHEME_ONE><<<G, nb, lds, s>>>(v, table, flux, psi, psib, out);
+  else if (scheme == DIFVM_SCHEME_UPWIND) k_div<T, NC, DIFVM_SCHEME_UPWIND><<<G, nb, lds, s>>>(v, table, flux, psi, psib, out);
+  else k_div<T, NC, DIFVM_SCHEME_LINEAR><<<G, nb, lds, s>>>(v, table, flux, psi, psib, out);
   DIFVM_HIP(hipGetLastError());
 }
 
@@ -449,7 +472,7 @@ void ldu_spmv_t(const difvm_mesh* mm, int ncomp, int transpose, const T* diag, c
   int nb = op_block(mm, DIFVM_TUNE_LDU_SPMV_F64, sizeof(T) == 4);
   int G = grid_for(d.nc, nb);
   if (ncomp == 1) k_ldu_spmv<T, 1><<<G, nb, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
-  else k_ldu_spmv<T, 3><<<G, nb, 0, stream_of(mm)>>>(v, diag, up, lo, x, y);
+  else k_ldu_spmv<T, 3><<<G, nb, 3 * nb * sizeof(T), stream_of(mm)>>>(v, diag, up, lo, x, y);
   DIFVM_HIP(hipGetLastError());
 }
 

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
                                                     double* __restrict__ b) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
   double Vdt = m.V[i] / dt;
   double d = Vdt;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(BLOCK) void k_dc(MeshView<double> m, const double* 
                                               double* __restrict__ out) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double pi_[NC], acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_dc(MeshView<double> m, const double* 
     acc[c] = 0.0;
   }
   const double* gi = g + 3 * NC * (size_t)i;
-  int n = row_len(m.nslot, i, R);
+  int n = row_len(m, i, R);
   for (int k = 0; k < n; ++k) {
     int at = R.base + k * SLICE;
     int sf = m.slot_face[at];
@@ -281,14 +281,14 @@ __global__ __launch_bounds__(BLOCK) void k_pred_rhs(int nc, const double* __rest
 }
 
 // H = b - sum_slots a U_j; HbyA = H / d; rAU = V / d
-__global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restrict__ slice_start,
+__global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restrict__ slice_start, int uw,
                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ diag, const double* __restrict__ V,
                                                 const double* __restrict__ b, const double* __restrict__ U,
                                                 double* __restrict__ HbyA, double* __restrict__ rAU) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= nc) return;
-  SlotRange R = slots_of(slice_start, i);
+  SlotRange R = slots_of(slice_start, uw, i);
   double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const d
                                                      double* __restrict__ rhs) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double d = 0.0, r = 0.0;
   const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
 #pragma unroll 4
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const doubl
                                                  const double* __restrict__ rAU, double* __restrict__ U) {
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
-  SlotRange R = slots_of(m.slice_start, i);
+  SlotRange R = slots_of(m, i);
   double pi = p[i];
   double acc[3] = {0.0, 0.0, 0.0};
   const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
@@ -718,7 +718,7 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
       dcopy(rec->Uin[corr], P->U, 3 * nc, s);
       dcopy(rec->pold[corr], P->p, nc, s);
     }
-    k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
+    k_hbya<<<Gc, BLOCK, 0, s>>>(d.nc, d.slice_start, d.uw, d.slot_col, P->valM, P->dM, d.V, P->bM, P->U, P->HbyA, P->rAU);
     // grad of the entering pressure: at the first corrector p and its boundary values are those of the
     // predictor, whose gradient P->gp still holds
     if (corr > 0) op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);

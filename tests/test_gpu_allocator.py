@@ -1,6 +1,8 @@
 """Device memory through the caller's allocator (difvm_ctx_set_allocator): every block the library
 holds comes from torch's caching allocator, solves and PISO steps allocate nothing after their first
 call (warm-up), results are bitwise those of a context on hipMalloc, and every block is returned."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -55,6 +57,7 @@ def piso_run(ctx, m, Ub, wk, nsteps, precond, graph=False, counter=None):
 def test_piso_steps_allocate_nothing_and_match_hipmalloc(precond, graph):
     m, Ub, wk = channel()
     note("allocator piso", precond, graph)
+    gc.collect()  # objects an earlier test left behind are freed now, not during this one
     tctx = B.Context(0)  # torch's caching allocator
     A = tctx.allocator
     base = torch().cuda.memory_allocated()

@@ -13,8 +13,9 @@
   within 1e-9 (the solution is unique up to the tolerance), and the distance of the benchmark's
   tol-1e-8 state from it is reported and bounded (1e-6 relative; it is set by the solver tolerance,
   not by the arithmetic).
-* Tube (1,999,872 tets, Re 500, p = 0 outlet, Jacobi): the first 2 steps against the oracle (1e-9,
-  equal Krylov counts).
+* Tube (1,999,872 tets, Re 500, p = 0 outlet, Jacobi): the first 2 steps, each recomputed by the
+  oracle from the GPU's solutions (1e-9, true residuals at the tolerance), equal Krylov counts and
+  the solver tolerance against the oracle's own run.
 * A 50,688-tet tube over 50 steps against the oracle (1e-9, equal Krylov counts)."""
 import numpy as np
 import pytest
@@ -132,10 +133,10 @@ def _tube_inlet(m):
     return Ub
 
 
-def _tube_parity(m, nsteps, maxit_p):
+def _tube_parity(m, nsteps, maxit_p, tol=TOL):
     Ub = _tube_inlet(m)
     pb = np.zeros(m.n_boundary_faces)
-    args = dict(nu=1e-3, dt=1e-3, n_corr=2, tol_p=TOL, tol_u=TOL, maxit_p=maxit_p, maxit_u=2000)
+    args = dict(nu=1e-3, dt=1e-3, n_corr=2, tol_p=tol, tol_u=tol, maxit_p=maxit_p, maxit_u=2000)
     U0, p0 = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
     phi0 = O.initial_flux(m, U0, Ub)
     M = B.Mesh(ctx(), m)
@@ -158,9 +159,50 @@ def _tube_parity(m, nsteps, maxit_p):
 
 @pytest.mark.timeout(900)
 def test_tube_full_size_first_two_steps_vs_oracle():
+    """The tube at the configuration's own tolerance (1e-8), Jacobi, first 2 steps.  About 2,000 CG
+    iterations per pressure solve amplify rounding: with equal Krylov counts the GPU's pressure and
+    the oracle's differ by about 1e-9 relative (1.07e-9 measured), so the step is checked in two parts.
+    Every operation of each GPU step is recomputed by the oracle from the GPU's state before it and the
+    GPU's own solve solutions (difvm_piso_step_trace): the next state must match within 1e-9 and each
+    solution's true relative residual must meet 1e-8 up to the rounding margin.  Against the oracle's
+    own run, the Krylov counts must be equal and the states agree within the solver tolerance."""
     m = mg.tube()  # n = 24, m = 10, 217 layers
     assert m.n_cells == 1_999_872
-    _tube_parity(m, 2, 20000)
+    Ub = _tube_inlet(m)
+    pb = np.zeros(m.n_boundary_faces)
+    args = dict(nu=1e-3, dt=1e-3, n_corr=2, tol_p=TOL, tol_u=TOL, maxit_p=20000, maxit_u=2000)
+    U0, p0 = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
+    phi0 = O.initial_flux(m, U0, Ub)
+    M = B.Mesh(ctx(), m)
+    P = B.Piso(M, B.piso_params(**args))
+    P.set_boundary(dev(Ub), dev(pb))
+    P.set_state(dev(U0), dev(p0), dev(phi0))
+    oprm = O.piso_params(**args)
+    its = []
+    for step in range(2):
+        U, p, phi, _ = (host(a) if not isinstance(a, np.ndarray) else a for a in P.get_state())
+        st, it, _, Us, pcorr = P.step_trace()
+        assert st == 0
+        its.append(it)
+        U1, p1, phi1, _ = (host(a) if not isinstance(a, np.ndarray) else a for a in P.get_state())
+        Uo, po, phio, _, ru, rp = O.piso_check_step(m, oprm, U, p, phi, Ub, pb, host(Us), host(pcorr))
+        res = np.concatenate([ru, rp])
+        note(f"tube {m.n_cells} step {step}: gpu iterations {it.tolist()}, true residuals {res.tolist()}")
+        assert np.all(res <= TOL + RES_MARGIN), res
+        for got, ref, name in ((U1, Uo, "U"), (p1, po, "p"), (phi1, phio, "phi")):
+            e = rel_err(got, ref)
+            note(f"tube {m.n_cells} step {step}: {name} against the oracle's step from the GPU's solutions {e:.3e}")
+            assert e <= PISO_BAR, (step, name, e)
+    note(f"tube {m.n_cells}: 2 oracle steps")
+    ro = _oracle_steps(m, oprm, U0, p0, phi0, Ub, pb, 2, label=f"tube {m.n_cells}")
+    assert ro[5] == 0
+    np.testing.assert_array_equal(np.array(its), ro[4])
+    for got, ref, name in ((U1, ro[0], "U"), (p1, ro[1], "p"), (phi1, ro[2], "phi")):
+        e = rel_err(got, ref)
+        note(f"tube {m.n_cells}: {name} against the oracle's own run {e:.3e}")
+        assert e <= TOL, (name, e)
+    P.close()
+    M.close()
 
 
 @pytest.mark.timeout(600)
