@@ -380,6 +380,21 @@ difvm_status difvm_ldu_assemble_laplace(const difvm_mesh* mesh, int bc, const vo
 difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* mesh, double nu, double dt, const void* flux,
                                          const void* U, const void* U_b, difvm_ldu* A, void* b);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): difvm_ldu_assemble_momentum with its scratch (the velocity
+ * gradient, 9 doubles per cell) in a fixed device array of 9 * DIFVM_NOALLOC_MAX_CELLS doubles (9 MiB)
+ * that every GPU the library runs on holds until the process ends; the call allocates nothing
+ * (no hipMalloc, no allocator callback) and computes bitwise what difvm_ldu_assemble_momentum
+ * computes.  The array's address on a device is taken by difvm_ctx_create on that device, so the
+ * mesh's context must exist (it does, the mesh holds it).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.  Synchronises the mesh's stream.  Errors as difvm_ldu_assemble_momentum, plus
+ * DIFVM_ERR_INVALID_ARG for a mesh of more than DIFVM_NOALLOC_MAX_CELLS cells or on a device ordinal
+ * of 64 or more. */
+#define DIFVM_NOALLOC_MAX_CELLS 131072
+difvm_status difvm_ldu_assemble_momentum_noalloc(const difvm_mesh* mesh, double nu, double dt, const void* flux,
+                                                 const void* U, const void* U_b, difvm_ldu* A, void* b);
+
 typedef struct {
   int32_t iters[3];
   double residual[3]; /* final ||r||_2 / ||b||_2 per component */

@@ -129,6 +129,8 @@ _SIGS = {
     "difvm_ldu_spmv": (C.c_int32, [_vp, C.c_int, C.c_int, C.POINTER(Ldu), _vp, _vp]),
     "difvm_ldu_assemble_laplace": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.POINTER(Ldu), _vp]),
     "difvm_ldu_assemble_momentum": (C.c_int32, [_vp, C.c_double, C.c_double, _vp, _vp, _vp, C.POINTER(Ldu), _vp]),
+    "difvm_ldu_assemble_momentum_noalloc": (C.c_int32, [_vp, C.c_double, C.c_double, _vp, _vp, _vp, C.POINTER(Ldu),
+                                                        _vp]),
     "difvm_solve_pcg": (C.c_int32, [_vp, C.POINTER(Ldu), _vp, _vp, C.c_double, C.c_int32, C.POINTER(SolveStats)]),
     "difvm_amg_create": (C.c_int32, [_vp, C.POINTER(Ldu), C.POINTER(_vp)]),
     "difvm_amg_destroy": (C.c_int32, [_vp]),
@@ -482,6 +484,14 @@ def difvm_ldu_assemble_laplace(m, bc, gamma_f, phi_b, A, rhs_bc):
 def difvm_ldu_assemble_momentum(m, nu, dt, flux, U, U_b, A, b):
     return _check(lib().difvm_ldu_assemble_momentum(m, float(nu), float(dt), _ptr(flux), _ptr(U), _ptr(U_b),
                                                     C.byref(A), _ptr(b)), "difvm_ldu_assemble_momentum")
+
+
+def difvm_ldu_assemble_momentum_noalloc(m, nu, dt, flux, U, U_b, A, b):
+    return _check(lib().difvm_ldu_assemble_momentum_noalloc(m, float(nu), float(dt), _ptr(flux), _ptr(U), _ptr(U_b),
+                                                            C.byref(A), _ptr(b)), "difvm_ldu_assemble_momentum_noalloc")
+
+
+NOALLOC_MAX_CELLS = 131072  # DIFVM_NOALLOC_MAX_CELLS of include/difvm.h
 
 
 def difvm_solve_pcg(m, A, b, x, tol, maxit):

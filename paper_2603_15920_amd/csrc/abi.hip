@@ -1,6 +1,7 @@
 // C entry points of libdifvm (declared in include/difvm.h): argument checks, object lifetimes and
 // dispatch to the kernels.  No exception crosses this boundary.
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "abi_util.h"
@@ -263,6 +264,32 @@ void mesh_release(difvm_mesh* m) {
   if (m && --m->refs == 0) free_mesh(m);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Fixed scratch of difvm_ldu_assemble_momentum_noalloc: the velocity gradient (9 doubles per cell)
+// of at most DIFVM_NOALLOC_MAX_CELLS cells, in a device array every GPU holds while the library is
+// loaded.  Host code never uses the array's name as an address: difvm_ctx_create takes the array's
+// device address on its device (hipGetSymbolAddress, once per device, that device current).
+// ---------------------------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[9 * (size_t)DIFVM_NOALLOC_MAX_CELLS];
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static void noalloc_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;  // the entry point refuses such devices
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return;
+  void* p = nullptr;
+  DIFVM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  DIFVM_CHECK(p != nullptr, DIFVM_ERR_HIP, "hipGetSymbolAddress returned NULL for the fixed scratch");
+  g_noalloc_ptr[device] = static_cast<double*>(p);
+}
+
+static double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return (device >= 0 && device < NOALLOC_MAX_DEVICES) ? g_noalloc_ptr[device] : nullptr;
+}
+
 }  // namespace difvm
 
 using namespace difvm;
@@ -284,6 +311,7 @@ difvm_status difvm_ctx_create(int device, void* hip_stream, difvm_ctx** out) {
   DIFVM_HIP(hipGetDeviceCount(&n));
   DIFVM_CHECK(device >= 0 && device < n, DIFVM_ERR_INVALID_ARG, "device ordinal out of range");
   DIFVM_HIP(hipSetDevice(device));
+  noalloc_init(device);  // device address of the fixed scratch on this device (once per device)
   difvm_ctx* c = new difvm_ctx();
   c->c.device = device;
   c->c.stream = static_cast<hipStream_t>(hip_stream);
@@ -648,6 +676,31 @@ difvm_status difvm_ldu_assemble_momentum(const difvm_mesh* m, double nu, double 
   DIFVM_CHECK(U_b || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "U_b is NULL");
   // the gradient of U lives in mesh scratch: no allocation after the first call
   double* gU = mesh_scratch(const_cast<difvm_mesh*>(m), 1, (size_t)9 * m->d.nc);
+  op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
+  op_assemble_momentum(m, DIFVM_CONV_UPWIND, DIFVM_TIME_BACKWARD_EULER, nu, nullptr, dt, (const double*)flux,
+                       (const double*)U, gU, (const double*)U_b, (double*)A->diag, (double*)A->upper,
+                       (double*)A->lower, nullptr, (double*)b);
+  DIFVM_HIP(hipStreamSynchronize(stream_of(m)));
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ldu_assemble_momentum_noalloc(const difvm_mesh* m, double nu, double dt, const void* flux,
+                                                 const void* U, const void* U_b, difvm_ldu* A, void* b) {
+  DIFVM_API_BEGIN
+  check_mesh(m); check_ptr(A, "A"); check_ptr(flux, "flux"); check_ptr(U, "U"); check_ptr(b, "b");
+  DIFVM_CHECK(A->dtype == DIFVM_F64, DIFVM_ERR_UNSUPPORTED, "assembly is F64 only");
+  check_ptr(A->diag, "A->diag");
+  DIFVM_CHECK((A->upper && A->lower) || m->d.nfi == 0, DIFVM_ERR_INVALID_ARG, "A->upper or A->lower is NULL");
+  DIFVM_CHECK(dt > 0, DIFVM_ERR_INVALID_ARG, "dt must be > 0");
+  DIFVM_CHECK(U_b || m->d.nfb == 0, DIFVM_ERR_INVALID_ARG, "U_b is NULL");
+  DIFVM_CHECK(m->d.nc <= DIFVM_NOALLOC_MAX_CELLS, DIFVM_ERR_INVALID_ARG,
+              "difvm_ldu_assemble_momentum_noalloc: the mesh has " + std::to_string(m->d.nc) +
+                  " cells, more than the fixed scratch holds (DIFVM_NOALLOC_MAX_CELLS = " +
+                  std::to_string(DIFVM_NOALLOC_MAX_CELLS) + ")");
+  double* gU = noalloc_scratch(ctx_of(m).device);
+  DIFVM_CHECK(gU != nullptr, DIFVM_ERR_INVALID_ARG, "no fixed scratch on the mesh's device (ordinal >= 64)");
+  // the gradient is written in full before the assembly reads it: nothing to clear
   op_grad(m, DIFVM_F64, 3, DIFVM_BC_U, U, U_b, gU);
   op_assemble_momentum(m, DIFVM_CONV_UPWIND, DIFVM_TIME_BACKWARD_EULER, nu, nullptr, dt, (const double*)flux,
                        (const double*)U, gU, (const double*)U_b, (double*)A->diag, (double*)A->upper,
