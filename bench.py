@@ -303,7 +303,7 @@ def poisson_run(B, mg, torch, ctx, sizes=(12, 18, 25, 56)):
 
 
 def tube_run(B, mg, torch, ctx, steps, precond="amg"):
-    """The full PISO configuration on the straight tube (1,999,872 tets, L/D 10, parabolic inlet at
+    """The full PISO configuration on the straight tube (2,000,640 tets, L/D 10, parabolic inlet at
     Re 500, p = 0 outlet, nu 1e-3, dt 1e-3, 2 correctors, PCG tol 1e-8), from rest: the first step
     untimed, then `steps` timed steps (graph mode off, tuned launch shapes)."""
     import numpy as np
@@ -333,7 +333,7 @@ def tube_run(B, mg, torch, ctx, steps, precond="amg"):
 
 
 def halo_run(B, mg, torch, ctx, n_parts=8, part=3, reps=50):
-    """The part of a single-mesh multi-GPU run that one GPU can show: the 1,999,872-tet tube split into
+    """The part of a single-mesh multi-GPU run that one GPU can show: the 2,000,640-tet tube split into
     n_parts RCM slabs; on one interior slab (one GPU's share) the pack and unpack kernels of one halo
     exchange (scalar and 3-vector rows) and the operators on the slab's cells plus ghosts, all timed
     with HIP events (average over reps back-to-back launches, warm).  The transfer between GPUs is not

@@ -545,7 +545,7 @@ difvm_status difvm_piso_transport_scalar(difvm_piso* piso, double D, int32_t bc,
  * (the graph reads the device buffers).  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */
 difvm_status difvm_piso_set_graph(difvm_piso* piso, int32_t enable, int32_t extra_iters);
 
-/* Graph-mode counters since creation: replayed steps, discarded-and-redone steps, captures. */
+/* Graph-mode counters since creation: kept replays, discarded-and-redone steps, captures. */
 difvm_status difvm_piso_graph_info(const difvm_piso* piso, int64_t* replays, int64_t* redos, int64_t* captures);
 
 /* Drops the AMG hierarchy of the pressure preconditioner (and a captured step using it); the next
@@ -618,8 +618,8 @@ difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* 
  * extra_iters (>= 0).  A shorter last segment (nsteps not a multiple of ckpt_every) runs eagerly, and a
  * new adj_tol recaptures the reverse graph.  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */
 difvm_status difvm_tape_set_graph(difvm_tape* tape, int32_t enable, int32_t extra_iters);
-/* Graph-mode counters of the tape since creation: replayed graphs (two per full segment after the
- * first), discarded-and-redone segments, captures. */
+/* Graph-mode counters of the tape since creation: kept replays (of the recomputation and reverse
+ * graphs; two per full segment after the first), discarded-and-redone replays, captures. */
 difvm_status difvm_tape_graph_info(const difvm_tape* tape, int64_t* replays, int64_t* redos, int64_t* captures);
 
 /* Cotangent of the fixed velocity boundary values U_b of the window from the last difvm_piso_adjoint

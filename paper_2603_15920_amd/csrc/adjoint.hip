@@ -913,7 +913,6 @@ static bool tape_replay(difvm_tape* T, int graph, int* cu, int* cp, int* worst) 
   size_t bytes = (size_t)T->every * G.per_step;
   DIFVM_HIP(hipMemcpyAsync(G.state_host, seg_state(T, graph, 0), bytes, hipMemcpyDeviceToHost, s));
   DIFVM_HIP(hipStreamSynchronize(s));
-  G.replays++;
   bool ok = true;
   int w = 0;
   *cu = *cp = 0;
@@ -931,8 +930,12 @@ static bool tape_replay(difvm_tape* T, int graph, int* cu, int* cp, int* worst) 
       w = std::max(w, rp.status);
     }
   }
-  // a replay that ran out of budget is discarded: its (incomplete) solves' statuses do not count
-  if (ok) *worst = std::max(*worst, w);
+  // a replay that ran out of budget is discarded (counted as a redo by the caller): its
+  // (incomplete) solves' statuses do not count
+  if (ok) {
+    *worst = std::max(*worst, w);
+    G.replays++;
+  }
   return ok;
 }
 

@@ -42,13 +42,18 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
                                                     double* __restrict__ diag, double* __restrict__ upper,
                                                     double* __restrict__ lower, double* __restrict__ slot_val,
                                                     double* __restrict__ b) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  if (i >= m.nc) return;
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * BLOCK;
+  const int i = base + threadIdx.x;
+  __shared__ double lds[NC * BLOCK];
+  double bi[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) bi[c] = 0.0;
+  if (i < m.nc) {
   SlotRange R = slots_of(m, i);
   double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
   double Vdt = m.V[i] / dt;
   double d = Vdt;
-  double bi[NC], ui[NC];
+  double ui[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     ui[c] = U[NC * (size_t)i + c];
@@ -128,8 +133,12 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
     if (slot_val) slot_val[at] = a;
   }
   diag[i] = d;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) b[NC * (size_t)i + c] = bi[c];
+  }
+  if constexpr (NC == 1) {
+    if (i < m.nc) b[i] = bi[0];
+  } else {
+    store_rows<NC>(b, base, m.nc, bi, lds);
+  }
 }
 
 // deferred-correction source alone: out_i = - sum_f sigma F_f (phi^HO - phi^U), internal faces
@@ -271,13 +280,12 @@ __global__ __launch_bounds__(BLOCK) void k_windkessel(int nfi, double dt, const 
 }
 
 // rhs = b - V grad p
+// (one thread per value, so consecutive lanes read and write consecutive doubles)
 __global__ __launch_bounds__(BLOCK) void k_pred_rhs(int nc, const double* __restrict__ V, const double* __restrict__ b,
                                                     const double* __restrict__ gp, double* __restrict__ rhs) {
-  int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= nc) return;
-  double v = V[i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) rhs[3 * (size_t)i + c] = b[3 * (size_t)i + c] - v * gp[3 * (size_t)i + c];
+  size_t e = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= 3 * (size_t)nc) return;
+  rhs[e] = b[e] - V[e / 3] * gp[e];
 }
 
 // H = b - sum_slots a U_j; HbyA = H / d; rAU = V / d
@@ -286,8 +294,11 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
                                                 const double* __restrict__ diag, const double* __restrict__ V,
                                                 const double* __restrict__ b, const double* __restrict__ U,
                                                 double* __restrict__ HbyA, double* __restrict__ rAU) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  if (i >= nc) return;
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * BLOCK;
+  const int i = base + threadIdx.x;
+  __shared__ double lds[3 * BLOCK];
+  double hd[3] = {0.0, 0.0, 0.0};
+  if (i < nc) {
   SlotRange R = slots_of(slice_start, uw, i);
   double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
 #pragma unroll 4
@@ -300,8 +311,10 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
   }
   double d = diag[i];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) HbyA[3 * (size_t)i + c] = h[c] / d;
+  for (int c = 0; c < 3; ++c) hd[c] = h[c] / d;
   rAU[i] = V[i] / d;
+  }
+  store_rows<3>(HbyA, base, nc, hd, lds);
 }
 
 // pressure face quantities: phiH (face flux of HbyA), aF = rAU_f delta_f (fixed-p boundaries only on
@@ -406,8 +419,11 @@ __global__ __launch_bounds__(BLOCK) void k_flux(MeshView<double> m, const double
 __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const double* __restrict__ p,
                                                  const double* __restrict__ pbv, const double* __restrict__ HbyA,
                                                  const double* __restrict__ rAU, double* __restrict__ U) {
-  int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-  if (i >= m.nc) return;
+  const int base = xcd_tile(blockIdx.x, gridDim.x) * BLOCK;
+  const int i = base + threadIdx.x;
+  __shared__ double lds[3 * BLOCK];
+  double un[3] = {0.0, 0.0, 0.0};
+  if (i < m.nc) {
   SlotRange R = slots_of(m, i);
   double pi = p[i];
   double acc[3] = {0.0, 0.0, 0.0};
@@ -438,7 +454,9 @@ __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const doubl
   }
   double s = rAU[i] / m.V[i];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) U[3 * (size_t)i + c] = HbyA[3 * (size_t)i + c] - s * acc[c];
+  for (int c = 0; c < 3; ++c) un[c] = HbyA[3 * (size_t)i + c] - s * acc[c];
+  }
+  store_rows<3>(U, base, m.nc, un, lds);
 }
 
 // phi = interp(U).S with boundary values from the velocity table
@@ -699,7 +717,7 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
                        P->valM, P->bM);
   // S2
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
-  k_pred_rhs<<<Gc, BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
+  k_pred_rhs<<<grid_for(3 * d.nc), BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
   DIFVM_HIP(hipGetLastError());
   SolveResult ru = bicgstab(m, 3, SellMatrix{P->dM, P->valM}, P->rhs, P->U, prm.tol_u, prm.maxit_u, qu ? &qu->u : nullptr,
                             &P->hint_u);
@@ -879,7 +897,6 @@ static void graph_step(difvm_piso* P, difvm_step_stats* out) {
   size_t bytes = G.bytes_u + (size_t)P->prm.n_corr * G.bytes_p;
   DIFVM_HIP(hipMemcpyAsync(G.state_host, G.state_dev, bytes, hipMemcpyDeviceToHost, s));
   DIFVM_HIP(hipStreamSynchronize(s));
-  G.replays++;
   const char* hs = static_cast<const char*>(G.state_host);
   bool ok = true, c1 = true;
   SolveResult ru = bicgstab_result(m, 3, hs, &c1);
@@ -903,6 +920,7 @@ static void graph_step(difvm_piso* P, difvm_step_stats* out) {
     *out = st;
     return;
   }
+  G.replays++;  // kept replays only; a discarded one counts as a redo
   for (int c = 0; c < 3; ++c) {
     st.it_u[c] = ru.iters[c];
     st.res_u[c] = ru.res[c];

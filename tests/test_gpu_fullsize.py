@@ -2,7 +2,7 @@
 * Channel on the 1,053,696-tet Kuhn cube (the benchmark's PISO workload, autotuned launch shapes as in
   the benchmark): the first step from rest against the oracle on the whole mesh (1e-9, equal Krylov
   counts).
-* Tube (1,999,872 tets, Re 500, p = 0 outlet; one oracle step takes minutes here, so properties that
+* Tube (2,000,640 tets, Re 500, p = 0 outlet; one oracle step takes minutes here, so properties that
   hold at any size instead): after four steps from rest the net boundary flux vanishes and every
   cell's flux sum is at the level of the pressure solver's tolerance.
 * Y-bifurcation (401,484 tets, three Windkessel outlets): gradient of a 64-probe misfit with respect
@@ -62,8 +62,8 @@ def test_channel_kuhn56_first_step_vs_oracle():
 
 
 def test_tube_full_size_properties():
-    m = mg.tube()  # n = 24, m = 10, 217 layers
-    assert m.n_cells == 1_999_872
+    m = mg.tube()  # n = 16, m = 6, 521 layers
+    assert m.n_cells == 2_000_640
     Fi = m.n_internal_faces
     Ub = np.zeros((m.n_boundary_faces, 3))
     p = m.patch("inlet")

@@ -208,10 +208,10 @@ def test_part_mesh_refuses_solvers():
 
 @pytest.mark.slow
 def test_full_size_tube_interior_slab():
-    """The 1,999,872-tet tube in 8 slabs: an interior slab (one GPU's share, about 250k cells) and
+    """The 2,000,640-tet tube in 8 slabs: an interior slab (one GPU's share, about 250k cells) and
     an end slab, chained gradient -> exchange -> Laplacian and the symmetric product, bitwise."""
     m = mg.tube()
-    assert m.n_cells == 1_999_872
+    assert m.n_cells == 2_000_640
     t = torch()
     M = B.Mesh(ctx(), m)
     H = Halo(m, 8)

@@ -13,7 +13,7 @@
   within 1e-9 (the solution is unique up to the tolerance), and the distance of the benchmark's
   tol-1e-8 state from it is reported and bounded (1e-6 relative; it is set by the solver tolerance,
   not by the arithmetic).
-* Tube (1,999,872 tets, Re 500, p = 0 outlet, Jacobi): the first 2 steps, each recomputed by the
+* Tube (2,000,640 tets, Re 500, p = 0 outlet, Jacobi): the first 2 steps, each recomputed by the
   oracle from the GPU's solutions (1e-9, true residuals at the tolerance), equal Krylov counts and
   the solver tolerance against the oracle's own run.
 * A 50,688-tet tube over 50 steps against the oracle (1e-9, equal Krylov counts)."""
@@ -166,8 +166,8 @@ def test_tube_full_size_first_two_steps_vs_oracle():
     GPU's own solve solutions (difvm_piso_step_trace): the next state must match within 1e-9 and each
     solution's true relative residual must meet 1e-8 up to the rounding margin.  Against the oracle's
     own run, the Krylov counts must be equal and the states agree within the solver tolerance."""
-    m = mg.tube()  # n = 24, m = 10, 217 layers
-    assert m.n_cells == 1_999_872
+    m = mg.tube()  # n = 16, m = 6, 521 layers
+    assert m.n_cells == 2_000_640
     Ub = _tube_inlet(m)
     pb = np.zeros(m.n_boundary_faces)
     args = dict(nu=1e-3, dt=1e-3, n_corr=2, tol_p=TOL, tol_u=TOL, maxit_p=20000, maxit_u=2000)

@@ -147,3 +147,31 @@ def test_windkessel_exact_exponential():
     np.testing.assert_allclose(hist[1:], closed, rtol=1e-9)
     outlet = m.patch("outlet")
     np.testing.assert_allclose(phi[outlet.start:outlet.start + outlet.size].sum(), Q, rtol=1e-9)
+
+
+def test_tube_section_stays_stable():
+    """The full-size tube's section (butterfly n = 16, m = 6, axial spacing 0.0192, jitter 0.1 h) over
+    the configuration's physics (parabolic inlet u_max = 1, Re 500, dt 1e-3, p = 0 outlet): a 48-layer
+    slice of it settles to the inlet's peak speed and stays there for 20 steps.  (Finer sections,
+    n = 20, m = 8 and n = 24, m = 10, grow a disturbance at the outlet by about 1.9x per step.)  Run on
+    the oracle's threaded build, which computes what the serial build computes (test_oracle_threads)."""
+    m = mg.tube(layers=48, L=48 * 10.0 / 521)
+    Fi = m.n_internal_faces
+    Ub = np.zeros((m.n_boundary_faces, 3))
+    inl = m.patch("inlet")
+    Ub[inl.start - Fi:inl.start - Fi + inl.size] = mg.parabolic_inlet(m.Cf[inl.start:inl.start + inl.size],
+                                                                      (0, 0, 0), m.meta["R"], 1.0)
+    prm = O.piso_params(1e-3, 1e-3, tol_p=1e-8, tol_u=1e-8, maxit_p=20000, maxit_u=2000)
+    U, p = np.zeros((m.n_cells, 3)), np.zeros(m.n_cells)
+    phi = O.initial_flux(m, U, Ub)
+    speed = []
+    try:
+        O.use_threads(True)
+        for k in range(20):
+            U, p, phi, _, it, res, st = O.piso_run(m, prm, U, p, phi, Ub, np.zeros(m.n_boundary_faces), nsteps=1)
+            assert st == 0
+            speed.append(np.linalg.norm(U, axis=1).max())
+    finally:
+        O.use_threads(False)
+    assert max(speed[5:]) < 1.02, speed
+    assert abs(speed[-1] - 1.0) < 0.01, speed
