@@ -206,10 +206,15 @@ def timed(torch, fn):
     return time.perf_counter() - t, r
 
 
-def graph_rate(P, torch, steps, wk, extra=16):
+def graph_rate(P, torch, steps, wk, extra=16, start=None):
     """Eager against graph mode over the same window: the state (U, p, phi, capacitor pressures with
-    Windkessel rows wk) is saved, `steps` eager steps are timed, the state is restored, one step
-    captures the graph, the state is restored again and the same `steps` are timed as replays."""
+    Windkessel rows wk) is saved (or `start` is loaded), `steps` eager steps are timed, the state is
+    restored, one step captures the graph, the state is restored again and the same `steps` are timed
+    as replays."""
+    if start is not None:
+        P.set_state(*start[:3])
+        for j, row in enumerate(wk):
+            P.set_windkessel(j, *row, start[3][j])
     U0, p0, phi0, pc0 = P.get_state()
 
     def restore():
@@ -444,6 +449,13 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=50, precond="amg"):
     cot = [dev(rng.standard_normal((m.n_cells, 3))), dev(rng.standard_normal(m.n_cells)), dev(rng.standard_normal(m.n_faces)),
            rng.standard_normal(len(wk))]
     t_adj, (st_a, gpc, gwk) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
+    # the same reverse sweep with its segments replayed as graphs (the first full segment captures)
+    gU_e = gU.clone()
+    B.difvm_tape_set_graph(T, True, 16)
+    t_adj_g1, (st_g1, _, _) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
+    t_adj_g, (st_g, _, _) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
+    g_info = B.difvm_tape_graph_info(T)
+    same = bool(torch.equal(gU, gU_e))
     B.difvm_tape_destroy(T)
     return {"workload": f"Y-bifurcation {m.n_cells} tets, 3 RCR outlets, nu 1e-3, dt 1e-3, {spinup}-step spin-up, "
                         f"{steps}-step window, checkpoint every {every}, tol 1e-8 ({precond} preconditioner)",
@@ -451,6 +463,10 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=50, precond="amg"):
             "forward_steps_per_s": round(steps / t_fwd, 3), "record_steps_per_s": round(steps / t_rec, 3),
             "adjoint_steps_per_s": round(steps / t_adj, 3), "adjoint_over_forward": round(t_adj / t_fwd, 3),
             "record_over_forward": round(t_rec / t_fwd, 3), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+            "graph_sweep": {"first_sweep_steps_per_s": round(steps / t_adj_g1, 3),
+                            "replayed_sweep_steps_per_s": round(steps / t_adj_g, 3),
+                            "speedup_vs_eager": round(t_adj / t_adj_g, 3), "bitwise_equal_to_eager": same,
+                            "replays_redos_captures": list(g_info), "status": [int(st_g1), int(st_g)]},
             "status": [int(st), int(st_r), int(st_a)]}
 
 
@@ -648,12 +664,13 @@ def main():
             first_iters = it[0].tolist()
         log(f"warmup step {k}: {time.time() - ts:.3f}s iters {it[0].tolist()} status {st}")
 
-    # the state the timed region starts from (the CPU oracle is timed on the step from it)
+    # the state the timed region starts from (the graph-mode window and the CPU oracle start from it)
+    U_s, p_s, phi_s, pc_s = P.get_state()
+    start_dev = (U_s.clone(), p_s.clone(), phi_s.clone(), np.array(pc_s, dtype=np.float64))
     state0 = None
     if not args.no_cpu:
-        U_s, p_s, phi_s, pc_s = P.get_state()
         state0 = (U_s.cpu().numpy(), p_s.cpu().numpy(), phi_s.cpu().numpy(), np.array(pc_s, dtype=np.float64))
-        del U_s, p_s, phi_s
+    del U_s, p_s, phi_s
     # timed region: eager steps, HIP events around every prof_every-th launch of each PCG kernel
     B.difvm_ctx_profile(ctx.h, args.prof_every)
     B.difvm_ctx_profile_read(ctx.h)
@@ -718,7 +735,8 @@ def main():
     if not args.no_graph:
         extras = [int(e) for e in args.graph_extra.split(",")]
         for e in extras:
-            graph = graph_rate(P, torch, args.steps, [wk], extra=e)
+            # the headline's own window (same start state, same steps), eagerly and as replays
+            graph = graph_rate(P, torch, args.steps, [wk], extra=e, start=start_dev)
             log("graph mode", graph)
         small = small_case(B, mg, torch, ctx, precond=args.precond)
         log("small case", small)
@@ -790,6 +808,7 @@ def main():
                    "cells": nc, "internal_faces": nfi, "boundary_faces": nfb, "nu": nu, "dt": dt, "n_corr": 2,
                    "tol_p": 1e-8, "tol_u": 1e-8, "pressure_preconditioner": args.precond},
         "roofline": roofline,
+        "vcycle_roofline": vcycle,
         "cpu_baseline": cpu,
         "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
                    "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st),

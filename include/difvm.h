@@ -539,7 +539,7 @@ difvm_status difvm_piso_transport_scalar(difvm_piso* piso, double D, int32_t bc,
  * bitwise those of eager stepping.  A step in which some solve had not stopped within its budget is
  * discarded (its starting state, saved by the graph, is restored on the device) and run eagerly; the
  * margin grows by one and the graph is recaptured with the larger counts.  The margin starts at
- * min(2, extra_iters) and never exceeds extra_iters (>= 0); when the recent counts fall two or more
+ * min(1, extra_iters) and never exceeds extra_iters (>= 0); when the recent counts fall two or more
  * below the budgets the step is recaptured with tighter ones.  enable = 0 returns to eager stepping.
  * Changing boundary values, Windkessel parameters, viscosity or the state between steps is allowed
  * (the graph reads the device buffers).  Errors: DIFVM_ERR_INVALID_ARG for extra_iters < 0. */

@@ -953,7 +953,7 @@ void piso_set_graph(difvm_piso* P, int enable, int extra) {
   graph_drop(G);
   G.on = enable != 0;
   G.extra = extra;
-  G.margin = std::min(2, extra);
+  G.margin = std::min(1, extra);
   G.nhist = G.hist_at = 0;
   if (!G.on) return;
   difvm_mesh* m = P->mesh;

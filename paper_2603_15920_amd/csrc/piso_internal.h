@@ -9,7 +9,7 @@
 struct PisoGraph {
   bool on = false;
   int extra = 16;                       // largest margin the budgets may carry
-  int margin = 2;                       // iterations added to the recent counts (adapts in [0, extra])
+  int margin = 1;                       // iterations added to the recent counts (adapts in [0, extra])
   int budget_u = 0, budget_p[8] = {};
   static constexpr int HIST = 8;
   int hist_u[HIST] = {}, hist_p[HIST] = {};  // largest counts of the last steps (ring)
