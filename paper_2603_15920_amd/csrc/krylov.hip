@@ -662,13 +662,14 @@ template <int NC, class F>
 __device__ __forceinline__ void sell_row_f(const SellView& A, int i, F&& f, double (&acc)[NC]) {
   SlotRange R = slots_of(A, i);
   double di = A.diag[i];
+  const bool off16 = A.off16 != nullptr;  // the same for every thread: a uniform branch
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * f(i, c);
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     double a = A.val[at];
-    int j = A.col[at];
+    int j = off16 ? i + A.off16[at] : A.col[at];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] += a * f(j, c);
   }
@@ -702,27 +703,19 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   const BiState* st = sts + ti.s;
   if (!st->any) return;
   double acc[NC];
-  bool keep[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    acc[c] = 0.0;
-    keep[c] = st->active[c] != 0;
-  }
-  __shared__ double lds[NC * BLOCK];
-  FOR_TILE_ROUNDS(base, i) {
-    double ay[NC] = {};
-    if (i < ti.hi) {
-      sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  // (staging these stores through LDS measured slower here: the rounds' barriers hold back the
+  // gathers of the waves that could run ahead)
+  FOR_TILE_CELLS(i) {
+    double ay[NC];
+    sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (!keep[c]) continue;
-        acc[c] += rh[(size_t)i * NC + c] * ay[c];
-      }
-    }
-    if constexpr (NC == 1) {
-      if (i < ti.hi && keep[0]) v[i] = ay[0];
-    } else {
-      store_rows_if<NC>(v, base, ti.hi, ay, keep, lds);
+    for (int c = 0; c < NC; ++c) {
+      if (!st->active[c]) continue;
+      size_t at = (size_t)i * NC + c;
+      v[at] = ay[c];
+      acc[c] += rh[at] * ay[c];
     }
   }
   put_partial<NC>(acc, part, T.ntile, ti.t);
@@ -740,36 +733,23 @@ __global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const doubl
   double acc[3 * NC];
 #pragma unroll
   for (int k = 0; k < 3 * NC; ++k) acc[k] = 0.0;
-  bool keep[NC];
+  FOR_TILE_CELLS(i) {
+    auto s_of = [&](int j, int c) {
+      size_t at = (size_t)j * NC + c;
+      return r[at] - st->alpha[c] * v[at];
+    };
+    double az[NC];
+    sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
 #pragma unroll
-  for (int c = 0; c < NC; ++c) keep[c] = st->active[c] != 0;
-  __shared__ double lds[NC * BLOCK];
-  auto s_of = [&](int j, int c) {
-    size_t at = (size_t)j * NC + c;
-    return r[at] - st->alpha[c] * v[at];
-  };
-  FOR_TILE_ROUNDS(base, i) {
-    double az[NC] = {}, sv[NC] = {};
-    if (i < ti.hi) {
-      sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (!keep[c]) continue;
-        double si = s_of(i, c);
-        sv[c] = si;
-        acc[c] += az[c] * si;
-        acc[NC + c] += az[c] * az[c];
-        acc[2 * NC + c] += si * si;
-      }
-    }
-    if constexpr (NC == 1) {
-      if (i < ti.hi && keep[0]) {
-        s[i] = sv[0];
-        t[i] = az[0];
-      }
-    } else {
-      store_rows_if<NC>(s, base, ti.hi, sv, keep, lds);
-      store_rows_if<NC>(t, base, ti.hi, az, keep, lds);
+    for (int c = 0; c < NC; ++c) {
+      if (!st->active[c]) continue;
+      size_t at = (size_t)i * NC + c;
+      double si = s_of(i, c);
+      s[at] = si;
+      t[at] = az[c];
+      acc[c] += az[c] * si;
+      acc[NC + c] += az[c] * az[c];
+      acc[2 * NC + c] += si * si;
     }
   }
   put_partial<3 * NC>(acc, part, T.ntile, ti.t);

@@ -32,11 +32,12 @@ __device__ __forceinline__ void sell_row(const SellView& A, int i, const double*
   double di = A.diag[i];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
+  const bool off16 = A.off16 != nullptr;  // the same for every thread: a uniform branch
 #pragma unroll 4
   for (int k = 0; k < R.width; ++k) {
     int at = R.base + k * SLICE;
     double a = A.val[at];
-    int j = A.col[at];
+    int j = off16 ? i + A.off16[at] : A.col[at];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
   }
