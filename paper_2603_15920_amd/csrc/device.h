@@ -111,6 +111,71 @@ __device__ __forceinline__ void walk_row(int n, F&& body) {
   for (; k0 < n; ++k0) body(std::integral_constant<int, 1>{}, k0);
 }
 
+__device__ __forceinline__ bool slot_internal(int sf, int nfi) { return sf != SLOT_PAD && sf < nfi; }
+__device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_internal(sf, nfi) ? (sf < 0 ? -sf - 1 : sf) : 0; }
+
+// Gauss-gradient face sum of cell i (the Gauss gradient times V_i): acc[c] = sum over the row's slots
+// of sigma phi_f S_f, phi_f = w phi_i + (1 - w) phi_j on internal faces (w this cell's weight), the
+// boundary table's fixed value or phi_i on boundary faces.  Slots in layout order, the first four
+// (two for vectors) with all their loads issued before any is used (walk_row).
+template <class T, int NC>
+__device__ __forceinline__ void gauss_row_sum(const MeshView<T>& m, int table, const T* __restrict__ phi,
+                                              const T* __restrict__ phib, int i, T (&acc)[NC][3]) {
+  SlotRange R = slots_of(m, i);
+  T pi[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    pi[c] = phi[(size_t)i * NC + c];
+    acc[c][0] = acc[c][1] = acc[c][2] = T(0);
+  }
+  const int8_t* code = m.bcode + table * m.nfb;
+  walk_row<(NC == 3 ? 2 : 4)>(row_len(m, i, R), [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    int sf[N], j[N];
+    typename Geo<T>::v4 g[N];
+    T pj[N][NC];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      int at = R.base + (k0 + k) * SLICE;
+      sf[k] = m.slot_face[at];
+      j[k] = m.slot_col[at];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      g[k] = m.geomS[slot_face_index(sf[k], m.nfi)];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pj[k][c] = phi[(size_t)j[k] * NC + c];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (sf[k] == SLOT_PAD) continue;
+      if (sf[k] < m.nfi) {
+        bool nb = sf[k] < 0;
+        T wself = nb ? T(1) - g[k].w : g[k].w;  // weight of this cell in phi_f
+        T sg = nb ? T(-1) : T(1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T pf = sg * (wself * pi[c] + (T(1) - wself) * pj[k][c]);
+          acc[c][0] += pf * g[k].x;
+          acc[c][1] += pf * g[k].y;
+          acc[c][2] += pf * g[k].z;
+        }
+      } else {
+        int b = sf[k] - m.nfi;
+        auto gb = m.bgeom[b];
+        bool fixed = code[b] == BC_FIXED;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T pf = fixed ? phib[(size_t)b * NC + c] : pi[c];
+          acc[c][0] += pf * gb.x;
+          acc[c][1] += pf * gb.y;
+          acc[c][2] += pf * gb.z;
+        }
+      }
+    }
+  });
+}
+
 // ---------------------------------------------------------------------------------------------
 // Stores of cell-major rows ([n][NC]: vectors, gradients).  One thread per row storing its NC values
 // writes at a stride of NC values, so each store instruction covers only part of every cache line it

@@ -105,8 +105,6 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_interp(MeshView<T> m, int tabl
 // one at a time.  (Two-slot chunks in the Laplacian raise occupancy but were slower: the second
 // chunk's loads wait for the first's.)
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ bool slot_internal(int sf, int nfi) { return sf != SLOT_PAD && sf < nfi; }
-__device__ __forceinline__ int slot_face_index(int sf, int nfi) { return slot_internal(sf, nfi) ? (sf < 0 ? -sf - 1 : sf) : 0; }
 
 
 // ---------------------------------------------------------------------------------------------
@@ -119,66 +117,13 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
   const int i = base + threadIdx.x;
   T res[3 * NC];
   if (i < m.nc) {
-  SlotRange R = slots_of(m, i);
-  T pi[NC], acc[NC][3];
+    T acc[NC][3];
+    gauss_row_sum<T, NC>(m, table, phi, phib, i, acc);
+    T rv = T(1) / m.V[i];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    pi[c] = phi[(size_t)i * NC + c];
-    acc[c][0] = acc[c][1] = acc[c][2] = T(0);
-  }
-  const int8_t* code = m.bcode + table * m.nfb;
-  walk_row<(NC == 3 ? 2 : 4)>(row_len(m, i, R), [&](auto Wc, int k0) {
-    constexpr int N = decltype(Wc)::value;
-    {
-      int sf[N], j[N];
-      typename Geo<T>::v4 g[N];
-      T pj[N][NC];
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        int at = R.base + (k0 + k) * SLICE;
-        sf[k] = m.slot_face[at];
-        j[k] = m.slot_col[at];
-      }
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        g[k] = m.geomS[slot_face_index(sf[k], m.nfi)];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) pj[k][c] = phi[(size_t)j[k] * NC + c];
-      }
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        if (sf[k] == SLOT_PAD) continue;
-        if (sf[k] < m.nfi) {
-          bool nb = sf[k] < 0;
-          T wself = nb ? T(1) - g[k].w : g[k].w;   // weight of this cell in phi_f
-          T sg = nb ? T(-1) : T(1);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            T pf = sg * (wself * pi[c] + (T(1) - wself) * pj[k][c]);
-            acc[c][0] += pf * g[k].x;
-            acc[c][1] += pf * g[k].y;
-            acc[c][2] += pf * g[k].z;
-          }
-        } else {
-          int b = sf[k] - m.nfi;
-          auto gb = m.bgeom[b];
-          bool fixed = code[b] == BC_FIXED;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            T pf = fixed ? phib[(size_t)b * NC + c] : pi[c];
-            acc[c][0] += pf * gb.x;
-            acc[c][1] += pf * gb.y;
-            acc[c][2] += pf * gb.z;
-          }
-        }
-      }
-    }
-  });
-  T rv = T(1) / m.V[i];
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int e = 0; e < 3; ++e) res[3 * c + e] = acc[c][e] * rv;
+      for (int e = 0; e < 3; ++e) res[3 * c + e] = acc[c][e] * rv;
   }
   store_rows<3 * NC>(out, base, m.nc, res, dyn_lds<T>());
 }

@@ -424,37 +424,11 @@ __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const doubl
   __shared__ double lds[3 * BLOCK];
   double un[3] = {0.0, 0.0, 0.0};
   if (i < m.nc) {
-  SlotRange R = slots_of(m, i);
-  double pi = p[i];
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    int j = m.slot_col[at];
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      auto g = m.geomS[f];
-      double wself = nb ? 1.0 - g.w : g.w;
-      double pf = (nb ? -1.0 : 1.0) * (wself * pi + (1.0 - wself) * p[j]);
-      acc[0] += pf * g.x;
-      acc[1] += pf * g.y;
-      acc[2] += pf * g.z;
-    } else {
-      int b = sf - m.nfi;
-      auto g = m.bgeom[b];
-      double pf = codeP[b] == BC_FIXED ? pbv[b] : pi;
-      acc[0] += pf * g.x;
-      acc[1] += pf * g.y;
-      acc[2] += pf * g.z;
-    }
-  }
-  double s = rAU[i] / m.V[i];
+    double acc[1][3];
+    gauss_row_sum<double, 1>(m, DIFVM_BC_P, p, pbv, i, acc);
+    double s = rAU[i] / m.V[i];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) un[c] = HbyA[3 * (size_t)i + c] - s * acc[c];
+    for (int c = 0; c < 3; ++c) un[c] = HbyA[3 * (size_t)i + c] - s * acc[0][c];
   }
   store_rows<3>(U, base, m.nc, un, lds);
 }

@@ -240,3 +240,19 @@ def test_full_size_operators(cube56):
         out = empty(m.n_faces, dt)
         B.difvm_op_interp(M.h, 1, B.BC_ALL_FIXED, p, pb, out)
         assert rel_err(to_user(M, out, B.KIND_FACE), refs["interp"]) <= bar
+    # LDU products (plain and transposed, one and three components) at the same size
+    d, u, l = random_ldu(m, 5)
+    r = B.difvm_mesh_renumber_host(m)
+    fl = r["face_flip"].astype(bool)
+    ui = np.where(fl, l[r["face_perm"]], u[r["face_perm"]])
+    li = np.where(fl, u[r["face_perm"]], l[r["face_perm"]])
+    rng = np.random.default_rng(6)
+    for ncomp, transpose in ((1, 0), (1, 1), (3, 0)):
+        x = rng.standard_normal((m.n_cells, ncomp)) if ncomp > 1 else rng.standard_normal(m.n_cells)
+        ref = O.spmv(m, d, u, l, x, transpose=bool(transpose))
+        for dt, bar in ((t.float64, F64_BAR), (t.float32, F32_BAR)):
+            note("full-size spmv", ncomp, transpose, dt)
+            A = B.ldu(to_int(M, d, B.KIND_CELL, dt), dev(ui, dt), dev(li, dt))
+            y = empty(x.shape, dt)
+            B.difvm_ldu_spmv(M.h, ncomp, transpose, A, to_int(M, x, B.KIND_CELL, dt), y)
+            assert rel_err(to_user(M, y, B.KIND_CELL), ref) <= bar, (ncomp, transpose, dt)
