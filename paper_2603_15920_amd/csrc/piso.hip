@@ -49,90 +49,109 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(MeshView<double> m, int tabl
 #pragma unroll
   for (int c = 0; c < NC; ++c) bi[c] = 0.0;
   if (i < m.nc) {
-  SlotRange R = slots_of(m, i);
-  double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
-  double Vdt = m.V[i] / dt;
-  double d = Vdt;
-  double ui[NC];
+    SlotRange R = slots_of(m, i);
+    double nu = nu_cell ? nu_cell[i] : nu_all;  // faces never join cells of different viscosity
+    double Vdt = m.V[i] / dt;
+    double d = Vdt;
+    double ui[NC], gi[3 * NC];  // own values and gradient, kept in registers
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    ui[c] = U[NC * (size_t)i + c];
-    bi[c] = Vdt * ui[c];
-  }
-  const double* gi = gU + 3 * NC * (size_t)i;
-  const int8_t* codeU = m.bcode + table * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    double a = 0.0;
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      int j = m.slot_col[at];
-      double F = flux[f];
-      auto kd = m.geomK[f];
-      double nd = nu * kd.w;
-      double Fp = F >= 0.0 ? F : 0.0;  // max(F,0): the tie F = 0 belongs to the owner
-      double Fm = F < 0.0 ? F : 0.0;   // min(F,0)
-      double ad = nb ? -Fm + nd : Fp + nd;  // this face's part of the diagonal
-      double ao = nb ? -Fp - nd : Fm - nd;  // coefficient of the other cell (lower / upper)
-      d += theta * ad;
-      a = theta * ao;
-      if (!nb) {
-        if (upper) upper[f] = a;
-      } else {
-        if (lower) lower[f] = a;
-      }
-      const double* uj = U + NC * (size_t)j;
-      if (theta != 1.0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * (ad * ui[c] + ao * uj[c]);
-      }
-      double w = m.w[f];
-      double wself = nb ? 1.0 - w : w;
-      const double* gj = gU + 3 * NC * (size_t)j;
-      double sg = nb ? -nu : nu;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        double corr = kd.x * (wself * gi[3 * c] + (1.0 - wself) * gj[3 * c]) +
-                      kd.y * (wself * gi[3 * c + 1] + (1.0 - wself) * gj[3 * c + 1]) +
-                      kd.z * (wself * gi[3 * c + 2] + (1.0 - wself) * gj[3 * c + 2]);
-        bi[c] += sg * corr;
-      }
-      if constexpr (CONV != DIFVM_CONV_UPWIND) {
-        double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
-        bool up = dc_self_up(F, nb);
-        double sF = nb ? F : -F;  // owner side: b -= F delta; neighbour side: b += F delta
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          bi[c] += sF * dc_delta<CONV>(up, wself, ui[c], uj[c], gi + 3 * c, gj + 3 * c, rs, ro);
-      }
-    } else {
-      int bf = sf - m.nfi;
-      int8_t code = codeU[bf];
-      double F = flux[m.nfi + bf];
-      if (code == BC_FIXED) {
-        double nd = nu * m.bgeom[bf].w;
-        d += theta * nd;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) bi[c] += (nd - F) * Ub[NC * (size_t)bf + c];
-        if (theta != 1.0) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * nd * ui[c];
-        }
-      } else if (code == BC_ZEROGRAD) {
-        d += theta * F;
-        if (theta != 1.0) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * F * ui[c];
-        }
-      }
+    for (int c = 0; c < NC; ++c) {
+      ui[c] = U[NC * (size_t)i + c];
+      bi[c] = Vdt * ui[c];
     }
-    if (slot_val) slot_val[at] = a;
-  }
-  diag[i] = d;
+#pragma unroll
+    for (int e = 0; e < 3 * NC; ++e) gi[e] = gU[3 * NC * (size_t)i + e];
+    const int8_t* codeU = m.bcode + table * m.nfb;
+    // slots in layout order; the first two (four for scalars) with all their loads issued before any
+    // is used (walk_row; every index in range whatever the slot holds)
+    walk_row<(NC == 3 ? 2 : 4)>(row_len(m, i, R), [&](auto Wc, int k0) {
+      constexpr int N = decltype(Wc)::value;
+      int sf[N], j[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        sf[k] = m.slot_face[at];
+        j[k] = m.slot_col[at];
+      }
+      double F[N], wf[N], uj[N][NC], gj[N][3 * NC];
+      double4 kd[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        int f = slot_face_index(sf[k], m.nfi);                            // 0 for boundary and padding
+        int fl = sf[k] == SLOT_PAD ? 0 : (sf[k] < m.nfi ? f : sf[k]);    // flux index (boundary: nfi + b)
+        F[k] = flux[fl];
+        kd[k] = m.geomK[f];
+        wf[k] = m.w[f];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uj[k][c] = U[NC * (size_t)j[k] + c];
+#pragma unroll
+        for (int e = 0; e < 3 * NC; ++e) gj[k][e] = gU[3 * NC * (size_t)j[k] + e];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        int at = R.base + (k0 + k) * SLICE;
+        if (sf[k] == SLOT_PAD) continue;
+        double a = 0.0;
+        if (sf[k] < m.nfi) {
+          bool nb = sf[k] < 0;
+          int f = nb ? -sf[k] - 1 : sf[k];
+          double nd = nu * kd[k].w;
+          double Fp = F[k] >= 0.0 ? F[k] : 0.0;  // max(F,0): the tie F = 0 belongs to the owner
+          double Fm = F[k] < 0.0 ? F[k] : 0.0;   // min(F,0)
+          double ad = nb ? -Fm + nd : Fp + nd;    // this face's part of the diagonal
+          double ao = nb ? -Fp - nd : Fm - nd;    // coefficient of the other cell (lower / upper)
+          d += theta * ad;
+          a = theta * ao;
+          if (!nb) {
+            if (upper) upper[f] = a;
+          } else {
+            if (lower) lower[f] = a;
+          }
+          if (theta != 1.0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * (ad * ui[c] + ao * uj[k][c]);
+          }
+          double wself = nb ? 1.0 - wf[k] : wf[k];
+          double sg = nb ? -nu : nu;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            double corr = kd[k].x * (wself * gi[3 * c] + (1.0 - wself) * gj[k][3 * c]) +
+                          kd[k].y * (wself * gi[3 * c + 1] + (1.0 - wself) * gj[k][3 * c + 1]) +
+                          kd[k].z * (wself * gi[3 * c + 2] + (1.0 - wself) * gj[k][3 * c + 2]);
+            bi[c] += sg * corr;
+          }
+          if constexpr (CONV != DIFVM_CONV_UPWIND) {
+            double4 rs = nb ? rN[f] : rO[f], ro = nb ? rO[f] : rN[f];
+            bool up = dc_self_up(F[k], nb);
+            double sF = nb ? F[k] : -F[k];  // owner side: b -= F delta; neighbour side: b += F delta
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+              bi[c] += sF * dc_delta<CONV>(up, wself, ui[c], uj[k][c], gi + 3 * c, gj[k] + 3 * c, rs, ro);
+          }
+        } else {
+          int bf = sf[k] - m.nfi;
+          int8_t code = codeU[bf];
+          if (code == BC_FIXED) {
+            double nd = nu * m.bgeom[bf].w;
+            d += theta * nd;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) bi[c] += (nd - F[k]) * Ub[NC * (size_t)bf + c];
+            if (theta != 1.0) {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * nd * ui[c];
+            }
+          } else if (code == BC_ZEROGRAD) {
+            d += theta * F[k];
+            if (theta != 1.0) {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) bi[c] -= (1.0 - theta) * F[k] * ui[c];
+            }
+          }
+        }
+        if (slot_val) slot_val[at] = a;
+      }
+    });
+    diag[i] = d;
   }
   if constexpr (NC == 1) {
     if (i < m.nc) b[i] = bi[0];
