@@ -13,16 +13,26 @@ import torch
 from .autograd import piso_window
 
 
+def patch_pressure_observer(mesh, patches, device="cuda:0", with_capacitors=False):
+    """obs(U, p, pc): the mean pressure over the cells next to each named patch, in the given order,
+    followed by the Windkessel capacitor pressures when with_capacitors (a differentiable torch
+    vector).  Next to an RCR outlet the pressure is about pc + Rp Q (eq. windkessel_Q), so observing
+    the outlets as well as the capacitors makes the proximal resistances identifiable."""
+    groups = []
+    for name in patches:
+        pt = mesh.patch(name)
+        groups.append(torch.as_tensor(sorted(set(mesh.owner[pt.start:pt.start + pt.size].tolist())), device=device))
+
+    def obs(U, p, pc):
+        v = torch.stack([p[c].mean() for c in groups])
+        return torch.cat([v, pc.to(v.device)]) if with_capacitors else v
+    return obs
+
+
 def inlet_pressure_observer(mesh, patch="inlet", device="cuda:0", with_capacitors=False):
     """obs(U, p, pc): the mean pressure over the cells next to a patch, followed by the Windkessel
     capacitor pressures when with_capacitors (a differentiable torch vector)."""
-    pt = mesh.patch(patch)
-    cells = torch.as_tensor(sorted(set(mesh.owner[pt.start:pt.start + pt.size].tolist())), device=device)
-
-    def obs(U, p, pc):
-        v = p[cells].mean().reshape(1)
-        return torch.cat([v, pc.to(v.device)]) if with_capacitors else v
-    return obs
+    return patch_pressure_observer(mesh, (patch,), device, with_capacitors)
 
 
 def simulate_series(piso, theta, state0, n_windows, steps, observe, ckpt_every=None, adj_tol=1e-10):
