@@ -539,6 +539,39 @@ def batch_run(B, mg, torch, ctx, n_members, steps, adj_steps, precond="amg"):
     return out
 
 
+def oracle_operator_times(O, m, reps=5):
+    """The oracle's FP64 face operators on the operator sweep's inputs (same fields and seeds), one
+    core, median of `reps` calls, with internal faces per second."""
+    import numpy as np
+    from paper_2603_15920_amd import meshgen as mg
+    nfi = m.n_internal_faces
+    f = mg.sinusoid_field(2603012)
+    phi, phib = f(m.C), f(m.Cf[nfi:])
+    U = np.stack([mg.sinusoid_field(2603013 + k)(m.C) for k in range(3)], 1)
+    Ub = np.stack([mg.sinusoid_field(2603013 + k)(m.Cf[nfi:]) for k in range(3)], 1)
+    g = O.grad(m, phi, phib)
+    flux = np.einsum("fi,fi->f", O.interp(m, U, Ub), m.Sf)
+    rng = np.random.default_rng(5)
+    d, up, lo = np.full(m.n_cells, 6.0), -rng.random(nfi), -rng.random(nfi)
+    calls = {"grad": lambda: O.grad(m, phi, phib),
+             "laplacian": lambda: O.laplacian(m, phi, g, phib),
+             "div_upwind_vec": lambda: O.div(m, flux, U, Ub, scheme=O.SCHEME_UPWIND),
+             "spmv": lambda: O.spmv(m, d, up, lo, phi),
+             "spmv_sym": lambda: O.spmv(m, d, up, up, phi),
+             "interp": lambda: O.interp(m, phi, phib)}
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[len(ts) // 2]
+        out[name] = {"ms": round(t * 1e3, 2), "faces_per_s": round(nfi / t, 1)}
+    return out
+
+
 def cpu_info():
     """CPU model from lscpu (else /proc/cpuinfo) and the host threads available to this process."""
     model = ""
@@ -783,6 +816,8 @@ def main():
                              "status": int(r[6])}
             log(f"cpu oracle ({variant})", legs[variant])
         O.use_threads(False)
+        ops_cpu = oracle_operator_times(O, m)
+        log("cpu oracle operators (one core)", ops_cpu)
         om = legs["omp"]
         cpu = {"value": round(1.0 / om["seconds"], 5), "unit": "steps/s", "cores": om["threads"], "kind": "oracle",
                "sample": f"one PISO step of the oracle from the GPU's state at the start of the timed region (step "
@@ -794,8 +829,9 @@ def main():
                                "seconds": legs["serial"]["seconds"]},
                "threading": "OpenMP over the Krylov kernels (LDU product and dot products: contiguous face and "
                             "cell ranges per thread, partial sums added in thread order)",
-               "cpu_model": cpu_info(), "compiler": OB.compiler_version(),
-               "flags": "-O2 -fno-fast-math -ffp-contract=off (-fopenmp)"}
+               "operators_single_core": {"sample": "the oracle's FP64 face operators on the operator workload's "
+                                                   "inputs, median of 5 calls", **ops_cpu},
+               "cpu_model": cpu_info(), "compiler": OB.compiler_version(), "flags": " ".join(OB.FLAGS_SHOWN)}
         log("cpu oracle", cpu)
 
     line = {

@@ -10,8 +10,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.cpp")
 OUT = os.path.join(HERE, "liboracle.so")
 OUT_OMP = os.path.join(HERE, "liboracle_omp.so")
-FLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra",
+# -O3 without -march=native: the library built here also runs on the GPU host, whose CPU may lack
+# instructions this one has; strict IEEE either way (no fast-math, no contraction, so no reordering)
+FLAGS = ["-std=c++17", "-O3", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra",
          "-Wno-unused-parameter", "-Wno-unknown-pragmas"]
+FLAGS_SHOWN = ["-O3", "-fno-fast-math", "-ffp-contract=off", "(-fopenmp for the all-threads build)"]
 
 
 def build(verbose=False):

@@ -172,14 +172,25 @@ __device__ __forceinline__ int slot_col_of(const SellView& K, int i, int at) {
 
 // Off-diagonal part of row i of K applied to f: sum over the row's slots of K_ij f(j) (padding and
 // boundary slots hold 0 and the row's own index)
+// (slots in layout order, the first four with every load issued before any is used)
 template <bool OFF16, class F>
 __device__ __forceinline__ double sell_offdiag(const SellView& K, int i, SlotRange R, F&& f) {
   double acc = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    acc += K.val[at] * f(slot_col_of<OFF16>(K, i, at));
-  }
+  walk_row<4>(R.width, [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    double a[N], fj[N];
+    int j[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      int at = R.base + (k0 + k) * SLICE;
+      a[k] = K.val[at];
+      j[k] = slot_col_of<OFF16>(K, i, at);
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) fj[k] = f(j[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc += a[k] * fj[k];
+  });
   return acc;
 }
 

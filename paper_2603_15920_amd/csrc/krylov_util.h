@@ -25,7 +25,9 @@ inline SellView sview(const difvm_mesh* m, SellMatrix A) {
   return {m->d.nc, m->d.cell_nslot, m->d.slice_start, m->d.slot_col, A.val, A.diag, m->d.slot_off16, m->d.uw};
 }
 
-// (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i
+// (A x)_i for NC interleaved components; padding and boundary slots carry val = 0, col = i.  The
+// row's slots in layout order (the slice's width; padding adds nothing), the first four with every
+// load issued before any is used (walk_row).
 template <int NC>
 __device__ __forceinline__ void sell_row(const SellView& A, int i, const double* __restrict__ x, double (&acc)[NC]) {
   SlotRange R = slots_of(A, i);
@@ -33,14 +35,25 @@ __device__ __forceinline__ void sell_row(const SellView& A, int i, const double*
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = di * x[(size_t)i * NC + c];
   const bool off16 = A.off16 != nullptr;  // the same for every thread: a uniform branch
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    double a = A.val[at];
-    int j = off16 ? i + A.off16[at] : A.col[at];
+  walk_row<4>(R.width, [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    double a[N], xj[N][NC];
+    int j[N];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += a * x[(size_t)j * NC + c];
-  }
+    for (int k = 0; k < N; ++k) {
+      int at = R.base + (k0 + k) * SLICE;
+      a[k] = A.val[at];
+      j[k] = off16 ? i + A.off16[at] : A.col[at];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xj[k][c] = x[(size_t)j[k] * NC + c];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += a[k] * xj[k][c];
+  });
 }
 
 // ---------------------------------------------------------------------------------------------

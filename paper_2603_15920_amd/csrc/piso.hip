@@ -320,14 +320,26 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
   if (i < nc) {
   SlotRange R = slots_of(slice_start, uw, i);
   double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    double a = val[at];
-    int j = col[at];
+  // slots in layout order, the first four with every load issued before any is used
+  walk_row<4>(R.width, [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    double a[N], uj[N][3];
+    int j[N];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) h[c] -= a * U[3 * (size_t)j + c];
-  }
+    for (int k = 0; k < N; ++k) {
+      int at = R.base + (k0 + k) * SLICE;
+      a[k] = val[at];
+      j[k] = col[at];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uj[k][c] = U[3 * (size_t)j[k] + c];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[c] -= a[k] * uj[k][c];
+  });
   double d = diag[i];
 #pragma unroll
   for (int c = 0; c < 3; ++c) hd[c] = h[c] / d;
