@@ -721,11 +721,27 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   put_partial<NC>(acc, part, T.ntile, ti.t);
 }
 
-// s = r - alpha v (stored for k_bi_x), t = A z with z = s / d (the neighbours' s formed from r and v);
-// partials t.s, t.t, s.s
+// s = r - alpha v, one thread per value of the tile's rows (as k_bi_dir)
 template <int NC>
-__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const double* __restrict__ r,
-                                                const double* __restrict__ v, double* __restrict__ s,
+__global__ __launch_bounds__(BLOCK) void k_bi_s(Tiles T, const double* __restrict__ r, const double* __restrict__ v,
+                                                double* __restrict__ s, const BiState* sts) {
+  TileIdx ti = tile_idx(T);
+  const BiState* st = sts + ti.s;
+  if (!st->any) return;
+  const int e1 = NC * ti.hi;
+#pragma unroll
+  for (int q = 0; q < NC * CPT; ++q) {
+    int e = NC * ti.lo + q * BLOCK + (int)threadIdx.x;
+    if (e >= e1) break;
+    int c = e % NC;
+    if (!st->active[c]) continue;
+    s[e] = r[e] - st->alpha[c] * v[e];
+  }
+}
+
+// t = A z with z = s / d (s gathered from the pass above); partials t.s, t.t, s.s
+template <int NC>
+__global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const double* __restrict__ s,
                                                 double* __restrict__ t, double* __restrict__ part, const BiState* sts) {
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
@@ -734,18 +750,13 @@ __global__ __launch_bounds__(BLOCK) void k_bi_t(SellView A, Tiles T, const doubl
 #pragma unroll
   for (int k = 0; k < 3 * NC; ++k) acc[k] = 0.0;
   FOR_TILE_CELLS(i) {
-    auto s_of = [&](int j, int c) {
-      size_t at = (size_t)j * NC + c;
-      return r[at] - st->alpha[c] * v[at];
-    };
     double az[NC];
-    sell_row_f<NC>(A, i, [&](int j, int c) { return s_of(j, c) / A.diag[j]; }, az);
+    sell_row_f<NC>(A, i, [&](int j, int c) { return s[(size_t)j * NC + c] / A.diag[j]; }, az);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
       size_t at = (size_t)i * NC + c;
-      double si = s_of(i, c);
-      s[at] = si;
+      double si = s[at];
       t[at] = az[c];
       acc[c] += az[c] * si;
       acc[NC + c] += az[c] * az[c];
@@ -861,7 +872,8 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
       k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->bi);
       k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->p, w->v, w->rh, part, w->bi);
       k_bi_fin<NC, NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
-      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->v, w->s, w->t, part, w->bi);
+      k_bi_s<NC><<<G, BLOCK, 0, s>>>(T, w->r, w->v, w->s, w->bi);
+      k_bi_t<NC><<<G, BLOCK, 0, s>>>(V, T, w->s, w->t, part, w->bi);
       k_bi_fin<NC, 3 * NC><<<nseg, BLOCK, 0, s>>>(BI_SO, part, T, w->bi);
       k_bi_x<NC><<<G, BLOCK, 0, s>>>(V, T, x, w->r, w->rh, w->p, w->s, w->t, part, w->bi);
       k_bi_fin<NC, 2 * NC><<<nseg, BLOCK, 0, s>>>(BI_X, part, T, w->bi);
