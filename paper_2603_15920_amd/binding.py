@@ -171,6 +171,9 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2603_15920_amd/build.py`")
+        # torch first: its bundled HIP runtime then serves this library too (same soname).  Loaded the
+        # other way round, the process holds two HIP runtimes and the second finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
