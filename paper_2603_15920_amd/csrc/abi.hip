@@ -177,9 +177,11 @@ static void upload_mesh(difvm_mesh* m) {
   d.slice_start = up_vec(m, L.slice_start);
   d.slot_face = up_vec(m, L.slot_face);
   d.slot_col = up_vec(m, L.slot_col);
+  // the PCG product reads columns as 16-bit offsets from the row when RCM keeps them that close
+  // (declared here, like every host array uploaded below, so that it outlives the asynchronous
+  // copies until the synchronisation at the end)
+  std::vector<int16_t> off(L.slot_col.size(), 0);
   {
-    // the PCG product reads columns as 16-bit offsets from the row when RCM keeps them that close
-    std::vector<int16_t> off(L.slot_col.size(), 0);
     bool fits = true;
     for (int sl = 0; sl < L.nslice && fits; ++sl)
       for (int at = L.slice_start[sl]; at < L.slice_start[sl + 1]; ++at) {
