@@ -631,7 +631,8 @@ def main():
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing in this build uses a second GPU.",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library computes on a single GPU "
+              "(the slab partition and halo kernels show one GPU's share of a multi-GPU run).",
               file=sys.stderr)
         sys.exit(2)
 
