@@ -596,8 +596,10 @@ difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm
  * gpc_N_host[n_windkessel] (host, NULL = zero).  Outputs: cotangents of the initial state (device,
  * user order, NULL to skip) gU_0, gp_0, gphi_0 (the initial flux is an independent input), gpc_0_host,
  * and of the Windkessel parameters gwk_host[n_windkessel*3] as (Rp, C, Rd) per outlet (host).
- * adj_tol is the relative tolerance of the transposed solves.  Synchronises; the PISO is left at the
- * window's final state. */
+ * adj_tol is the relative tolerance of the transposed solves.  Each transposed pressure solve starts
+ * from the same corrector's solution of the step reversed just before (the later time step), the
+ * sweep's first from zero, so results depend on the window and adj_tol alone, not on earlier calls.
+ * Synchronises; the PISO is left at the window's final state. */
 difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* gU_N, const void* gp_N,
                                 const void* gphi_N, const double* gpc_N_host, double adj_tol, void* gU_0, void* gp_0,
                                 void* gphi_0, double* gpc_0_host, double* gwk_host);
@@ -606,13 +608,16 @@ difvm_status difvm_piso_adjoint(difvm_piso* piso, difvm_tape* tape, const void* 
  * "Computational Efficiency"; here the checkpoint segments are replayed hipGraphs).  With enable != 0,
  * difvm_piso_adjoint runs each segment of ckpt_every steps as two graphs: the recomputation of the
  * segment from its checkpoint (forward steps with their records) and its reverse sweep (the adjoint
- * steps, last first).  The first full segment runs eagerly and records the Krylov counts; both
+ * steps, last first).  The sweep's first segment (the window's last) is always reversed eagerly, its
+ * first pressure solves starting from zero.  The first full segment runs eagerly and records the
+ * Krylov counts; both
  * graphs are then captured with a budget per solve kind (momentum, pressure) of the segment's largest
  * count plus a margin plus 1/64 of that count, and each later full segment is two hipGraphLaunches
  * and one read of the solvers' states per graph.  Iterations past a solve's stop are predicated
  * no-ops, so results are bitwise those of the eager sweep.  A replay in which some solve had not
  * stopped within its budget is discarded (the recomputation restarts from the checkpoint; the reverse
- * sweep restores the cotangents saved by the graph's first nodes), run eagerly, and the graph is
+ * sweep restores the cotangents and the pressure solves' starting values saved by the graph's first
+ * nodes), run eagerly, and the graph is
  * recaptured with the margin widened by one; when the counts fall two or more below the budgets the
  * graph is recaptured with tighter ones.  The margin starts at min(2, extra_iters) and never exceeds
  * extra_iters (>= 0).  A shorter last segment (nsteps not a multiple of ckpt_every) runs eagerly, and a

@@ -658,7 +658,8 @@ void tape_create(difvm_piso* P, int nsteps, int every, difvm_tape** out) {
     T->Hbar = tape_alloc(T, 3 * nc); T->bbar = tape_alloc(T, 3 * nc); T->dbar = tape_alloc(T, nc);
     T->valbar = tape_alloc(T, d.nslot); T->valT = tape_alloc(T, d.nslot); T->fHb = tape_alloc(T, nf);
     T->faF = tape_alloc(T, nf); T->fnc = tape_alloc(T, std::max<size_t>(1, d.nfi)); T->g = tape_alloc(T, nf);
-    T->tmp = tape_alloc(T, 3 * nc); T->lam = tape_alloc(T, nc); T->mu = tape_alloc(T, 3 * nc);
+    T->tmp = tape_alloc(T, 3 * nc); T->mu = tape_alloc(T, 3 * nc);
+    T->lam = tape_alloc(T, (size_t)P->prm.n_corr * nc);  // one pressure multiplier per corrector
     T->Ubar0 = tape_alloc(T, 3 * nc); T->wkbar = tape_alloc(T, nwk); T->Ubbar = tape_alloc(T, 3 * (size_t)d.nfb);
     if (P->prm.conv != DIFVM_CONV_UPWIND) T->gUn = tape_alloc(T, 9 * nc);
     T->endU = tape_alloc(T, 3 * nc); T->endp = tape_alloc(T, nc); T->endphi = tape_alloc(T, nf);
@@ -763,13 +764,15 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
                                     T->fnc, T->g, T->pbvbar);
     op_div(m, DIFVM_F64, DIFVM_SCHEME_ONE, 1, DIFVM_BC_P, T->g, nullptr, nullptr, T->tmp);
     k_axpy<<<Gc, BLOCK, 0, s>>>(nc, 1.0, T->tmp, T->pbar);
-    // pressure solve: lambda = K^-1 pbar (K symmetric)
-    zero(T->lam, nc, s);
-    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, T->lam, adj_tol, maxit_p, q ? &q->p[c] : nullptr,
+    // pressure solve: lambda = K^-1 pbar (K symmetric), started from this corrector's lambda of the
+    // step reversed before (the later time step: the multipliers change little from step to step, so
+    // the solve needs far fewer iterations than from zero; the sweep's first step starts from zero)
+    double* lam = T->lam + (size_t)c * nc;
+    SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, T->pbar, lam, adj_tol, maxit_p, q ? &q->p[c] : nullptr,
                          P->amg, &P->hint_adj_p[c]);
     worst = std::max(worst, rp.status);
     if (counts && !q) counts[1 + c] = rp.iters[0];
-    k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, T->lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
+    k_adj_psolve<<<Gf, BLOCK, 0, s>>>(mv, lam, R.pnew[c], R.rAU, R.pbv, P->is_ref, prm.p_ref_value, T->fHb, T->faF,
                                       T->fnc, T->pbvbar);
     k_adj_corr_cells<<<Gc, BLOCK, 0, s>>>(mv, T->fHb, T->faF, T->fnc, R.rAU, R.gpo[c], T->rAUbar, T->HbyAbar, T->gbar);
     if (d.nfb) k_adj_ub_flux<<<grid_for(d.nfb), BLOCK, 0, s>>>(mv, T->fHb, T->Ubbar);
@@ -826,18 +829,23 @@ static int reverse_step(difvm_piso* P, difvm_tape* T, const StepRecord& R, const
 }
 
 // ---- graph mode of the reverse sweep ----------------------------------------------------------
-static size_t seg_words(const DMesh& d) { return 4 * (size_t)d.nc + d.nfi + d.nfb + 3 * (size_t)d.nfb; }
+// the words backup_cot saves, in its order
+static size_t seg_words(const DMesh& d, int n_corr) {
+  return 4 * (size_t)d.nc + d.nfi + d.nfb + 3 * (size_t)d.nfb + 4 * (size_t)d.n_wk + (size_t)n_corr * d.nc;
+}
 
-// save (to backup) or restore the cotangents entering a reverse segment: Ubar, pbar, phibar_in,
-// Ubbar (summed over the window), and the Windkessel cotangents
+// save (to backup) or restore the state entering a reverse segment: the cotangents Ubar, pbar,
+// phibar_in, Ubbar (summed over the window) and the Windkessel cotangents, and the pressure
+// multipliers the segment's first solves start from
 static void backup_cot(difvm_tape* T, bool save, hipStream_t s) {
   const DMesh& d = T->piso->mesh->d;
   size_t nc = d.nc, nf = (size_t)d.nfi + d.nfb;
   int nwk = d.n_wk;
   double* b = T->gr.backup;
-  double* a[6] = {T->Ubar, T->pbar, T->phibar_in, T->Ubbar, T->pcbar, T->wkacc};
-  size_t len[6] = {3 * nc, nc, nf, 3 * (size_t)d.nfb, (size_t)nwk, 3 * (size_t)nwk};
-  for (int k = 0; k < 6; ++k) {
+  double* a[7] = {T->Ubar, T->pbar, T->phibar_in, T->Ubbar, T->pcbar, T->wkacc, T->lam};
+  size_t len[7] = {3 * nc, nc, nf, 3 * (size_t)d.nfb, (size_t)nwk, 3 * (size_t)nwk,
+                   (size_t)T->piso->prm.n_corr * nc};
+  for (int k = 0; k < 7; ++k) {
     if (save) dcopy(b, a[k], len[k], s);
     else dcopy(a[k], b, len[k], s);
     b += len[k];
@@ -963,7 +971,7 @@ void tape_set_graph(difvm_tape* T, int enable, int extra) {
   if (!G.state_dev) {
     size_t bytes = 2 * (size_t)T->every * G.per_step;
     G.state_dev = tape_alloc(T, (bytes + 7) / 8);
-    G.backup = tape_alloc(T, seg_words(m->d));
+    G.backup = tape_alloc(T, seg_words(m->d, P->prm.n_corr));
     DIFVM_HIP(hipHostMalloc(&G.state_host, (size_t)T->every * G.per_step, hipHostMallocDefault));
   }
 }
@@ -1011,6 +1019,7 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
   zero(T->Ubbar, 3 * (size_t)d.nfb, s);
   zero(T->wkacc, 3 * (size_t)nwk, s);
   zero(T->pcbar, nwk, s);
+  zero(T->lam, (size_t)P->prm.n_corr * nc, s);  // the sweep's first pressure solves start from zero
   if (gU) permute(m, DIFVM_F64, 3, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gU, T->Ubar);
   if (gp) permute(m, DIFVM_F64, 1, DIFVM_KIND_CELL, DIFVM_TO_INTERNAL, gp, T->pbar);
   if (gphi) permute(m, DIFVM_F64, 1, DIFVM_KIND_FACE_FLUX, DIFVM_TO_INTERNAL, gphi, T->phibar_in);
@@ -1047,8 +1056,9 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
       tape_drop_one(T, 0);
       tape_capture(T, 0, adj_tol);
     }
-    // reverse sweep of the segment
-    if (!graphed) {
+    // reverse sweep of the segment; the sweep's first segment runs eagerly: its first pressure
+    // solves start from zero and take more iterations than a replay's budget allows for the others
+    if (!graphed || seg == T->nseg - 1) {
       worst = std::max(worst, reverse_eager(T, s0, s1, adj_tol, &cu, &cp));
     } else if (!G.x[1]) {
       worst = std::max(worst, reverse_eager(T, s0, s1, adj_tol, &cu, &cp));
