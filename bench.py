@@ -746,6 +746,26 @@ def main():
                   "frac": round(vbytes / v_s / 1e9 / HBM_PEAK_GBS, 4), "timed_vcycles": vl}
         log("v-cycle roofline", vcycle)
 
+    # per-phase breakdown of the step: 10 more eager steps after the timed region with only the phase
+    # events on (HIP events on the stream around each phase; kernel events off)
+    nph = 10
+    B.difvm_ctx_profile_phases(ctx.h, 1)
+    B.difvm_ctx_profile_read(ctx.h)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    P.step(nph)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    phd = B.difvm_ctx_profile_read(ctx.h)
+    B.difvm_ctx_profile_phases(ctx.h, 0)
+    phases = {k[len("step: "):].replace(" ", "_") + "_ms": round(v[1] / nph, 3)
+              for k, v in phd.items() if k.startswith("step: ")}
+    phase_breakdown = {"steps": nph, "ms_per_step": round(1e3 * (tp1 - tp0) / nph, 3), **phases,
+                       "outside_phases_ms": round(1e3 * (tp1 - tp0) / nph - sum(phases.values()), 3),
+                       "note": "per step, summed over the correctors; the pressure solve includes the GPU's idle "
+                               "time while the host polls the solver"}
+    log("phase breakdown", phase_breakdown)
+
     # passive scalar carried by the flow of the last step (D = 1e-4, zeroGradient walls and outlet)
     scalar = None
     if not args.no_poisson:
@@ -846,7 +866,7 @@ def main():
                    "tol_p": 1e-8, "tol_u": 1e-8, "pressure_preconditioner": args.precond},
         "roofline": roofline,
         "vcycle_roofline": vcycle,
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu, "phase_breakdown": phase_breakdown,
         "solver": {"pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
                    "bicgstab_iters_per_component": round(float(it[:, :3].mean()), 1), "status": int(st),
                    "pressure_preconditioner": args.precond},

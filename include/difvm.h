@@ -152,6 +152,16 @@ typedef struct {
   double total_ms;
 } difvm_kernel_time;
 difvm_status difvm_ctx_profile(difvm_ctx* ctx, int every_nth);
+/* Phase timing of eager PISO steps (the per-phase breakdown of a step): with enable != 0 every eager
+ * step made by difvm_piso_step brackets its phases with HIP events on the context's stream, named
+ * "step: momentum assembly" (Windkessel update, velocity gradient, momentum matrix and source),
+ * "step: momentum solve" (pressure gradient, predictor right-hand side, BiCGStab), and per corrector
+ * "step: pressure assembly" (HbyA, face fluxes, pressure matrix), "step: pressure solve" (CG with its
+ * preconditioner, including the GPU's idle time while the host polls the solver) and
+ * "step: correction" (flux and velocity correction).  Independent of difvm_ctx_profile's kernel
+ * timing and of its stride; the AMG setup and captured steps are not timed.  Read with
+ * difvm_ctx_profile_read; enable = 0 stops it. */
+difvm_status difvm_ctx_profile_phases(difvm_ctx* ctx, int enable);
 difvm_status difvm_ctx_profile_read(difvm_ctx* ctx, difvm_kernel_time* out, int32_t max_out, int32_t* n_out);
 
 /* ---- mesh ----------------------------------------------------------------------------------

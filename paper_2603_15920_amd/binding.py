@@ -103,6 +103,7 @@ _SIGS = {
     "difvm_ctx_destroy": (C.c_int32, [_vp]),
     "difvm_ctx_set_allocator": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "difvm_ctx_profile": (C.c_int32, [_vp, C.c_int]),
+    "difvm_ctx_profile_phases": (C.c_int32, [_vp, C.c_int]),
     "difvm_ctx_profile_read": (C.c_int32, [_vp, C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]),
     "difvm_mesh_renumber_host": (C.c_int32, [C.POINTER(MeshDesc), C.c_uint32] + [_vp] * 14),
     "difvm_mesh_create": (C.c_int32, [_vp, C.POINTER(MeshDesc), C.c_uint32, C.POINTER(_vp)]),
@@ -296,6 +297,11 @@ def difvm_ctx_destroy(ctx):
 def difvm_ctx_profile(ctx, every_nth):
     """every_nth >= 1: time every n-th launch of each PCG kernel with HIP events; 0: off."""
     _check(lib().difvm_ctx_profile(ctx, int(every_nth)), "difvm_ctx_profile")
+
+
+def difvm_ctx_profile_phases(ctx, enable):
+    """enable != 0: time the phases of every eager PISO step ("step: ..." names); 0: off."""
+    _check(lib().difvm_ctx_profile_phases(ctx, int(enable)), "difvm_ctx_profile_phases")
 
 
 def difvm_ctx_profile_read(ctx):

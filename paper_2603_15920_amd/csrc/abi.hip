@@ -55,9 +55,11 @@ static int prof_id(Profiler& P, const std::string& name) {
 
 int prof_begin(Ctx& c, const char* name, long iter) {
   Profiler& P = c.prof;
-  if (!P.on || c.capturing) return -1;
+  if (c.capturing) return -1;
+  const bool phase = std::strncmp(name, "step: ", 6) == 0;  // phases: every time, kernels: every stride-th
+  if (phase ? !P.phases : !P.on) return -1;
   int id = prof_id(P, name);
-  if (P.seen[id]++ % P.stride != 0) return -1;
+  if (!phase && P.seen[id]++ % P.stride != 0) return -1;
   Profiler::Rec r{id, pool_event(P), pool_event(P), iter};
   DIFVM_HIP(hipEventRecord(r.a, c.stream));
   P.pending.push_back(r);
@@ -359,6 +361,15 @@ difvm_status difvm_ctx_profile(difvm_ctx* ctx, int enable) {
     P.stride = enable;
     std::fill(P.seen.begin(), P.seen.end(), 0L);
   }
+  DIFVM_API_END
+  return DIFVM_OK;
+}
+
+difvm_status difvm_ctx_profile_phases(difvm_ctx* ctx, int enable) {
+  DIFVM_API_BEGIN
+  check_ptr(ctx, "ctx");
+  if (!enable) prof_collect(ctx->c);
+  ctx->c.prof.phases = enable != 0;
   DIFVM_API_END
   return DIFVM_OK;
 }

@@ -45,6 +45,7 @@ struct DevBuf {
 // event-pair timing of selected kernel launches (difvm_ctx_profile)
 struct Profiler {
   bool on = false;
+  bool phases = false;        // time the phases of each eager PISO step (scope names "step: ...")
   int stride = 1;             // time every stride-th launch of each kernel name
   std::vector<long> seen;     // launches per name since profiling was enabled
   struct Rec {
@@ -164,6 +165,23 @@ inline Ctx& ctx_of(const difvm_mesh* m) { return m->ctx->c; }
 // scratch buffer `slot` of the mesh (n doubles), allocated at its first use and kept with the mesh
 double* mesh_scratch(difvm_mesh* m, int slot, size_t n);
 // RAII event bracket around one launch
+// consecutive timed phases: next() ends the current one and starts another; the destructor ends the
+// last (also when an exception leaves the scope, so no record is left without its end event)
+struct PhaseScope {
+  Ctx& c;
+  int h;
+  PhaseScope(const difvm_mesh* m, const char* name) : c(ctx_of(m)), h(prof_begin(ctx_of(m), name)) {}
+  void next(const char* name) {
+    prof_end(c, h);
+    h = prof_begin(c, name);
+  }
+  void end() {
+    prof_end(c, h);
+    h = -1;
+  }
+  ~PhaseScope() { prof_end(c, h); }
+};
+
 struct ProfScope {
   Ctx& c;
   int h;

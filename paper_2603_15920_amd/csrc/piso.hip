@@ -706,6 +706,8 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   int Gc = grid_for(d.nc), Gf = grid_for(d.nfi + d.nfb);
   size_t nc = d.nc;
   difvm_step_stats st{};
+  // phases of the step timed with events while the context's phase profiling is on (eager steps only)
+  PhaseScope ph(m, "step: momentum assembly");
   // S0
   if (rec) dcopy(rec->phi_in, P->phi, (size_t)d.nfi + d.nfb, s);
   if (rec && d.n_wk) dcopy(rec->pc_in, P->pc, d.n_wk, s);
@@ -720,6 +722,7 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   if (rec && rec->Un) dcopy(rec->Un, P->U, 3 * nc, s);
   op_assemble_momentum(m, prm.conv, prm.time, prm.nu, P->nu_cell, prm.dt, P->phi, P->U, P->gU, P->Ub, P->dM, nullptr, nullptr,
                        P->valM, P->bM);
+  ph.next("step: momentum solve");
   // S2
   op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, P->gp);
   k_pred_rhs<<<grid_for(3 * d.nc), BLOCK, 0, s>>>(d.nc, d.V, P->bM, P->gp, P->rhs);
@@ -737,6 +740,7 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
   }
   // S3
   for (int corr = 0; corr < prm.n_corr; ++corr) {
+    ph.next("step: pressure assembly");
     if (rec) {
       dcopy(rec->Uin[corr], P->U, 3 * nc, s);
       dcopy(rec->pold[corr], P->p, nc, s);
@@ -754,20 +758,24 @@ void piso_advance_q(difvm_piso* P, difvm_step_stats* stp, StepRecord* rec, const
     k_passemble<<<Gc, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->pbv, P->is_ref, prm.p_ref_value, P->dK, P->valK,
                                      P->rhsK);
     DIFVM_HIP(hipGetLastError());
+    ph.end();  // (the AMG setup, once, is not part of a phase)
     if (prm.precond == DIFVM_PRECOND_AMG && !P->amg) {
       DIFVM_CHECK(!ctx_of(m).capturing, DIFVM_ERR_INVALID_ARG, "AMG hierarchy must exist before a step is captured");
       P->amg = amg_create(m, SellMatrix{P->dK, P->valK}, AmgOptions{});
     }
+    ph.next("step: pressure solve");
     SolveResult rp = pcg(m, SellMatrix{P->dK, P->valK}, P->rhsK, P->p, prm.tol_p, prm.maxit_p, qu ? &qu->p[corr] : nullptr,
                          P->amg, &P->hint_p[corr]);
     st.it_p[corr] = rp.iters[0];
     st.res_p[corr] = rp.res[0];
     st.status = std::max(st.status, rp.status);
     if (!qu) set_seg_stats_p(P, corr, rp);
+    ph.next("step: correction");
     if (P->trace_p) dcopy(P->trace_p + (size_t)corr * nc, P->p, nc, s);
     k_flux<<<Gf, BLOCK, 0, s>>>(mv, P->phiH, P->aF, P->ncorr, P->p, P->pbv, P->phi);
     k_ucorr<<<Gc, BLOCK, 0, s>>>(mv, P->p, P->pbv, P->HbyA, P->rAU, P->U);
     DIFVM_HIP(hipGetLastError());
+    ph.end();
     if (rec) {
       dcopy(rec->pnew[corr], P->p, nc, s);
       op_grad(m, DIFVM_F64, 1, DIFVM_BC_P, P->p, P->pbv, rec->gpn[corr]);

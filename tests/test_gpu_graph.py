@@ -212,3 +212,33 @@ def test_adaptive_budgets_track_the_counts():
     note("graph adaptive: replays", replays, "redos", redos, "captures", captures)
     assert replays + redos == 39
     assert replays >= 30 and captures <= 1 + redos + 8, (replays, redos, captures)
+
+
+def test_phase_events():
+    """Phase timing: every eager step's five phases (three per corrector) are timed once each, kernel
+    timing stays off, and replays of a captured step add no records."""
+    m = mg.cavity(16)
+    Ub = lid(m)
+    cx = B.Context(0)
+    M = B.Mesh(cx, m)
+    P = B.Piso(M, B.piso_params(0.01, 1e-3))
+    P.set_boundary(dev(Ub), dev(np.zeros(m.n_boundary_faces)))
+    U0 = np.zeros((m.n_cells, 3))
+    P.set_state(dev(U0), dev(np.zeros(m.n_cells)), dev(O.initial_flux(m, U0, Ub)))
+    B.difvm_ctx_profile_phases(cx.h, 1)
+    P.step(3)
+    prof = B.difvm_ctx_profile_read(cx.h)
+    note("phase events", prof)
+    assert prof["step: momentum assembly"][0] == 3 and prof["step: momentum solve"][0] == 3
+    for k in ("step: pressure assembly", "step: pressure solve", "step: correction"):
+        assert prof[k][0] == 6, (k, prof)
+    assert all(v[1] > 0 for v in prof.values())
+    assert not any(k.startswith("pcg_") for k in prof)
+    P.set_graph(True, 8)
+    r0 = P.graph_info()
+    P.step(4)
+    prof = B.difvm_ctx_profile_read(cx.h)
+    B.difvm_ctx_profile_phases(cx.h, 0)
+    r1 = P.graph_info()
+    eager = 4 - (r1[0] - r0[0])
+    assert prof.get("step: momentum assembly", (0, 0.0))[0] == eager, (prof, r0, r1)
