@@ -449,6 +449,9 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=50, precond="amg"):
     cot = [dev(rng.standard_normal((m.n_cells, 3))), dev(rng.standard_normal(m.n_cells)), dev(rng.standard_normal(m.n_faces)),
            rng.standard_normal(len(wk))]
     t_adj, (st_a, gpc, gwk) = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
+    # a second sweep on the same tape recomputes every segment (the first reverses the window's last
+    # segment from the forward record's own step records): the eager reference for the graph sweeps
+    t_adj2, _ = timed(torch, lambda: B.difvm_piso_adjoint(P.h, T, *cot, 1e-8, gU, gp, gphi, len(wk)))
     # the same reverse sweep with its segments replayed as graphs (the first full segment captures)
     gU_e = gU.clone()
     B.difvm_tape_set_graph(T, True, 16)
@@ -463,9 +466,10 @@ def adjoint_window(B, mg, torch, ctx, steps, every, spinup=50, precond="amg"):
             "forward_steps_per_s": round(steps / t_fwd, 3), "record_steps_per_s": round(steps / t_rec, 3),
             "adjoint_steps_per_s": round(steps / t_adj, 3), "adjoint_over_forward": round(t_adj / t_fwd, 3),
             "record_over_forward": round(t_rec / t_fwd, 3), "pcg_iters_per_solve": round(float(it[:, 3:].mean()), 1),
+            "resweep_steps_per_s": round(steps / t_adj2, 3),
             "graph_sweep": {"first_sweep_steps_per_s": round(steps / t_adj_g1, 3),
                             "replayed_sweep_steps_per_s": round(steps / t_adj_g, 3),
-                            "speedup_vs_eager": round(t_adj / t_adj_g, 3), "bitwise_equal_to_eager": same,
+                            "speedup_vs_eager": round(t_adj2 / t_adj_g, 3), "bitwise_equal_to_eager": same,
                             "replays_redos_captures": list(g_info), "status": [int(st_g1), int(st_g)]},
             "status": [int(st), int(st_r), int(st_a)]}
 

@@ -597,8 +597,10 @@ typedef struct difvm_tape difvm_tape;
 difvm_status difvm_tape_create(difvm_piso* piso, int32_t nsteps, int32_t ckpt_every, difvm_tape** out);
 difvm_status difvm_tape_destroy(difvm_tape* tape); /* NULL is a no-op */
 
-/* Runs the window's nsteps forward steps, storing checkpoints (synchronises).  stats_host[nsteps]
- * may be NULL.  The PISO ends at the window's final state. */
+/* Runs the window's nsteps forward steps, storing checkpoints and the step records of the last
+ * checkpoint segment, which the following difvm_piso_adjoint then reverses without recomputing it
+ * (later sweeps on the same tape recompute every segment; the results are the same bits).
+ * Synchronises.  stats_host[nsteps] may be NULL.  The PISO ends at the window's final state. */
 difvm_status difvm_piso_forward_record(difvm_piso* piso, difvm_tape* tape, difvm_step_stats* stats_host);
 
 /* Vector-Jacobian product of the window (eq. vjp).  Cotangents of the final state in USER order

@@ -600,6 +600,7 @@ __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double*
 struct difvm_tape {
   difvm_piso* piso = nullptr;
   int nsteps = 0, every = 1, nseg = 0, recorded = 0, reversed = 0;
+  int rec_seg = -1;  // the segment whose step records `rec` holds (-1: none)
   std::vector<double*> ckU, ckp, ckphi;   // per checkpoint, internal order
   std::vector<std::vector<double>> ckpc;  // host copies of the capacitor pressures
   std::vector<difvm::StepRecord> rec;     // one per step of a segment
@@ -762,20 +763,25 @@ static void load_state(difvm_piso* P, const double* U, const double* p, const do
   set_pc(P, pc);
 }
 
+// The last segment's steps keep their records, so the reverse sweep that follows need not recompute
+// that segment from its checkpoint (the recomputation would reproduce the same bits).
 int forward_record(difvm_piso* P, difvm_tape* T, difvm_step_stats* stats) {
   int worst = 0;
+  const int last = T->nseg - 1, last_s0 = last * T->every;
+  T->rec_seg = -1;
   for (int n = 0; n < T->nsteps; ++n) {
     if (n % T->every == 0) {
       int k = n / T->every;
       save_state(P, T->ckU[k], T->ckp[k], T->ckphi[k], T->ckpc[k]);
     }
     difvm_step_stats st{};
-    piso_advance(P, &st, nullptr);
+    piso_advance(P, &st, n >= last_s0 ? &T->rec[n - last_s0] : nullptr);
     worst = std::max(worst, st.status);
     if (stats) stats[n] = st;
   }
   save_state(P, T->endU, T->endp, T->endphi, T->endpc);
   T->recorded = 1;
+  T->rec_seg = last;
   return worst;
 }
 
@@ -1084,9 +1090,16 @@ int adjoint(difvm_piso* P, difvm_tape* T, const double* gU, const double* gp, co
     int s0 = seg * T->every, s1 = std::min(T->nsteps, s0 + T->every);
     bool graphed = G.on && s1 - s0 == T->every;
     int cu = 0, cp = 0;
-    // recompute the segment from its checkpoint, keeping every step's intermediates
-    load_state(P, T->ckU[seg], T->ckp[seg], T->ckphi[seg], T->ckpc[seg]);
-    if (!graphed) {
+    // recompute the segment from its checkpoint, keeping every step's intermediates, unless the
+    // records still hold this segment (the window's last, right after the forward record)
+    const bool have_records = seg == T->rec_seg;
+    if (!have_records) {
+      load_state(P, T->ckU[seg], T->ckp[seg], T->ckphi[seg], T->ckpc[seg]);
+      T->rec_seg = seg;
+    }
+    if (have_records) {
+      // nothing to recompute
+    } else if (!graphed) {
       worst = std::max(worst, recompute_eager(T, s0, s1, &cu, &cp));
     } else if (!G.x[0]) {
       worst = std::max(worst, recompute_eager(T, s0, s1, &cu, &cp));

@@ -281,7 +281,21 @@ __global__ __launch_bounds__(BLOCK) void k_windkessel(int nfi, double dt, const 
   int j = blockIdx.x;
   int s0 = wk_start[j], s1 = wk_start[j + 1];
   double v[1] = {0.0};
-  for (int q = s0 + threadIdx.x; q < s1; q += BLOCK) v[0] += phi[nfi + wk_faces[q]];
+  // each thread adds the fluxes of faces q = s0 + tid, s0 + tid + BLOCK, ... in that order, the loads
+  // of UN such faces issued together (an outlet has thousands of faces: one dependent index-then-flux
+  // load pair per face would make the sum a long latency chain)
+  constexpr int UN = 8;
+  for (int q = s0 + threadIdx.x; q < s1; q += UN * BLOCK) {
+    int f[UN];
+    double fl[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) f[u] = wk_faces[min(q + u * BLOCK, s1 - 1)];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) fl[u] = phi[nfi + f[u]];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      if (q + u * BLOCK < s1) v[0] += fl[u];
+  }
   __shared__ double lds[1][BLOCK / 64];
   block_sum<1>(v, lds);
   double Q = v[0];

@@ -85,13 +85,13 @@ def test_graph_sweep_equals_eager(case, nsteps, every, precond):
     same(eager[0], eager[1])
     replays, redos, captures = info
     n_full = nsteps // every
-    # two sweeps.  Recomputation graph: the first full segment of the first sweep runs eagerly.
-    # Reverse graph: every sweep reverses its first segment (the window's last) eagerly, and the first
-    # sweep also its first full segment after that one.
-    last_full = nsteps % every == 0
-    recompute = (n_full - 1) + n_full
-    reverse = (n_full - 1 - last_full) + (n_full - last_full)
-    assert replays + redos == recompute + reverse, info
+    # two sweeps.  The first sweep does not recompute the window's last segment (the forward record
+    # kept its steps) and runs the next one eagerly for each graph (learning the counts, then the
+    # captures); every sweep reverses its first segment (the window's last) eagerly.  The second sweep
+    # replays every full segment's recomputation.
+    last_full = int(nsteps % every == 0)
+    first = n_full - 1 - last_full
+    assert replays + redos == first + n_full + first + (n_full - last_full), info
     assert replays >= 2, info
 
 
@@ -103,9 +103,9 @@ def test_graph_sweep_zero_margin():
     graph, info = window(m, Ub, wk, pc0, 15, 3, True, 0, "jacobi")
     note("adjoint graph zero margin (replays, redos, captures)", info)
     same(eager[0], graph[0])
-    # 5 full segments, one sweep: 4 recomputation replays, 3 reverse replays (the window's last
-    # segment and the first full one after it run eagerly)
-    assert info[0] + info[1] == 4 + 3
+    # 5 full segments, one sweep: the window's last segment is not recomputed and is reversed eagerly,
+    # the next one runs eagerly for both graphs, the other three are replayed
+    assert info[0] + info[1] == 3 + 3
 
 
 def test_tape_graph_errors():
