@@ -267,23 +267,31 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
   bool skip = true;
   double beta = 0.0;
   for (int t = tw.t; t < tw.end; t += tw.step) {
-    int s = T.seg[t];
+    const int s = T.seg[t], lo = T.lo[t], hi = T.hi[t];
     if (s != cur) {
-      // first tile of segment s for this block: the segment's stopping test and beta
+      // first tile of segment s for this block: the segment's stopping test and beta.  Every load
+      // that needs only s (the flag's included) is issued at once, then the partials', so the block
+      // waits for two load latencies before its sum instead of five.
       cur = s;
       PcgCtl* ctl = ctls + s;
-      skip = block_flag(&ctl->done);
+      const int f = T.first[s], n = T.count[s], maxit = ctl->maxit, done = ctl->done;
+      const double tol = ctl->tol, bn = ctl->bn, rho_older = ctl->rho[k & 1];  // rho_{k-2}
+      double s2[2];  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+      seg_thread_sum<2, NT>(partB, T.ntile, f, n, s2);
+      // thread 0's read decides for the block: the segment's first tile may be setting the flag
+      // during this launch
+      skip = block_share(done);
+      __shared__ double lds[2][NT / 64];
+      block_sum<2, NT>(s2, lds);
       if (!skip) {
-        bool lead = t == T.first[s] && threadIdx.x == 0;  // the block holding the segment's first tile
-        double s2[2];
-        sum_seg<2, NT>(partB, T, s, s2);  // (r_{k-1}.r_{k-1}, r_{k-1}.z_{k-1})
+        bool lead = t == f && threadIdx.x == 0;  // the block holding the segment's first tile
         double rho = s2[1];
         if (lead) ctl->rho[(k - 1) & 1] = rho;
         beta = 0.0;
         if (k >= 2) {
-          double rn = sqrt(s2[0]), bn = ctl->bn;
-          bool conv = rn <= ctl->tol * bn;
-          if (conv || k - 1 >= ctl->maxit) {
+          double rn = sqrt(s2[0]);
+          bool conv = rn <= tol * bn;
+          if (conv || k - 1 >= maxit) {
             if (lead) {
               ctl->done = 1;
               ctl->iters = k - 1;
@@ -292,9 +300,9 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
             }
             skip = true;
           } else {
-            beta = rho / ctl->rho[k & 1];  // rho_{k-1} / rho_{k-2}
+            beta = rho / rho_older;  // rho_{k-1} / rho_{k-2}
           }
-        } else if (ctl->maxit <= 0) {
+        } else if (maxit <= 0) {
           if (lead) {
             ctl->done = 1;
             ctl->status = DIFVM_WARN_NOT_CONVERGED;
@@ -304,7 +312,6 @@ __global__ __launch_bounds__(PCG_SPMV_NT) void k_pcg_spmv(SellView A, Tiles T, i
       }
     }
     if (skip) continue;
-    int lo = T.lo[t], hi = T.hi[t];
     double v[1] = {0.0};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -342,7 +349,11 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, doubl
                                                       double* __restrict__ partB, int k, PcgCtl* ctls) {
   TileIdx ti = tile_idx(T);
   PcgCtl* ctl = ctls + ti.s;
-  if (block_flag(&ctl->done)) return;
+  // only earlier launches write the flag, so every wave reads the same value and the block needs
+  // no barrier to agree on it
+  if (ctl->done) return;
+  const int f = T.first[ti.s], n = T.count[ti.s];
+  const double rho = ctl->rho[(k - 1) & 1];
   double xv[CPT], pv[CPT], rv[CPT], qv[CPT], dv[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -354,8 +365,10 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(SellView A, Tiles T, doubl
     dv[c] = A.diag[i];
   }
   double pq[1];
-  sum_seg<1>(partA, T, ti.s, pq);
-  double alpha = ctl->rho[(k - 1) & 1] / pq[0];
+  seg_thread_sum<1>(partA, T.ntile, f, n, pq);
+  __shared__ double lds[1][BLOCK / 64];
+  block_sum<1, BLOCK>(pq, lds);
+  double alpha = rho / pq[0];
   double v[2] = {0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {

@@ -85,15 +85,15 @@ __device__ __forceinline__ TileIdx tile_idx(const Tiles& T) {
   return {t, T.seg[t], T.lo[t], T.hi[t]};
 }
 
-// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles) by a block of
-// NT threads; every thread ends with the totals.  Each thread adds the partials q = tid, tid + NT,
-// ... in that order; the loads of four such steps (all NV arrays) are issued together, past the end
-// at the clamped index n - 1 and not added, so the chain is one load latency per 4 NT tiles.
+// fixed-order sum of a segment's tile partials (NV arrays, value-major over all tiles, the segment's
+// n tiles from tile f) by a block of NT threads; every thread ends with the totals (sum_seg).  Each
+// thread adds the partials q = tid, tid + NT, ... in that order (seg_thread_sum); the loads of four
+// such steps (all NV arrays) are issued together, past the end at the clamped index n - 1 and not
+// added, so the chain is one load latency per 4 NT tiles.  A block reduction then gives the totals.
 template <int NV, int NT = BLOCK>
-__device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
-  __shared__ double lds[NV][NT / 64];
+__device__ __forceinline__ void seg_thread_sum(const double* __restrict__ part, int ntile, int f, int n,
+                                               double (&out)[NV]) {
   constexpr int UN = 4;
-  int f = T.first[s], n = T.count[s];
 #pragma unroll
   for (int k = 0; k < NV; ++k) out[k] = 0.0;
   for (int q = threadIdx.x; q < n; q += UN * NT) {
@@ -102,7 +102,7 @@ __device__ __forceinline__ void sum_seg(const double* __restrict__ part, const T
     for (int u = 0; u < UN; ++u) {
       int at = f + min(q + u * NT, n - 1);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) v[u][k] = part[(size_t)k * T.ntile + at];
+      for (int k = 0; k < NV; ++k) v[u][k] = part[(size_t)k * ntile + at];
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u)
@@ -110,6 +110,11 @@ __device__ __forceinline__ void sum_seg(const double* __restrict__ part, const T
 #pragma unroll
         for (int k = 0; k < NV; ++k) out[k] += v[u][k];
   }
+}
+template <int NV, int NT = BLOCK>
+__device__ __forceinline__ void sum_seg(const double* __restrict__ part, const Tiles& T, int s, double (&out)[NV]) {
+  __shared__ double lds[NV][NT / 64];
+  seg_thread_sum<NV, NT>(part, T.ntile, T.first[s], T.count[s], out);
   block_sum<NV, NT>(out, lds);
 }
 
@@ -128,6 +133,16 @@ __device__ __forceinline__ bool block_flag(const int* flag) {
   __shared__ int f;
   __syncthreads();  // a previous call's readers are done with f
   if (threadIdx.x == 0) f = *flag;
+  __syncthreads();
+  return f != 0;
+}
+
+// thread 0's copy of a flag the block has already loaded, shared through LDS (as block_flag), so
+// that the flag's load can be in flight together with others
+__device__ __forceinline__ bool block_share(int v) {
+  __shared__ int f;
+  __syncthreads();  // a previous call's readers are done with f
+  if (threadIdx.x == 0) f = v;
   __syncthreads();
   return f != 0;
 }

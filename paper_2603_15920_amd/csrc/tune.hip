@@ -170,7 +170,16 @@ int tune(difvm_mesh* m, const char* cache_path) {
           if (t < best) { best = t; best_v = v; }
         }
       } else {
-        for (int v : {0, 1024, 512, 256}) {
+        // one block per tile (0), fixed persistent grids, and the grids that give every block of an
+        // XCD's eighth of the tiles at most 2 or 4 of them (a fixed grid can leave one block a tile
+        // more than the others, which then finishes alone)
+        const int per_xcd = (d.ntile + 7) / 8;
+        std::vector<int> grids = {0, 1024, 512, 256};
+        for (int most : {2, 4}) {
+          int g = 8 * ((per_xcd + most - 1) / most);
+          if (std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
+        }
+        for (int v : grids) {
           if (v && v >= d.ntile) continue;
           double t = time_pcg_spmv(m, v, 10, e0, e1);
           if (t < best) { best = t; best_v = v; }

@@ -95,7 +95,7 @@ def test_pcg_independent_of_grid(packed):
     ntile = sum(-(-int(c) // 1024) for c in np.diff(starts)) if packed else -(-m.n_cells // 1024)
     note("pcg grids", m.n_cells, "tiles", ntile)
     ref = None
-    for grid in (0, 8, 16, 32, 64, 4096):
+    for grid in (0, 8, 16, 24, 32, 48, 64, 4096):
         st, x = pcg_solve(M, m, grid)
         if ref is None:
             ref = (st, x)
