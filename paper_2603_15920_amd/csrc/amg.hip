@@ -250,25 +250,27 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_post1(SellView K, const doub
 }
 
 // level 0, up, second pass: z = t + d0 + d1 with rh1 = theta d0 - D^-1 K d0, and per-tile partials
-// of r.z
+// of r.z.  A block per tile and one cell per thread, like the other finest-level passes (four cells
+// per thread in 256-thread blocks left each thread's rows one after another).
+constexpr int POST2_NT = TILE;
 template <bool OFF16>
-__global__ __launch_bounds__(BLOCK) void k_amg_cheb_post2(SellView K, Tiles T, const double* __restrict__ r,
-                                                          const double* __restrict__ t, const double* __restrict__ d0,
-                                                          double* __restrict__ z, double* __restrict__ part, Cheb c,
-                                                          StopFlags ctl) {
+__global__ __launch_bounds__(POST2_NT) void k_amg_cheb_post2(SellView K, Tiles T, const double* __restrict__ r,
+                                                             const double* __restrict__ t, const double* __restrict__ d0,
+                                                             double* __restrict__ z, double* __restrict__ part, Cheb c,
+                                                             StopFlags ctl) {
   TileIdx ti = tile_idx(T);
   if (stopped(ctl)) return;
   double v[1] = {0.0};
-  FOR_TILE_CELLS(i) {
+  if (const int i = ti.lo + (int)threadIdx.x; i < ti.hi) {
     SlotRange R = slots_of(K, i);
     double di = K.diag[i], d0i = d0[i];
     double kd0 = di * d0i + sell_offdiag<OFF16>(K, i, R, [&](int j) { return d0[j]; });
     double rh1 = c.theta * d0i - kd0 / di;
     double zi = t[i] + d0i + (c.c_d * d0i + c.c_r * rh1);
     z[i] = zi;
-    v[0] += r[i] * zi;
+    v[0] = r[i] * zi;
   }
-  if (part) put_partial<1>(v, part, T.ntile, ti.t);
+  if (part) put_partial<1, POST2_NT>(v, part, T.ntile, ti.t);
 }
 
 // SW lanes per row: partial sums of the row's entries, then a fixed xor-shuffle tree
@@ -690,10 +692,10 @@ static void launch_vcycle(const AmgDev* a, hipStream_t s, SellMatrix Km, const d
   Tiles T = tiles_of(m);
   if (K.off16) {
     k_amg_cheb_post1<true><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->t[0], a->d0[0], c[0], ctl);
-    k_amg_cheb_post2<true><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
+    k_amg_cheb_post2<true><<<T.ntile, POST2_NT, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
   } else {
     k_amg_cheb_post1<false><<<grid_for(nc), BLOCK, 0, s>>>(K, r, a->t[0], a->d0[0], c[0], ctl);
-    k_amg_cheb_post2<false><<<T.ntile, BLOCK, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
+    k_amg_cheb_post2<false><<<T.ntile, POST2_NT, 0, s>>>(K, T, r, a->t[0], a->d0[0], z, part, c[0], ctl);
   }
   DIFVM_HIP(hipGetLastError());
 }
