@@ -232,8 +232,9 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_pre2(SellView K, const doubl
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   SlotRange R = slots_of(K, min(i, K.nc - 1));
   if (stopped(ctl) || i >= K.nc) return;
+  const double ri = r[i];
   double kx = K.diag[i] * xs[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return xs[j]; });
-  res[i] = r[i] - kx;
+  res[i] = ri - kx;
 }
 
 // level 0, up, first pass (x = t): d0 = D^-1 (r - K t) / theta
@@ -244,9 +245,9 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb_post1(SellView K, const doub
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   SlotRange R = slots_of(K, min(i, K.nc - 1));
   if (stopped(ctl) || i >= K.nc) return;
-  double di = K.diag[i];
+  const double di = K.diag[i], ri = r[i];
   double kt = di * t[i] + sell_offdiag<OFF16>(K, i, R, [&](int j) { return t[j]; });
-  d0[i] = (r[i] - kt) / di * c.inv_theta;
+  d0[i] = (ri - kt) / di * c.inv_theta;
 }
 
 // level 0, up, second pass: z = t + d0 + d1 with rh1 = theta d0 - D^-1 K d0, and per-tile partials
@@ -263,12 +264,12 @@ __global__ __launch_bounds__(POST2_NT) void k_amg_cheb_post2(SellView K, Tiles T
   double v[1] = {0.0};
   if (const int i = ti.lo + (int)threadIdx.x; i < ti.hi) {
     SlotRange R = slots_of(K, i);
-    double di = K.diag[i], d0i = d0[i];
+    const double di = K.diag[i], d0i = d0[i], ti = t[i], ri = r[i];
     double kd0 = di * d0i + sell_offdiag<OFF16>(K, i, R, [&](int j) { return d0[j]; });
     double rh1 = c.theta * d0i - kd0 / di;
-    double zi = t[i] + d0i + (c.c_d * d0i + c.c_r * rh1);
+    double zi = ti + d0i + (c.c_d * d0i + c.c_r * rh1);
     z[i] = zi;
-    v[0] = r[i] * zi;
+    v[0] = ri * zi;
   }
   if (part) put_partial<1, POST2_NT>(v, part, T.ntile, ti.t);
 }
@@ -284,13 +285,16 @@ __device__ __forceinline__ double lane_sum(double s) {
 // Coarse levels smooth with the same degree-2 Chebyshev sweep as level 0 (interval [hi / 10, hi],
 // hi from the setup), two CSR passes per sweep.
 // Row bounds are loaded at a clamped index before the flag reads (no branch around the loads, so
-// both are in flight together); rows past the end get an empty range.  Blocks map to rows XCD by XCD
+// both are in flight together); rows past the end get an empty range.  The kernels load their own
+// row's values (at the clamped index rr) before the row's entries, so that those loads are in flight
+// with the entries' and not issued after the gathers.  Blocks map to rows XCD by XCD
 // (each XCD a contiguous run of rows), so the finer-level entries that neighbouring rows gather meet
 // in one L2.
 #define DIFVM_AMG_ROW(ptr, n)                                  \
   int g = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x; \
   int row = g / SW, lane = g % SW;                             \
-  int p0 = ptr[min(row, n - 1)], p1 = ptr[min(row, n - 1) + 1]; \
+  const int rr = min(row, n - 1);                              \
+  int p0 = ptr[rr], p1 = ptr[rr + 1];                          \
   if (stopped(ctl)) return;                                    \
   int lo = p0 + lane, hi = row < n ? p1 : 0
 
@@ -303,11 +307,12 @@ __global__ __launch_bounds__(BLOCK) void k_amg_restrict(int n, const int32_t* __
                                                         double* __restrict__ out, double* __restrict__ outd,
                                                         StopFlags ctl) {
   DIFVM_AMG_ROW(ptr, n);
+  const double dg = diag ? diag[rr] : 1.0;
   double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return xin[j]; });
   s = lane_sum<SW>(s);
   if (row < n && lane == 0) {
     out[row] = s;
-    if (diag) outd[row] = s / diag[row];
+    if (diag) outd[row] = s / dg;
   }
 }
 
@@ -318,10 +323,11 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cpre1(int n, const int32_t* __res
                                                      const double* __restrict__ diag, const double* __restrict__ bd,
                                                      double* __restrict__ xs, Cheb c, StopFlags ctl) {
   DIFVM_AMG_ROW(ptr, n);
+  const double di = diag[rr], rh0 = bd[rr];
   double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return bd[j]; });
   s = lane_sum<SW>(s);
   if (row < n && lane == 0) {
-    double di = diag[row], rh0 = bd[row], d0 = rh0 * c.inv_theta;
+    double d0 = rh0 * c.inv_theta;
     double kd0 = di * d0 + s * c.inv_theta;
     double rh1 = rh0 - kd0 / di;
     xs[row] = d0 + (c.c_d * d0 + c.c_r * rh1);
@@ -336,9 +342,10 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cpre2(int n, const int32_t* __res
                                                      const double* __restrict__ xs, double* __restrict__ res,
                                                      StopFlags ctl) {
   DIFVM_AMG_ROW(ptr, n);
+  const double bi = b[rr], di = diag[rr], xi = xs[rr];
   double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return xs[j]; });
   s = lane_sum<SW>(s);
-  if (row < n && lane == 0) res[row] = b[row] - diag[row] * xs[row] - s;
+  if (row < n && lane == 0) res[row] = bi - di * xi - s;
 }
 
 // coarse level, up, first pass: t = xs + P xc and, since b - A t = res - (A P) xc,
@@ -351,13 +358,14 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cup1(int n, const int32_t* __rest
                                                     const double* __restrict__ xc, double* __restrict__ t,
                                                     double* __restrict__ d0, Cheb c, StopFlags ctl) {
   DIFVM_AMG_ROW(ptr, n);
+  const double xi = xs[rr], ri = res[rr], di = diag[rr];
   double sp, sq;
   csr_lane_dot2<SW>(lo, hi, col, pv, ap, [&](int j) { return xc[j]; }, sp, sq);
   sp = lane_sum<SW>(sp);
   sq = lane_sum<SW>(sq);
   if (row < n && lane == 0) {
-    t[row] = xs[row] + sp;
-    d0[row] = (res[row] - sq) / diag[row] * c.inv_theta;
+    t[row] = xi + sp;
+    d0[row] = (ri - sq) / di * c.inv_theta;
   }
 }
 
@@ -369,12 +377,12 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cup2(int n, const int32_t* __rest
                                                     const double* __restrict__ d0, double* __restrict__ x, Cheb c,
                                                     StopFlags ctl) {
   DIFVM_AMG_ROW(ptr, n);
+  const double di = diag[rr], d0i = d0[rr], ti = t[rr];
   double s = csr_lane_dot<SW>(lo, hi, col, val, [&](int j) { return d0[j]; });
   s = lane_sum<SW>(s);
   if (row < n && lane == 0) {
-    double di = diag[row], d0i = d0[row];
     double rh1 = c.theta * d0i - (di * d0i + s) / di;
-    x[row] = t[row] + d0i + (c.c_d * d0i + c.c_r * rh1);
+    x[row] = ti + d0i + (c.c_d * d0i + c.c_r * rh1);
   }
 }
 
@@ -387,8 +395,9 @@ __global__ __launch_bounds__(BLOCK) void k_amg_prolong(int n, const int32_t* __r
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   int lo = ptr[min(i, n - 1)], hi = ptr[min(i, n - 1) + 1];
   if (stopped(ctl) || i >= n) return;
+  const double xi = xs[i];
   double s = csr_lane_dot<1, 4>(lo, hi, col, val, [&](int j) { return xc[j]; });
-  t[i] = xs[i] + s;
+  t[i] = xi + s;
 }
 
 // coarsest: x = A_L^-1 b with the dense inverse (row-major, n <= 2048): one block per row, threads

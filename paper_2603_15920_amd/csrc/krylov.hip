@@ -721,14 +721,16 @@ __global__ __launch_bounds__(BLOCK) void k_bi_v(SellView A, Tiles T, const doubl
   // (staging these stores through LDS measured slower here: the rounds' barriers hold back the
   // gathers of the waves that could run ahead)
   FOR_TILE_CELLS(i) {
-    double ay[NC];
+    double rhi[NC], ay[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rhi[c] = rh[(size_t)i * NC + c];  // in flight with the row's loads
     sell_row_f<NC>(A, i, [&](int j, int c) { return p[(size_t)j * NC + c] / A.diag[j]; }, ay);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!st->active[c]) continue;
       size_t at = (size_t)i * NC + c;
       v[at] = ay[c];
-      acc[c] += rh[at] * ay[c];
+      acc[c] += rhi[c] * ay[c];
     }
   }
   put_partial<NC>(acc, part, T.ntile, ti.t);

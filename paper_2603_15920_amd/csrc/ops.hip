@@ -117,9 +117,10 @@ __global__ __launch_bounds__(OP_MAX_BLOCK) void k_grad(MeshView<T> m, int table,
   const int i = base + threadIdx.x;
   T res[3 * NC];
   if (i < m.nc) {
+    const T vi = m.V[i];  // in flight with the row's loads
     T acc[NC][3];
     gauss_row_sum<T, NC>(m, table, phi, phib, i, acc);
-    T rv = T(1) / m.V[i];
+    T rv = T(1) / vi;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll

@@ -334,6 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
   if (i < nc) {
   SlotRange R = slots_of(slice_start, uw, i);
   double h[3] = {b[3 * (size_t)i], b[3 * (size_t)i + 1], b[3 * (size_t)i + 2]};
+  const double d = diag[i], vi = V[i];  // in flight with the row's loads
   // slots in layout order, the first four with every load issued before any is used
   walk_row<4>(R.width, [&](auto Wc, int k0) {
     constexpr int N = decltype(Wc)::value;
@@ -354,10 +355,9 @@ __global__ __launch_bounds__(BLOCK) void k_hbya(int nc, const int32_t* __restric
 #pragma unroll
       for (int c = 0; c < 3; ++c) h[c] -= a[k] * uj[k][c];
   });
-  double d = diag[i];
 #pragma unroll
   for (int c = 0; c < 3; ++c) hd[c] = h[c] / d;
-  rAU[i] = V[i] / d;
+  rAU[i] = vi / d;
   }
   store_rows<3>(HbyA, base, nc, hd, lds);
 }
@@ -407,34 +407,49 @@ __global__ __launch_bounds__(BLOCK) void k_passemble(MeshView<double> m, const d
   int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (i >= m.nc) return;
   SlotRange R = slots_of(m, i);
+  const int8_t ref = is_ref[i];
   double d = 0.0, r = 0.0;
   const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
-#pragma unroll 4
-  for (int k = 0; k < R.width; ++k) {
-    int at = R.base + k * SLICE;
-    int sf = m.slot_face[at];
-    if (sf == SLOT_PAD) continue;
-    double a = 0.0;
-    if (sf < m.nfi) {
-      bool nb = sf < 0;
-      int f = nb ? -sf - 1 : sf;
-      double af = aF[f];
-      d += af;
-      a = -af;
-      double t = -phiH[f] + ncorr[f];
-      r += nb ? -t : t;
-    } else {
-      int b = sf - m.nfi;
-      r -= phiH[m.nfi + b];
-      if (codeP[b] == BC_FIXED) {
-        double af = aF[m.nfi + b];
-        d += af;
-        r += af * pbv[b];
-      }
+  // slots in layout order, the first four with all their loads issued before any is used
+  walk_row<4>(R.width, [&](auto Wc, int k0) {
+    constexpr int N = decltype(Wc)::value;
+    int sf[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) sf[k] = m.slot_face[R.base + (k0 + k) * SLICE];
+    double af[N], ph[N], nc[N], pb[N];
+    int8_t cp[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      // internal face f, or the boundary face's entries at nfi + b; padding reads entry 0
+      const bool in = slot_internal(sf[k], m.nfi), bnd = sf[k] != SLOT_PAD && sf[k] >= m.nfi;
+      const int fe = in ? (sf[k] < 0 ? -sf[k] - 1 : sf[k]) : (bnd ? sf[k] : 0);
+      af[k] = aF[fe];
+      ph[k] = phiH[fe];
+      nc[k] = in ? ncorr[fe] : 0.0;
+      cp[k] = bnd ? codeP[sf[k] - m.nfi] : int8_t(0);
+      pb[k] = bnd ? pbv[sf[k] - m.nfi] : 0.0;
     }
-    val[at] = a;
-  }
-  if (is_ref[i]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (sf[k] == SLOT_PAD) continue;
+      double a = 0.0;
+      if (sf[k] < m.nfi) {
+        bool nb = sf[k] < 0;
+        d += af[k];
+        a = -af[k];
+        double t = -ph[k] + nc[k];
+        r += nb ? -t : t;
+      } else {
+        r -= ph[k];
+        if (cp[k] == BC_FIXED) {
+          d += af[k];
+          r += af[k] * pb[k];
+        }
+      }
+      val[R.base + (k0 + k) * SLICE] = a;
+    }
+  });
+  if (ref) {
     r += d * pref;
     d = d + d;
   }
@@ -469,11 +484,16 @@ __global__ __launch_bounds__(BLOCK) void k_ucorr(MeshView<double> m, const doubl
   __shared__ double lds[3 * BLOCK];
   double un[3] = {0.0, 0.0, 0.0};
   if (i < m.nc) {
+    // own values first, in flight with the row's loads
+    const double ra = rAU[i], vi = m.V[i];
+    double hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hi[c] = HbyA[3 * (size_t)i + c];
     double acc[1][3];
     gauss_row_sum<double, 1>(m, DIFVM_BC_P, p, pbv, i, acc);
-    double s = rAU[i] / m.V[i];
+    double s = ra / vi;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) un[c] = HbyA[3 * (size_t)i + c] - s * acc[0][c];
+    for (int c = 0; c < 3; ++c) un[c] = hi[c] - s * acc[0][c];
   }
   store_rows<3>(U, base, m.nc, un, lds);
 }
