@@ -44,9 +44,12 @@ __global__ __launch_bounds__(BLOCK) void k_gradT(MeshView<double> m, int table, 
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int e = 0; e < 3; ++e) gi[c][e] = gbar[((size_t)i * NC + c) * 3 + e] * rvi;
-    double acc[NC];
+    double acc[NC], pb0[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+      acc[c] = 0.0;
+      pb0[c] = phibar[(size_t)i * NC + c];  // read before the row's loads, added after
+    }
     const int8_t* code = m.bcode + table * m.nfb;
     // slots in layout order; for one component the first four with every load issued before any
     // is used (indices in range whatever the slot holds).  For three components one at a time: two
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradT(MeshView<double> m, int table, 
       }
     });
 #pragma unroll
-    for (int c = 0; c < NC; ++c) phibar[(size_t)i * NC + c] += acc[c];
+    for (int c = 0; c < NC; ++c) phibar[(size_t)i * NC + c] = pb0[c] + acc[c];
   }
 }
 
@@ -221,6 +224,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_corr_cells(MeshView<double> m, co
     double ra = 0.0, hb[3] = {0.0, 0.0, 0.0};
     double gi[3] = {gpo[3 * (size_t)i], gpo[3 * (size_t)i + 1], gpo[3 * (size_t)i + 2]};
     const double rAUi = rAU[i];
+    // the accumulated cotangents of this cell, read before the row's loads and added after
+    const double ra0 = rAUbar[i];
+    double hb0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hb0[c] = HbyAbar[3 * (size_t)i + c];
     const int8_t* codeU = m.bcode + DIFVM_BC_U * m.nfb;
     const int8_t* codeP = m.bcode + DIFVM_BC_P * m.nfb;
     // slots in layout order, two at a time with every load issued before any is used
@@ -279,9 +287,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_corr_cells(MeshView<double> m, co
         }
       }
     });
-    rAUbar[i] += ra;
+    rAUbar[i] = ra0 + ra;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) hout[c] = HbyAbar[3 * (size_t)i + c] + hb[c];
+    for (int c = 0; c < 3; ++c) hout[c] = hb0[c] + hb[c];
   }
   store_rows<3>(HbyAbar, base, m.nc, hout, lds);
   store_rows<3>(gpobar, base, m.nc, gb, lds);
