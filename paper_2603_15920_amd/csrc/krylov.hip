@@ -560,75 +560,83 @@ enum BiStage { BI_INIT = 0, BI_ALPHA = 1, BI_SO = 2, BI_X = 3 };
 template <int NC, int NV>
 __global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __restrict__ part, Tiles T, BiState* sts) {
   BiState* st = sts + blockIdx.x;
-  if (stage != BI_INIT && !st->any) return;
+  // the segment's state and tile range loaded together, before the partials (thread 0 works on the
+  // copy and stores it back whole; no other block touches this segment's state).  No early return
+  // for a stopped segment, which would hold the other loads back behind the flag's: with no active
+  // component the update below changes nothing.
+  BiState S = *st;
+  const int f = T.first[blockIdx.x], n = T.count[blockIdx.x];
   double tot[NV];
-  sum_seg<NV>(part, T, blockIdx.x, tot);
+  seg_thread_sum<NV>(part, T.ntile, f, n, tot);
+  __shared__ double lds[NV][BLOCK / 64];
+  block_sum<NV>(tot, lds);
   if (threadIdx.x != 0) return;
   int any = 0;
   for (int c = 0; c < NC; ++c) {
     if (stage == BI_INIT) {
       double bn = sqrt(tot[c]), rn = sqrt(tot[NC + c]);
-      st->bn[c] = bn;
-      st->iters[c] = 0;
-      st->status[c] = 0;
-      st->phase[c] = 0;
-      st->zero_b[c] = bn == 0.0;
-      st->res[c] = bn == 0.0 ? 0.0 : rn / bn;
-      st->active[c] = (bn == 0.0 || rn <= st->tol * bn) ? 0 : 1;
-      st->rho[c] = st->alpha[c] = st->omega[c] = 1.0;
-      st->rho1[c] = tot[NC + c];  // rhat = r, so rhat.r = r.r
-      if (st->active[c] && st->maxit <= 0) {
-        st->active[c] = 0;
-        st->status[c] = DIFVM_WARN_NOT_CONVERGED;
-      } else if (st->active[c] && st->rho1[c] == 0.0) {
-        st->active[c] = 0;
-        st->status[c] = DIFVM_WARN_BREAKDOWN;
+      S.bn[c] = bn;
+      S.iters[c] = 0;
+      S.status[c] = 0;
+      S.phase[c] = 0;
+      S.zero_b[c] = bn == 0.0;
+      S.res[c] = bn == 0.0 ? 0.0 : rn / bn;
+      S.active[c] = (bn == 0.0 || rn <= S.tol * bn) ? 0 : 1;
+      S.rho[c] = S.alpha[c] = S.omega[c] = 1.0;
+      S.rho1[c] = tot[NC + c];  // rhat = r, so rhat.r = r.r
+      if (S.active[c] && S.maxit <= 0) {
+        S.active[c] = 0;
+        S.status[c] = DIFVM_WARN_NOT_CONVERGED;
+      } else if (S.active[c] && S.rho1[c] == 0.0) {
+        S.active[c] = 0;
+        S.status[c] = DIFVM_WARN_BREAKDOWN;
       }
-      if (st->active[c]) st->beta[c] = (st->rho1[c] / st->rho[c]) * (st->alpha[c] / st->omega[c]);
-    } else if (!st->active[c]) {
+      if (S.active[c]) S.beta[c] = (S.rho1[c] / S.rho[c]) * (S.alpha[c] / S.omega[c]);
+    } else if (!S.active[c]) {
       continue;
     } else if (stage == BI_ALPHA) {
-      st->alpha[c] = st->rho1[c] / tot[c];
+      S.alpha[c] = S.rho1[c] / tot[c];
     } else if (stage == BI_SO) {
       // the test on |s| first (the iteration ends with x += alpha y if it passes), then omega
       double sn = sqrt(tot[(2 * NC + c) % NV]);  // NV = 3 NC in this stage
-      if (sn <= st->tol * st->bn[c]) {
-        st->phase[c] = 1;
-        st->res[c] = sn / st->bn[c];
+      if (sn <= S.tol * S.bn[c]) {
+        S.phase[c] = 1;
+        S.res[c] = sn / S.bn[c];
       } else if (tot[NC + c] == 0.0) {
-        st->active[c] = 0;
-        st->status[c] = DIFVM_WARN_BREAKDOWN;
+        S.active[c] = 0;
+        S.status[c] = DIFVM_WARN_BREAKDOWN;
       } else {
-        st->omega[c] = tot[c] / tot[NC + c];
+        S.omega[c] = tot[c] / tot[NC + c];
       }
     } else {  // BI_X
-      int it = st->iters[c] + 1;
-      st->iters[c] = it;
-      if (st->phase[c]) {
-        st->active[c] = 0;
+      int it = S.iters[c] + 1;
+      S.iters[c] = it;
+      if (S.phase[c]) {
+        S.active[c] = 0;
       } else {
-        st->rho[c] = st->rho1[c];
+        S.rho[c] = S.rho1[c];
         double rn = sqrt(tot[c]);
-        st->res[c] = rn / st->bn[c];
-        if (rn <= st->tol * st->bn[c]) {
-          st->active[c] = 0;
-        } else if (it >= st->maxit) {
-          st->active[c] = 0;
-          st->status[c] = DIFVM_WARN_NOT_CONVERGED;
+        S.res[c] = rn / S.bn[c];
+        if (rn <= S.tol * S.bn[c]) {
+          S.active[c] = 0;
+        } else if (it >= S.maxit) {
+          S.active[c] = 0;
+          S.status[c] = DIFVM_WARN_NOT_CONVERGED;
         } else {
-          st->rho1[c] = tot[NC + c];
-          if (st->rho1[c] == 0.0) {
-            st->active[c] = 0;
-            st->status[c] = DIFVM_WARN_BREAKDOWN;
+          S.rho1[c] = tot[NC + c];
+          if (S.rho1[c] == 0.0) {
+            S.active[c] = 0;
+            S.status[c] = DIFVM_WARN_BREAKDOWN;
           } else {
-            st->beta[c] = (st->rho1[c] / st->rho[c]) * (st->alpha[c] / st->omega[c]);
+            S.beta[c] = (S.rho1[c] / S.rho[c]) * (S.alpha[c] / S.omega[c]);
           }
         }
       }
     }
-    any |= st->active[c];
+    any |= S.active[c];
   }
-  st->any = any;
+  S.any = any;
+  *st = S;
 }
 
 template <int NC>
