@@ -639,11 +639,12 @@ __global__ __launch_bounds__(BLOCK) void k_bi_fin(int stage, const double* __res
   *st = S;
 }
 
+// r = b - A x, rhat = r, partials b.b and r.r (p and v start at zero: the first direction pass
+// writes p = r without reading them)
 template <int NC>
 __global__ __launch_bounds__(BLOCK) void k_bi_init(SellView A, Tiles T, const double* __restrict__ b,
                                                    const double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ rh, double* __restrict__ p, double* __restrict__ v,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ rh, double* __restrict__ part) {
   TileIdx ti = tile_idx(T);
   double acc[2 * NC];
 #pragma unroll
@@ -657,8 +658,6 @@ __global__ __launch_bounds__(BLOCK) void k_bi_init(SellView A, Tiles T, const do
       double bi = b[at], ri = bi - ax[c];
       r[at] = ri;
       rh[at] = ri;
-      p[at] = 0.0;
-      v[at] = 0.0;
       acc[c] += bi * bi;
       acc[NC + c] += ri * ri;
     }
@@ -697,10 +696,10 @@ __device__ __forceinline__ void sell_row_f(const SellView& A, int i, F&& f, doub
 }
 
 // The right-preconditioned vectors y = p / d and z = s / d are formed where they are used, not stored.
-// p = r + beta (p - omega v)
+// p = r + beta (p - omega v); the first iteration's p = r (p and v are zero then and not read)
 template <int NC>
 __global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, Tiles T, const double* __restrict__ r, double* __restrict__ p,
-                                                  const double* __restrict__ v, const BiState* sts) {
+                                                  const double* __restrict__ v, const BiState* sts, int first) {
   TileIdx ti = tile_idx(T);
   const BiState* st = sts + ti.s;
   if (!st->any) return;
@@ -712,7 +711,8 @@ __global__ __launch_bounds__(BLOCK) void k_bi_dir(SellView A, Tiles T, const dou
     if (e >= e1) break;
     int c = e % NC;
     if (!st->active[c]) continue;
-    p[e] = r[e] + st->beta[c] * (p[e] - st->omega[c] * v[e]);
+    if (first) p[e] = r[e];
+    else p[e] = r[e] + st->beta[c] * (p[e] - st->omega[c] * v[e]);
   }
 }
 
@@ -885,14 +885,14 @@ static SolveResult bicgstab_nc(difvm_mesh* m, SellMatrix A, const double* b, dou
   int G = T.ntile, nseg = m->d.nseg;
   k_bi_state_init<<<(nseg + 63) / 64, 64, 0, s>>>(w->bi, nseg, tol, maxit);
   double* part = w->partials;
-  k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, T, b, x, w->r, w->rh, w->p, w->v, part);
+  k_bi_init<NC><<<G, BLOCK, 0, s>>>(V, T, b, x, w->r, w->rh, part);
   k_bi_fin<NC, 2 * NC><<<nseg, BLOCK, 0, s>>>(BI_INIT, part, T, w->bi);
   k_bi_zero<NC><<<G, BLOCK, 0, s>>>(T, x, w->bi);
   DIFVM_HIP(hipGetLastError());
   int done = 0;  // iterations queued
   auto queue_iters = [&](int nb) {
     for (int it = 0; it < nb; ++it) {
-      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->bi);
+      k_bi_dir<NC><<<G, BLOCK, 0, s>>>(V, T, w->r, w->p, w->v, w->bi, done + it == 0 ? 1 : 0);
       k_bi_v<NC><<<G, BLOCK, 0, s>>>(V, T, w->p, w->v, w->rh, part, w->bi);
       k_bi_fin<NC, NC><<<nseg, BLOCK, 0, s>>>(BI_ALPHA, part, T, w->bi);
       k_bi_s<NC><<<G, BLOCK, 0, s>>>(T, w->r, w->v, w->s, w->bi);
