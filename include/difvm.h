@@ -313,7 +313,8 @@ difvm_status difvm_mesh_get_launch(const difvm_mesh* mesh, int32_t knob, int32_t
 
 /* Autotuner: for every knob, times each candidate value on this mesh (HIP events on the context's
  * stream, scratch inputs allocated and freed here, one warm-up and repeated launches) and keeps the
- * fastest.  cache_path (may be NULL) names a JSON file of choices keyed by GPU architecture, knob and
+ * fastest.  The PCG grid's candidates are one block per tile, 1024, 512 and 256 blocks, and the
+ * grids that give every block at most 2 or 4 of the tiles its XCD owns.  cache_path (may be NULL) names a JSON file of choices keyed by GPU architecture, knob and
  * mesh size bucket (floor(log2(cells)), and whether the mesh has one or several segments): knobs
  * found there are applied without timing, the others are timed and the file is rewritten with them
  * added.  n_timed (may be NULL) receives the number of knobs timed.  Synchronises.  Errors:
